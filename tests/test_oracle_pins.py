@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, brute force over all states, hand-worked fixtures,
+closed forms, exact rational arithmetic, or invariants that a plausible
+mistake (dropped factor 2, wrong sign, transposed operand, off-by-one in a
+tenure or an index) would break.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_13947_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_sym(n, seed, lo=-20, hi=20, density=1.0):
+    rng = np.random.default_rng(seed)
+    U = rng.integers(lo, hi + 1, size=(n, n)) * (rng.random((n, n)) < density)
+    Q = np.triu(U, 1)
+    Q = Q + Q.T + np.diag(rng.integers(lo, hi + 1, size=n))
+    return Q.astype(np.int16)
+
+
+def all_states(n):
+    return np.array(list(itertools.product([0, 1], repeat=n)), np.uint8)
+
+
+# --------------------------------------------------------------------------- Philox
+def test_philox_known_answer_vectors():
+    kat = json.load(open(os.path.join(GOLDEN, "philox_kat.json")))
+    for v in kat["vectors"]:
+        ctr = [int(w, 16) for w in v["ctr"]]
+        key = [int(w, 16) for w in v["key"]]
+        out = [int(w, 16) for w in v["out"]]
+        assert list(oracle.philox(ctr, key)) == out
+
+
+def test_init_bits_are_fair():
+    X = oracle.init_x(4096, 8, seed=12345)
+    assert set(np.unique(X)) <= {0, 1}
+    frac = X.mean()
+    assert abs(frac - 0.5) < 5 * math.sqrt(0.25 / X.size)
+    # different solutions differ
+    assert (X[0] != X[1]).mean() > 0.4
+
+
+# --------------------------------------------------------------------------- eq. 1
+def test_energy_matches_quadratic_form_and_brute_force_optimum():
+    Q = rand_sym(10, 1)
+    S = all_states(10)
+    Ed = np.array([oracle.energy_def(Q, s) for s in S])
+    Q64 = Q.astype(np.int64)
+    Eq = np.einsum("bi,ij,bj->b", S.astype(np.int64), Q64, S.astype(np.int64))
+    assert (Ed == Eq).all()
+
+
+def test_energy_diagonal_only_closed_form():
+    rng = np.random.default_rng(3)
+    d = rng.integers(-50, 51, size=12)
+    Q = np.diag(d).astype(np.int16)
+    S = all_states(12)
+    best = min(oracle.energy_def(Q, s) for s in S)
+    assert best == int(np.minimum(d, 0).sum())
+
+
+def test_field_and_energy_identity():
+    Q = rand_sym(40, 2, -100, 100, 0.3)
+    X = inputs.random_solutions(5, 40, 7)
+    H = oracle.field(Q, X)
+    assert (H == (X.astype(np.int64) @ Q.astype(np.int64).T)).all()
+    E = oracle.energy(X, H)
+    for p in range(5):
+        assert E[p] == oracle.energy_def(Q, X[p])
+
+
+def test_flip_delta_is_exact_energy_difference():
+    Q = rand_sym(25, 4, -100, 100, 0.5)
+    X = inputs.random_solutions(6, 25, 8)
+    H = oracle.field(Q, X)
+    for p in range(6):
+        e0 = oracle.energy_def(Q, X[p])
+        for i in range(25):
+            x1 = X[p].copy()
+            x1[i] ^= 1
+            assert oracle.flip_delta(Q, X[p], H[p], i) == oracle.energy_def(Q, x1) - e0
+
+
+def test_eta_is_column_abs_sum():
+    Q = rand_sym(30, 5, -100, 100, 0.4)
+    assert (oracle.eta(Q) == np.abs(Q.astype(np.int64)).sum(0)).all()
+
+
+# --------------------------------------------------------------------------- Alg. 1 Tabu
+def test_tabu_hand_worked_fixtures():
+    fx = json.load(open(os.path.join(GOLDEN, "tabu_fixtures.json")))
+    for f in fx["fixtures"]:
+        Q = np.array(f["Q"], np.int16)
+        x0 = np.array(f["x0"], np.uint8)
+        h0 = (Q.astype(np.int64) @ x0).astype(np.int32)
+        ov0 = oracle.energy_def(Q, x0)
+        x, h, ov, T, LF = oracle.tabu(Q, x0, h0, ov0, f["alpha"], f["tenure"], f["aspiration"])
+        assert list(x) == f["x_min"], f["name"]
+        assert list(h) == f["h_min"], f["name"]
+        assert ov == f["ov_min"], f["name"]
+        assert list(T) == f["T"], f["name"]
+        assert list(LF) == f["lastflip"], f["name"]
+
+
+@pytest.mark.parametrize("asp", [True, False])
+def test_tabu_invariants(asp):
+    n = 60
+    Q = rand_sym(n, 9, -100, 100, 0.3)
+    x0 = inputs.random_solutions(1, n, 10)[0]
+    h0 = oracle.field(Q, x0)[0]
+    ov0 = oracle.energy_def(Q, x0)
+    alpha = 5 * n
+    x, h, ov, T, LF = oracle.tabu(Q, x0, h0, ov0, alpha, max(1, n // 10), asp)
+    assert (h == (Q.astype(np.int64) @ x)).all()          # field follows x_min
+    assert ov == oracle.energy_def(Q, x)                    # OV_min is the energy of x_min
+    assert ov <= ov0
+    assert T.sum() == alpha                                 # one flip per step
+    assert LF.max() <= alpha and (LF[T == 0] == 0).all()
+
+
+def test_tabu_zero_steps_is_identity():
+    Q = rand_sym(20, 11)
+    x0 = inputs.random_solutions(1, 20, 12)[0]
+    h0 = oracle.field(Q, x0)[0]
+    ov0 = oracle.energy_def(Q, x0)
+    x, h, ov, T, LF = oracle.tabu(Q, x0, h0, ov0, 0, 3, True)
+    assert (x == x0).all() and (h == h0).all() and ov == ov0 and T.sum() == 0
+
+
+def test_tabu_reaches_brute_force_optimum_on_tiny_instances():
+    hits = 0
+    for seed in range(10):
+        n = 12
+        Q = rand_sym(n, 100 + seed, -30, 30)
+        opt = min(oracle.energy_def(Q, s) for s in all_states(n))
+        x0 = inputs.random_solutions(1, n, 200 + seed)[0]
+        h0 = oracle.field(Q, x0)[0]
+        _, _, ov, _, _ = oracle.tabu(Q, x0, h0, oracle.energy_def(Q, x0), 20 * n, 3, True)
+        assert ov >= opt
+        hits += ov == opt
+    assert hits >= 8
+
+
+# --------------------------------------------------------------------------- Alg. 4 keys
+def test_keys_equal_exact_rational_aggregation():
+    n, z = 17, 5
+    Q = rand_sym(n, 13, -100, 100, 0.5)
+    X = inputs.random_solutions(z, n, 14)
+    rng = np.random.default_rng(15)
+    T = rng.integers(0, 9, size=(z, n)).astype(np.int32)
+    T[2] = 0                                   # no flips: Delta := 1 everywhere
+    et = oracle.eta(Q)
+    K = oracle.keys(et, X, T, W=(2, 2, 1))
+    w1, w2, w3 = Fraction(1), Fraction(1), Fraction(1, 2)   # default weight table
+    emax = int(et.max())
+    for p in range(z):
+        tmax = max(int(T[p].max()), 1)
+        D = Fraction(2 * emax * z * tmax)
+        for j in range(n):
+            eta_hat = Fraction(int(et[j]), emax)
+            gam = 1 - abs(Fraction(int(X[:, j].sum())) - Fraction(z, 2)) / Fraction(z, 2)
+            delta = 1 - Fraction(int(T[p, j]), tmax)
+            A = w1 * eta_hat + w2 * gam - w3 * delta
+            assert Fraction(int(K[p, j])) == A * D
+
+
+def test_order_matches_lexsort():
+    rng = np.random.default_rng(16)
+    K = rng.integers(-5, 5, size=300).astype(np.int64)     # many ties
+    o = oracle.order(K)
+    ref = np.lexsort((np.arange(300), -K))
+    assert (o == ref).all()
+
+
+# --------------------------------------------------------------------------- eq. 4
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_subqubo_energy_differs_from_full_energy_by_a_constant(seed):
+    n, m = 14, 7
+    Q = rand_sym(n, 20 + seed, -50, 50, 0.7)
+    x = inputs.random_solutions(1, n, 30 + seed)[0]
+    h = oracle.field(Q, x)[0]
+    S = np.sort(np.random.default_rng(seed).permutation(n)[:m]).astype(np.int32)
+    Tq, c, F0, y0 = oracle.extract(Q, x, h, S)
+    assert (np.diag(Tq) == 0).all() and (Tq == Tq.T).all()
+    assert (y0 == x[S]).all()
+    consts = set()
+    for y in all_states(m):
+        xx = x.copy()
+        xx[S] = y
+        consts.add(oracle.energy_def(Q, xx) - oracle.sub_energy(Tq, c, y))
+    assert len(consts) == 1
+    # flip basis: flipping y_a changes f_S by (1 - 2 y_a) F0_a
+    f0 = oracle.sub_energy(Tq, c, y0)
+    for a in range(m):
+        y1 = y0.copy()
+        y1[a] ^= 1
+        assert oracle.sub_energy(Tq, c, y1) - f0 == (1 - 2 * int(y0[a])) * int(F0[a])
+
+
+def test_subqubo_linear_term_uses_outside_variables_only():
+    n = 9
+    Q = rand_sym(n, 40)
+    x = np.ones(n, np.uint8)
+    S = np.array([0, 4, 8], np.int32)
+    Tq, c, F0, y0 = oracle.extract(Q, x, oracle.field(Q, x)[0], S)
+    outside = [j for j in range(n) if j not in S]
+    for a, i in enumerate(S):
+        assert c[a] == Q[i, i] + 2 * sum(int(Q[i, j]) for j in outside)
+
+
+# --------------------------------------------------------------------------- schedules
+def test_mutation_rate_closed_forms():
+    assert oracle.mutation_rate(0) == pytest.approx(0.6, abs=1e-15)
+    assert oracle.mutation_rate(15) == 0.0
+    assert oracle.mutation_rate(30) == pytest.approx(0.6 * 0.99 ** 30, rel=1e-14)
+    assert oracle.mutation_rate(5) == pytest.approx(0.3 * 1.5 * 0.99 ** 5, rel=1e-14)
+
+
+def test_temperature_schedule_endpoints_and_shape():
+    nsw = 101
+    assert oracle.temperature(0, nsw, 100.0, 1.0) == 100.0
+    assert oracle.temperature(nsw - 1, nsw, 100.0, 1.0) == pytest.approx(1.0, abs=1e-12)
+    assert oracle.temperature(50, nsw, 100.0, 1.0) == pytest.approx(50.5, abs=1e-12)
+    ts = [oracle.temperature(s, nsw, 100.0, 1.0) for s in range(nsw)]
+    assert all(a >= b for a, b in zip(ts, ts[1:]))
+    assert oracle.temperature(0, 1, 7.0, 1.0) == 7.0
+
+
+def test_threshold_table_closed_form():
+    B = 6
+    thr = oracle.threshold_table(5, B, 40.0, 0.0)
+    assert (thr[-1] == 0).all()                       # zero temperature: only dE <= 0
+    for s in range(5):
+        T = oracle.temperature(s, 5, 40.0, 0.0)
+        for b in range(1 << B):
+            expect = math.floor(T * (B * math.log(2) - math.log(b + 0.5)))
+            assert abs(int(thr[s, b]) - expect) <= 1       # libm rounding only
+            assert thr[s, b] >= 0
+        assert (np.diff(thr[s]) <= 0).all()
+    big = oracle.threshold_table(1, 10, 1e12, 1e12)
+    assert big.max() == 2**31 - 1
+
+
+# --------------------------------------------------------------------------- annealer
+def _job(n=40, m=16, seed=0):
+    Q = rand_sym(n, 50 + seed, -100, 100, 0.5)
+    x = inputs.random_solutions(1, n, 60 + seed)[0]
+    h = oracle.field(Q, x)[0]
+    S = np.sort(np.random.default_rng(seed).permutation(n)[:m]).astype(np.int32)
+    return oracle.extract(Q, x, h, S)
+
+
+def test_anneal_all_accept_table_flips_every_variable_each_sweep():
+    Tq, c, F0, y0 = _job()
+    for nsw in (1, 2, 3):
+        thr = np.full((nsw, 16), 2**31 - 1, np.int32)
+        Y, e = oracle.anneal(Tq, F0, y0, thr, R=2, seed=1, inst=0, B=4)
+        expect = y0 ^ (nsw & 1)
+        assert (Y == expect).all()
+        for r in range(2):
+            assert e[r] == oracle.sub_energy(Tq, c, expect) - oracle.sub_energy(Tq, c, y0)
+
+
+def test_anneal_none_accept_table_keeps_the_start():
+    Tq, c, F0, y0 = _job(seed=1)
+    thr = np.full((3, 16), -(2**31), np.int32)
+    Y, e = oracle.anneal(Tq, F0, y0, thr, R=3, seed=1, inst=0, B=4)
+    assert (Y == y0).all() and (e == 0).all()
+
+
+def test_anneal_energy_bookkeeping_and_strict_descent_local_optimum():
+    Tq, c, F0, y0 = _job(n=60, m=24, seed=2)
+    thr = np.full((30, 16), -1, np.int32)                # accept only dE <= -1
+    Y, e = oracle.anneal(Tq, F0, y0, thr, R=2, seed=3, inst=5, B=4)
+    for r in range(2):
+        fy = oracle.sub_energy(Tq, c, Y[r])
+        assert e[r] == fy - oracle.sub_energy(Tq, c, y0)
+        assert e[r] <= 0
+        for a in range(len(y0)):                          # 1-flip local minimum
+            y1 = Y[r].copy()
+            y1[a] ^= 1
+            assert oracle.sub_energy(Tq, c, y1) >= fy
+
+
+def test_anneal_random_table_energy_bookkeeping():
+    Tq, c, F0, y0 = _job(n=50, m=20, seed=4)
+    thr = oracle.threshold_table(40, 10, 2000.0, 5.0)
+    Y, e = oracle.anneal(Tq, F0, y0, thr, R=4, seed=99, inst=7, B=10)
+    for r in range(4):
+        assert e[r] == oracle.sub_energy(Tq, c, Y[r]) - oracle.sub_energy(Tq, c, y0)
+    assert len({bytes(Y[r]) for r in range(4)}) > 1           # replicas differ
+
+
+def test_anneal_single_variable_acceptance_frequency_matches_table():
+    # m = 1, F0 = dE > 0 fixed, y0 = 0: every sweep is one independent trial
+    # as long as it rejects; use many instances and count first-sweep accepts.
+    B = 8
+    thr = np.zeros((1, 1 << B), np.int32)
+    thr[0] = np.arange(1 << B)[::-1] * 4                 # decreasing thresholds
+    dE = 300
+    p_exact = np.mean(thr[0] >= dE)
+    Tq = np.zeros((1, 1), np.int32)
+    acc = 0
+    N = 4000
+    for inst in range(N):
+        Y, e = oracle.anneal(Tq, np.array([dE], np.int32), np.zeros(1, np.uint8), thr, 1, 77, inst, B)
+        acc += int(Y[0, 0])
+    se = math.sqrt(p_exact * (1 - p_exact) / N)
+    assert abs(acc / N - p_exact) < 5 * se
+
+
+# --------------------------------------------------------------------------- mutation
+def _mut_case(n=200, seed=0):
+    rng = np.random.default_rng(seed)
+    K = rng.integers(-1000, 1000, size=n).astype(np.int64)
+    inU = np.zeros(n, np.uint8)
+    inU[rng.permutation(n)[:40]] = 1
+    x = inputs.random_solutions(1, n, seed)[0]
+    return x, K, inU
+
+
+def test_mutation_zero_rate_at_half_period():
+    x, K, inU = _mut_case()
+    x1, flip, k = oracle.mutate(x, K, inU, t=15, p=0, seed=5)
+    assert k == 0 and flip.sum() == 0 and (x1 == x).all()
+
+
+def test_mutation_subset_is_top_k_outside_the_im_set():
+    x, K, inU = _mut_case(seed=1)
+    x1, flip, k = oracle.mutate(x, K, inU, t=0, p=3, seed=5)
+    nc = int((inU == 0).sum())
+    assert k == math.floor(nc * 0.6)
+    cand = np.flatnonzero(inU == 0)
+    top = cand[np.lexsort((cand, -K[cand]))][:k]
+    assert set(np.flatnonzero(flip)) <= set(top)
+    assert (x1 ^ x == flip).all()
+    assert flip[inU == 1].sum() == 0
+
+
+def test_mutation_probability_extremes():
+    n = 400
+    x = np.zeros(n, np.uint8)
+    inU = np.zeros(n, np.uint8)
+    K = np.full(n, 7, np.int64)                             # K_hi == K_lo -> P = 1/2
+    _, flip, k = oracle.mutate(x, K, inU, t=0, p=0, seed=9)
+    assert k == 240
+    assert abs(flip.sum() / k - 0.5) < 5 * math.sqrt(0.25 / k)
+    K2 = np.zeros(n, np.int64)
+    K2[:300] = 10                                            # top 240 all at K_hi -> P = 2^32-1
+    _, flip2, k2 = oracle.mutate(x, K2, inU, t=0, p=0, seed=9)
+    assert flip2[:240].sum() == 240 and flip2[240:].sum() == 0
+
+
+# --------------------------------------------------------------------------- Alg. 2
+def test_run_state_is_consistent_and_reaches_optimum_on_tiny_instances():
+    hits = 0
+    for seed in range(6):
+        n = 14
+        Q = rand_sym(n, 300 + seed, -30, 30)
+        opt = min(oracle.energy_def(Q, s) for s in all_states(n))
+        thr = oracle.threshold_table(20, 8, 30.0, 0.5)
+        res = oracle.run(Q, z=4, seed=seed, iters=4, alpha=5 * n, tenure=1,
+                         job_m=np.full((4, 1), 5, np.int32), init_m=7, thr_init=thr, thr=thr,
+                         B=8, R=2)
+        H = oracle.field(Q, res["X"])
+        assert (res["H"] == H).all()
+        assert (res["E"] == oracle.energy(res["X"], H)).all()
+        assert res["ebest"] == oracle.energy_def(Q, res["xbest"])
+        assert res["ebest"] >= opt
+        assert all(a >= b for a, b in zip(res["trace"], res["trace"][1:]))
+        hits += res["ebest"] == opt
+    assert hits >= 5
