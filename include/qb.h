@@ -1,0 +1,245 @@
+/*
+ * qb.h -- C ABI of the MI355X (gfx950) IC-D^2S hot path.
+ *
+ * Paper: "IC-D^2S: A Hybrid Ising-Classical-Machines Data-Driven QUBO Solver
+ * Method", Abdollahi, Kamal, Pedram (ASP-DAC 2025, arXiv 2502.13947).
+ * The method minimises x^T Q x over binary x (eq. 1) by alternating Tabu
+ * search (Alg. 1), control-parameter selection (Alg. 4), an Ising-machine
+ * stage on extracted sub-QUBOs (eq. 4, Alg. 3) and mutation (Alg. 2).
+ *
+ * General rules for every call:
+ *  - Pointers named *_d are DEVICE pointers owned by the caller; they must
+ *    stay valid until the enqueued work completes.  Host pointers are named
+ *    *_h.  No call frees or retains caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    calls only enqueue work on it, except qb_problem_create_dense and
+ *    qb_check, which synchronise it.  Results are valid after the stream has
+ *    synchronised.
+ *  - Every call returns a qb_status; argument errors are detected on the host
+ *    before anything is enqueued.  Errors a kernel detects (a value outside a
+ *    documented range) are latched in the problem's device status word and
+ *    returned by qb_check.  No C++ exception crosses this boundary.
+ *  - No call allocates device memory except the handle constructors
+ *    qb_problem_create_dense and qb_batch_create.
+ *  - Layouts (row-major): Q int16 [n][n] symmetric; X uint8 [z][n] (0/1);
+ *    H int32 [z][n] with H[p][i] = sum_j Q[i][j] X[p][j]; E int64 [z].
+ *  - Results depend only on inputs, seeds and instance numbers: never on
+ *    stream, launch order or occupancy.
+ */
+#ifndef QB_H
+#define QB_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qb_status;
+#define QB_OK 0
+#define QB_E_ARG (-1)          /* bad pointer, size or flag */
+#define QB_E_NOT_SYMMETRIC (-2)/* Q != Q^T (eq. 1 is read as x^T Q x with Q symmetric) */
+#define QB_E_RANGE (-3)        /* a value would overflow the int32 field / key packing */
+#define QB_E_OVERLAP (-4)      /* jobs of one solution share a variable */
+#define QB_E_CAPACITY (-5)     /* size beyond what a kernel supports (see each call) */
+#define QB_E_HIP (-6)          /* a HIP runtime call failed; see qb_last_hip_error */
+#define QB_E_STATE (-7)        /* a device-side check failed (qb_check) */
+#define QB_E_UNSUPPORTED (-8)
+
+typedef struct qb_problem_s *qb_problem;
+
+typedef struct {
+    int32_t n;
+    int32_t int8_ok;     /* 1 when max |Q_ij| <= 127: an int8 copy of Q is kept */
+    int32_t qmax;        /* max |Q_ij| */
+    int64_t eta_max;     /* max_j eta_j */
+    double sigma;        /* sqrt(sum_{i != j} Q_ij^2 / n): the typical |dE| scale */
+} qb_problem_info;
+
+const char *qb_status_str(qb_status s);
+/* Last HIP error code seen by this thread (0 if none). */
+int32_t qb_last_hip_error(void);
+/* Library version string. */
+const char *qb_version(void);
+
+/* ---------------------------------------------------------------- problem
+ * Eq. 1 input.  Validates symmetry (QB_E_NOT_SYMMETRIC) and the range bound
+ * (2n+1) max|Q| < 2^31 that keeps local fields and move values in int32
+ * (QB_E_RANGE).  Builds the int8 copy (when |Q| <= 127), eta_j = sum_i |Q_ij|
+ * (Weight_Effect_Extraction) and the statistics of qb_problem_info.  The
+ * handle BORROWS Q_d (it must outlive the handle) and OWNS its derived
+ * buffers.  Synchronises `stream`.  n in [1, 65535]. */
+qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const int16_t *Q_d, void *stream);
+void qb_problem_destroy(qb_problem P);
+qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info_h);
+/* Copies eta (int64 [n]) into eta_d. */
+qb_status qb_problem_eta(qb_problem P, int64_t *eta_d, void *stream);
+/* Synchronises `stream` and returns QB_E_STATE if any kernel latched an error
+ * since the last qb_check (the latch is then cleared), else QB_OK. */
+qb_status qb_check(qb_problem P, void *stream);
+
+/* ---------------------------------------------------------------- a1
+ * Generate_Initial_Solution_Set (Alg. 2): X[p][j] = top bit of Philox4x32-10
+ * word (j mod 4) at counter (j/4, p, 0, 3<<28), key (seed lo, seed hi). */
+qb_status qb_init_solutions(int32_t n, int32_t z, uint64_t seed, uint8_t *X_d, void *stream);
+
+/* ---------------------------------------------------------------- a0/a8
+ * Local field H = X Q (all z solutions, from scratch). */
+qb_status qb_field(qb_problem P, int32_t z, const uint8_t *X_d, int32_t *H_d, void *stream);
+/* Exact energy E[p] = sum_i X[p][i] H[p][i] = x^T Q x (eq. 1), int64. */
+qb_status qb_energy(int32_t n, int32_t z, const uint8_t *X_d, const int32_t *H_d, int64_t *E_d,
+                    void *stream);
+/* Best tracking (Alg. 1/2 x_min, OV_min): for p = 0..z-1 in order, if
+ * E[p] < *ebest_d then *ebest_d = E[p] and xbest_d = X[p].  Initialise
+ * *ebest_d to INT64_MAX before the first call. */
+qb_status qb_best(int32_t n, int32_t z, const uint8_t *X_d, const int64_t *E_d, int64_t *ebest_d,
+                  uint8_t *xbest_d, void *stream);
+
+/* ---------------------------------------------------------------- a2
+ * Tabu search (Alg. 1) on every solution, in place.  Move value of k is the
+ * exact energy change Q_kk + 2(1-2x_k)h_k; each of `alpha` steps flips the
+ * lowest-index argmin among variables whose tenure counter is <= 0 or, when
+ * `aspiration` != 0, whose move reaches OV + move < OV_min (if none is
+ * allowed, the argmin over all); then C_i += tenure and every positive C is
+ * decremented.  On return X[p] = x_min, H[p] = Q x_min, E[p] = OV_min
+ * (E[p] must hold x^T Q x on entry), T[p][j] = flips of j, LF[p][j] = the
+ * 1-based step of j's last flip (0 if none).  Capacity: n <= 16384.  T_d and
+ * LF_d may not be NULL. */
+qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d, int64_t *E_d,
+                  int32_t alpha, int32_t tenure, int32_t aspiration, int32_t *T_d, int32_t *LF_d,
+                  void *stream);
+
+/* ---------------------------------------------------------------- a3
+ * Control parameters (eta, Delta, gamma) aggregated per Alg. 4 as exact
+ * integer keys with the same order as A within each solution:
+ *   K[p][j] = W1 eta_j z T'_p + W2 (z - |2 c_j - z|) eta_max T'_p
+ *             - W3 (T'_p - T[p][j]) eta_max z,
+ * c_j = sum_p X[p][j], T'_p = max(max_j T[p][j], 1), i.e. A scaled by
+ * eta_max z T'_p with weights (W1, W2, W3) / common denominator (Table 1's
+ * (1, 1, 0.5) is (2, 2, 1)).  T entries must be in [0, t_bound]; QB_E_RANGE
+ * if (W1+W2+W3) eta_max z max(t_bound,1) >= 2^47 (the rank packing). */
+qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const int32_t *T_d, int32_t W1,
+                  int32_t W2, int32_t W3, int32_t t_bound, int64_t *K_d, void *stream);
+/* order[p][r] = variable of rank r when sorting solution p by (K desc, index
+ * asc) (Alg. 3 "highest values in A"; ties to the lower index).  Keys must
+ * satisfy |K| < 2^47 (guaranteed by qb_keys).  Capacity: n <= 16384. */
+qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *order_d, void *stream);
+
+/* ---------------------------------------------------------------- jobs
+ * A batch of J sub-QUBO jobs (the multi-IM fabric of Alg. 3: several
+ * sub-QUBOs per solution solved at once).  Job q belongs to solution sol[q]
+ * (sol non-decreasing: the jobs of one solution are consecutive) and has
+ * m_q = size[q] variables; its index set idx[off[q] .. off[q+1]) is stored
+ * ascending, off being the prefix sum of the sizes.  rank0[q] is the first
+ * rank of qb_rank's order the job takes (NULL = consecutive chunks from rank
+ * 0 per solution, in job order).  The handle OWNS its device metadata (sol,
+ * off, rank0, idx, tile offsets, dispatch order) and the side streams used to
+ * run the annealer's size classes concurrently; create/destroy are not hot
+ * calls.  Capacity: 1 <= m_q <= 1024, sum of a solution's sizes <= n. */
+typedef struct qb_batch_s *qb_batch;
+typedef struct {
+    int32_t J;
+    int32_t total;            /* off[J] */
+    int32_t m_max;
+    int64_t tile_elems;       /* elements a tile buffer for qb_extract needs */
+    const int32_t *sol_d;     /* [J] */
+    const int32_t *off_d;     /* [J+1] */
+    int32_t *idx_d;           /* [total] */
+} qb_batch_info;
+
+qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_t J, const int32_t *sol_h,
+                          const int32_t *size_h, const int32_t *rank0_h);
+void qb_batch_destroy(qb_batch b);
+qb_status qb_batch_get_info(qb_batch b, qb_batch_info *info_h);
+/* Host-provided index sets (e.g. the contiguous blocks of the initial pass):
+ * validated on the host (ascending within a job, in [0,n), disjoint within a
+ * solution: QB_E_ARG / QB_E_OVERLAP), then copied to the handle's idx. */
+qb_status qb_batch_set_idx(qb_batch b, const int32_t *idx_h, void *stream);
+/* Copies the handle's index sets (int32 [total]) into idx_d. */
+qb_status qb_batch_copy_idx(qb_batch b, int32_t *idx_d, void *stream);
+
+/* Plain selection (Alg. 3 line 2): job q takes the ranks [rank0[q],
+ * rank0[q] + m_q) of its solution in order_d and stores their indices
+ * ascending in the handle's idx. */
+qb_status qb_select(qb_batch b, const int32_t *order_d, void *stream);
+
+/* ---------------------------------------------------------------- a4
+ * Sub-QUBO extraction, eq. 4 / Alg. 3 lines 3-5, against the state (X, H).
+ * For job q with S = idx of q, m = m_q, MS = the power of two >= ceil(m/64)
+ * (1, 2, 4, 8 or 16) and mp = 64 MS:
+ *   tile  (int8 if the problem is int8_ok, else int16), element
+ *         [tile_off[q] + a*mp + L*MS + s] = T[a][64 s + L] with
+ *         T[a][b] = Q[S_a][S_b] for a != b, 0 on the diagonal and padding;
+ *         tile_off is the prefix sum of mp^2 over the jobs (the buffer holds
+ *         qb_batch_info.tile_elems elements, 16-byte aligned);
+ *   c[off[q]+a]  = Q_aa + b_a,  b_a = 2 sum_{j not in S} Q[S_a][j] x_j;
+ *   F0[off[q]+a] = c_a + 2 sum_{b != a} T[a][b] y0_b (flip basis);
+ *   y0[off[q]+a] = X[p][S_a].
+ * c_d may be NULL. */
+qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t *H_d,
+                     void *tile_d, int32_t *c_d, int32_t *F0_d, uint8_t *y0_d, void *stream);
+
+/* ---------------------------------------------------------------- a5
+ * The Ising-machine stage on every job at once: R replicas of a sequential
+ * Metropolis sweep (positions 0..m-1 in order, nsw sweeps), warm-started at
+ * y0 with flip basis F0.  The uniform of (replica r, sweep s, position k) is
+ * word ((k>>6)&3) of Philox4x32-10 at counter (((k>>8)<<6)|(k&63), s, r,
+ * (1<<28)|(inst_base+q)), key (seed lo, seed hi); the move (1-2y_k) F_k is
+ * accepted iff it is <= thr[s][u >> (32-B)].  Outputs, per job q, replica r:
+ *   Y[off[q]*R + r*m_q + k] final state, e[q*R + r] = f_S(Y_r) - f_S(y0).
+ * thr_d: int32 [nsw][2^B] (see qb_threshold_table).  tile as qb_extract;
+ * int8_tile selects its element type.  Jobs are grouped by padded size and
+ * the groups run concurrently (side streams joined back into `stream`),
+ * largest first.  Capacity: 1 <= R <= 16, 1 <= B <= 16, nsw >= 1,
+ * inst_base + J <= 2^28. */
+qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
+                    const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                    uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream);
+
+/* Host builder of the acceptance table (cosine-waveform temperature, the
+ * MRAnnealer's waveform used as the IM temperature schedule):
+ *   T_s = tmin + 0.5 (tmax - tmin)(1 + cos(pi s / (nsw - 1)))   (T_0 = tmax
+ *   when nsw == 1), thr[s][b] = floor(T_s (-ln((b + 1/2) / 2^B))) capped at
+ *   2^31 - 1.  thr_h: host int32 [nsw][2^B]. */
+qb_status qb_threshold_table(int32_t nsw, int32_t B, double tmax, double tmin, int32_t *thr_h);
+
+/* ---------------------------------------------------------------- a6/a7/a8
+ * Write-back (Alg. 3 line 7): per job the replica with the lowest e (lowest
+ * r on ties) is written into X[sol][S] unconditionally, and dX[sol][S] =
+ * Y - y0 (int8 in {-1,0,1}).  dX_d (int8 [z][n]) must be all zero on entry
+ * outside the jobs' variables.  ebest_job_d (optional, int64 [J]) receives
+ * the chosen e.  Jobs of one solution are disjoint (qb_select builds them
+ * so; qb_batch_set_idx checks it). */
+qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d,
+                       const uint8_t *y0_d, uint8_t *X_d, int8_t *dX_d, int64_t *ebest_job_d,
+                       void *stream);
+/* Rank-k local-field update H[p] += Q dX[p] for all p (the O(n) move-value
+ * update of the Tabu section generalised to many flipped variables).
+ * variant: 0 = automatic, 1 = VALU gather over the changed columns,
+ * 2 = int8 MFMA dense contraction (int8_ok problems only).  Exact (int32). */
+qb_status qb_rankk(qb_problem P, int32_t z, const int8_t *dX_d, int32_t *H_d, int32_t variant,
+                   void *stream);
+/* Fill an int8 buffer with zeros (a kernel, safe under graph capture). */
+qb_status qb_zero(void *buf_d, size_t bytes, void *stream);
+
+/* ---------------------------------------------------------------- a9
+ * Mutation (end of the heuristic section).  For every solution p the
+ * candidates are the variables not solved by the IM (not in any job of p);
+ * the first k_p = floor((n - |U_p|) * rate) of them in qb_rank order are
+ * flipped with probability P_j = min(floor(2^32 (K_j - K_lo)/(K_hi - K_lo)),
+ * 2^32-1) (2^31 when K_hi == K_lo; K_lo/K_hi the min/max of K[p]); the flip
+ * happens iff word (j mod 4) of Philox4x32-10 at counter (j/4, t, p, 2<<28)
+ * is < P_j.  rate is r_t of the MRAnnealer (qb_mutation_rate).  X updated in
+ * place; dX (all zero on entry) receives the +-1 changes; kcount_d
+ * (optional, int32 [z]) receives k_p.  Solutions without jobs in the batch
+ * have U_p empty.  Capacity: n <= 65535. */
+qb_status qb_mutate(qb_batch b, const int64_t *K_d, const int32_t *order_d, double rate,
+                    int32_t t, uint64_t seed, uint8_t *X_d, int8_t *dX_d, int32_t *kcount_d,
+                    void *stream);
+/* r_t = 0.3 (1 + cos(pi t / 15)) 0.99^t. */
+double qb_mutation_rate(int32_t t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

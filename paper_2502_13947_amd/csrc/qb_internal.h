@@ -1,0 +1,114 @@
+// Internal declarations shared by the gfx950 kernels and the C-ABI wrappers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "qb.h"
+
+// Bits of the per-problem device status word.
+#define QB_FLAG_RANGE 1
+#define QB_FLAG_STATE 2
+
+struct qb_problem_s {
+    int n = 0;
+    const int16_t *Q = nullptr;   // borrowed, device
+    int8_t *Q8 = nullptr;         // owned, device (null unless int8_ok)
+    int64_t *eta = nullptr;       // owned, device [n]
+    int32_t *colcnt = nullptr;    // owned, device [n] scratch for qb_keys
+    int32_t *status = nullptr;    // owned, device status word
+    int int8_ok = 0;
+    int qmax = 0;
+    int64_t eta_max = 0;
+    double sigma = 0.0;
+};
+
+// Anneal size classes by padded width MS = mp / 64.
+static constexpr int QB_NCLASS = 5;          // MS = 16, 8, 4, 2, 1
+static inline int qb_class_of_ms(int ms) { return ms > 8 ? 0 : ms > 4 ? 1 : ms > 2 ? 2 : ms > 1 ? 3 : 4; }
+static inline int qb_ms_of_class(int c) { return 16 >> c; }
+// Padded tile width of a job of m variables: 64 * (power of two >= ceil(m/64)),
+// i.e. exactly the width of the annealer class that runs it.
+static inline __host__ __device__ int qb_tile_ms(int m)
+{
+    const int ms = (m + 63) >> 6;
+    return ms > 8 ? 16 : ms > 4 ? 8 : ms > 2 ? 4 : ms > 1 ? 2 : 1;
+}
+
+struct qb_batch_s {
+    int n = 0, z = 0, J = 0, total = 0, m_max = 0;
+    int64_t tile_elems = 0;
+    std::vector<int32_t> sol_h, off_h, size_h, rank0_h;
+    int32_t *sol_d = nullptr, *off_d = nullptr, *rank0_d = nullptr, *idx_d = nullptr;
+    int32_t *sol_begin_d = nullptr;   // [z+1] first job of each solution
+    int64_t *tile_off_d = nullptr;    // [J]
+    int32_t *lpt_d = nullptr;         // [J] jobs by class, then size descending
+    int cls_begin[QB_NCLASS] = {0}, cls_end[QB_NCLASS] = {0};
+    hipStream_t side[QB_NCLASS] = {nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[QB_NCLASS] = {nullptr};
+};
+
+// thread-local last HIP error
+void qb_set_hip_error(hipError_t e);
+
+#define QB_TRY_HIP(expr)                                   \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) {                            \
+            qb_set_hip_error(_e);                          \
+            return QB_E_HIP;                               \
+        }                                                  \
+    } while (0)
+
+#define QB_LAUNCH_CHECK()                                  \
+    do {                                                   \
+        hipError_t _e = hipGetLastError();                 \
+        if (_e != hipSuccess) {                            \
+            qb_set_hip_error(_e);                          \
+            return QB_E_HIP;                               \
+        }                                                  \
+    } while (0)
+
+static inline hipStream_t qb_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------------ device helpers
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// with the published multipliers, the key advanced by the published Weyl
+// increments between rounds.
+__device__ __forceinline__ uint4 qb_philox(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t qb_word(uint4 v, int w)
+{
+    return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+}
+
+__device__ __forceinline__ int64_t qb_wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t qb_wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}

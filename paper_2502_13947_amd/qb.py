@@ -1,0 +1,285 @@
+"""Thin ctypes binding of the gfx950 library ``libqb.so`` (C ABI in include/qb.h).
+
+Argument marshalling only: every step runs in the HIP kernels.  Device
+buffers are torch tensors on a ROCm device; their ``data_ptr()`` and the
+current torch stream are handed to the C calls.  Importing this module never
+falls back to any CPU path: if the library is missing, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqb.so")
+_lib = None
+
+QB_OK = 0
+STATUS = {0: "ok", -1: "E_ARG", -2: "E_NOT_SYMMETRIC", -3: "E_RANGE", -4: "E_OVERLAP",
+          -5: "E_CAPACITY", -6: "E_HIP", -7: "E_STATE", -8: "E_UNSUPPORTED"}
+
+
+class QBError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().qb_status_str(status).decode()
+        extra = f" (hip error {lib().qb_last_hip_error()})" if status == -6 else ""
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}{extra}")
+
+
+class ProblemInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("int8_ok", ctypes.c_int32), ("qmax", ctypes.c_int32),
+                ("eta_max", ctypes.c_int64), ("sigma", ctypes.c_double)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_int32), ("total", ctypes.c_int32), ("m_max", ctypes.c_int32),
+                ("tile_elems", ctypes.c_int64), ("sol_d", ctypes.c_void_p),
+                ("off_d", ctypes.c_void_p), ("idx_d", ctypes.c_void_p)]
+
+
+# name -> (restype, argtypes)
+_P, _I32, _I64, _U32, _U64, _F64, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                          ctypes.c_size_t)
+SIGNATURES = {
+    "qb_status_str": (ctypes.c_char_p, [_I32]),
+    "qb_last_hip_error": (_I32, []),
+    "qb_version": (ctypes.c_char_p, []),
+    "qb_problem_create_dense": (_I32, [ctypes.POINTER(_P), _I32, _P, _P]),
+    "qb_problem_destroy": (None, [_P]),
+    "qb_problem_get_info": (_I32, [_P, ctypes.POINTER(ProblemInfo)]),
+    "qb_problem_eta": (_I32, [_P, _P, _P]),
+    "qb_check": (_I32, [_P, _P]),
+    "qb_init_solutions": (_I32, [_I32, _I32, _U64, _P, _P]),
+    "qb_field": (_I32, [_P, _I32, _P, _P, _P]),
+    "qb_energy": (_I32, [_I32, _I32, _P, _P, _P, _P]),
+    "qb_best": (_I32, [_I32, _I32, _P, _P, _P, _P, _P]),
+    "qb_tabu": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _I32, _P, _P, _P]),
+    "qb_keys": (_I32, [_P, _I32, _P, _P, _I32, _I32, _I32, _I32, _P, _P]),
+    "qb_rank": (_I32, [_I32, _I32, _P, _P, _P]),
+    "qb_batch_create": (_I32, [ctypes.POINTER(_P), _I32, _I32, _I32, _P, _P, _P]),
+    "qb_batch_destroy": (None, [_P]),
+    "qb_batch_get_info": (_I32, [_P, ctypes.POINTER(BatchInfo)]),
+    "qb_batch_set_idx": (_I32, [_P, _P, _P]),
+    "qb_batch_copy_idx": (_I32, [_P, _P, _P]),
+    "qb_select": (_I32, [_P, _P, _P]),
+    "qb_extract": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_anneal": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P]),
+    "qb_threshold_table": (_I32, [_I32, _I32, _F64, _F64, _P]),
+    "qb_writeback": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_rankk": (_I32, [_P, _I32, _P, _P, _I32, _P]),
+    "qb_zero": (_I32, [_P, _SZ, _P]),
+    "qb_mutate": (_I32, [_P, _P, _P, _F64, _I32, _U64, _P, _P, _P, _P]),
+    "qb_mutation_rate": (_F64, [_I32]),
+}
+
+
+def lib():
+    """Load libqb.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _chk(rc: int, where: str):
+    if rc != QB_OK:
+        raise QBError(rc, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous ROCm tensors"
+        return t.data_ptr()
+    return t
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# --------------------------------------------------------------------------- handles
+class Problem:
+    """Dense QUBO problem (eq. 1) on the device.  Keeps a reference to Q."""
+
+    def __init__(self, Q: torch.Tensor, stream=None):
+        assert Q.dtype == torch.int16 and Q.dim() == 2 and Q.shape[0] == Q.shape[1]
+        self.Q = Q.contiguous()
+        h = ctypes.c_void_p()
+        _chk(lib().qb_problem_create_dense(ctypes.byref(h), self.Q.shape[0], _ptr(self.Q),
+                                           _stream(stream)), "qb_problem_create_dense")
+        self.h = h
+        info = ProblemInfo()
+        _chk(lib().qb_problem_get_info(self.h, ctypes.byref(info)), "qb_problem_get_info")
+        self.n, self.int8_ok, self.qmax = info.n, bool(info.int8_ok), info.qmax
+        self.eta_max, self.sigma = info.eta_max, info.sigma
+
+    def eta(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.int64, device=self.Q.device)
+        _chk(lib().qb_problem_eta(self.h, _ptr(out), _stream(stream)), "qb_problem_eta")
+        return out
+
+    def check(self, stream=None):
+        _chk(lib().qb_check(self.h, _stream(stream)), "qb_check")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.qb_problem_destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """A batch of sub-QUBO jobs (sol non-decreasing; sizes 1..1024)."""
+
+    def __init__(self, n: int, z: int, sol, sizes, rank0=None):
+        self.n, self.z = n, z
+        self.sol = np.ascontiguousarray(sol, np.int32)
+        self.sizes = np.ascontiguousarray(sizes, np.int32)
+        self.rank0 = None if rank0 is None else np.ascontiguousarray(rank0, np.int32)
+        h = ctypes.c_void_p()
+        _chk(lib().qb_batch_create(ctypes.byref(h), n, z, len(self.sol),
+                                   self.sol.ctypes.data, self.sizes.ctypes.data,
+                                   None if self.rank0 is None else self.rank0.ctypes.data),
+             "qb_batch_create")
+        self.h = h
+        info = BatchInfo()
+        _chk(lib().qb_batch_get_info(self.h, ctypes.byref(info)), "qb_batch_get_info")
+        self.J, self.total, self.m_max, self.tile_elems = info.J, info.total, info.m_max, info.tile_elems
+        self.off = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self._idx_ptr = info.idx_d
+
+    def set_idx(self, idx_h, stream=None):
+        idx_h = np.ascontiguousarray(idx_h, np.int32)
+        assert idx_h.shape[0] == self.total
+        _chk(lib().qb_batch_set_idx(self.h, idx_h.ctypes.data, _stream(stream)), "qb_batch_set_idx")
+
+    def idx(self, device, stream=None) -> torch.Tensor:
+        """Copy of the handle's index sets."""
+        out = torch.empty(self.total, dtype=torch.int32, device=device)
+        _chk(lib().qb_batch_copy_idx(self.h, _ptr(out), _stream(stream)), "qb_batch_copy_idx")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.qb_batch_destroy(self.h)
+            self.h = None
+
+
+# --------------------------------------------------------------------------- calls
+def init_solutions(n, z, seed, X, stream=None):
+    _chk(lib().qb_init_solutions(n, z, seed, _ptr(X), _stream(stream)), "qb_init_solutions")
+
+
+def field(P: Problem, X, H, stream=None):
+    _chk(lib().qb_field(P.h, X.shape[0], _ptr(X), _ptr(H), _stream(stream)), "qb_field")
+
+
+def energy(X, H, E, stream=None):
+    z, n = X.shape
+    _chk(lib().qb_energy(n, z, _ptr(X), _ptr(H), _ptr(E), _stream(stream)), "qb_energy")
+
+
+def best(X, E, ebest, xbest, stream=None):
+    z, n = X.shape
+    _chk(lib().qb_best(n, z, _ptr(X), _ptr(E), _ptr(ebest), _ptr(xbest), _stream(stream)), "qb_best")
+
+
+def tabu(P: Problem, X, H, E, alpha, tenure, aspiration, T, LF, stream=None):
+    _chk(lib().qb_tabu(P.h, X.shape[0], _ptr(X), _ptr(H), _ptr(E), alpha, tenure, int(bool(aspiration)),
+                       _ptr(T), _ptr(LF), _stream(stream)), "qb_tabu")
+
+
+def keys(P: Problem, X, T, K, W=(2, 2, 1), t_bound=None, stream=None):
+    tb = int(t_bound) if t_bound is not None else 2**30
+    _chk(lib().qb_keys(P.h, X.shape[0], _ptr(X), _ptr(T), W[0], W[1], W[2], tb, _ptr(K), _stream(stream)),
+         "qb_keys")
+
+
+def rank(K, order, stream=None):
+    z, n = K.shape
+    _chk(lib().qb_rank(n, z, _ptr(K), _ptr(order), _stream(stream)), "qb_rank")
+
+
+def select(b: Batch, order, stream=None):
+    _chk(lib().qb_select(b.h, _ptr(order), _stream(stream)), "qb_select")
+
+
+def extract(P: Problem, b: Batch, X, H, tile, F0, y0, c=None, stream=None):
+    _chk(lib().qb_extract(P.h, b.h, _ptr(X), _ptr(H), _ptr(tile), _ptr(c), _ptr(F0), _ptr(y0),
+                          _stream(stream)), "qb_extract")
+
+
+def anneal(b: Batch, tile, F0, y0, thr, R, seed, inst_base, Y, e, B, stream=None):
+    nsw = thr.shape[0]
+    assert thr.shape[1] == (1 << B)
+    int8_tile = 1 if tile.dtype == torch.int8 else 0
+    _chk(lib().qb_anneal(b.h, _ptr(tile), int8_tile, _ptr(F0), _ptr(y0), nsw, B, _ptr(thr), R, seed,
+                         inst_base, _ptr(Y), _ptr(e), _stream(stream)), "qb_anneal")
+
+
+def threshold_table(nsw, B, tmax, tmin) -> np.ndarray:
+    thr = np.zeros((nsw, 1 << B), np.int32)
+    _chk(lib().qb_threshold_table(nsw, B, float(tmax), float(tmin), thr.ctypes.data), "qb_threshold_table")
+    return thr
+
+
+def writeback(b: Batch, R, Y, e, y0, X, dX, ebest_job=None, stream=None):
+    _chk(lib().qb_writeback(b.h, R, _ptr(Y), _ptr(e), _ptr(y0), _ptr(X), _ptr(dX), _ptr(ebest_job),
+                            _stream(stream)), "qb_writeback")
+
+
+def rankk(P: Problem, dX, H, variant=0, stream=None):
+    _chk(lib().qb_rankk(P.h, dX.shape[0], _ptr(dX), _ptr(H), variant, _stream(stream)), "qb_rankk")
+
+
+def zero(t, stream=None):
+    _chk(lib().qb_zero(_ptr(t), t.numel() * t.element_size(), _stream(stream)), "qb_zero")
+
+
+def mutate(b: Batch, K, order, rate, t, seed, X, dX, kcount=None, stream=None):
+    _chk(lib().qb_mutate(b.h, _ptr(K), _ptr(order), float(rate), t, seed, _ptr(X), _ptr(dX), _ptr(kcount),
+                         _stream(stream)), "qb_mutate")
+
+
+def mutation_rate(t) -> float:
+    return float(lib().qb_mutation_rate(int(t)))
+
+
+def tile_dtype(P: Problem):
+    return torch.int8 if P.int8_ok else torch.int16
+
+
+def tile_ms(m: int) -> int:
+    """Slots per lane of a job's padded tile: the power of two >= ceil(m/64)."""
+    ms = (m + 63) // 64
+    p = 1
+    while p < ms:
+        p *= 2
+    return p
+
+
+def untile(tile: torch.Tensor, b: Batch, q: int) -> np.ndarray:
+    """Row-major [m, m] view of job q's tile (layout documented with qb_extract)."""
+    m = int(b.sizes[q])
+    ms = tile_ms(m)
+    mp = 64 * ms
+    off = 0
+    for qq in range(q):
+        mm = 64 * tile_ms(int(b.sizes[qq]))
+        off += mm * mm
+    t = tile[off:off + mp * mp].cpu().numpy().astype(np.int32).reshape(mp, 64, ms)
+    return np.ascontiguousarray(t.transpose(0, 2, 1).reshape(mp, mp)[:m, :m])

@@ -1,0 +1,120 @@
+"""IC-D^2S outer loop (Alg. 2) driven through the C ABI.
+
+Host-side sequencing only: every step is a kernel of libqb.so.  The state
+(X, H, E, T, LF, K, order, dX, tiles, ...) lives in HBM for the whole run;
+one outer iteration is a fixed sequence of launches on one stream, so it can
+also be captured into a HIP graph (see ``capture_iteration``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import qb
+
+
+class Solver:
+    def __init__(self, Q: torch.Tensor, *, z: int, seed: int, job_m, init_m: int, thr_init, thr,
+                 B: int, R: int, alpha: int, tenure: int, aspiration: bool = True, W=(2, 2, 1),
+                 rankk_variant: int = 0):
+        dev = Q.device
+        self.dev = dev
+        self.P = qb.Problem(Q)
+        n = self.n = self.P.n
+        self.z, self.seed, self.B, self.R = z, int(seed), B, R
+        self.alpha, self.tenure, self.aspiration, self.W = alpha, tenure, aspiration, W
+        self.rankk_variant = rankk_variant
+        job_m = np.atleast_2d(np.asarray(job_m, np.int32))
+        assert job_m.shape[0] == z
+        self.job_m = job_m
+        k = job_m.shape[1]
+        self.batch = qb.Batch(n, z, np.repeat(np.arange(z, dtype=np.int32), k), job_m.reshape(-1))
+        b = self.batch
+        self.tile_dtype = qb.tile_dtype(self.P)
+        self.X = torch.zeros((z, n), dtype=torch.uint8, device=dev)
+        self.H = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        self.E = torch.zeros(z, dtype=torch.int64, device=dev)
+        self.T = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        self.LF = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        self.K = torch.zeros((z, n), dtype=torch.int64, device=dev)
+        self.order = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        self.dX = torch.zeros((z, n), dtype=torch.int8, device=dev)
+        self.xbest = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.ebest = torch.full((1,), 2**63 - 1, dtype=torch.int64, device=dev)
+        self.kcount = torch.zeros(z, dtype=torch.int32, device=dev)
+        self.tiles = torch.zeros(max(b.tile_elems, 16), dtype=self.tile_dtype, device=dev)
+        self.F0 = torch.zeros(b.total, dtype=torch.int32, device=dev)
+        self.y0 = torch.zeros(b.total, dtype=torch.uint8, device=dev)
+        self.Y = torch.zeros(b.total * R, dtype=torch.uint8, device=dev)
+        self.e = torch.zeros(b.J * R, dtype=torch.int64, device=dev)
+        self.thr = torch.as_tensor(np.ascontiguousarray(thr, np.int32), device=dev)
+        self.init_m = init_m
+        if init_m:
+            self.thr_init = torch.as_tensor(np.ascontiguousarray(thr_init, np.int32), device=dev)
+            self.ib = qb.Batch(n, z, np.arange(z, dtype=np.int32), np.full(z, init_m, np.int32))
+            ib = self.ib
+            self.itiles = torch.zeros(max(ib.tile_elems, 16), dtype=self.tile_dtype, device=dev)
+            self.iF0 = torch.zeros(ib.total, dtype=torch.int32, device=dev)
+            self.iy0 = torch.zeros(ib.total, dtype=torch.uint8, device=dev)
+            self.iY = torch.zeros(ib.total * R, dtype=torch.uint8, device=dev)
+            self.ie = torch.zeros(ib.J * R, dtype=torch.int64, device=dev)
+        self.inst = 0
+        self.t = 0
+
+    # ------------------------------------------------------------------ stages
+    def _apply(self, stream=None):
+        qb.rankk(self.P, self.dX, self.H, self.rankk_variant, stream=stream)
+        qb.energy(self.X, self.H, self.E, stream=stream)
+        qb.best(self.X, self.E, self.ebest, self.xbest, stream=stream)
+
+    def init(self):
+        """Alg. 2 lines 1-2: random set, field, energy, then the initial pass."""
+        n, z = self.n, self.z
+        qb.init_solutions(n, z, self.seed, self.X)
+        qb.field(self.P, self.X, self.H)
+        qb.energy(self.X, self.H, self.E)
+        self.ebest.fill_(2**63 - 1)
+        qb.best(self.X, self.E, self.ebest, self.xbest)
+        if self.init_m:
+            m0 = self.init_m
+            for l in range(n // m0):
+                self.ib.set_idx(np.tile(np.arange(l * m0, (l + 1) * m0, dtype=np.int32), z))
+                qb.extract(self.P, self.ib, self.X, self.H, self.itiles, self.iF0, self.iy0)
+                qb.anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.R, self.seed,
+                          self.inst, self.iY, self.ie, self.B)
+                self.inst += z
+                qb.zero(self.dX)
+                qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX)
+                self._apply()
+
+    def iterate(self, stream=None):
+        """One outer iteration of Alg. 2 (lines 6-11)."""
+        s = stream
+        b = self.batch
+        qb.tabu(self.P, self.X, self.H, self.E, self.alpha, self.tenure, self.aspiration, self.T, self.LF,
+                stream=s)
+        qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
+        qb.keys(self.P, self.X, self.T, self.K, self.W, t_bound=max(self.alpha, 1), stream=s)
+        qb.rank(self.K, self.order, stream=s)
+        qb.select(b, self.order, stream=s)
+        qb.extract(self.P, b, self.X, self.H, self.tiles, self.F0, self.y0, stream=s)
+        qb.anneal(b, self.tiles, self.F0, self.y0, self.thr, self.R, self.seed, self.inst, self.Y, self.e,
+                  self.B, stream=s)
+        self.inst += b.J
+        qb.zero(self.dX, stream=s)
+        qb.writeback(b, self.R, self.Y, self.e, self.y0, self.X, self.dX, stream=s)
+        self._apply(stream=s)
+        qb.zero(self.dX, stream=s)
+        qb.mutate(b, self.K, self.order, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
+                  self.kcount, stream=s)
+        self._apply(stream=s)
+        self.t += 1
+
+    def run(self, iters: int):
+        self.init()
+        trace = []
+        for _ in range(iters):
+            self.iterate()
+            trace.append(self.ebest.clone())
+        torch.cuda.synchronize()
+        return [int(v.item()) for v in trace]

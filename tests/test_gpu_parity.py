@@ -1,0 +1,376 @@
+"""GPU-vs-oracle parity of every entry point of the C ABI (bit-exact).
+
+Inputs are seeded and synthetic; the oracle (tests-only) computes the
+expected values on the host from the same inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_13947_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2502_13947_amd import qb
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    qb.lib()
+
+
+def qb():
+    from paper_2502_13947_amd import qb as m
+    return m
+
+
+def dq(Q):
+    return torch.as_tensor(np.ascontiguousarray(Q, np.int16), device=DEV)
+
+
+def wide_qubo(n, seed, density=0.3):
+    """int16 weights beyond int8 (exercises the int16 paths)."""
+    Q = inputs.dense_qubo(n, density, seed, lo=-3000, hi=3000)
+    return Q
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------------------------- a0/a1
+def test_problem_validation_and_eta():
+    Q = inputs.dense_qubo(300, 0.4, 1)
+    P = qb().Problem(dq(Q))
+    assert P.int8_ok and P.qmax == np.abs(Q).max()
+    assert (P.eta().cpu().numpy() == oracle.eta(Q)).all()
+    Qw = wide_qubo(200, 2)
+    Pw = qb().Problem(dq(Qw))
+    assert not Pw.int8_ok
+    bad = Q.copy()
+    bad[3, 7] += 1
+    with pytest.raises(qb().QBError) as ei:
+        qb().Problem(dq(bad))
+    assert ei.value.status == -2
+    big = np.zeros((4, 4), np.int16)
+    big[0, 0] = 32767
+    P4 = qb().Problem(dq(big))              # (2n+1)*qmax < 2^31: accepted
+    assert P4.qmax == 32767
+
+
+@pytest.mark.parametrize("n,z", [(1, 1), (5, 3), (1000, 7), (2501, 4)])
+def test_init_solutions_bit_exact(n, z):
+    say("init", n, z)
+    X = torch.zeros((z, n), dtype=torch.uint8, device=DEV)
+    qb().init_solutions(n, z, 0xDEADBEEF12345, X)
+    assert (X.cpu().numpy() == oracle.init_x(n, z, 0xDEADBEEF12345)).all()
+
+
+@pytest.mark.parametrize("int8", [True, False])
+@pytest.mark.parametrize("n,z", [(1, 1), (70, 3), (777, 9)])
+def test_field_energy_best(n, z, int8):
+    say("field", n, z, int8)
+    Q = inputs.dense_qubo(n, 0.5, 3) if int8 else wide_qubo(n, 3)
+    X = inputs.random_solutions(z, n, 4)
+    P = qb().Problem(dq(Q))
+    Xd = torch.as_tensor(X, device=DEV)
+    H = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    E = torch.zeros(z, dtype=torch.int64, device=DEV)
+    qb().field(P, Xd, H)
+    qb().energy(Xd, H, E)
+    Ho = oracle.field(Q, X)
+    assert (H.cpu().numpy() == Ho).all()
+    assert (E.cpu().numpy() == oracle.energy(X, Ho)).all()
+    eb = torch.full((1,), 2**63 - 1, dtype=torch.int64, device=DEV)
+    xb = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    qb().best(Xd, E, eb, xb)
+    Eo = oracle.energy(X, Ho)
+    p = int(np.argmin(Eo))
+    assert int(eb.item()) == Eo[p] and (xb.cpu().numpy() == X[p]).all()
+
+
+# ----------------------------------------------------------------------------- a2
+@pytest.mark.parametrize("int8", [True, False])
+@pytest.mark.parametrize("n,z,alpha,tenure,asp", [(3, 1, 7, 2, True), (50, 3, 250, 4, True),
+                                                  (1100, 4, 2000, 7, True), (2500, 2, 3000, 16, False),
+                                                  (5000, 2, 800, 33, True)])
+def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
+    say("tabu", n, z, alpha, tenure, asp, int8)
+    Q = inputs.dense_qubo(n, 0.3, 5) if int8 else wide_qubo(n, 5)
+    X = inputs.random_solutions(z, n, 6)
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    P = qb().Problem(dq(Q))
+    Xd, Hd, Ed = (torch.as_tensor(a, device=DEV) for a in (X, H, E))
+    T = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    LF = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().tabu(P, Xd, Hd, Ed, alpha, tenure, asp, T, LF)
+    for p in range(z):
+        x, h, ov, To, LFo = oracle.tabu(Q, X[p], H[p], int(E[p]), alpha, tenure, asp)
+        assert (Xd[p].cpu().numpy() == x).all(), p
+        assert (Hd[p].cpu().numpy() == h).all(), p
+        assert int(Ed[p].item()) == ov
+        assert (T[p].cpu().numpy() == To).all()
+        assert (LF[p].cpu().numpy() == LFo).all()
+
+
+def test_tabu_golden_fixtures_on_gpu():
+    import json, os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tabu_fixtures.json")))
+    for f in fx["fixtures"]:
+        Q = np.array(f["Q"], np.int16)
+        x0 = np.array(f["x0"], np.uint8)[None]
+        H = (Q.astype(np.int64) @ x0[0]).astype(np.int32)[None]
+        E = np.array([int(x0[0] @ Q.astype(np.int64) @ x0[0])], np.int64)
+        P = qb().Problem(dq(Q))
+        Xd, Hd, Ed = (torch.as_tensor(a, device=DEV) for a in (x0, H, E))
+        T = torch.zeros((1, len(x0[0])), dtype=torch.int32, device=DEV)
+        LF = torch.zeros_like(T)
+        qb().tabu(P, Xd, Hd, Ed, f["alpha"], f["tenure"], f["aspiration"], T, LF)
+        assert list(Xd[0].cpu().numpy()) == f["x_min"]
+        assert list(Hd[0].cpu().numpy()) == f["h_min"]
+        assert int(Ed.item()) == f["ov_min"]
+        assert list(T[0].cpu().numpy()) == f["T"]
+        assert list(LF[0].cpu().numpy()) == f["lastflip"]
+
+
+# ----------------------------------------------------------------------------- a3
+@pytest.mark.parametrize("n,z", [(1, 1), (33, 5), (3000, 6), (16384, 2)])
+def test_keys_rank_select(n, z):
+    say("keys", n, z)
+    Q = inputs.dense_qubo(n, 0.2, 7)
+    X = inputs.random_solutions(z, n, 8)
+    rng = np.random.default_rng(9)
+    T = rng.integers(0, 6, size=(z, n)).astype(np.int32)
+    if z > 1:
+        T[1] = 0
+    P = qb().Problem(dq(Q))
+    Xd, Td = torch.as_tensor(X, device=DEV), torch.as_tensor(T, device=DEV)
+    K = torch.zeros((z, n), dtype=torch.int64, device=DEV)
+    qb().keys(P, Xd, Td, K, (2, 2, 1), t_bound=10)
+    Ko = oracle.keys(oracle.eta(Q), X, T, (2, 2, 1))
+    assert (K.cpu().numpy() == Ko).all()
+    order = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().rank(K, order)
+    for p in range(z):
+        assert (order[p].cpu().numpy() == oracle.order(Ko[p])).all(), p
+    # jobs: 3 per solution of mixed sizes, consecutive rank chunks
+    sizes = [min(n, s) for s in (5, 64, 130)]
+    k = 3 if sum(sizes) <= n else 1
+    sizes = sizes[:k] if k == 3 else [min(n, 7)]
+    b = qb().Batch(n, z, np.repeat(np.arange(z), len(sizes)), np.tile(sizes, z))
+    qb().select(b, order)
+    idx = b.idx(DEV).cpu().numpy()
+    off = 0
+    for p in range(z):
+        o = oracle.order(Ko[p])
+        r = 0
+        for m in sizes:
+            assert (idx[off:off + m] == np.sort(o[r:r + m])).all()
+            off += m
+            r += m
+
+
+def test_keys_range_rejected():
+    Q = inputs.dense_qubo(64, 1.0, 10)
+    P = qb().Problem(dq(Q))
+    z = 4
+    X = torch.zeros((z, 64), dtype=torch.uint8, device=DEV)
+    T = torch.zeros((z, 64), dtype=torch.int32, device=DEV)
+    K = torch.zeros((z, 64), dtype=torch.int64, device=DEV)
+    with pytest.raises(qb().QBError) as ei:
+        qb().keys(P, X, T, K, (2, 2, 1), t_bound=2**30)
+    assert ei.value.status == -3
+    T[0, 0] = 50                                     # above t_bound -> latched
+    qb().keys(P, X, T, K, (2, 2, 1), t_bound=10)
+    with pytest.raises(qb().QBError) as ei:
+        P.check()
+    assert ei.value.status == -3
+    P.check()                                        # latch cleared
+
+
+# ----------------------------------------------------------------------------- a4/a5/a6
+def _jobs(n, z, sizes_per_sol, seed):
+    job_m = np.array(sizes_per_sol, np.int32)
+    if job_m.ndim == 1:
+        job_m = np.tile(job_m, (z, 1))
+    sol, off, idx = inputs.random_index_sets(z, n, job_m, seed)
+    return sol, job_m.reshape(-1), idx
+
+
+@pytest.mark.parametrize("int8", [True, False])
+@pytest.mark.parametrize("n,z,sizes", [(40, 2, [1, 7]), (700, 3, [64, 100, 256]), (1500, 2, [300, 512]),
+                                       (2600, 2, [1024, 700, 63])])
+def test_extract_bit_exact(n, z, sizes, int8):
+    say("extract", n, z, sizes, int8)
+    Q = inputs.dense_qubo(n, 0.6, 11) if int8 else wide_qubo(n, 11, 0.6)
+    X = inputs.random_solutions(z, n, 12)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, sizes, 13)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    tiles = torch.zeros(b.tile_elems, dtype=qb().tile_dtype(P), device=DEV)
+    c = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0, c=c)
+    cc, FF, yy = c.cpu().numpy(), F0.cpu().numpy(), y0.cpu().numpy()
+    for q in range(b.J):
+        p = sol[q]
+        S = idx[b.off[q]:b.off[q + 1]]
+        Tq, co, Fo, yo = oracle.extract(Q, X[p], H[p], S)
+        assert (qb().untile(tiles, b, q) == Tq).all(), q
+        sl = slice(b.off[q], b.off[q + 1])
+        assert (cc[sl] == co).all() and (FF[sl] == Fo).all() and (yy[sl] == yo).all(), q
+
+
+ANNEAL_CASES = [
+    # (n, z, sizes, nsw, R, int8)
+    (200, 2, [1, 5], 9, 1, True),
+    (600, 2, [64, 65, 127], 20, 2, True),
+    (1200, 2, [128, 200, 256], 15, 3, True),
+    (1500, 2, [300, 512], 12, 2, True),
+    (2200, 1, [700, 1024], 6, 2, True),
+    (900, 2, [100, 256], 10, 2, False),
+    (1500, 1, [512, 400], 6, 1, False),
+    (1100, 1, [1024], 4, 2, False),
+]
+
+
+@pytest.mark.parametrize("n,z,sizes,nsw,R,int8", ANNEAL_CASES)
+def test_anneal_bit_exact(n, z, sizes, nsw, R, int8):
+    say("anneal", n, z, sizes, nsw, R, int8)
+    Q = inputs.dense_qubo(n, 0.5, 21) if int8 else wide_qubo(n, 21, 0.5)
+    X = inputs.random_solutions(z, n, 22)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, sizes, 23)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    tiles = torch.zeros(b.tile_elems, dtype=qb().tile_dtype(P), device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
+    B = 10
+    sig = P.sigma
+    thr = oracle.threshold_table(nsw, B, 0.5 * sig, 0.002 * sig)
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    seed, inst = 0x1234ABCD5678, 1000
+    qb().anneal(b, tiles, F0, y0, torch.as_tensor(thr, device=DEV), R, seed, inst, Y, e, B)
+    Yh, eh = Y.cpu().numpy(), e.cpu().numpy()
+    for q in range(b.J):
+        p = sol[q]
+        S = idx[b.off[q]:b.off[q + 1]]
+        Tq, c, F, yy = oracle.extract(Q, X[p], H[p], S)
+        Yo, eo = oracle.anneal(Tq, F, yy, thr, R, seed, inst + q, B)
+        mm = len(S)
+        got = Yh[b.off[q] * R:(b.off[q] + mm) * R].reshape(R, mm)
+        assert (got == Yo).all(), (q, mm)
+        assert (eh[q * R:(q + 1) * R] == eo).all(), (q, mm)
+
+
+def test_threshold_table_matches_oracle():
+    for nsw, B, tmax, tmin in [(1, 10, 100.0, 1.0), (200, 10, 2047.3, 8.2), (37, 4, 5.0, 0.0),
+                               (3, 16, 1e9, 1e8)]:
+        assert (qb().threshold_table(nsw, B, tmax, tmin) == oracle.threshold_table(nsw, B, tmax, tmin)).all()
+    for t in range(40):
+        assert qb().mutation_rate(t) == oracle.mutation_rate(t)
+
+
+@pytest.mark.parametrize("variant", [1])
+def test_writeback_rankk(variant):
+    n, z, R = 900, 3, 3
+    Q = inputs.dense_qubo(n, 0.5, 31)
+    X = inputs.random_solutions(z, n, 32)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, [100, 200], 33)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    Xd, Hd = torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV)
+    tiles = torch.zeros(b.tile_elems, dtype=torch.int8, device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, Xd, Hd, tiles, F0, y0)
+    thr = oracle.threshold_table(8, 10, 0.5 * P.sigma, 0.01 * P.sigma)
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    qb().anneal(b, tiles, F0, y0, torch.as_tensor(thr, device=DEV), R, 7, 0, Y, e, 10)
+    dX = torch.zeros((z, n), dtype=torch.int8, device=DEV)
+    eb = torch.zeros(b.J, dtype=torch.int64, device=DEV)
+    qb().writeback(b, R, Y, e, y0, Xd, dX, eb)
+    Xw = Xd.cpu().numpy()
+    eh, Yh = e.cpu().numpy(), Y.cpu().numpy()
+    Xo = X.copy()
+    for q in range(b.J):
+        rb = int(np.argmin(eh[q * R:(q + 1) * R]))
+        mm = m[q]
+        S = idx[b.off[q]:b.off[q + 1]]
+        Xo[sol[q], S] = Yh[b.off[q] * R + rb * mm: b.off[q] * R + (rb + 1) * mm]
+        assert eb[q].item() == eh[q * R + rb]
+    assert (Xw == Xo).all()
+    assert (dX.cpu().numpy() == (Xo.astype(np.int16) - X).astype(np.int8)).all()
+    qb().rankk(P, dX, Hd, variant)
+    Ho = oracle.field(Q, Xo)
+    assert (Hd.cpu().numpy() == Ho).all()
+
+
+# ----------------------------------------------------------------------------- a9
+@pytest.mark.parametrize("t", [0, 3, 15, 29])
+def test_mutate_bit_exact(t):
+    n, z = 1300, 5
+    Q = inputs.dense_qubo(n, 0.4, 41)
+    X = inputs.random_solutions(z, n, 42)
+    rng = np.random.default_rng(43)
+    T = rng.integers(0, 9, size=(z, n)).astype(np.int32)
+    P = qb().Problem(dq(Q))
+    Xd, Td = torch.as_tensor(X, device=DEV), torch.as_tensor(T, device=DEV)
+    K = torch.zeros((z, n), dtype=torch.int64, device=DEV)
+    qb().keys(P, Xd, Td, K, (2, 2, 1), t_bound=10)
+    order = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().rank(K, order)
+    sizes = [100, 37]
+    b = qb().Batch(n, z, np.repeat(np.arange(z), 2), np.tile(sizes, z))
+    qb().select(b, order)
+    idx = b.idx(DEV).cpu().numpy()
+    dX = torch.zeros((z, n), dtype=torch.int8, device=DEV)
+    kc = torch.zeros(z, dtype=torch.int32, device=DEV)
+    seed = 99
+    qb().mutate(b, K, order, qb().mutation_rate(t), t, seed, Xd, dX, kc)
+    Kh = K.cpu().numpy()
+    for p in range(z):
+        inU = np.zeros(n, np.uint8)
+        inU[idx[p * 137:(p + 1) * 137]] = 1
+        xo, flip, k = oracle.mutate(X[p], Kh[p], inU, t, p, seed)
+        assert int(kc[p].item()) == k
+        assert (Xd[p].cpu().numpy() == xo).all(), p
+        assert (dX[p].cpu().numpy() == (xo.astype(np.int16) - X[p]).astype(np.int8)).all()
+
+
+# ----------------------------------------------------------------------------- a11
+def test_full_trajectory_small_config():
+    """Alg. 2 end to end (initial pass, Tabu, keys, selection, extraction,
+    annealing, write-back, rank-k, mutation, best tracking): every iteration's
+    best energy and the final state are bit-exact with the oracle."""
+    from paper_2502_13947_amd.solver import Solver
+    n, z, iters, B, R = 600, 4, 4, 10, 2
+    Q = inputs.dense_qubo(n, 0.1, 51)
+    job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
+    P = qb().Problem(dq(Q))
+    thr = oracle.threshold_table(30, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr0 = oracle.threshold_table(20, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    S = Solver(dq(Q), z=z, seed=5, job_m=job_m, init_m=128, thr_init=thr0, thr=thr, B=B, R=R,
+               alpha=5 * n, tenure=max(1, n // 150))
+    trace = S.run(iters)
+    ref = oracle.run(Q, z=z, seed=5, iters=iters, alpha=5 * n, tenure=max(1, n // 150), job_m=job_m,
+                     init_m=128, thr_init=thr0, thr=thr, B=B, R=R)
+    assert trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all()
+    assert (S.H.cpu().numpy() == ref["H"]).all()
+    assert (S.E.cpu().numpy() == ref["E"]).all()
+    assert int(S.ebest.item()) == ref["ebest"] and (S.xbest.cpu().numpy() == ref["xbest"]).all()
