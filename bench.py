@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the IC-D^2S hot path on one MI355X.
+
+A step is one outer iteration of Alg. 2 over the whole solution set: Tabu
+search, control-parameter keys, rank and selection, sub-QUBO extraction, the
+batched annealer (the Ising-machine stage), write-back, rank-k field update,
+exact energy, best tracking, mutation and its field update.  The metric is
+spin-flip attempts per second of the whole step (attempts = sum over jobs of
+replicas x sub-QUBO size x sweeps), with every input resident in HBM.
+
+Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# int32 VALU: 256 CUs x 64 lanes x 2.4 GHz, one op per lane per clock
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# ALU work charged per annealer attempt: a quarter of a Philox4x32-10 block
+# (10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) = 80 ops / 4 words) plus the
+# move value, threshold index and compare (3 ops).
+ANNEAL_OPS_PER_ATTEMPT = 80 / 4 + 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2_n5000_d50")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="solutions in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--no-init-pass", action="store_true")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2502_13947_amd import inputs
+    w = dict(inputs.WORKLOADS[name])
+    n = w["n"]
+    w.update(alpha=5 * n, tenure=max(1, n // 150), B=10, seed=2025)
+    w["job_m"] = inputs.job_sizes(w["z"], w["k"], w["sizes"], seed=w["qseed"] + 100)
+    return w
+
+
+def cpu_baseline(Q, w, thr, nsol):
+    """The oracle, untuned, on a bounded sample: `nsol` solutions through one
+    full outer iteration (Tabu, keys, selection, extraction, annealing,
+    write-back, field, mutation) on one host thread."""
+    import oracle
+    n = w["n"]
+    X = oracle.init_x(n, nsol, w["seed"])
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    et = oracle.eta(Q)
+    t0 = time.perf_counter()
+    T = np.zeros((nsol, n), np.int32)
+    for p in range(nsol):
+        X[p], H[p], ov, T[p], _ = oracle.tabu(Q, X[p], H[p], int(E[p]), w["alpha"], w["tenure"], True)
+        E[p] = ov
+    K = oracle.keys(et, X, T, (2, 2, 1))
+    attempts = 0
+    for p in range(nsol):
+        o = oracle.order(K[p])
+        off = 0
+        inU = np.zeros(n, np.uint8)
+        for m in w["job_m"][p]:
+            S = np.sort(o[off:off + m]).astype(np.int32)
+            off += m
+            Tq, c, F0, y0 = oracle.extract(Q, X[p], H[p], S)
+            Y, e = oracle.anneal(Tq, F0, y0, thr, w["R"], w["seed"], p, w["B"])
+            X[p, S] = Y[int(np.argmin(e))]
+            inU[S] = 1
+            attempts += w["R"] * m * thr.shape[0]
+        X[p], _, _ = oracle.mutate(X[p], K[p], inU, 0, p, w["seed"])
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    dt = time.perf_counter() - t0
+    return dict(value=attempts / dt, unit="spin-flip attempts/s", cores=1, kind="oracle",
+                sample=f"{nsol} of {w['z']} solutions through one outer iteration "
+                       f"({attempts} attempts, {dt:.1f} s, single thread)")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2502_13947_amd import inputs, qb
+    from paper_2502_13947_amd.solver import Solver
+
+    w = workload(a.workload)
+    n, z = w["n"], w["z"]
+    Q = inputs.dense_qubo(n, w["density"], w["qseed"])
+    dev = torch.device("cuda:0")
+    Qd = torch.as_tensor(Q, device=dev)
+    sigma = qb.Problem(Qd).sigma
+    thr = qb.threshold_table(w["nsw"], w["B"], 0.5 * sigma, 0.002 * sigma)
+    S = Solver(Qd, z=z, seed=w["seed"], job_m=w["job_m"], init_m=0 if a.no_init_pass else w["init_m"],
+               thr_init=thr, thr=thr, B=w["B"], R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
+    S.init()
+    for _ in range(a.warmup):
+        S.iterate()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    stage_ev = []
+
+    def marks_for(step_events):
+        def mark(name):
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            step_events.append((name, ev))
+        return mark
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for _ in range(a.steps):
+        evs = []
+        S.iterate(marks=marks_for(evs))
+        stage_ev.append(evs)
+    end.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(end)
+
+    stages = {}
+    for evs in stage_ev:
+        for (name, e0), (_, e1) in zip(evs, evs[1:]):
+            stages[name] = stages.get(name, 0.0) + e0.elapsed_time(e1)
+    stages = {k: v / a.steps for k, v in stages.items()}
+
+    b = S.batch
+    attempts_per_step = int(w["R"] * w["nsw"] * int(np.sum(w["job_m"])))
+    value = attempts_per_step * a.steps / (total_ms / 1e3)
+
+    # roofline of the dominant kernel (Tabu and the annealer are single launches)
+    qbytes = 1 if S.P.int8_ok else 2
+    tabu_bytes = z * w["alpha"] * n * qbytes + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
+    t_tabu, t_ann = stages["tabu"] / 1e3, stages["anneal"] / 1e3
+    if t_tabu >= t_ann:
+        ach = tabu_bytes / t_tabu / 1e9
+        roof = dict(kernel="k_tabu", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS, traffic=None,
+                    algorithmic=f"{z} solutions x {w['alpha']} steps x one {n}-entry int{8 * qbytes} row of Q")
+    else:
+        ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
+        ach = ops / t_ann / 1e12
+        roof = dict(kernel="k_anneal", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
+                    frac=ach / ALU_PEAK_TOPS, traffic=None,
+                    algorithmic=f"{attempts_per_step} attempts x {ANNEAL_OPS_PER_ATTEMPT} int ops")
+    other = {}
+    ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
+    other["k_anneal"] = dict(ms=stages["anneal"], attempts_per_s=attempts_per_step / t_ann,
+                             alu_frac=ops / t_ann / 1e12 / ALU_PEAK_TOPS)
+    other["k_tabu"] = dict(ms=stages["tabu"], GBps=tabu_bytes / t_tabu / 1e9,
+                           hbm_frac=tabu_bytes / t_tabu / 1e9 / HBM_PEAK_GBS)
+
+    cpu = None
+    if a.cpu_sample > 0:
+        cpu = cpu_baseline(Q, w, thr, a.cpu_sample)
+
+    out = {
+        "metric": "spin-flip attempts/sec",
+        "value": value,
+        "unit": "spin-flip attempts/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": total_ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": n, "density": w["density"], "z": z,
+                   "subqubos_per_step": b.J, "m": sorted(set(int(v) for v in np.ravel(w["job_m"]))),
+                   "sweeps": w["nsw"], "replicas": w["R"], "tabu_alpha": w["alpha"],
+                   "attempts_per_step": attempts_per_step},
+        "sweeps_per_s": b.J * w["R"] * w["nsw"] * a.steps / (total_ms / 1e3),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms": stages,
+        "kernels": other,
+        "wall_s": t_wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -30,27 +30,39 @@ extern "C" const char *qb_status_str(qb_status s)
 }
 
 // ------------------------------------------------------------------ problem scan
-// One pass over Q: symmetry, max |Q|, sum of squared off-diagonal entries.
-__global__ void k_problem_scan(const int16_t *__restrict__ Q, int n, int32_t *__restrict__ flags,
-                               int32_t *__restrict__ qmax, unsigned long long *__restrict__ sumsq)
+// One pass over Q in 64x64 tiles: symmetry (each tile against its mirror,
+// both staged through LDS so every global read is coalesced), max |Q|, and
+// the sum of squared off-diagonal entries.
+__global__ void __launch_bounds__(256) k_problem_scan(const int16_t *__restrict__ Q, int n,
+                                                      int32_t *__restrict__ flags, int32_t *__restrict__ qmax,
+                                                      unsigned long long *__restrict__ sumsq)
 {
-    const int i = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t amax = 0;
+    __shared__ int16_t A[64][65], B[64][65];
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
+        const int r = t >> 6, c = t & 63;
+        A[r][c] = (r0 + r < n && c0 + c < n) ? Q[(int64_t)(r0 + r) * n + c0 + c] : 0;
+        B[r][c] = (c0 + r < n && r0 + c < n) ? Q[(int64_t)(c0 + r) * n + r0 + c] : 0;
+    }
+    __syncthreads();
+    int32_t amax = 0, bad = 0;
     unsigned long long sq = 0;
-    if (j < n) {
-        const int32_t v = Q[(int64_t)i * n + j];
-        if (v != Q[(int64_t)j * n + i]) atomicOr(flags, 1);
-        amax = v < 0 ? -v : v;
-        if (i != j) sq = (unsigned long long)(v * v);
+    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
+        const int r = t >> 6, c = t & 63;
+        const int32_t v = A[r][c];
+        bad |= v != B[c][r];
+        amax = max(amax, v < 0 ? -v : v);
+        if (r0 + r != c0 + c) sq += (unsigned long long)(v * v);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         amax = max(amax, __shfl_xor(amax, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
         sq += __shfl_xor(sq, o, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicMax(qmax, amax);
+        if (bad) atomicOr(flags, 1);
         if (sq) atomicAdd(sumsq, sq);
     }
 }
@@ -66,6 +78,15 @@ __global__ void k_eta(const int16_t *__restrict__ Q, int n, int64_t *__restrict_
         acc += v < 0 ? -v : v;
     }
     eta[j] = acc;
+}
+
+// Row-padded copy of Q (pitch ld elements, zero padding), int8 or int16.
+template <typename T>
+__global__ void k_pad_copy(const int16_t *__restrict__ Q, int n, int ld, T *__restrict__ out)
+{
+    const int i = blockIdx.y;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ld; j += gridDim.x * blockDim.x)
+        out[(int64_t)i * ld + j] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
 }
 
 __global__ void k_to_int8(const int16_t *__restrict__ Q, int8_t *__restrict__ Q8, int64_t count)
@@ -98,7 +119,7 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
     do {
         if (hipMalloc(&scan_d, sizeof(Scan)) != hipSuccess) { fail(QB_E_HIP); break; }
         if (hipMemsetAsync(scan_d, 0, sizeof(Scan), s) != hipSuccess) { fail(QB_E_HIP); break; }
-        dim3 grid((n + 255) / 256, n);
+        dim3 grid((n + 63) / 64, (n + 63) / 64);
         k_problem_scan<<<grid, 256, 0, s>>>(Q_d, n, &scan_d->flags, &scan_d->qmax, &scan_d->sumsq);
         if (hipMemcpyAsync(&scan_h, scan_d, sizeof(Scan), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
@@ -123,6 +144,17 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
             if (hipMalloc(&P->Q8, (size_t)n * n) != hipSuccess) { fail(QB_E_HIP); break; }
             k_to_int8<<<1024, 256, 0, s>>>(Q_d, P->Q8, (int64_t)n * n);
         }
+        const int ept = qb_tabu_ept(n);
+        if (ept) {
+            P->ldp = 256 * ept;
+            const size_t esz = P->int8_ok ? 1 : 2;
+            if (hipMalloc(&P->Qp, esz * (size_t)n * P->ldp) != hipSuccess) { fail(QB_E_HIP); break; }
+            dim3 g((P->ldp + 255) / 256, n);
+            if (P->int8_ok)
+                k_pad_copy<int8_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, (int8_t *)P->Qp);
+            else
+                k_pad_copy<int16_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, (int16_t *)P->Qp);
+        }
         std::vector<int64_t> eta_h(n);
         if (hipMemcpyAsync(eta_h.data(), P->eta, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
@@ -145,6 +177,7 @@ extern "C" void qb_problem_destroy(qb_problem P)
 {
     if (!P) return;
     if (P->Q8) hipFree(P->Q8);
+    if (P->Qp) hipFree(P->Qp);
     if (P->eta) hipFree(P->eta);
     if (P->colcnt) hipFree(P->colcnt);
     if (P->status) hipFree(P->status);

@@ -18,11 +18,23 @@ struct qb_problem_s {
     int64_t *eta = nullptr;       // owned, device [n]
     int32_t *colcnt = nullptr;    // owned, device [n] scratch for qb_keys
     int32_t *status = nullptr;    // owned, device status word
+    void *Qp = nullptr;           // owned, device: Q with rows padded to ldp (int8 if int8_ok)
+    int ldp = 0;                  // row pitch of Qp in elements
     int int8_ok = 0;
     int qmax = 0;
     int64_t eta_max = 0;
     double sigma = 0.0;
 };
+
+// Elements per thread of the 256-thread Tabu workgroup for n variables (a
+// multiple of 4 so that row chunks are dword aligned); 0 if n is too large.
+static inline int qb_tabu_ept(int n)
+{
+    static const int opts[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 64};
+    for (int e : opts)
+        if (n <= 256 * e) return e;
+    return 0;
+}
 
 // Anneal size classes by padded width MS = mp / 64.
 static constexpr int QB_NCLASS = 5;          // MS = 16, 8, 4, 2, 1

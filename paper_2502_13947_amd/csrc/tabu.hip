@@ -1,113 +1,212 @@
-// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 1024-thread
-// workgroup per solution.  Every thread keeps EPT variables' local field,
-// tenure counter and diagonal entry in registers (flip counts and last-flip
-// steps, touched only by the owner of the flipped variable, live in LDS); one
-// step is a
-// lexicographic (move value, index) argmin (wave shuffles + one LDS exchange,
-// a single barrier per step thanks to double-buffered slots), then the
-// chosen variable's row of Q (int8 copy when it fits) updates every field.
-// x_min is never copied: a per-variable "flipped since the last improvement"
-// bit recovers it at the end, and the field is moved to x_min by the rows of
-// the differing variables.
+// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 256-thread
+// workgroup (four waves, one per SIMD) per solution.
+//
+// Thread t owns the EPT consecutive variables [t*EPT, (t+1)*EPT) and keeps in
+// registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
+// to be non-negative), the factor S_j = 2(1-2x_j), and the step U_j after
+// which the variable is free again.  U replaces the tenure vector of the
+// listing: "C_j <= 0 at step t" is exactly "U_j <= t-1" when U is updated
+// only for the flipped variable, so no per-step decrement pass is needed.
+//
+// One step: every lane forms a 32-bit key (move value, element) for each of
+// its allowed variables (not tabu, or aspirating: OV + D < OV_min) and keeps
+// the minimum; the wave minimum comes from DPP row operations plus four
+// readlanes, the lowest lane whose minimum has that move value gives the
+// lowest index (lane-major order of the indices), and the four wave
+// winners meet in LDS (one barrier per step, double-buffered slots).  The
+// chosen variable's row of the padded copy of Q is read with wide loads and
+// every D is updated by one multiply-add; the owner of the flipped variable
+// patches its own element through a scalar switch.  x_min is never copied:
+// per-variable "flipped since the last improvement" bits recover it, and the
+// field is moved to x_min with the rows of the differing variables.
 #include "qb_internal.h"
 
 namespace {
 
-constexpr int TB = 1024;           // threads per solution
-constexpr int NW = TB / 64;        // waves
+constexpr int TB = 256;
+constexpr int NW = TB / 64;
 
-// (move value, index, x) packed so that unsigned order = (move asc, index asc)
-__device__ __forceinline__ uint64_t pack_move(int32_t d, int j, uint32_t x)
+constexpr int ceil_log2(int v) { return v <= 1 ? 0 : 1 + ceil_log2((v + 1) / 2); }
+
+// Wave minimum of an unsigned value, returned uniform.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 {
-    return ((uint64_t)((uint32_t)d ^ 0x80000000u) << 32) | ((uint64_t)(uint32_t)j << 1) | x;
+    // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// EPT consecutive row elements (EPT * sizeof(QT) bytes, 4-byte aligned).
+template <int EPT, typename QT>
+__device__ __forceinline__ void load_chunk(const QT *__restrict__ p, int32_t (&q)[EPT])
+{
+    constexpr int NW4 = EPT * (int)sizeof(QT) / 4;
+    uint32_t w[NW4];
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+    for (int k = 0; k < NW4; ++k) w[k] = src[k];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        if constexpr (sizeof(QT) == 1)
+            q[e] = (int32_t)(int8_t)(w[e >> 2] >> (8 * (e & 3)));
+        else
+            q[e] = (int32_t)(int16_t)(w[e >> 1] >> (16 * (e & 1)));
+    }
+}
+
+// wave key: (biased move << 32) | (index << 1) | x_index
+__device__ __forceinline__ uint64_t pack_winner(uint32_t dbias, int j, uint32_t x)
+{
+    return ((uint64_t)dbias << 32) | ((uint64_t)(uint32_t)j << 1) | x;
 }
 
 template <int EPT, typename QT>
-__global__ void __launch_bounds__(TB) k_tabu(const int16_t *__restrict__ Q16, const QT *__restrict__ Qr,
+__global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp, const int16_t *__restrict__ Q16,
                                              int n, uint8_t *__restrict__ X, int32_t *__restrict__ H,
                                              int64_t *__restrict__ E, int alpha, int tenure, int asp,
-                                             int32_t *__restrict__ Tout, int32_t *__restrict__ LFout)
+                                             int32_t *__restrict__ Tout, int32_t *__restrict__ LFout,
+                                             uint32_t bias)
 {
+    constexpr int EB = ceil_log2(EPT);           // bits of the element index
+    constexpr uint32_t EMASK = (1u << EB) - 1u;
     __shared__ uint64_t red[2][NW];
     __shared__ uint64_t red2[NW];
     __shared__ int32_t list[TB];
     __shared__ int lcount;
-    extern __shared__ int32_t tl[];           // [0,n): flip counts, [n,2n): last-flip steps
+    extern __shared__ int32_t tl[];              // [0,n): flips, [n,2n): last-flip step
     int32_t *Ts = tl, *Ls = tl + n;
 
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t rowoff = (int64_t)p * n;
-    int32_t h[EPT], C[EPT], qd[EPT];
-    uint32_t xb = 0, pb = 0;
+    const int64_t ro = (int64_t)p * n;
+    const int j0 = tid * EPT;
+    // padding elements carry the largest possible key and are never chosen
+    const uint32_t dpad = 0xFFFFFFFFu >> EB;
+
+    uint32_t Db[EPT];      // D + bias
+    int32_t S[EPT];        // 2 (1 - 2 x)
+    int32_t U[EPT];        // tabu through step U
+    uint64_t xb = 0;       // x bits of the owned variables
+    uint64_t pb = 0;       // flipped since the last improvement
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int j = tid + TB * e;
-        h[e] = 0; qd[e] = 0; C[e] = 0;
+        const int j = j0 + e;
+        U[e] = 0;
         if (j < n) {
+            const int32_t x = X[ro + j] & 1;
+            const int32_t qjj = Q16[(int64_t)j * n + j];
+            S[e] = x ? -2 : 2;
+            xb |= (uint64_t)x << e;
+            Db[e] = (uint32_t)(qjj + S[e] * H[ro + j]) + bias;
             Ts[j] = 0;
             Ls[j] = 0;
-            h[e] = H[rowoff + j];
-            qd[e] = Q16[(int64_t)j * n + j];
-            xb |= (uint32_t)(X[rowoff + j] & 1) << e;
+        } else {
+            S[e] = 2;
+            Db[e] = dpad;
+            U[e] = 0x7fffffff;                   // never allowed
         }
     }
     int64_t OV = E[p], OVmin = OV;
 
     for (int step = 1; step <= alpha; ++step) {
-        uint64_t best = ~0ull;
+        // aspiration in the biased domain: D + bias < (OVmin - OV) + bias
+        const int64_t tau = OVmin - OV + (int64_t)bias;
+        const uint32_t tb = tau <= 0 ? 0u : (uint32_t)tau;
+        const int32_t free_at = step - 1;
+        uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int j = tid + TB * e;
-            if (j < n) {
-                const uint32_t xe = (xb >> e) & 1u;
-                const int32_t d = qd[e] + 2 * (xe ? -h[e] : h[e]);
-                const bool allowed = C[e] <= 0 || (asp && OV + d < OVmin);
-                const uint64_t key = pack_move(d, j, xe);
-                if (allowed && key < best) best = key;
-            }
+            const bool allowed = U[e] <= free_at || (asp && Db[e] < tb);
+            const uint32_t key = (Db[e] << EB) | (uint32_t)e;
+            best = min(best, allowed ? key : 0xFFFFFFFFu);
         }
-        best = qb_wave_min_u64(best);
-        if (lane == 0) red[step & 1][wid] = best;
+        const uint32_t wmin = wave_min_u32(best);
+        uint64_t wkey = ~0ull;
+        if (wmin != 0xFFFFFFFFu) {
+            // lowest index among the minimal moves: the lowest lane holding the
+            // minimal move value, then that lane's own lowest element
+            const uint64_t who = __ballot((best >> EB) == (wmin >> EB));
+            const int L = __builtin_ctzll(who);
+            const int ew = (int)((uint32_t)__builtin_amdgcn_readlane((int)best, L) & EMASK);
+            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
+            wkey = pack_winner(wmin >> EB, (wid * 64 + L) * EPT + ew, xw);
+        }
+        if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
         uint64_t kb = red[step & 1][0];
 #pragma unroll
         for (int w = 1; w < NW; ++w) kb = min(kb, red[step & 1][w]);
         if (kb == ~0ull) {
-            // every variable is tabu and none aspirates: argmin over all
-            uint64_t b2 = ~0ull;
+            // every variable is tabu and none aspirates: argmin over all of them
+            uint32_t b2 = 0xFFFFFFFFu;
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int j = tid + TB * e;
-                if (j < n) {
-                    const uint32_t xe = (xb >> e) & 1u;
-                    const int32_t d = qd[e] + 2 * (xe ? -h[e] : h[e]);
-                    b2 = min(b2, pack_move(d, j, xe));
-                }
-            }
-            b2 = qb_wave_min_u64(b2);
-            if (lane == 0) red2[wid] = b2;
+            for (int e = 0; e < EPT; ++e) b2 = min(b2, (Db[e] << EB) | (uint32_t)e);
+            const uint32_t w2 = wave_min_u32(b2);
+            const uint64_t who = __ballot((b2 >> EB) == (w2 >> EB));
+            const int L = __builtin_ctzll(who);
+            const int ew = (int)((uint32_t)__builtin_amdgcn_readlane((int)b2, L) & EMASK);
+            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
+            if (lane == 0) red2[wid] = pack_winner(w2 >> EB, (wid * 64 + L) * EPT + ew, xw);
             __syncthreads();
             kb = red2[0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) kb = min(kb, red2[w]);
         }
-        const int32_t di = (int32_t)((uint32_t)(kb >> 32) ^ 0x80000000u);
-        const int i = (int)((kb >> 1) & 0x7fffffffu);
-        const int32_t sgn = (kb & 1) ? -1 : 1;
-        OV += di;
-        const QT *row = Qr + (int64_t)i * n;
+        const uint32_t dib = (uint32_t)(kb >> 32);
+        const int i = (int)((uint32_t)kb >> 1);
+        const int32_t s = (kb & 1) ? -1 : 1;       // direction of x_i
+        OV += (int64_t)(int32_t)(dib - bias);
+        int32_t q[EPT];
+        load_chunk<EPT, QT>(Qp + (int64_t)i * ldp + j0, q);
+        // h_j += s Q_ji  =>  D_j += S_j s Q_ji (the owner is patched below)
+        if (s > 0) {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int j = tid + TB * e;
-            if (j < n) h[e] += sgn * (int32_t)row[j];
-            if (j == i) {
-                xb ^= 1u << e;
-                pb ^= 1u << e;
-                Ts[j] += 1;
-                Ls[j] = step;
-                C[e] += tenure;
+            for (int e = 0; e < EPT; ++e) Db[e] += (uint32_t)__mul24(q[e], S[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) Db[e] -= (uint32_t)__mul24(q[e], S[e]);
+        }
+        const int ti = i / EPT;
+        if (tid == ti) {
+            const int ei = i - ti * EPT;
+            xb ^= 1ull << ei;
+            pb ^= 1ull << ei;
+            Ts[i] += 1;
+            Ls[i] = step;
+            switch (ei) {
+#define QB_OWNER_CASE(K)                                                         \
+    case K:                                                                      \
+        if constexpr (K < EPT) {                                                 \
+            Db[K] = 2u * bias - dib;                                             \
+            S[K] = -S[K];                                                        \
+            U[K] = step + max(max(U[K] - (step - 1), 0) + tenure - 1, 0);        \
+        }                                                                        \
+        break;
+                QB_OWNER_CASE(0) QB_OWNER_CASE(1) QB_OWNER_CASE(2) QB_OWNER_CASE(3)
+                QB_OWNER_CASE(4) QB_OWNER_CASE(5) QB_OWNER_CASE(6) QB_OWNER_CASE(7)
+                QB_OWNER_CASE(8) QB_OWNER_CASE(9) QB_OWNER_CASE(10) QB_OWNER_CASE(11)
+                QB_OWNER_CASE(12) QB_OWNER_CASE(13) QB_OWNER_CASE(14) QB_OWNER_CASE(15)
+                QB_OWNER_CASE(16) QB_OWNER_CASE(17) QB_OWNER_CASE(18) QB_OWNER_CASE(19)
+                QB_OWNER_CASE(20) QB_OWNER_CASE(21) QB_OWNER_CASE(22) QB_OWNER_CASE(23)
+                QB_OWNER_CASE(24) QB_OWNER_CASE(25) QB_OWNER_CASE(26) QB_OWNER_CASE(27)
+                QB_OWNER_CASE(28) QB_OWNER_CASE(29) QB_OWNER_CASE(30) QB_OWNER_CASE(31)
+                QB_OWNER_CASE(32) QB_OWNER_CASE(33) QB_OWNER_CASE(34) QB_OWNER_CASE(35)
+                QB_OWNER_CASE(36) QB_OWNER_CASE(37) QB_OWNER_CASE(38) QB_OWNER_CASE(39)
+                QB_OWNER_CASE(40) QB_OWNER_CASE(41) QB_OWNER_CASE(42) QB_OWNER_CASE(43)
+                QB_OWNER_CASE(44) QB_OWNER_CASE(45) QB_OWNER_CASE(46) QB_OWNER_CASE(47)
+                QB_OWNER_CASE(48) QB_OWNER_CASE(49) QB_OWNER_CASE(50) QB_OWNER_CASE(51)
+                QB_OWNER_CASE(52) QB_OWNER_CASE(53) QB_OWNER_CASE(54) QB_OWNER_CASE(55)
+                QB_OWNER_CASE(56) QB_OWNER_CASE(57) QB_OWNER_CASE(58) QB_OWNER_CASE(59)
+                QB_OWNER_CASE(60) QB_OWNER_CASE(61) QB_OWNER_CASE(62) QB_OWNER_CASE(63)
+#undef QB_OWNER_CASE
+            default: break;
             }
-            if (C[e] > 0) C[e] -= 1;
         }
         if (OV < OVmin) {
             OVmin = OV;
@@ -115,87 +214,90 @@ __global__ void __launch_bounds__(TB) k_tabu(const int16_t *__restrict__ Q16, co
         }
     }
 
-    // move the field from the final x to x_min = x ^ pb
+    // field of the final x from D, then moved to x_min = x ^ pb row by row
+    int32_t h[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int j = j0 + e;
+        h[e] = 0;
+        if (j < n) {
+            const int32_t qjj = Q16[(int64_t)j * n + j];
+            h[e] = ((int32_t)(Db[e] - bias) - qjj) * S[e] / 4;
+        }
+    }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         if (tid == 0) lcount = 0;
         __syncthreads();
-        const int j = tid + TB * e;
-        if (j < n && ((pb >> e) & 1u)) {
+        if (j0 + e < n && ((pb >> e) & 1ull)) {
             const int pos = atomicAdd(&lcount, 1);
-            list[pos] = ((xb >> e) & 1u) ? -(j + 1) : (j + 1);
+            // x_min_j - x_j = +1 when x_j = 0, -1 when x_j = 1
+            list[pos] = ((xb >> e) & 1ull) ? -(j0 + e + 1) : (j0 + e + 1);
         }
         __syncthreads();
         const int cnt = lcount;
         for (int u = 0; u < cnt; ++u) {
             const int32_t v = list[u];
-            const int32_t s = v < 0 ? -1 : 1;
-            const QT *row = Qr + (int64_t)(v < 0 ? -v - 1 : v - 1) * n;
+            const int32_t sg = v < 0 ? -1 : 1;
+            int32_t q[EPT];
+            load_chunk<EPT, QT>(Qp + (int64_t)(v < 0 ? -v - 1 : v - 1) * ldp + j0, q);
 #pragma unroll
-            for (int e2 = 0; e2 < EPT; ++e2) {
-                const int jj = tid + TB * e2;
-                if (jj < n) h[e2] += s * (int32_t)row[jj];
-            }
+            for (int e2 = 0; e2 < EPT; ++e2) h[e2] += sg * q[e2];
         }
         __syncthreads();
     }
-    xb ^= pb;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int j = tid + TB * e;
+        const int j = j0 + e;
         if (j < n) {
-            X[rowoff + j] = (uint8_t)((xb >> e) & 1u);
-            H[rowoff + j] = h[e];
-            Tout[rowoff + j] = Ts[j];
-            LFout[rowoff + j] = Ls[j];
+            X[ro + j] = (uint8_t)(((xb ^ pb) >> e) & 1ull);
+            H[ro + j] = h[e];
+            Tout[ro + j] = Ts[j];
+            LFout[ro + j] = Ls[j];
         }
     }
     if (tid == 0) E[p] = OVmin;
 }
 
-template <typename QT>
-qb_status launch_tabu(qb_problem P, const QT *Qr, int z, uint8_t *X, int32_t *H, int64_t *E,
-                      int alpha, int tenure, int asp, int32_t *T, int32_t *LF, hipStream_t s)
+template <int EPT, typename QT>
+void launch_one(const QT *Qp, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
+                int tenure, int asp, int32_t *T, int32_t *LF, uint32_t bias, hipStream_t s)
 {
-    const int ept = (P->n + TB - 1) / TB;
     const size_t lds = sizeof(int32_t) * 2 * (size_t)P->n;
-#define QB_TABU_CASE(K)                                                                       \
-    case K:                                                                                   \
-        (void)hipFuncSetAttribute((const void *)k_tabu<K, QT>,                                      \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
-        k_tabu<K, QT><<<z, TB, lds, s>>>(P->Q, Qr, P->n, X, H, E, alpha, tenure, asp, T, LF); \
-        break;
-    switch (ept) {
-        QB_TABU_CASE(1)
-        QB_TABU_CASE(2)
-        QB_TABU_CASE(3)
-        QB_TABU_CASE(4)
-        QB_TABU_CASE(5)
-        QB_TABU_CASE(6)
-        QB_TABU_CASE(7)
-        QB_TABU_CASE(8)
-        QB_TABU_CASE(10)
-        QB_TABU_CASE(12)
-        QB_TABU_CASE(16)
-    case 9:
-        (void)hipFuncSetAttribute((const void *)k_tabu<10, QT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_tabu<10, QT><<<z, TB, lds, s>>>(P->Q, Qr, P->n, X, H, E, alpha, tenure, asp, T, LF);
-        break;
-    case 11:
-        (void)hipFuncSetAttribute((const void *)k_tabu<12, QT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_tabu<12, QT><<<z, TB, lds, s>>>(P->Q, Qr, P->n, X, H, E, alpha, tenure, asp, T, LF);
-        break;
-    case 13:
-    case 14:
-    case 15:
-        (void)hipFuncSetAttribute((const void *)k_tabu<16, QT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_tabu<16, QT><<<z, TB, lds, s>>>(P->Q, Qr, P->n, X, H, E, alpha, tenure, asp, T, LF);
-        break;
-    default: return QB_E_CAPACITY;
+    (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_tabu<EPT, QT><<<z, TB, lds, s>>>(Qp, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
+}
+
+template <typename QT>
+qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
+                      int tenure, int asp, int32_t *T, int32_t *LF, hipStream_t s)
+{
+    const int ept = qb_tabu_ept(P->n);
+    if (ept == 0 || ldp != TB * ept) return QB_E_CAPACITY;
+    // |D_j| <= |Q_jj| + 2 sum_i |Q_ij| <= qmax + 2 eta_max; the biased move
+    // (D + bias) << EB | e must stay below the padding key for every real D
+    const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
+    const uint32_t bias = (uint32_t)dmax;
+#define QB_T(K)                                                                                    \
+    if (ept == K) {                                                                               \
+        if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> ceil_log2(K))) return QB_E_RANGE;             \
+        launch_one<K, QT>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);             \
+        QB_LAUNCH_CHECK();                                                                         \
+        return QB_OK;                                                                              \
     }
-#undef QB_TABU_CASE
-    QB_LAUNCH_CHECK();
-    return QB_OK;
+    QB_T(4)
+    QB_T(8)
+    QB_T(12)
+    QB_T(16)
+    QB_T(20)
+    QB_T(24)
+    QB_T(28)
+    QB_T(32)
+    QB_T(40)
+    QB_T(48)
+    QB_T(64)
+#undef QB_T
+    return QB_E_CAPACITY;
 }
 
 }  // namespace
@@ -206,11 +308,11 @@ extern "C" qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d
 {
     if (!P || z < 1 || !X_d || !H_d || !E_d || !T_d || !LF_d || alpha < 0 || tenure < 0)
         return QB_E_ARG;
-    if (P->n > 16 * TB) return QB_E_CAPACITY;
+    if (P->n > 64 * TB) return QB_E_CAPACITY;
     hipStream_t s = qb_stream(stream);
     if (P->int8_ok)
-        return launch_tabu<int8_t>(P, P->Q8, z, X_d, H_d, E_d, alpha, tenure, aspiration != 0, T_d,
-                                   LF_d, s);
-    return launch_tabu<int16_t>(P, P->Q, z, X_d, H_d, E_d, alpha, tenure, aspiration != 0, T_d, LF_d,
-                                s);
+        return launch_tabu<int8_t>(P, (const int8_t *)P->Qp, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
+                                   aspiration != 0, T_d, LF_d, s);
+    return launch_tabu<int16_t>(P, (const int16_t *)P->Qp, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
+                                aspiration != 0, T_d, LF_d, s);
 }

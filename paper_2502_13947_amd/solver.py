@@ -87,27 +87,37 @@ class Solver:
                 qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX)
                 self._apply()
 
-    def iterate(self, stream=None):
-        """One outer iteration of Alg. 2 (lines 6-11)."""
+    def iterate(self, stream=None, marks=None):
+        """One outer iteration of Alg. 2 (lines 6-11).  ``marks`` (optional) is
+        a callable invoked with a stage name between launches, e.g. to record
+        timing events on the stream."""
         s = stream
         b = self.batch
+        mark = marks or (lambda name: None)
+        mark("tabu")
         qb.tabu(self.P, self.X, self.H, self.E, self.alpha, self.tenure, self.aspiration, self.T, self.LF,
                 stream=s)
+        mark("select")
         qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
         qb.keys(self.P, self.X, self.T, self.K, self.W, t_bound=max(self.alpha, 1), stream=s)
         qb.rank(self.K, self.order, stream=s)
         qb.select(b, self.order, stream=s)
+        mark("extract")
         qb.extract(self.P, b, self.X, self.H, self.tiles, self.F0, self.y0, stream=s)
+        mark("anneal")
         qb.anneal(b, self.tiles, self.F0, self.y0, self.thr, self.R, self.seed, self.inst, self.Y, self.e,
                   self.B, stream=s)
+        mark("apply")
         self.inst += b.J
         qb.zero(self.dX, stream=s)
         qb.writeback(b, self.R, self.Y, self.e, self.y0, self.X, self.dX, stream=s)
         self._apply(stream=s)
+        mark("mutate")
         qb.zero(self.dX, stream=s)
         qb.mutate(b, self.K, self.order, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
                   self.kcount, stream=s)
         self._apply(stream=s)
+        mark("end")
         self.t += 1
 
     def run(self, iters: int):
