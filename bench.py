@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--workload", default="c2_n5000_d50")
     ap.add_argument("--cpu-sample", type=int, default=8, help="solutions in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-init-pass", action="store_true")
+    ap.add_argument("--graph", type=int, default=1, help="also time a captured HIP graph of the same steps")
     return ap.parse_args()
 
 
@@ -110,11 +111,13 @@ def main():
     S = Solver(Qd, z=z, seed=w["seed"], job_m=w["job_m"], init_m=0 if a.no_init_pass else w["init_m"],
                thr_init=thr, thr=thr, B=w["B"], R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
     S.init()
-    for _ in range(a.warmup):
-        S.iterate()
-    torch.cuda.synchronize()
+    tuned_variant, tuned_ms = S.autotune()
+    with torch.cuda.stream(S.stream):
+        for _ in range(a.warmup):
+            S.iterate()
+    S.stream.synchronize()
 
-    stream = torch.cuda.current_stream()
+    stream = S.stream
     stage_ev = []
 
     def marks_for(step_events):
@@ -126,17 +129,31 @@ def main():
 
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    stream.synchronize()
     t_wall = time.perf_counter()
-    start.record(stream)
-    for _ in range(a.steps):
-        evs = []
-        S.iterate(marks=marks_for(evs))
-        stage_ev.append(evs)
-    end.record(stream)
-    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(a.steps):
+            evs = []
+            S.iterate(marks=marks_for(evs))
+            stage_ev.append(evs)
+        end.record(stream)
+    stream.synchronize()
     t_wall = time.perf_counter() - t_wall
     total_ms = start.elapsed_time(end)
+
+    # the same number of iterations replayed from one captured HIP graph
+    graph_ms = None
+    if a.graph:
+        g = S.capture(a.steps)
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        stream.synchronize()
+        g0.record(stream)
+        g.launch()
+        g1.record(stream)
+        stream.synchronize()
+        graph_ms = g0.elapsed_time(g1) / a.steps
 
     stages = {}
     for evs in stage_ev:
@@ -196,6 +213,8 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms": stages,
         "kernels": other,
+        "graph_ms_per_step": graph_ms,
+        "rankk_variant": {"chosen": tuned_variant, "ms": tuned_ms, "by": "autotuner"},
         "wall_s": t_wall,
     }
     print(json.dumps(out), flush=True)

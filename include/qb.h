@@ -20,7 +20,8 @@
  *    documented range) are latched in the problem's device status word and
  *    returned by qb_check.  No C++ exception crosses this boundary.
  *  - No call allocates device memory except the handle constructors
- *    qb_problem_create_dense and qb_batch_create.
+ *    qb_problem_create_dense and qb_batch_create, and the setup-time
+ *    autotuner qb_autotune_rankk.
  *  - Layouts (row-major): Q int16 [n][n] symmetric; X uint8 [z][n] (0/1);
  *    H int32 [z][n] with H[p][i] = sum_j Q[i][j] X[p][j]; E int64 [z].
  *  - Results depend only on inputs, seeds and instance numbers: never on
@@ -238,6 +239,26 @@ qb_status qb_mutate(qb_batch b, const int64_t *K_d, const int32_t *order_d, doub
                     void *stream);
 /* r_t = 0.3 (1 + cos(pi t / 15)) 0.99^t. */
 double qb_mutation_rate(int32_t t);
+
+/* ---------------------------------------------------------------- a11
+ * Outer-loop orchestration (Alg. 2).  Work the caller enqueues on `stream`
+ * (a non-default stream) between qb_graph_begin and qb_graph_end -- e.g. a
+ * fixed number of outer iterations, with every per-iteration scalar (t, r_t,
+ * instance numbers) baked into the launches -- becomes one executable HIP
+ * graph; qb_graph_launch replays it.  Capture uses relaxed mode and follows
+ * the annealer's side streams.  The handle is owned by the caller
+ * (qb_graph_destroy). */
+qb_status qb_graph_begin(void *stream);
+qb_status qb_graph_end(void *stream, void **graph_exec_out);
+qb_status qb_graph_launch(void *graph_exec, void *stream);
+void qb_graph_destroy(void *graph_exec);
+/* Autotuner for the result-invariant rank-k variants: times each applicable
+ * variant `reps` times on (dX, H) (H unchanged on return), checks that all of
+ * them produce the same field (else QB_E_STATE), and returns the fastest in
+ * *variant_out (its mean time in *ms_out if not NULL).  Not a hot call: it
+ * allocates scratch and synchronises `stream`. */
+qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX_d, const int32_t *H_d, int32_t reps,
+                            int32_t *variant_out, float *ms_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -271,9 +271,17 @@ __global__ void __launch_bounds__(256) k_field(const int16_t *__restrict__ Q, in
             if (p0 + pp < z) H[(int64_t)(p0 + pp) * n + i] = acc[pp];
 }
 
+qb_status qb_rankk_mfma_launch(qb_problem P, int z, const int8_t *dX, int32_t *H, hipStream_t s);
+
 extern "C" qb_status qb_field(qb_problem P, int32_t z, const uint8_t *X_d, int32_t *H_d, void *stream)
 {
-    if (!P || z < 1 || z > 65535 * 8 || !X_d || !H_d) return QB_E_ARG;
+    if (!P || z < 1 || z > 65535 || !X_d || !H_d) return QB_E_ARG;
+    if (P->int8_ok && P->Qp && z >= 32) {
+        // H = 0 + X Q on the int8 matrix cores (X in {0,1} read as int8)
+        qb_status rc = qb_zero(H_d, sizeof(int32_t) * (size_t)z * P->n, stream);
+        if (rc != QB_OK) return rc;
+        return qb_rankk_mfma_launch(P, z, (const int8_t *)X_d, H_d, qb_stream(stream));
+    }
     dim3 grid((P->n + 255) / 256, (z + 7) / 8);
     k_field<<<grid, 256, 0, qb_stream(stream)>>>(P->Q, P->n, z, X_d, H_d);
     QB_LAUNCH_CHECK();

@@ -1,0 +1,96 @@
+// Orchestration helpers: HIP-graph capture of the outer loop of Alg. 2 and
+// the autotuner of result-invariant kernel variants.
+#include <vector>
+
+#include "qb_internal.h"
+
+extern "C" qb_status qb_graph_begin(void *stream)
+{
+    hipStream_t s = qb_stream(stream);
+    if (!s) return QB_E_ARG;   // the legacy default stream cannot be captured
+    QB_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    return QB_OK;
+}
+
+extern "C" qb_status qb_graph_end(void *stream, void **graph_exec_out)
+{
+    if (!graph_exec_out) return QB_E_ARG;
+    *graph_exec_out = nullptr;
+    hipGraph_t g = nullptr;
+    QB_TRY_HIP(hipStreamEndCapture(qb_stream(stream), &g));
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        qb_set_hip_error(e);
+        return QB_E_HIP;
+    }
+    *graph_exec_out = ge;
+    return QB_OK;
+}
+
+extern "C" qb_status qb_graph_launch(void *graph_exec, void *stream)
+{
+    if (!graph_exec) return QB_E_ARG;
+    QB_TRY_HIP(hipGraphLaunch((hipGraphExec_t)graph_exec, qb_stream(stream)));
+    return QB_OK;
+}
+
+extern "C" void qb_graph_destroy(void *graph_exec)
+{
+    if (graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+}
+
+// ------------------------------------------------------------------ autotuner
+// Times every applicable rank-k variant on the caller's (dX, H) and returns
+// the fastest.  All variants must produce identical fields (checked on the
+// host); a mismatch is reported as QB_E_STATE.  H_d is left unchanged.  Not a
+// hot call: it allocates scratch and synchronises.
+extern "C" qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX_d, const int32_t *H_d,
+                                      int32_t reps, int32_t *variant_out, float *ms_out, void *stream)
+{
+    if (!P || z < 1 || !dX_d || !H_d || !variant_out || reps < 1) return QB_E_ARG;
+    hipStream_t s = qb_stream(stream);
+    const size_t bytes = sizeof(int32_t) * (size_t)z * P->n;
+    int32_t *Hw = nullptr;
+    QB_TRY_HIP(hipMalloc(&Hw, bytes));
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    std::vector<int32_t> ref, cur;
+    int best = 1;
+    float best_ms = 1e30f;
+    qb_status rc = QB_OK;
+    const int cand[2] = {1, 2};
+    for (int vi = 0; vi < 2 && rc == QB_OK; ++vi) {
+        const int v = cand[vi];
+        if (v == 2 && (!P->int8_ok || !P->Qp)) continue;
+        float tot = 0.f;
+        for (int r = 0; r < reps + 1 && rc == QB_OK; ++r) {
+            if (hipMemcpyAsync(Hw, H_d, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = QB_E_HIP; break; }
+            (void)hipEventRecord(e0, s);
+            rc = qb_rankk(P, z, dX_d, Hw, v, stream);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = QB_E_HIP; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) tot += ms;   // first run is a warm-up
+        }
+        if (rc != QB_OK) break;
+        cur.resize((size_t)z * P->n);
+        if (hipMemcpy(cur.data(), Hw, bytes, hipMemcpyDeviceToHost) != hipSuccess) { rc = QB_E_HIP; break; }
+        if (ref.empty())
+            ref = cur;
+        else if (ref != cur)
+            rc = QB_E_STATE;
+        const float avg = tot / reps;
+        if (avg < best_ms) { best_ms = avg; best = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(Hw);
+    if (rc != QB_OK) return rc;
+    *variant_out = best;
+    if (ms_out) *ms_out = best_ms;
+    return QB_OK;
+}

@@ -75,6 +75,11 @@ SIGNATURES = {
     "qb_zero": (_I32, [_P, _SZ, _P]),
     "qb_mutate": (_I32, [_P, _P, _P, _F64, _I32, _U64, _P, _P, _P, _P]),
     "qb_mutation_rate": (_F64, [_I32]),
+    "qb_graph_begin": (_I32, [_P]),
+    "qb_graph_end": (_I32, [_P, ctypes.POINTER(_P)]),
+    "qb_graph_launch": (_I32, [_P, _P]),
+    "qb_graph_destroy": (None, [_P]),
+    "qb_autotune_rankk": (_I32, [_P, _I32, _P, _P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
 }
 
 
@@ -253,6 +258,44 @@ def zero(t, stream=None):
 def mutate(b: Batch, K, order, rate, t, seed, X, dX, kcount=None, stream=None):
     _chk(lib().qb_mutate(b.h, _ptr(K), _ptr(order), float(rate), t, seed, _ptr(X), _ptr(dX), _ptr(kcount),
                          _stream(stream)), "qb_mutate")
+
+
+class Graph:
+    """Executable HIP graph of the launches made on `stream` inside the
+    ``with`` block (a non-default torch stream)."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.h = None
+
+    def __enter__(self):
+        _chk(lib().qb_graph_begin(self.stream.cuda_stream), "qb_graph_begin")
+        return self
+
+    def __exit__(self, et, ev, tb):
+        h = ctypes.c_void_p()
+        rc = lib().qb_graph_end(self.stream.cuda_stream, ctypes.byref(h))
+        if et is None:
+            _chk(rc, "qb_graph_end")
+            self.h = h
+        return False
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else self.stream
+        _chk(lib().qb_graph_launch(self.h, s.cuda_stream), "qb_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.qb_graph_destroy(self.h)
+            self.h = None
+
+
+def autotune_rankk(P: "Problem", dX, H, reps=3, stream=None):
+    v = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _chk(lib().qb_autotune_rankk(P.h, dX.shape[0], _ptr(dX), _ptr(H), reps, ctypes.byref(v), ctypes.byref(ms),
+                                 _stream(stream)), "qb_autotune_rankk")
+    return int(v.value), float(ms.value)
 
 
 def mutation_rate(t) -> float:

@@ -2,8 +2,9 @@
 
 Host-side sequencing only: every step is a kernel of libqb.so.  The state
 (X, H, E, T, LF, K, order, dX, tiles, ...) lives in HBM for the whole run;
-one outer iteration is a fixed sequence of launches on one stream, so it can
-also be captured into a HIP graph (see ``capture_iteration``).
+one outer iteration is a fixed sequence of launches on the solver's own
+stream, so any number of iterations can be captured into one HIP graph
+(``capture``) and replayed without host involvement.
 """
 from __future__ import annotations
 
@@ -19,7 +20,8 @@ class Solver:
                  rankk_variant: int = 0):
         dev = Q.device
         self.dev = dev
-        self.P = qb.Problem(Q)
+        self.stream = torch.cuda.Stream(device=dev)
+        self.P = qb.Problem(Q, stream=self.stream)
         n = self.n = self.P.n
         self.z, self.seed, self.B, self.R = z, int(seed), B, R
         self.alpha, self.tenure, self.aspiration, self.W = alpha, tenure, aspiration, W
@@ -69,29 +71,48 @@ class Solver:
 
     def init(self):
         """Alg. 2 lines 1-2: random set, field, energy, then the initial pass."""
-        n, z = self.n, self.z
-        qb.init_solutions(n, z, self.seed, self.X)
-        qb.field(self.P, self.X, self.H)
-        qb.energy(self.X, self.H, self.E)
-        self.ebest.fill_(2**63 - 1)
-        qb.best(self.X, self.E, self.ebest, self.xbest)
+        n, z, s = self.n, self.z, self.stream
+        qb.init_solutions(n, z, self.seed, self.X, stream=s)
+        qb.field(self.P, self.X, self.H, stream=s)
+        qb.energy(self.X, self.H, self.E, stream=s)
+        with torch.cuda.stream(s):
+            self.ebest.fill_(2**63 - 1)
+        qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
         if self.init_m:
             m0 = self.init_m
             for l in range(n // m0):
-                self.ib.set_idx(np.tile(np.arange(l * m0, (l + 1) * m0, dtype=np.int32), z))
-                qb.extract(self.P, self.ib, self.X, self.H, self.itiles, self.iF0, self.iy0)
+                self.ib.set_idx(np.tile(np.arange(l * m0, (l + 1) * m0, dtype=np.int32), z), stream=s)
+                qb.extract(self.P, self.ib, self.X, self.H, self.itiles, self.iF0, self.iy0, stream=s)
                 qb.anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.R, self.seed,
-                          self.inst, self.iY, self.ie, self.B)
+                          self.inst, self.iY, self.ie, self.B, stream=s)
                 self.inst += z
-                qb.zero(self.dX)
-                qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX)
-                self._apply()
+                qb.zero(self.dX, stream=s)
+                qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, stream=s)
+                self._apply(stream=s)
+
+    def autotune(self, reps=3, density=0.3, seed=0):
+        """Pick the fastest rank-k variant for this problem and solution count
+        (all variants give the identical field; the autotuner checks it)."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        d = rng.integers(-1, 2, size=(self.z, self.n)) * (rng.random((self.z, self.n)) < density)
+        dX = torch.as_tensor(d.astype(np.int8), device=self.dev)
+        self.stream.synchronize()
+        self.rankk_variant, ms = qb.autotune_rankk(self.P, dX, self.H, reps=reps, stream=self.stream)
+        return self.rankk_variant, ms
+
+    def capture(self, iters: int) -> "qb.Graph":
+        """One HIP graph holding the next `iters` outer iterations."""
+        g = qb.Graph(self.stream)
+        with torch.cuda.stream(self.stream), g:
+            for _ in range(iters):
+                self.iterate()
+        return g
 
     def iterate(self, stream=None, marks=None):
         """One outer iteration of Alg. 2 (lines 6-11).  ``marks`` (optional) is
         a callable invoked with a stage name between launches, e.g. to record
         timing events on the stream."""
-        s = stream
+        s = stream if stream is not None else self.stream
         b = self.batch
         mark = marks or (lambda name: None)
         mark("tabu")
@@ -123,8 +144,9 @@ class Solver:
     def run(self, iters: int):
         self.init()
         trace = []
-        for _ in range(iters):
-            self.iterate()
-            trace.append(self.ebest.clone())
-        torch.cuda.synchronize()
+        with torch.cuda.stream(self.stream):
+            for _ in range(iters):
+                self.iterate()
+                trace.append(self.ebest.clone())
+        self.stream.synchronize()
         return [int(v.item()) for v in trace]

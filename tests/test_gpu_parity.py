@@ -320,6 +320,34 @@ def test_writeback_rankk(variant):
     assert (Hd.cpu().numpy() == Ho).all()
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("n,z,int8", [(37, 5, True), (1000, 70, True), (1003, 129, True), (5000, 256, True),
+                                      (300, 40, False)])
+def test_rankk_variants(n, z, int8, variant):
+    """H(X_old) + Q (X_new - X_old) must equal the field of X_new."""
+    say("rankk", n, z, int8, variant)
+    Q = inputs.dense_qubo(n, 0.5, 35) if int8 else wide_qubo(n, 35)
+    P = qb().Problem(dq(Q))
+    if variant == 2 and not P.int8_ok:
+        with pytest.raises(qb().QBError):
+            qb().rankk(P, torch.zeros((z, n), dtype=torch.int8, device=DEV),
+                       torch.zeros((z, n), dtype=torch.int32, device=DEV), variant)
+        return
+    X0 = inputs.random_solutions(z, n, 36)
+    X1 = X0.copy()
+    rng = np.random.default_rng(37)
+    flip = rng.random((z, n)) < 0.3
+    X1[flip] ^= 1
+    dX = (X1.astype(np.int16) - X0).astype(np.int8)
+    Hd = torch.as_tensor(oracle.field(Q, X0), device=DEV)
+    qb().rankk(P, torch.as_tensor(dX, device=DEV), Hd, variant)
+    assert (Hd.cpu().numpy() == oracle.field(Q, X1)).all()
+    # field from scratch (uses the matrix cores when int8 and z >= 32)
+    H2 = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().field(P, torch.as_tensor(X1, device=DEV), H2)
+    assert (H2.cpu().numpy() == oracle.field(Q, X1)).all()
+
+
 # ----------------------------------------------------------------------------- a9
 @pytest.mark.parametrize("t", [0, 3, 15, 29])
 def test_mutate_bit_exact(t):
@@ -374,3 +402,49 @@ def test_full_trajectory_small_config():
     assert (S.H.cpu().numpy() == ref["H"]).all()
     assert (S.E.cpu().numpy() == ref["E"]).all()
     assert int(S.ebest.item()) == ref["ebest"] and (S.xbest.cpu().numpy() == ref["xbest"]).all()
+
+
+def test_graph_replay_matches_eager_and_oracle():
+    """Outer iterations captured into one HIP graph: every replay (state reset
+    eagerly in between) reproduces the eager trajectory, which is the
+    oracle's."""
+    from paper_2502_13947_amd.solver import Solver
+    n, z, B, R = 700, 4, 10, 1
+    Q = inputs.dense_qubo(n, 0.2, 61)
+    job_m = np.tile([128, 64], (z, 1)).astype(np.int32)
+    P = qb().Problem(dq(Q))
+    thr = oracle.threshold_table(25, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    kw = dict(z=z, seed=9, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=B, R=R, alpha=5 * n, tenure=4)
+    G = Solver(dq(Q), **kw)
+    G.init()
+    G.stream.synchronize()
+    snap = [t.clone() for t in (G.X, G.H, G.E, G.ebest, G.xbest)]
+    graph = G.capture(2)
+    ref = oracle.run(Q, iters=2, **{k: v for k, v in kw.items()})
+    for rep in range(3):
+        with torch.cuda.stream(G.stream):
+            for t, s0 in zip((G.X, G.H, G.E, G.ebest, G.xbest), snap):
+                t.copy_(s0)
+        G.stream.synchronize()
+        graph.launch()
+        G.stream.synchronize()
+        assert (G.X.cpu().numpy() == ref["X"]).all(), rep
+        assert (G.H.cpu().numpy() == ref["H"]).all(), rep
+        assert int(G.ebest.item()) == ref["ebest"], rep
+
+
+def test_autotuner_picks_a_variant_and_keeps_parity():
+    from paper_2502_13947_amd.solver import Solver
+    n, z = 900, 64
+    Q = inputs.dense_qubo(n, 0.5, 71)
+    P = qb().Problem(dq(Q))
+    thr = oracle.threshold_table(5, 10, 0.5 * P.sigma, 0.002 * P.sigma)
+    S = Solver(dq(Q), z=z, seed=3, job_m=np.full((z, 1), 64, np.int32), init_m=0, thr_init=thr, thr=thr,
+               B=10, R=1, alpha=50, tenure=6)
+    S.init()
+    v, ms = S.autotune()
+    assert v in (1, 2) and ms > 0
+    H0 = S.H.clone()
+    S.stream.synchronize()
+    assert (S.H.cpu().numpy() == oracle.field(Q, S.X.cpu().numpy())).all()
+    assert (H0 == S.H).all()
