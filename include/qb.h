@@ -240,6 +240,54 @@ qb_status qb_mutate(qb_batch b, const int64_t *K_d, const int32_t *order_d, doub
 /* r_t = 0.3 (1 + cos(pi t / 15)) 0.99^t. */
 double qb_mutation_rate(int32_t t);
 
+/* ---------------------------------------------------------------- a3' / a10
+ * Learned selection.  An MLP scores every (solution, variable) and the top
+ * scores go to the annealer instead of the top control-parameter values;
+ * the plain keys still drive the mutation, and the exact integer energy still
+ * judges every result, so the network only changes which variables are
+ * chosen, never the arithmetic.
+ *
+ * qb_features: eight features per (p, j), each an FP32 product of an integer
+ * state quantity and a caller-supplied FP32 scale, rounded to BF16 (round to
+ * nearest even), stored F[p][j][0..7] (uint16 BF16 bits, 16-byte aligned):
+ *   0 H[p][j] sc0    1 Q_jj sc1    2 T[p][j] sc2 (Tabu flips)
+ *   3 age sc3, age = alpha - LF[p][j] if LF > 0 else alpha (Tabu steps since
+ *     the last flip)   4 G[p][j] sc4 (gain of the last IM job that changed j,
+ *     see qb_gain_update)   5 eta_j sc5   6 (z - |2 c_j - z|) sc6 (gamma z)
+ *   7 (T'_p - T[p][j]) / T'_p, T'_p = max(max_j T[p][j], 1) (Delta).
+ * scales_h: host float[7] (sc0..sc6). */
+qb_status qb_features(qb_problem P, int32_t z, const uint8_t *X_d, const int32_t *H_d, const int32_t *T_d,
+                      const int32_t *LF_d, const int32_t *G_d, int32_t alpha, const float *scales_h,
+                      uint16_t *F_d, void *stream);
+/* MLP 8 -> 64 -> 64 -> 1 with ReLU; W_d holds 4801 BF16 parameters in the
+ * order W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3.  Each layer sums in
+ * index order in FP32 from its bias; hidden activations are rounded to BF16.
+ * For each of `count` feature rows: score_d (optional, float) and the order
+ * key K_d (int64, larger score -> larger key, -0 == +0), which qb_rank and
+ * qb_select consume like the plain keys. */
+qb_status qb_mlp_score(int64_t count, const uint16_t *F_d, const uint16_t *W_d, float *score_d, int64_t *K_d,
+                       void *stream);
+/* Improvement traces: for every job variable a, outF[off[q]+a] = F[sol][S_a]
+ * and outL[off[q]+a] = 1 iff the chosen replica changed it and lowered the
+ * sub-QUBO energy (e < 0). */
+qb_status qb_trace(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_d, const int64_t *e_d,
+                   const uint8_t *y0_d, uint16_t *outF_d, uint8_t *outL_d, void *stream);
+/* G[sol][S_a] = -e (saturated to int32) of the chosen replica for every
+ * variable the job changed. */
+qb_status qb_gain_update(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d, const uint8_t *y0_d,
+                         int32_t *G_d, void *stream);
+/* Mean binary cross-entropy of sigmoid(score) against the labels over B
+ * samples and its gradient (float [4801]) with respect to the parameters:
+ * the forward pass is the inference pass, the BF16 rounding is taken as the
+ * identity backward, per-64-sample partial sums are added in a fixed order
+ * (deterministic).  work_d: qb_mlp_train_workspace(B) bytes. */
+size_t qb_mlp_train_workspace(int32_t B);
+qb_status qb_mlp_grad(int32_t B, const uint16_t *feat_d, const uint8_t *label_d, const uint16_t *W_d,
+                      float *grad_d, float *loss_d, void *work_d, void *stream);
+/* Adam on FP32 master weights (count 4801), then W_d = BF16(master). */
+qb_status qb_mlp_adam(const float *grad_d, float *master_d, float *m_d, float *v_d, int32_t step, float lr,
+                      float beta1, float beta2, float eps, uint16_t *W_d, void *stream);
+
 /* ---------------------------------------------------------------- a11
  * Outer-loop orchestration (Alg. 2).  Work the caller enqueues on `stream`
  * (a non-default stream) between qb_graph_begin and qb_graph_end -- e.g. a

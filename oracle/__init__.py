@@ -67,6 +67,19 @@ def lib():
         L.qbo_mutate.restype = i32
         L.qbo_run.argtypes = [P, P, P, P, P, P, P, P]
         L.qbo_run.restype = i32
+        f32 = ctypes.c_float
+        L.qbo_bf16_rne.argtypes = [f32]
+        L.qbo_bf16_rne.restype = ctypes.c_uint16
+        L.qbo_bf16_to_f32.argtypes = [ctypes.c_uint16]
+        L.qbo_bf16_to_f32.restype = f32
+        L.qbo_features.argtypes = [i32, i32, P, P, P, P, P, P, P, i32, P, P]
+        L.qbo_mlp_forward.argtypes = [P, P]
+        L.qbo_mlp_forward.restype = f32
+        L.qbo_score_key.argtypes = [f32]
+        L.qbo_score_key.restype = i64
+        L.qbo_mlp_scores.argtypes = [i32, P, P, P, P]
+        L.qbo_mlp_grad.argtypes = [P, i32, P, P, P, P, i32]
+        L.qbo_adam.argtypes = [i32, P, P, P, P, i32, f32, f32, f32, f32, P]
         _lib = L
     return _lib
 
@@ -263,3 +276,58 @@ def run(Q, *, z, seed, iters, alpha, tenure, job_m, init_m, thr_init, thr, B, R,
     if rc != 0:
         raise ValueError("oracle run rejected its configuration")
     return dict(X=X, H=H, E=E, xbest=xb, ebest=int(eb[0]), trace=tr[:iters])
+
+
+# --------------------------------------------------------------------------- learned selector
+NPARAM = 4801
+
+
+def bf16(values) -> np.ndarray:
+    """Round-to-nearest-even BF16 bits of FP32 values (element by element)."""
+    v = np.ascontiguousarray(values, np.float32).ravel()
+    return np.array([lib().qbo_bf16_rne(float(x)) for x in v], np.uint16)
+
+
+def bf16_to_f32(bits) -> np.ndarray:
+    b = np.ascontiguousarray(bits, np.uint16).ravel()
+    return np.array([lib().qbo_bf16_to_f32(int(x)) for x in b], np.float32)
+
+
+def features(Q, eta_v, X, H, T, LF, G, alpha, scales) -> np.ndarray:
+    Q = _c(Q, np.int16)
+    X = _c(np.atleast_2d(X), np.uint8)
+    z, n = X.shape
+    F = np.zeros((z, n, 8), np.uint16)
+    lib().qbo_features(n, z, _p(Q), _p(_c(eta_v, np.int64)), _p(X), _p(_c(H, np.int32)), _p(_c(T, np.int32)),
+                       _p(_c(LF, np.int32)), _p(_c(G, np.int32)), int(alpha), _p(_c(scales, np.float32)), _p(F))
+    return F
+
+
+def mlp_scores(Wbf, F):
+    """Scores and order keys of every feature row (bit-exact inference)."""
+    Wbf = _c(Wbf, np.uint16)
+    F = _c(F, np.uint16).reshape(-1, 8)
+    s = np.zeros(F.shape[0], np.float32)
+    K = np.zeros(F.shape[0], np.int64)
+    lib().qbo_mlp_scores(F.shape[0], _p(Wbf), _p(F), _p(s), _p(K))
+    return s, K
+
+
+def mlp_grad(Wbf, feat, label, round_acts=True):
+    Wbf = _c(Wbf, np.uint16)
+    feat = _c(feat, np.uint16).reshape(-1, 8)
+    label = _c(label, np.uint8)
+    g = np.zeros(NPARAM, np.float64)
+    loss = np.zeros(1, np.float64)
+    lib().qbo_mlp_grad(_p(Wbf), feat.shape[0], _p(feat), _p(label), _p(g), _p(loss), int(bool(round_acts)))
+    return g, float(loss[0])
+
+
+def adam(master, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    master = _c(master, np.float32).copy()
+    m = _c(m, np.float32).copy()
+    v = _c(v, np.float32).copy()
+    Wbf = np.zeros(master.shape[0], np.uint16)
+    lib().qbo_adam(master.shape[0], _p(master), _p(m), _p(v), _p(_c(grad, np.float32)), int(step), float(lr),
+                   float(beta1), float(beta2), float(eps), _p(Wbf))
+    return master, m, v, Wbf

@@ -564,3 +564,205 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
     free(Tq); free(c); free(F0); free(y0); free(Y); free(e); free(inU); free(flip);
     return 0;
 }
+
+/* ======================================================================== */
+/* Learned selector (test infrastructure for the MLP path).
+ *
+ * Eight per-(solution, variable) features, each an FP32 product of an
+ * integer state quantity and a caller-supplied FP32 scale (except Delta, an
+ * FP32 quotient), rounded to BF16 with round-to-nearest-even:
+ *   0 h_pj sc0   1 Q_jj sc1   2 T_pj sc2   3 age_pj sc3 (age = alpha - LF,
+ *   or alpha if never flipped)   4 G_pj sc4 (gain of the last IM job that
+ *   changed j)   5 eta_j sc5   6 (z - |2 c_j - z|) sc6   7 (T'_p - T_pj)/T'_p.
+ * MLP 8 -> 64 -> 64 -> 1 with ReLU; weights BF16 in the order W1[64][8],
+ * b1[64], W2[64][64], b2[64], W3[64], b3 (4801 values); every layer sums in
+ * index order in FP32 starting from the bias, hidden activations are rounded
+ * to BF16.  Parity status: BF16 rounding pinned against torch's CPU
+ * conversion; forward pinned by closed forms and an FP32 reference within
+ * rounding; gradients pinned by FP64 central differences. */
+uint16_t qbo_bf16_rne(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+float qbo_bf16_to_f32(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+void qbo_features(int n, int z, const int16_t *Q, const int64_t *eta, const uint8_t *X, const int32_t *H,
+                  const int32_t *T, const int32_t *LF, const int32_t *G, int alpha, const float *sc, uint16_t *F)
+{
+    for (int j = 0; j < n; ++j) {
+        int32_t cnt = 0;
+        for (int p = 0; p < z; ++p) cnt += X[(int64_t)p * n + j];
+        int32_t dev = 2 * cnt - z;
+        if (dev < 0) dev = -dev;
+        for (int p = 0; p < z; ++p) {
+            int32_t Tp = 1;
+            for (int k = 0; k < n; ++k)
+                if (T[(int64_t)p * n + k] > Tp) Tp = T[(int64_t)p * n + k];
+            const int64_t at = (int64_t)p * n + j;
+            const int32_t age = LF[at] > 0 ? alpha - LF[at] : alpha;
+            float f[8];
+            f[0] = (float)H[at] * sc[0];
+            f[1] = (float)Q[(int64_t)j * n + j] * sc[1];
+            f[2] = (float)T[at] * sc[2];
+            f[3] = (float)age * sc[3];
+            f[4] = (float)G[at] * sc[4];
+            f[5] = (float)eta[j] * sc[5];
+            f[6] = (float)(z - dev) * sc[6];
+            f[7] = (float)(Tp - T[at]) / (float)Tp;
+            for (int k = 0; k < 8; ++k) F[at * 8 + k] = qbo_bf16_rne(f[k]);
+        }
+    }
+}
+
+/* offsets of the parameter blocks */
+#define QBO_W1 0
+#define QBO_B1 512
+#define QBO_W2 576
+#define QBO_B2 4672
+#define QBO_W3 4736
+#define QBO_B3 4800
+#define QBO_NPARAM 4801
+
+float qbo_mlp_forward(const uint16_t *W, const uint16_t *feat)
+{
+    float x[8], h1[64], h2[64];
+    for (int i = 0; i < 8; ++i) x[i] = qbo_bf16_to_f32(feat[i]);
+    for (int k = 0; k < 64; ++k) {
+        float acc = qbo_bf16_to_f32(W[QBO_B1 + k]);
+        for (int i = 0; i < 8; ++i) acc = acc + qbo_bf16_to_f32(W[QBO_W1 + k * 8 + i]) * x[i];
+        h1[k] = qbo_bf16_to_f32(qbo_bf16_rne(acc > 0.0f ? acc : 0.0f));
+    }
+    for (int k = 0; k < 64; ++k) {
+        float acc = qbo_bf16_to_f32(W[QBO_B2 + k]);
+        for (int i = 0; i < 64; ++i) acc = acc + qbo_bf16_to_f32(W[QBO_W2 + k * 64 + i]) * h1[i];
+        h2[k] = qbo_bf16_to_f32(qbo_bf16_rne(acc > 0.0f ? acc : 0.0f));
+    }
+    float s = qbo_bf16_to_f32(W[QBO_B3]);
+    for (int i = 0; i < 64; ++i) s = s + qbo_bf16_to_f32(W[QBO_W3 + i]) * h2[i];
+    return s;
+}
+
+/* Order key of a score: larger score -> larger key, -0 and +0 equal. */
+int64_t qbo_score_key(float s)
+{
+    uint32_t u;
+    if (s == 0.0f) s = 0.0f;
+    memcpy(&u, &s, 4);
+    const uint32_t k = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return (int64_t)k - 2147483648LL;
+}
+
+void qbo_mlp_scores(int count, const uint16_t *W, const uint16_t *F, float *score, int64_t *K)
+{
+    for (int e = 0; e < count; ++e) {
+        const float s = qbo_mlp_forward(W, F + (int64_t)e * 8);
+        if (score) score[e] = s;
+        if (K) K[e] = qbo_score_key(s);
+    }
+}
+
+/* Mean binary cross-entropy of sigmoid(score) against the labels and its
+ * gradient with respect to the BF16 parameters.  With round_acts != 0 the
+ * forward pass is the FP32 inference pass (BF16 hidden activations) and the
+ * backward pass runs in FP64 with the rounding taken as the identity; with
+ * round_acts == 0 everything is FP64 (the smooth function the finite
+ * differences pin). */
+void qbo_mlp_grad(const uint16_t *W, int B, const uint16_t *feat, const uint8_t *label, double *grad,
+                  double *loss, int round_acts)
+{
+    for (int k = 0; k < QBO_NPARAM; ++k) grad[k] = 0.0;
+    double L = 0.0;
+    for (int b = 0; b < B; ++b) {
+        double x[8], z1[64], h1[64], z2[64], h2[64], s;
+        for (int i = 0; i < 8; ++i) x[i] = qbo_bf16_to_f32(feat[(int64_t)b * 8 + i]);
+        if (round_acts) {
+            /* the inference pass itself (FP32, index order, BF16 activations) */
+            float xf[8], h1f[64], h2f[64];
+            for (int i = 0; i < 8; ++i) xf[i] = (float)x[i];
+            for (int k = 0; k < 64; ++k) {
+                float acc = qbo_bf16_to_f32(W[QBO_B1 + k]);
+                for (int i = 0; i < 8; ++i) acc = acc + qbo_bf16_to_f32(W[QBO_W1 + k * 8 + i]) * xf[i];
+                z1[k] = acc;
+                h1f[k] = qbo_bf16_to_f32(qbo_bf16_rne(acc > 0.0f ? acc : 0.0f));
+                h1[k] = h1f[k];
+            }
+            for (int k = 0; k < 64; ++k) {
+                float acc = qbo_bf16_to_f32(W[QBO_B2 + k]);
+                for (int i = 0; i < 64; ++i) acc = acc + qbo_bf16_to_f32(W[QBO_W2 + k * 64 + i]) * h1f[i];
+                z2[k] = acc;
+                h2f[k] = qbo_bf16_to_f32(qbo_bf16_rne(acc > 0.0f ? acc : 0.0f));
+                h2[k] = h2f[k];
+            }
+            float sf = qbo_bf16_to_f32(W[QBO_B3]);
+            for (int i = 0; i < 64; ++i) sf = sf + qbo_bf16_to_f32(W[QBO_W3 + i]) * h2f[i];
+            s = sf;
+        } else {
+            for (int k = 0; k < 64; ++k) {
+                double acc = qbo_bf16_to_f32(W[QBO_B1 + k]);
+                for (int i = 0; i < 8; ++i) acc += (double)qbo_bf16_to_f32(W[QBO_W1 + k * 8 + i]) * x[i];
+                z1[k] = acc;
+                h1[k] = acc > 0 ? acc : 0;
+            }
+            for (int k = 0; k < 64; ++k) {
+                double acc = qbo_bf16_to_f32(W[QBO_B2 + k]);
+                for (int i = 0; i < 64; ++i) acc += (double)qbo_bf16_to_f32(W[QBO_W2 + k * 64 + i]) * h1[i];
+                z2[k] = acc;
+                h2[k] = acc > 0 ? acc : 0;
+            }
+            s = qbo_bf16_to_f32(W[QBO_B3]);
+            for (int i = 0; i < 64; ++i) s += (double)qbo_bf16_to_f32(W[QBO_W3 + i]) * h2[i];
+        }
+        const double y = label[b] ? 1.0 : 0.0;
+        /* softplus(s) - y s, computed stably */
+        L += (s > 0 ? s + log1p(exp(-s)) : log1p(exp(s))) - y * s;
+        const double ds = (1.0 / (1.0 + exp(-s)) - y) / B;
+        double dz2[64], dh1[64];
+        grad[QBO_B3] += ds;
+        for (int i = 0; i < 64; ++i) {
+            grad[QBO_W3 + i] += ds * h2[i];
+            const double dh2 = ds * qbo_bf16_to_f32(W[QBO_W3 + i]);
+            dz2[i] = z2[i] > 0 ? dh2 : 0.0;
+        }
+        for (int i = 0; i < 64; ++i) dh1[i] = 0.0;
+        for (int k = 0; k < 64; ++k) {
+            grad[QBO_B2 + k] += dz2[k];
+            for (int i = 0; i < 64; ++i) {
+                grad[QBO_W2 + k * 64 + i] += dz2[k] * h1[i];
+                dh1[i] += dz2[k] * qbo_bf16_to_f32(W[QBO_W2 + k * 64 + i]);
+            }
+        }
+        for (int k = 0; k < 64; ++k) {
+            const double dz1 = z1[k] > 0 ? dh1[k] : 0.0;
+            grad[QBO_B1 + k] += dz1;
+            for (int i = 0; i < 8; ++i) grad[QBO_W1 + k * 8 + i] += dz1 * x[i];
+        }
+    }
+    if (loss) *loss = L / B;
+}
+
+/* Adam (Kingma & Ba) on FP32 master weights, then the BF16 copy. */
+void qbo_adam(int count, float *master, float *m, float *v, const float *grad, int step, float lr,
+              float beta1, float beta2, float eps, uint16_t *Wbf)
+{
+    const float c1 = 1.0f - powf(beta1, (float)step);
+    const float c2 = 1.0f - powf(beta2, (float)step);
+    for (int k = 0; k < count; ++k) {
+        m[k] = beta1 * m[k] + (1.0f - beta1) * grad[k];
+        v[k] = beta2 * v[k] + (1.0f - beta2) * grad[k] * grad[k];
+        const float mh = m[k] / c1, vh = v[k] / c2;
+        master[k] = master[k] - lr * mh / (sqrtf(vh) + eps);
+        if (Wbf) Wbf[k] = qbo_bf16_rne(master[k]);
+    }
+}

@@ -83,6 +83,19 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
 int qbo_mutate(int n, uint8_t *x, const int64_t *K, const uint8_t *inU, int t, int p,
                uint64_t seed, uint8_t *flip);
 
+/* Learned selector (see qbo.c). */
+uint16_t qbo_bf16_rne(float f);
+float qbo_bf16_to_f32(uint16_t b);
+void qbo_features(int n, int z, const int16_t *Q, const int64_t *eta, const uint8_t *X, const int32_t *H,
+                  const int32_t *T, const int32_t *LF, const int32_t *G, int alpha, const float *sc, uint16_t *F);
+float qbo_mlp_forward(const uint16_t *W, const uint16_t *feat);
+int64_t qbo_score_key(float s);
+void qbo_mlp_scores(int count, const uint16_t *W, const uint16_t *F, float *score, int64_t *K);
+void qbo_mlp_grad(const uint16_t *W, int B, const uint16_t *feat, const uint8_t *label, double *grad,
+                  double *loss, int round_acts);
+void qbo_adam(int count, float *master, float *m, float *v, const float *grad, int step, float lr,
+              float beta1, float beta2, float eps, uint16_t *Wbf);
+
 /* Full IC-D^2S run (Alg. 2).  See qbo.c for the exact sequence. */
 typedef struct {
     int n, z;

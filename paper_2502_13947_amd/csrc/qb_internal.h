@@ -61,6 +61,9 @@ struct qb_batch_s {
     hipEvent_t ev_fork = nullptr, ev_join[QB_NCLASS] = {nullptr};
 };
 
+// Column counts c_j = sum_p X[p][j] into P->colcnt (enqueued on stream).
+qb_status qb_column_counts(qb_problem P, int z, const uint8_t *X, void *stream);
+
 // thread-local last HIP error
 void qb_set_hip_error(hipError_t e);
 

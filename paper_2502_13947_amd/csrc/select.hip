@@ -204,6 +204,13 @@ __global__ void __launch_bounds__(1024) k_mutate(int n, const int32_t *__restric
 
 }  // namespace
 
+qb_status qb_column_counts(qb_problem P, int z, const uint8_t *X, void *stream)
+{
+    k_colcount<<<(P->n + 255) / 256, 256, 0, qb_stream(stream)>>>(X, P->n, z, P->colcnt);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
 extern "C" qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const int32_t *T_d,
                             int32_t W1, int32_t W2, int32_t W3, int32_t t_bound, int64_t *K_d,
                             void *stream)
@@ -214,7 +221,8 @@ extern "C" qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const 
                          (double)std::max(t_bound, 1) * 2.0;
     if (bound >= 140737488355328.0) return QB_E_RANGE;   // 2^47
     hipStream_t s = qb_stream(stream);
-    k_colcount<<<(P->n + 255) / 256, 256, 0, s>>>(X_d, P->n, z, P->colcnt);
+    qb_status rc = qb_column_counts(P, z, X_d, stream);
+    if (rc != QB_OK) return rc;
     k_keys<<<z, 256, 0, s>>>(P->n, z, P->eta, P->eta_max, P->colcnt, T_d, W1, W2, W3, t_bound, K_d,
                              P->status);
     QB_LAUNCH_CHECK();

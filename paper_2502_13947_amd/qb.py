@@ -75,6 +75,14 @@ SIGNATURES = {
     "qb_zero": (_I32, [_P, _SZ, _P]),
     "qb_mutate": (_I32, [_P, _P, _P, _F64, _I32, _U64, _P, _P, _P, _P]),
     "qb_mutation_rate": (_F64, [_I32]),
+    "qb_features": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
+    "qb_mlp_score": (_I32, [_I64, _P, _P, _P, _P, _P]),
+    "qb_trace": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_gain_update": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
+    "qb_mlp_train_workspace": (_SZ, [_I32]),
+    "qb_mlp_grad": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_mlp_adam": (_I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _P, _P]),
     "qb_graph_begin": (_I32, [_P]),
     "qb_graph_end": (_I32, [_P, ctypes.POINTER(_P)]),
     "qb_graph_launch": (_I32, [_P, _P]),
@@ -258,6 +266,44 @@ def zero(t, stream=None):
 def mutate(b: Batch, K, order, rate, t, seed, X, dX, kcount=None, stream=None):
     _chk(lib().qb_mutate(b.h, _ptr(K), _ptr(order), float(rate), t, seed, _ptr(X), _ptr(dX), _ptr(kcount),
                          _stream(stream)), "qb_mutate")
+
+
+NPARAM = 4801
+
+
+def features(P: "Problem", X, H, T, LF, G, alpha, scales, F, stream=None):
+    sc = (ctypes.c_float * 7)(*[float(v) for v in scales[:7]])
+    _chk(lib().qb_features(P.h, X.shape[0], _ptr(X), _ptr(H), _ptr(T), _ptr(LF), _ptr(G), int(alpha),
+                           ctypes.cast(sc, ctypes.c_void_p), _ptr(F), _stream(stream)), "qb_features")
+
+
+def mlp_score(F, W, K, score=None, stream=None):
+    count = F.numel() // 8
+    _chk(lib().qb_mlp_score(count, _ptr(F), _ptr(W), _ptr(score), _ptr(K), _stream(stream)), "qb_mlp_score")
+
+
+def trace(b: "Batch", R, F, Y, e, y0, outF, outL, stream=None):
+    _chk(lib().qb_trace(b.h, R, _ptr(F), _ptr(Y), _ptr(e), _ptr(y0), _ptr(outF), _ptr(outL), _stream(stream)),
+         "qb_trace")
+
+
+def gain_update(b: "Batch", R, Y, e, y0, G, stream=None):
+    _chk(lib().qb_gain_update(b.h, R, _ptr(Y), _ptr(e), _ptr(y0), _ptr(G), _stream(stream)), "qb_gain_update")
+
+
+def mlp_train_workspace(B) -> int:
+    return int(lib().qb_mlp_train_workspace(int(B)))
+
+
+def mlp_grad(feat, label, W, grad, loss, work, stream=None):
+    B = label.numel()
+    _chk(lib().qb_mlp_grad(B, _ptr(feat), _ptr(label), _ptr(W), _ptr(grad), _ptr(loss), _ptr(work),
+                           _stream(stream)), "qb_mlp_grad")
+
+
+def mlp_adam(grad, master, m, v, step, lr, W, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _chk(lib().qb_mlp_adam(_ptr(grad), _ptr(master), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                           float(beta2), float(eps), _ptr(W), _stream(stream)), "qb_mlp_adam")
 
 
 class Graph:

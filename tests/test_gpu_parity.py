@@ -448,3 +448,116 @@ def test_autotuner_picks_a_variant_and_keeps_parity():
     S.stream.synchronize()
     assert (S.H.cpu().numpy() == oracle.field(Q, S.X.cpu().numpy())).all()
     assert (H0 == S.H).all()
+
+
+# ----------------------------------------------------------------------------- a3' / a10
+def _rand_params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return oracle.bf16(rng.normal(0, scale, size=oracle.NPARAM).astype(np.float32))
+
+
+@pytest.mark.parametrize("n,z", [(1, 1), (300, 5), (2500, 16)])
+def test_features_bit_exact(n, z):
+    Q = inputs.dense_qubo(n, 0.4, 81)
+    X = inputs.random_solutions(z, n, 82)
+    H = oracle.field(Q, X)
+    rng = np.random.default_rng(83)
+    T = rng.integers(0, 7, size=(z, n)).astype(np.int32)
+    LF = (rng.integers(0, 50, size=(z, n)) * (T > 0)).astype(np.int32)
+    G = rng.integers(-5000, 5000, size=(z, n)).astype(np.int32)
+    P = qb().Problem(dq(Q))
+    sg = max(P.sigma, 1.0)
+    sc = np.array([1 / sg, 1 / sg, 1 / 50, 1 / 50, 1 / sg, 1 / max(P.eta_max, 1), 1 / z], np.float32)
+    F = torch.zeros((z, n, 8), dtype=torch.int16, device=DEV)
+    qb().features(P, *(torch.as_tensor(a, device=DEV) for a in (X, H, T, LF, G)), 50, sc, F)
+    Fo = oracle.features(Q, oracle.eta(Q), X, H, T, LF, G, 50, sc)
+    assert (F.cpu().numpy().view(np.uint16) == Fo).all()
+
+
+@pytest.mark.parametrize("count", [1, 257, 20000])
+def test_mlp_scores_bit_exact(count):
+    W = _rand_params(84)
+    rng = np.random.default_rng(85)
+    Fh = oracle.bf16(rng.normal(0, 1.5, size=(count, 8)).astype(np.float32)).reshape(count, 8)
+    F = torch.as_tensor(Fh.view(np.int16), device=DEV)
+    Wd = torch.as_tensor(W.view(np.int16), device=DEV)
+    K = torch.zeros(count, dtype=torch.int64, device=DEV)
+    s = torch.zeros(count, dtype=torch.float32, device=DEV)
+    qb().mlp_score(F, Wd, K, score=s)
+    so, Ko = oracle.mlp_scores(W, Fh)
+    assert (s.cpu().numpy().view(np.uint32) == so.view(np.uint32)).all()
+    assert (K.cpu().numpy() == Ko).all()
+
+
+@pytest.mark.parametrize("B", [1, 64, 1000, 4096])
+def test_mlp_gradient_and_adam_vs_oracle(B):
+    W = _rand_params(86, 0.2)
+    rng = np.random.default_rng(87)
+    feat = oracle.bf16(rng.normal(0, 1, size=(B, 8)).astype(np.float32)).reshape(B, 8)
+    label = (rng.random(B) < 0.3).astype(np.uint8)
+    g_o, loss_o = oracle.mlp_grad(W, feat, label)
+    fd = torch.as_tensor(feat.view(np.int16), device=DEV)
+    ld = torch.as_tensor(label, device=DEV)
+    Wd = torch.as_tensor(W.view(np.int16), device=DEV)
+    grad = torch.zeros(oracle.NPARAM, dtype=torch.float32, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    work = torch.zeros(qb().mlp_train_workspace(B), dtype=torch.uint8, device=DEV)
+    qb().mlp_grad(fd, ld, Wd, grad, loss, work)
+    g = grad.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(g - g_o)) <= 1e-4 * np.max(np.abs(g_o)) + 1e-8
+    assert abs(float(loss.item()) - loss_o) <= 1e-5 * max(1.0, abs(loss_o))
+    # deterministic: a second evaluation is bit-identical
+    grad2 = torch.zeros_like(grad)
+    qb().mlp_grad(fd, ld, Wd, grad2, loss, work)
+    assert torch.equal(grad, grad2)
+    # Adam step from the same gradient
+    master = oracle.bf16_to_f32(W)
+    mo, m_o, v_o, Wbf_o = oracle.adam(master, np.zeros(oracle.NPARAM), np.zeros(oracle.NPARAM),
+                                      g.astype(np.float32), 1, 1e-3)
+    md = torch.as_tensor(master, device=DEV)
+    m1 = torch.zeros(oracle.NPARAM, dtype=torch.float32, device=DEV)
+    v1 = torch.zeros_like(m1)
+    qb().mlp_adam(grad, md, m1, v1, 1, 1e-3, Wd)
+    assert np.max(np.abs(md.cpu().numpy() - mo)) <= 1e-6
+    assert np.mean(Wd.cpu().numpy().view(np.uint16) == Wbf_o) > 0.999
+
+
+def test_trace_and_gain_vs_oracle():
+    n, z, R = 800, 3, 2
+    Q = inputs.dense_qubo(n, 0.5, 91)
+    X = inputs.random_solutions(z, n, 92)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, [64, 100], 93)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    Xd, Hd = torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV)
+    tiles = torch.zeros(b.tile_elems, dtype=torch.int8, device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, Xd, Hd, tiles, F0, y0)
+    thr = oracle.threshold_table(6, 10, 0.3 * P.sigma, 0.01 * P.sigma)
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    qb().anneal(b, tiles, F0, y0, torch.as_tensor(thr, device=DEV), R, 5, 0, Y, e, 10)
+    rng = np.random.default_rng(94)
+    Fh = rng.integers(0, 2**16, size=(z, n, 8), dtype=np.uint16)
+    Fd = torch.as_tensor(Fh.view(np.int16), device=DEV)
+    outF = torch.zeros((b.total, 8), dtype=torch.int16, device=DEV)
+    outL = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().trace(b, R, Fd, Y, e, y0, outF, outL)
+    G = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().gain_update(b, R, Y, e, y0, G)
+    Ge = np.zeros((z, n), np.int32)
+    for q in range(b.J):
+        p = sol[q]
+        S = idx[b.off[q]:b.off[q + 1]]
+        Tq, c, Fq, yy = oracle.extract(Q, X[p], H[p], S)
+        Yo, eo = oracle.anneal(Tq, Fq, yy, thr, R, 5, q, 10)
+        rb = int(np.argmin(eo))
+        changed = Yo[rb] != yy
+        sl = slice(b.off[q], b.off[q + 1])
+        assert (outF.cpu().numpy().view(np.uint16)[sl] == Fh[p, S]).all()
+        assert (outL.cpu().numpy()[sl] == (changed & (eo[rb] < 0))).all()
+        Ge[p, S[changed]] = -eo[rb]
+    assert (G.cpu().numpy() == Ge).all()

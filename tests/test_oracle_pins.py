@@ -382,3 +382,124 @@ def test_run_state_is_consistent_and_reaches_optimum_on_tiny_instances():
         assert all(a >= b for a, b in zip(res["trace"], res["trace"][1:]))
         hits += res["ebest"] == opt
     assert hits >= 5
+
+
+# --------------------------------------------------------------------------- learned selector
+def _rand_params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return oracle.bf16(rng.normal(0, scale, size=oracle.NPARAM).astype(np.float32))
+
+
+def test_bf16_rounding_matches_torch_round_to_nearest_even():
+    import torch
+    rng = np.random.default_rng(1)
+    bits = rng.integers(0, 2**32, size=20000, dtype=np.uint64).astype(np.uint32)
+    vals = bits.view(np.float32)
+    vals = vals[np.isfinite(vals)]
+    special = np.array([0.0, -0.0, 1.0, 1.0 + 2**-8, 1.0 + 3 * 2**-8, 1.0 + 2**-9, -3.0e38, 1e-40],
+                       np.float32)
+    vals = np.concatenate([vals, special])
+    ref = torch.from_numpy(vals).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert (oracle.bf16(vals) == ref).all()
+
+
+def test_mlp_forward_closed_forms():
+    W = np.zeros(oracle.NPARAM, np.uint16)
+    W[4800] = oracle.bf16([0.75])[0]
+    s, _ = oracle.mlp_scores(W, np.zeros((3, 8), np.uint16))
+    assert (s == 0.75).all()
+    # one path: h1_0 = relu(x0), h2_0 = relu(h1_0), s = 2 h2_0
+    W = np.zeros(oracle.NPARAM, np.uint16)
+    W[0] = oracle.bf16([1.0])[0]            # W1[0][0]
+    W[576] = oracle.bf16([1.0])[0]          # W2[0][0]
+    W[4736] = oracle.bf16([2.0])[0]         # W3[0]
+    xs = np.array([1.5, -2.0, 0.0, 3.25], np.float32)
+    F = np.zeros((4, 8), np.uint16)
+    F[:, 0] = oracle.bf16(xs)
+    s, K = oracle.mlp_scores(W, F)
+    assert list(s) == [3.0, 0.0, 0.0, 6.5]
+    assert K[1] == K[2] and K[0] > K[1] and K[3] > K[0]
+
+
+def test_mlp_forward_matches_real_arithmetic_within_rounding():
+    W = _rand_params(2)
+    Wf = oracle.bf16_to_f32(W).astype(np.float64)
+    rng = np.random.default_rng(3)
+    F = oracle.bf16(rng.normal(0, 1, size=(200, 8)).astype(np.float32)).reshape(200, 8)
+    x = oracle.bf16_to_f32(F).reshape(200, 8).astype(np.float64)
+    W1, b1 = Wf[:512].reshape(64, 8), Wf[512:576]
+    W2, b2 = Wf[576:4672].reshape(64, 64), Wf[4672:4736]
+    W3, b3 = Wf[4736:4800], Wf[4800]
+    h1 = np.maximum(x @ W1.T + b1, 0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0)
+    ref = h2 @ W3 + b3
+    s, _ = oracle.mlp_scores(W, F)
+    # two BF16 roundings of the hidden layers: relative error of a few 2^-8
+    assert np.max(np.abs(s - ref)) <= 0.03 * (np.max(np.abs(ref)) + 1)
+
+
+def test_score_keys_preserve_order():
+    vals = np.array([-3.5, -1e-30, -0.0, 0.0, 1e-30, 2.0, 7.0], np.float32)
+    keys = [int(oracle.lib().qbo_score_key(float(v))) for v in vals]
+    assert keys[2] == keys[3]                      # -0 and +0 share a key
+    assert keys == sorted(keys)                    # order preserved
+    assert len(set(keys)) == len(vals) - 1
+
+
+def test_mlp_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    W = _rand_params(5)
+    feat = oracle.bf16(rng.normal(0, 1, size=(40, 8)).astype(np.float32)).reshape(40, 8)
+    label = (rng.random(40) < 0.4).astype(np.uint8)
+    g, loss = oracle.mlp_grad(W, feat, label, round_acts=False)
+    Wf = oracle.bf16_to_f32(W).astype(np.float64)
+
+    def loss_at(wvec):
+        x = oracle.bf16_to_f32(feat).reshape(40, 8).astype(np.float64)
+        h1 = np.maximum(x @ wvec[:512].reshape(64, 8).T + wvec[512:576], 0)
+        h2 = np.maximum(h1 @ wvec[576:4672].reshape(64, 64).T + wvec[4672:4736], 0)
+        s = h2 @ wvec[4736:4800] + wvec[4800]
+        return np.mean(np.logaddexp(0, s) - label * s)
+
+    assert abs(loss_at(Wf) - loss) < 1e-9
+    for k in [0, 7, 100, 511, 520, 600, 3000, 4680, 4740, 4800]:
+        e = np.zeros_like(Wf)
+        e[k] = 1e-6
+        fd = (loss_at(Wf + e) - loss_at(Wf - e)) / 2e-6
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, k
+
+
+def test_adam_first_step_closed_form():
+    master = np.array([1.0, -2.0, 0.5], np.float32)
+    grad = np.array([0.1, -3.0, 0.0], np.float32)
+    m2, m, v, Wbf = oracle.adam(master, np.zeros(3), np.zeros(3), grad, step=1, lr=0.01)
+    # bias-corrected first step moves each weight by lr * sign(g)
+    assert m2[0] == pytest.approx(0.99, abs=1e-6)
+    assert m2[1] == pytest.approx(-1.99, abs=1e-6)
+    assert m2[2] == 0.5
+    assert (Wbf == oracle.bf16(m2)).all()
+
+
+def test_features_closed_forms():
+    n, z = 6, 4
+    Q = rand_sym(n, 77)
+    X = np.zeros((z, n), np.uint8)
+    X[:2, 0] = 1                     # c_0 = z/2: gamma = 1; other columns c = 0: gamma = 0
+    H = oracle.field(Q, X)
+    T = np.zeros((z, n), np.int32)
+    T[1, 3] = 4                      # T'_1 = 4
+    LF = np.zeros((z, n), np.int32)
+    LF[1, 3] = 7
+    G = np.zeros((z, n), np.int32)
+    G[2, 5] = 1000
+    alpha = 10
+    et = oracle.eta(Q)
+    sc = np.array([1.0, 1.0, 0.5, 0.1, 0.001, 1.0 / et.max(), 1.0 / z], np.float32)
+    F = oracle.bf16_to_f32(oracle.features(Q, et, X, H, T, LF, G, alpha, sc)).reshape(z, n, 8)
+    assert F[1, 3, 2] == 2.0 and F[1, 3, 3] == pytest.approx(0.3, rel=1e-2)
+    assert F[1, 3, 7] == 0.0 and F[1, 2, 7] == 1.0 and F[0, 3, 7] == 1.0
+    assert F[0, 0, 6] == 1.0 and F[0, 1, 6] == 0.0
+    assert F[2, 5, 4] == 1.0 and F[3, 5, 4] == 0.0
+    assert F[:, :, 5].max() == 1.0
+    assert F[0, 4, 3] == 1.0                       # never flipped: age = alpha
+    assert F[0, 2, 1] == float(Q[2, 2])
