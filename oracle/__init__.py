@@ -248,11 +248,11 @@ class _RunCfg(ctypes.Structure):
                 ("job_m", ctypes.c_void_p), ("init_m", ctypes.c_int32),
                 ("nsw_init", ctypes.c_int32), ("thr_init", ctypes.c_void_p),
                 ("nsw", ctypes.c_int32), ("B", ctypes.c_int32), ("thr", ctypes.c_void_p),
-                ("R", ctypes.c_int32), ("max_solutions", ctypes.c_int32)]
+                ("R", ctypes.c_int32), ("mlp_W", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
 
 
 def run(Q, *, z, seed, iters, alpha, tenure, job_m, init_m, thr_init, thr, B, R,
-        aspiration=True, W=(2, 2, 1)):
+        aspiration=True, W=(2, 2, 1), mlp_W=None, scales=None):
     """Full Alg. 2 run.  job_m: [z, k] sub-QUBO sizes.  Returns a dict with the
     final X, H, E, the best solution/energy, and E_best after each iteration."""
     Q = _c(Q, np.int16)
@@ -265,7 +265,12 @@ def run(Q, *, z, seed, iters, alpha, tenure, job_m, init_m, thr_init, thr, B, R,
                   aspiration=int(bool(aspiration)), W1=W[0], W2=W[1], W3=W[2],
                   jobs_per_sol=job_m.shape[1], job_m=_p(job_m).value, init_m=init_m,
                   nsw_init=thr_init.shape[0], thr_init=_p(thr_init).value,
-                  nsw=thr.shape[0], B=B, thr=_p(thr).value, R=R, max_solutions=0)
+                  nsw=thr.shape[0], B=B, thr=_p(thr).value, R=R, mlp_W=None, scales=None)
+    if mlp_W is not None:
+        mlp_W = _c(mlp_W, np.uint16)
+        scales = _c(scales, np.float32)
+        cfg.mlp_W = _p(mlp_W).value
+        cfg.scales = _p(scales).value
     X = np.zeros((z, n), np.uint8)
     H = np.zeros((z, n), np.int32)
     E = np.zeros(z, np.int64)

@@ -417,6 +417,11 @@ int qbo_mutate(int n, uint8_t *x, const int64_t *K, const uint8_t *inU, int t, i
 }
 
 /* ------------------------------------------------------------------------ */
+uint16_t qbo_bf16_rne(float f);
+void qbo_features(int n, int z, const int16_t *Q, const int64_t *eta, const uint8_t *X, const int32_t *H,
+                  const int32_t *T, const int32_t *LF, const int32_t *G, int alpha, const float *sc, uint16_t *F);
+void qbo_mlp_scores(int count, const uint16_t *W, const uint16_t *F, float *score, int64_t *K);
+
 static void best_update(int n, int z, const uint8_t *X, const int64_t *E,
                         uint8_t *xbest, int64_t *ebest)
 {
@@ -451,7 +456,11 @@ static void pick_and_write(int m, const int32_t *S, const uint8_t *Y, const int6
  *       replica on ties) written back unconditionally; h, E; best.
  *     Mutation with r_t; h, E; best.
  *   Best: strictly lower energy wins, scanning solutions in order, so ties go
- *   to the earliest stage and the lowest solution index. */
+ *   to the earliest stage and the lowest solution index.
+ *   Learned selection (cfg->mlp_W != NULL): the IM variables are the top
+ *   MLP scores of the eight features instead of the top A; mutation still
+ *   uses A.  G (gain of the last IM job that changed a variable) feeds
+ *   feature 4. */
 int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, int64_t *E,
             uint8_t *xbest, int64_t *ebest, int64_t *trace_best)
 {
@@ -464,13 +473,16 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
         }
         if (tot > n) return -1;
     }
+    const int learned = cfg->mlp_W != NULL;
     int64_t *eta = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int32_t *T = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * z);
-    int32_t *LF = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *LF = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * z);
+    int32_t *G = (int32_t *)calloc((size_t)n * z, sizeof(int32_t));
     int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * z);
+    int64_t *KL = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * z);
+    uint16_t *F = (uint16_t *)malloc(sizeof(uint16_t) * 8 * (size_t)n * z);
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     uint8_t *X0 = (uint8_t *)malloc((size_t)n * z);
-    int32_t *Hs = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int mmax = cfg->init_m;
     for (int i = 0; i < z * kj; ++i)
         if (cfg->job_m[i] > mmax) mmax = cfg->job_m[i];
@@ -514,12 +526,16 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
     for (int t = 0; t < cfg->iters; ++t) {
         for (int p = 0; p < z; ++p)
             qbo_tabu(n, Q, X + (int64_t)p * n, H + (int64_t)p * n, E + p, cfg->alpha,
-                     cfg->tenure, cfg->aspiration, T + (int64_t)p * n, LF);
+                     cfg->tenure, cfg->aspiration, T + (int64_t)p * n, LF + (int64_t)p * n);
         best_update(n, z, X, E, xbest, ebest);
 
         qbo_keys(n, z, eta, X, T, cfg->W1, cfg->W2, cfg->W3, K);
+        if (learned) {
+            qbo_features(n, z, Q, eta, X, H, T, LF, G, cfg->alpha, cfg->scales, F);
+            qbo_mlp_scores(n * z, cfg->mlp_W, F, NULL, KL);
+        }
         for (int p = 0; p < z; ++p) {
-            qbo_order(n, K + (int64_t)p * n, order);
+            qbo_order(n, (learned ? KL : K) + (int64_t)p * n, order);
             int off = 0;
             for (int q = 0; q < kj; ++q) {
                 int m = cfg->job_m[p * kj + q];
@@ -539,6 +555,15 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
                 qbo_anneal(m, Tq, F0, y0, cfg->nsw, cfg->B, cfg->thr, cfg->R, cfg->seed,
                            inst + (uint32_t)(p * kj + q), Y, e);
                 pick_and_write(m, Sq, Y, e, cfg->R, X + (int64_t)p * n);
+                /* last-improvement gain of every variable this job changed */
+                int rb = 0;
+                for (int r = 1; r < cfg->R; ++r)
+                    if (e[r] < e[rb]) rb = r;
+                int64_t g = -e[rb];
+                if (g > INT32_MAX) g = INT32_MAX;
+                if (g < INT32_MIN) g = INT32_MIN;
+                for (int a = 0; a < m; ++a)
+                    if (Y[(int64_t)rb * m + a] != y0[a]) G[(int64_t)p * n + Sq[a]] = (int32_t)g;
                 off += m;
             }
         }
@@ -559,8 +584,7 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
         best_update(n, z, X, E, xbest, ebest);
         if (trace_best) trace_best[t] = *ebest;
     }
-    (void)Hs;
-    free(eta); free(T); free(LF); free(K); free(order); free(X0); free(Hs); free(S);
+    free(eta); free(T); free(LF); free(G); free(K); free(KL); free(F); free(order); free(X0); free(S);
     free(Tq); free(c); free(F0); free(y0); free(Y); free(e); free(inU); free(flip);
     return 0;
 }

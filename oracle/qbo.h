@@ -108,7 +108,8 @@ typedef struct {
     int init_m;                /* initial-pass block size (0 = no initial pass) */
     int nsw_init; const int32_t *thr_init;
     int nsw; int B; const int32_t *thr; int R;
-    int max_solutions;         /* unused placeholder, keep 0 */
+    const uint16_t *mlp_W;     /* NULL: plain selection; else the BF16 MLP picks the IM variables */
+    const float *scales;       /* 7 feature scales (learned selection) */
 } qbo_run_cfg;
 
 /* Outputs: X,H,E final state; xbest[n], *ebest; trace_best[iters] = E_best

@@ -14,10 +14,20 @@ import torch
 from . import qb
 
 
+def feature_scales(P: "qb.Problem", alpha: int, z: int) -> np.ndarray:
+    """FP32 scales of features 0..6 (local field, diagonal, flips, tabu age,
+    last gain, eta, gamma z): the field scale sigma, the Tabu length, eta_max
+    and z bring each feature to order one."""
+    sg = max(P.sigma, 1.0)
+    a = max(alpha, 1)
+    return np.array([1.0 / sg, 1.0 / sg, 1.0 / a, 1.0 / a, 1.0 / sg, 1.0 / max(P.eta_max, 1), 1.0 / z],
+                    np.float32)
+
+
 class Solver:
     def __init__(self, Q: torch.Tensor, *, z: int, seed: int, job_m, init_m: int, thr_init, thr,
                  B: int, R: int, alpha: int, tenure: int, aspiration: bool = True, W=(2, 2, 1),
-                 rankk_variant: int = 0):
+                 rankk_variant: int = 0, mlp_W=None, trace_capacity: int = 0):
         dev = Q.device
         self.dev = dev
         self.stream = torch.cuda.Stream(device=dev)
@@ -60,6 +70,21 @@ class Solver:
             self.iy0 = torch.zeros(ib.total, dtype=torch.uint8, device=dev)
             self.iY = torch.zeros(ib.total * R, dtype=torch.uint8, device=dev)
             self.ie = torch.zeros(ib.J * R, dtype=torch.int64, device=dev)
+        # learned selection and traces (features of the Tabu state)
+        self.G = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        self.scales = feature_scales(self.P, alpha, z)
+        self.learned = mlp_W is not None
+        self.tracing = trace_capacity > 0
+        if self.learned or self.tracing:
+            self.F = torch.zeros((z, n, 8), dtype=torch.int16, device=dev)
+        if self.learned:
+            self.mlp_W = torch.as_tensor(np.ascontiguousarray(mlp_W, np.uint16).view(np.int16), device=dev)
+            self.KL = torch.zeros((z, n), dtype=torch.int64, device=dev)
+            self.orderL = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        if self.tracing:
+            self.trF = torch.zeros((trace_capacity, 8), dtype=torch.int16, device=dev)
+            self.trL = torch.zeros(trace_capacity, dtype=torch.uint8, device=dev)
+            self.trN = 0
         self.inst = 0
         self.t = 0
 
@@ -122,7 +147,15 @@ class Solver:
         qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
         qb.keys(self.P, self.X, self.T, self.K, self.W, t_bound=max(self.alpha, 1), stream=s)
         qb.rank(self.K, self.order, stream=s)
-        qb.select(b, self.order, stream=s)
+        if self.learned or self.tracing:
+            qb.features(self.P, self.X, self.H, self.T, self.LF, self.G, self.alpha, self.scales, self.F,
+                        stream=s)
+        if self.learned:
+            qb.mlp_score(self.F, self.mlp_W, self.KL, stream=s)
+            qb.rank(self.KL, self.orderL, stream=s)
+            qb.select(b, self.orderL, stream=s)
+        else:
+            qb.select(b, self.order, stream=s)
         mark("extract")
         qb.extract(self.P, b, self.X, self.H, self.tiles, self.F0, self.y0, stream=s)
         mark("anneal")
@@ -130,6 +163,11 @@ class Solver:
                   self.B, stream=s)
         mark("apply")
         self.inst += b.J
+        qb.gain_update(b, self.R, self.Y, self.e, self.y0, self.G, stream=s)
+        if self.tracing and self.trN + b.total <= self.trF.shape[0]:
+            qb.trace(b, self.R, self.F, self.Y, self.e, self.y0, self.trF[self.trN:], self.trL[self.trN:],
+                     stream=s)
+            self.trN += b.total
         qb.zero(self.dX, stream=s)
         qb.writeback(b, self.R, self.Y, self.e, self.y0, self.X, self.dX, stream=s)
         self._apply(stream=s)

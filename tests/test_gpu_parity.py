@@ -561,3 +561,55 @@ def test_trace_and_gain_vs_oracle():
         assert (outL.cpu().numpy()[sl] == (changed & (eo[rb] < 0))).all()
         Ge[p, S[changed]] = -eo[rb]
     assert (G.cpu().numpy() == Ge).all()
+
+
+def test_learned_selection_full_trajectory_vs_oracle():
+    """Alg. 2 with the MLP choosing the IM variables: bit-exact trajectory."""
+    from paper_2502_13947_amd.solver import Solver, feature_scales
+    n, z, iters, B, R = 500, 4, 3, 10, 2
+    Q = inputs.dense_qubo(n, 0.15, 101)
+    job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
+    P = qb().Problem(dq(Q))
+    thr = oracle.threshold_table(20, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    W = _rand_params(102, 0.25)
+    alpha = 5 * n
+    S = Solver(dq(Q), z=z, seed=13, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=B, R=R, alpha=alpha,
+               tenure=3, mlp_W=W)
+    trace = S.run(iters)
+    ref = oracle.run(Q, z=z, seed=13, iters=iters, alpha=alpha, tenure=3, job_m=job_m, init_m=0, thr_init=thr,
+                     thr=thr, B=B, R=R, mlp_W=W, scales=feature_scales(P, alpha, z))
+    assert trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all()
+    assert (S.H.cpu().numpy() == ref["H"]).all()
+
+
+def test_traces_and_training_are_deterministic():
+    from paper_2502_13947_amd import learn
+    from paper_2502_13947_amd.solver import Solver
+    n, z = 600, 8
+    Q = inputs.dense_qubo(n, 0.3, 111)
+    P = qb().Problem(dq(Q))
+    thr = oracle.threshold_table(30, 10, 0.5 * P.sigma, 0.002 * P.sigma)
+    job_m = np.full((z, 1), 128, np.int32)
+    S = Solver(dq(Q), z=z, seed=1, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=10, R=1, alpha=5 * n,
+               tenure=4, trace_capacity=z * 128 * 4)
+    S.run(4)
+    feat, lab = S.trF[:S.trN].clone(), S.trL[:S.trN].clone()
+    assert S.trN == z * 128 * 4
+    assert 0 < float(lab.float().mean()) < 1
+    def full_loss(W):
+        g = torch.zeros(qb().NPARAM, dtype=torch.float32, device=DEV)
+        l = torch.zeros(1, dtype=torch.float32, device=DEV)
+        work = torch.zeros(qb().mlp_train_workspace(lab.numel()), dtype=torch.uint8, device=DEV)
+        qb().mlp_grad(feat, lab, W, g, l, work)
+        return float(l.item())
+
+    ws = []
+    for _ in range(2):
+        tr = learn.Trainer(DEV, batch=256, lr=3e-3, seed=7)
+        before = full_loss(tr.W)
+        tr.fit(feat, lab, epochs=6)
+        after = full_loss(tr.W)
+        ws.append(tr.weights())
+    assert (ws[0] == ws[1]).all()
+    assert after < before
