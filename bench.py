@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=8, help="solutions in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-init-pass", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="also time a captured HIP graph of the same steps")
+    ap.add_argument("--ttt", action="store_true",
+                    help="time-to-target: learned vs plain selection (trains the selector first)")
+    ap.add_argument("--ttt-seeds", type=int, default=5)
+    ap.add_argument("--ttt-iters", type=int, default=10)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (counter calibration)")
     return ap.parse_args()
 
 
@@ -91,11 +97,99 @@ def cpu_baseline(Q, w, thr, nsol):
                        f"({attempts} attempts, {dt:.1f} s, single thread)")
 
 
+def run_timed(S, iters, torch):
+    """Outer iterations with an event after each; returns (ms since the first
+    iteration started, E_best) per iteration."""
+    st = S.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    evs, bests = [], []
+    with torch.cuda.stream(st):
+        ev0.record(st)
+        for _ in range(iters):
+            S.iterate()
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(st)
+            evs.append(e)
+            bests.append(S.ebest.clone())
+    st.synchronize()
+    return [ev0.elapsed_time(e) for e in evs], [int(b.item()) for b in bests]
+
+
+def ttt_main(a):
+    """Time to reach the plain selector's best energy, learned vs plain, on
+    n=5000 / 50% instances never used for training (median over seeds)."""
+    import torch
+
+    from paper_2502_13947_amd import inputs, learn, qb
+    from paper_2502_13947_amd.solver import Solver
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    feat1, lab1 = learn.collect_traces(["c1_n2500_d10"], seeds=[1, 2, 3], iters=10, device=dev)
+    feat2, lab2 = learn.collect_traces(["c2_n5000_d50"], seeds=[1, 2], iters=4, device=dev)
+    feat, lab = torch.cat([feat1, feat2]), torch.cat([lab1, lab2])
+    t_collect = time.perf_counter() - t0
+    tr = learn.Trainer(dev, batch=4096, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = tr.fit(feat, lab, epochs=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    W = tr.weights()
+
+    w = workload("c2_n5000_d50")
+    n, z = w["n"], w["z"]
+    rows = []
+    for sd in range(a.ttt_seeds):
+        Q = inputs.dense_qubo(n, 0.5, 7000 + sd)
+        Qd = torch.as_tensor(Q, device=dev)
+        sigma = qb.Problem(Qd).sigma
+        thr = qb.threshold_table(w["nsw"], 10, 0.5 * sigma, 0.002 * sigma)
+        kw = dict(z=z, seed=9000 + sd, job_m=w["job_m"], init_m=w["init_m"], thr_init=thr, thr=thr, B=10,
+                  R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
+        P = Solver(Qd, **kw)
+        P.init()
+        P.autotune()
+        tp, bp = run_timed(P, a.ttt_iters, torch)
+        target = bp[-1]
+        t_plain = next(t for t, b in zip(tp, bp) if b <= target)
+        del P
+        L = Solver(Qd, mlp_W=W, **kw)
+        L.init()
+        L.autotune()
+        tl, bl = run_timed(L, 2 * a.ttt_iters, torch)
+        hit = [t for t, b in zip(tl, bl) if b <= target]
+        t_learned = hit[0] if hit else None
+        # best energy of the learned run within the plain run's wall-clock
+        within = [b for t, b in zip(tl, bl) if t <= tp[-1]]
+        rows.append(dict(seed=sd, target=target, t_plain_ms=t_plain, t_learned_ms=t_learned,
+                         learned_best_at_equal_time=min(within) if within else None,
+                         plain_best=bp[-1], learned_best_2x=bl[-1]))
+        del L
+    ratios = [r["t_learned_ms"] / r["t_plain_ms"] for r in rows if r["t_learned_ms"] is not None]
+    out = {
+        "metric": "time-to-target-energy, learned vs plain selection",
+        "workload": "n=5000, 50% dense, z=256, one 512-variable sub-QUBO per solution, 1000 sweeps",
+        "target": "best energy of the plain selector after %d outer iterations" % a.ttt_iters,
+        "seeds": a.ttt_seeds,
+        "reached": len(ratios),
+        "median_ratio_learned_over_plain": float(np.median(ratios)) if ratios else None,
+        "learned_wins_at_equal_time": sum(1 for r in rows if r["learned_best_at_equal_time"] is not None
+                                          and r["learned_best_at_equal_time"] <= r["plain_best"]),
+        "training": {"samples": int(lab.numel()), "positive_rate": float(lab.float().mean()),
+                     "collect_s": t_collect, "train_s": t_train, "epochs": 3, "batch": 4096,
+                     "loss_per_epoch": losses},
+        "runs": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if a.ttt:
+        return ttt_main(a)
     import torch
 
     from paper_2502_13947_amd import inputs, qb
@@ -186,6 +280,16 @@ def main():
                              alu_frac=ops / t_ann / 1e12 / ALU_PEAK_TOPS)
     other["k_tabu"] = dict(ms=stages["tabu"], GBps=tabu_bytes / t_tabu / 1e9,
                            hbm_frac=tabu_bytes / t_tabu / 1e9 / HBM_PEAK_GBS)
+
+    if a.copy_probe > 0:
+        nb = a.copy_probe << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                dst.copy_(src)
+        stream.synchronize()
+        del src, dst
 
     cpu = None
     if a.cpu_sample > 0:
