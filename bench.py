@@ -97,6 +97,22 @@ def cpu_baseline(Q, w, thr, nsol):
                        f"({attempts} attempts, {dt:.1f} s, single thread)")
 
 
+def measured_traffic(workload_name, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def run_timed(S, iters, torch):
     """Outer iterations with an event after each; returns (ms since the first
     iteration started, E_best) per iteration."""
@@ -266,13 +282,13 @@ def main():
     if t_tabu >= t_ann:
         ach = tabu_bytes / t_tabu / 1e9
         roof = dict(kernel="k_tabu", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None,
+                    frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(a.workload, "k_tabu"),
                     algorithmic=f"{z} solutions x {w['alpha']} steps x one {n}-entry int{8 * qbytes} row of Q")
     else:
         ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
         ach = ops / t_ann / 1e12
         roof = dict(kernel="k_anneal", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
-                    frac=ach / ALU_PEAK_TOPS, traffic=None,
+                    frac=ach / ALU_PEAK_TOPS, traffic=measured_traffic(a.workload, "k_anneal"),
                     algorithmic=f"{attempts_per_step} attempts x {ANNEAL_OPS_PER_ATTEMPT} int ops")
     other = {}
     ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
