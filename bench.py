@@ -137,7 +137,7 @@ def ttt_main(a):
     import torch
 
     from paper_2502_13947_amd import inputs, learn, qb
-    from paper_2502_13947_amd.solver import Solver
+    from paper_2502_13947_amd.solver import Solver, default_thresholds
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     feat1, lab1 = learn.collect_traces(["c1_n2500_d10"], seeds=[1, 2, 3], iters=10, device=dev)
@@ -159,7 +159,7 @@ def ttt_main(a):
         Q = inputs.dense_qubo(n, 0.5, 7000 + sd)
         Qd = torch.as_tensor(Q, device=dev)
         sigma = qb.Problem(Qd).sigma
-        thr = qb.threshold_table(w["nsw"], 10, 0.5 * sigma, 0.002 * sigma)
+        thr = default_thresholds(qb.Problem(Qd), w["nsw"])
         kw = dict(z=z, seed=9000 + sd, job_m=w["job_m"], init_m=w["init_m"], thr_init=thr, thr=thr, B=10,
                   R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
         P = Solver(Qd, **kw)
@@ -209,7 +209,7 @@ def main():
     import torch
 
     from paper_2502_13947_amd import inputs, qb
-    from paper_2502_13947_amd.solver import Solver
+    from paper_2502_13947_amd.solver import Solver, default_thresholds
 
     w = workload(a.workload)
     n, z = w["n"], w["z"]
@@ -217,7 +217,7 @@ def main():
     dev = torch.device("cuda:0")
     Qd = torch.as_tensor(Q, device=dev)
     sigma = qb.Problem(Qd).sigma
-    thr = qb.threshold_table(w["nsw"], w["B"], 0.5 * sigma, 0.002 * sigma)
+    thr = default_thresholds(qb.Problem(Qd), w["nsw"], w["B"])
     S = Solver(Qd, z=z, seed=w["seed"], job_m=w["job_m"], init_m=0 if a.no_init_pass else w["init_m"],
                thr_init=thr, thr=thr, B=w["B"], R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
     S.init()

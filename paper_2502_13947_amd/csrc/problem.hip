@@ -146,7 +146,7 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
         }
         const int ept = qb_tabu_ept(n);
         if (ept) {
-            P->ldp = 256 * ept;
+            P->ldp = QB_TABU_THREADS * ept;
             const size_t esz = P->int8_ok ? 1 : 2;
             if (hipMalloc(&P->Qp, esz * (size_t)n * P->ldp) != hipSuccess) { fail(QB_E_HIP); break; }
             dim3 g((P->ldp + 255) / 256, n);

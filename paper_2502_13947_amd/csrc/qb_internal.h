@@ -26,13 +26,14 @@ struct qb_problem_s {
     double sigma = 0.0;
 };
 
-// Elements per thread of the 256-thread Tabu workgroup for n variables (a
-// multiple of 4 so that row chunks are dword aligned); 0 if n is too large.
+// Threads of the Tabu workgroup and elements per thread for n variables;
+// the padded copy of Q has pitch QB_TABU_THREADS * EPT.  0 if n is too large.
+#define QB_TABU_THREADS 512
 static inline int qb_tabu_ept(int n)
 {
-    static const int opts[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 64};
+    static const int opts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
     for (int e : opts)
-        if (n <= 256 * e) return e;
+        if (n <= QB_TABU_THREADS * e) return e;
     return 0;
 }
 

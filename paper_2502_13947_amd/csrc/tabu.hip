@@ -1,8 +1,9 @@
-// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 256-thread
-// workgroup (four waves, one per SIMD) per solution.
+// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 512-thread
+// workgroup (eight waves, two per SIMD, so one wave's latency overlaps the
+// other's work) per solution.
 //
-// Thread t owns the EPT consecutive variables [t*EPT, (t+1)*EPT) and keeps in
-// registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
+// Thread t owns the variables j = e*512 + t (e < EPT; every row chunk read is
+// coalesced across the workgroup) and keeps in registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
 // to be non-negative), the factor S_j = 2(1-2x_j), and the step U_j after
 // which the variable is free again.  U replaces the tenure vector of the
 // listing: "C_j <= 0 at step t" is exactly "U_j <= t-1" when U is updated
@@ -11,10 +12,10 @@
 // One step: every lane forms a 32-bit key (move value, element) for each of
 // its allowed variables (not tabu, or aspirating: OV + D < OV_min) and keeps
 // the minimum; the wave minimum comes from DPP row operations plus four
-// readlanes, the lowest lane whose minimum has that move value gives the
-// lowest index (lane-major order of the indices), and the four wave
+// readlanes; index order inside a wave is (element, lane), so the lowest
+// lane holding the minimal key gives the lowest index; the eight wave
 // winners meet in LDS (one barrier per step, double-buffered slots).  The
-// chosen variable's row of the padded copy of Q is read with wide loads and
+// chosen variable's row of the padded copy of Q is read (coalesced) and
 // every D is updated by one multiply-add; the owner of the flipped variable
 // patches its own element through a scalar switch.  x_min is never copied:
 // per-variable "flipped since the last improvement" bits recover it, and the
@@ -23,7 +24,7 @@
 
 namespace {
 
-constexpr int TB = 256;
+constexpr int TB = QB_TABU_THREADS;
 constexpr int NW = TB / 64;
 
 constexpr int ceil_log2(int v) { return v <= 1 ? 0 : 1 + ceil_log2((v + 1) / 2); }
@@ -41,24 +42,6 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
     const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
     const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
     return min(min(a, b), min(c, d));
-}
-
-// EPT consecutive row elements (EPT * sizeof(QT) bytes, 4-byte aligned).
-template <int EPT, typename QT>
-__device__ __forceinline__ void load_chunk(const QT *__restrict__ p, int32_t (&q)[EPT])
-{
-    constexpr int NW4 = EPT * (int)sizeof(QT) / 4;
-    uint32_t w[NW4];
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
-#pragma unroll
-    for (int k = 0; k < NW4; ++k) w[k] = src[k];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        if constexpr (sizeof(QT) == 1)
-            q[e] = (int32_t)(int8_t)(w[e >> 2] >> (8 * (e & 3)));
-        else
-            q[e] = (int32_t)(int16_t)(w[e >> 1] >> (16 * (e & 1)));
-    }
 }
 
 // wave key: (biased move << 32) | (index << 1) | x_index
@@ -85,7 +68,6 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t ro = (int64_t)p * n;
-    const int j0 = tid * EPT;
     // padding elements carry the largest possible key and are never chosen
     const uint32_t dpad = 0xFFFFFFFFu >> EB;
 
@@ -96,7 +78,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     uint64_t pb = 0;       // flipped since the last improvement
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int j = j0 + e;
+        const int j = e * TB + tid;
         U[e] = 0;
         if (j < n) {
             const int32_t x = X[ro + j] & 1;
@@ -131,11 +113,11 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         if (wmin != 0xFFFFFFFFu) {
             // lowest index among the minimal moves: the lowest lane holding the
             // minimal move value, then that lane's own lowest element
-            const uint64_t who = __ballot((best >> EB) == (wmin >> EB));
+            const uint64_t who = __ballot(best == wmin);
             const int L = __builtin_ctzll(who);
-            const int ew = (int)((uint32_t)__builtin_amdgcn_readlane((int)best, L) & EMASK);
+            const int ew = (int)(wmin & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            wkey = pack_winner(wmin >> EB, (wid * 64 + L) * EPT + ew, xw);
+            wkey = pack_winner(wmin >> EB, ew * TB + wid * 64 + L, xw);
         }
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
@@ -148,11 +130,11 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 #pragma unroll
             for (int e = 0; e < EPT; ++e) b2 = min(b2, (Db[e] << EB) | (uint32_t)e);
             const uint32_t w2 = wave_min_u32(b2);
-            const uint64_t who = __ballot((b2 >> EB) == (w2 >> EB));
+            const uint64_t who = __ballot(b2 == w2);
             const int L = __builtin_ctzll(who);
-            const int ew = (int)((uint32_t)__builtin_amdgcn_readlane((int)b2, L) & EMASK);
+            const int ew = (int)(w2 & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            if (lane == 0) red2[wid] = pack_winner(w2 >> EB, (wid * 64 + L) * EPT + ew, xw);
+            if (lane == 0) red2[wid] = pack_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
             __syncthreads();
             kb = red2[0];
 #pragma unroll
@@ -163,7 +145,11 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         const int32_t s = (kb & 1) ? -1 : 1;       // direction of x_i
         OV += (int64_t)(int32_t)(dib - bias);
         int32_t q[EPT];
-        load_chunk<EPT, QT>(Qp + (int64_t)i * ldp + j0, q);
+        {
+            const QT *rowp = Qp + (int64_t)i * ldp + tid;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) q[e] = rowp[e * TB];
+        }
         // h_j += s Q_ji  =>  D_j += S_j s Q_ji (the owner is patched below)
         if (s > 0) {
 #pragma unroll
@@ -172,9 +158,9 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 #pragma unroll
             for (int e = 0; e < EPT; ++e) Db[e] -= (uint32_t)__mul24(q[e], S[e]);
         }
-        const int ti = i / EPT;
+        const int ti = i % TB;
         if (tid == ti) {
-            const int ei = i - ti * EPT;
+            const int ei = i / TB;
             xb ^= 1ull << ei;
             pb ^= 1ull << ei;
             Ts[i] += 1;
@@ -218,7 +204,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     int32_t h[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int j = j0 + e;
+        const int j = e * TB + tid;
         h[e] = 0;
         if (j < n) {
             const int32_t qjj = Q16[(int64_t)j * n + j];
@@ -229,10 +215,10 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     for (int e = 0; e < EPT; ++e) {
         if (tid == 0) lcount = 0;
         __syncthreads();
-        if (j0 + e < n && ((pb >> e) & 1ull)) {
+        if (e * TB + tid < n && ((pb >> e) & 1ull)) {
             const int pos = atomicAdd(&lcount, 1);
-            // x_min_j - x_j = +1 when x_j = 0, -1 when x_j = 1
-            list[pos] = ((xb >> e) & 1ull) ? -(j0 + e + 1) : (j0 + e + 1);
+            const int jj = e * TB + tid;
+            list[pos] = ((xb >> e) & 1ull) ? -(jj + 1) : (jj + 1);
         }
         __syncthreads();
         const int cnt = lcount;
@@ -240,7 +226,9 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const int32_t v = list[u];
             const int32_t sg = v < 0 ? -1 : 1;
             int32_t q[EPT];
-            load_chunk<EPT, QT>(Qp + (int64_t)(v < 0 ? -v - 1 : v - 1) * ldp + j0, q);
+            const QT *rowp = Qp + (int64_t)(v < 0 ? -v - 1 : v - 1) * ldp + tid;
+#pragma unroll
+            for (int e2 = 0; e2 < EPT; ++e2) q[e2] = rowp[e2 * TB];
 #pragma unroll
             for (int e2 = 0; e2 < EPT; ++e2) h[e2] += sg * q[e2];
         }
@@ -248,7 +236,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int j = j0 + e;
+        const int j = e * TB + tid;
         if (j < n) {
             X[ro + j] = (uint8_t)(((xb ^ pb) >> e) & 1ull);
             H[ro + j] = h[e];
@@ -274,8 +262,6 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
 {
     const int ept = qb_tabu_ept(P->n);
     if (ept == 0 || ldp != TB * ept) return QB_E_CAPACITY;
-    // |D_j| <= |Q_jj| + 2 sum_i |Q_ij| <= qmax + 2 eta_max; the biased move
-    // (D + bias) << EB | e must stay below the padding key for every real D
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
     const uint32_t bias = (uint32_t)dmax;
 #define QB_T(K)                                                                                    \
@@ -285,17 +271,8 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
     }
-    QB_T(4)
-    QB_T(8)
-    QB_T(12)
-    QB_T(16)
-    QB_T(20)
-    QB_T(24)
-    QB_T(28)
-    QB_T(32)
-    QB_T(40)
-    QB_T(48)
-    QB_T(64)
+    QB_T(1) QB_T(2) QB_T(3) QB_T(4) QB_T(5) QB_T(6) QB_T(7) QB_T(8) QB_T(10) QB_T(12) QB_T(14) QB_T(16)
+    QB_T(20) QB_T(24) QB_T(28) QB_T(32)
 #undef QB_T
     return QB_E_CAPACITY;
 }
@@ -308,7 +285,7 @@ extern "C" qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d
 {
     if (!P || z < 1 || !X_d || !H_d || !E_d || !T_d || !LF_d || alpha < 0 || tenure < 0)
         return QB_E_ARG;
-    if (P->n > 64 * TB) return QB_E_CAPACITY;
+    if (qb_tabu_ept(P->n) == 0) return QB_E_CAPACITY;
     hipStream_t s = qb_stream(stream);
     if (P->int8_ok)
         return launch_tabu<int8_t>(P, (const int8_t *)P->Qp, P->ldp, z, X_d, H_d, E_d, alpha, tenure,

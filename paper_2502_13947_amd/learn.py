@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import inputs, qb
-from .solver import Solver
+from .solver import Solver, default_thresholds
 
 
 def collect_traces(workloads, seeds, iters, device, capacity=None):
@@ -27,7 +27,7 @@ def collect_traces(workloads, seeds, iters, device, capacity=None):
             Q = inputs.dense_qubo(n, w["density"], 1000 + 17 * sd + w["qseed"])
             Qd = torch.as_tensor(Q, device=device)
             sigma = qb.Problem(Qd).sigma
-            thr = qb.threshold_table(w["nsw"], 10, 0.5 * sigma, 0.002 * sigma)
+            thr = default_thresholds(qb.Problem(Qd), w["nsw"])
             job_m = inputs.job_sizes(w["z"], w["k"], w["sizes"], seed=sd)
             cap = capacity or int(np.sum(job_m)) * iters
             S = Solver(Qd, z=w["z"], seed=5000 + sd, job_m=job_m, init_m=w["init_m"], thr_init=thr, thr=thr,
