@@ -20,8 +20,8 @@
  *    documented range) are latched in the problem's device status word and
  *    returned by qb_check.  No C++ exception crosses this boundary.
  *  - No call allocates device memory except the handle constructors
- *    qb_problem_create_dense and qb_batch_create, and the setup-time
- *    autotuner qb_autotune_rankk.
+ *    qb_problem_create_dense, qb_problem_create_csr and qb_batch_create, and
+ *    the setup-time autotuners qb_autotune_rankk and qb_autotune_anneal_ell.
  *  - Layouts (row-major): Q int16 [n][n] symmetric; X uint8 [z][n] (0/1);
  *    H int32 [z][n] with H[p][i] = sum_j Q[i][j] X[p][j]; E int64 [z].
  *  - Results depend only on inputs, seeds and instance numbers: never on
@@ -55,6 +55,8 @@ typedef struct {
     int32_t qmax;        /* max |Q_ij| */
     int64_t eta_max;     /* max_j eta_j */
     double sigma;        /* sqrt(sum_{i != j} Q_ij^2 / n): the typical |dE| scale */
+    int32_t sparse;      /* 1 for a problem made by qb_problem_create_csr */
+    int32_t ell_width;   /* sparse: most off-diagonal entries in one row (>= 1) */
 } qb_problem_info;
 
 const char *qb_status_str(qb_status s);
@@ -71,6 +73,18 @@ const char *qb_version(void);
  * handle BORROWS Q_d (it must outlive the handle) and OWNS its derived
  * buffers.  Synchronises `stream`.  n in [1, 65535]. */
 qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const int16_t *Q_d, void *stream);
+/* Eq. 1 input in compressed sparse rows (the storage of large sparse
+ * instances): rowptr_d int32 [n+1] (rowptr[0] = 0, non-decreasing), col_d
+ * int32 [nnz] (strictly ascending within a row, in [0, n)), val_d int16
+ * [nnz]; a diagonal entry is optional, a stored zero is allowed.  Checks the
+ * structure (QB_E_ARG), symmetry (every (i, j, v) has (j, i, v):
+ * QB_E_NOT_SYMMETRIC) and the dense form's range bound (QB_E_RANGE).  The
+ * handle COPIES what it needs -- the off-diagonal entries as a column-major
+ * ELL of width ell_width (word (v << 16) | j at [t][i]), the diagonal and eta
+ * -- so the caller's arrays may be released once the call returns.
+ * Synchronises `stream`.  n in [1, 65535]. */
+qb_status qb_problem_create_csr(qb_problem *out, int32_t n, const int32_t *rowptr_d, const int32_t *col_d,
+                                const int16_t *val_d, void *stream);
 void qb_problem_destroy(qb_problem P);
 qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info_h);
 /* Copies eta (int64 [n]) into eta_d. */
@@ -104,7 +118,10 @@ qb_status qb_best(int32_t n, int32_t z, const uint8_t *X_d, const int64_t *E_d, 
  * allowed, the argmin over all); then C_i += tenure and every positive C is
  * decremented.  On return X[p] = x_min, H[p] = Q x_min, E[p] = OV_min
  * (E[p] must hold x^T Q x on entry), T[p][j] = flips of j, LF[p][j] = the
- * 1-based step of j's last flip (0 if none).  Capacity: n <= 16384.  T_d and
+ * 1-based step of j's last flip (0 if none).  Capacity: n <= 16384 (dense
+ * problems; one workgroup of 512 threads per solution, every step reads one
+ * row of Q) or n <= 20480 (sparse problems; 1024 threads per solution, every
+ * step reads the flipped variable's off-diagonal entries only).  T_d and
  * LF_d may not be NULL. */
 qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d, int64_t *E_d,
                   int32_t alpha, int32_t tenure, int32_t aspiration, int32_t *T_d, int32_t *LF_d,
@@ -123,7 +140,9 @@ qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const int32_t *T_
                   int32_t W2, int32_t W3, int32_t t_bound, int64_t *K_d, void *stream);
 /* order[p][r] = variable of rank r when sorting solution p by (K desc, index
  * asc) (Alg. 3 "highest values in A"; ties to the lower index).  Keys must
- * satisfy |K| < 2^47 (guaranteed by qb_keys).  Capacity: n <= 16384. */
+ * satisfy |K| < 2^47 (guaranteed by qb_keys).  n <= 16384 sorts in LDS;
+ * larger n (up to 65535) sorts indices in place in order_d with only the
+ * short strides in LDS. */
 qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *order_d, void *stream);
 
 /* ---------------------------------------------------------------- jobs
@@ -176,7 +195,8 @@ qb_status qb_select(qb_batch b, const int32_t *order_d, void *stream);
  *   c[off[q]+a]  = Q_aa + b_a,  b_a = 2 sum_{j not in S} Q[S_a][j] x_j;
  *   F0[off[q]+a] = c_a + 2 sum_{b != a} T[a][b] y0_b (flip basis);
  *   y0[off[q]+a] = X[p][S_a].
- * c_d may be NULL. */
+ * c_d may be NULL.  Dense problems only (QB_E_UNSUPPORTED for a sparse one:
+ * use qb_extract_ell). */
 qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t *H_d,
                      void *tile_d, int32_t *c_d, int32_t *F0_d, uint8_t *y0_d, void *stream);
 
@@ -196,6 +216,23 @@ qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t
 qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
                     const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
                     uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream);
+
+/* Sparse sub-QUBOs (eq. 4 on a problem made by qb_problem_create_csr).  Same
+ * c, F0 and y0 as qb_extract; the tile is an ELL of width W = ell_width:
+ * uint32 word [off[q]*W + a*W + t] = (T[a][b] << 16) | b for the t-th
+ * non-zero T[a][b] (b != a, ascending b) of row a, zero words after the last
+ * one.  The buffer holds off[J]*W words, 16-byte aligned. */
+qb_status qb_extract_ell(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t *H_d, uint32_t *tile_d,
+                         int32_t *c_d, int32_t *F0_d, uint8_t *y0_d, void *stream);
+/* qb_anneal on ELL tiles (qb_extract_ell, width W): the same sweep, the same
+ * random numbers and thresholds, bit-identical results (Y, e).  rw replicas
+ * share a workgroup and its tile copy (1 <= rw <= 16; 0 = automatic); rw only
+ * changes the schedule, never the result.  Capacity as qb_anneal, and
+ * m_q * W + rw * 64 * ceil(m_q/64) words must fit the 160 KiB of LDS of one
+ * workgroup (QB_E_CAPACITY). */
+qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d, const uint8_t *y0_d,
+                        int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R, int32_t rw, uint64_t seed,
+                        uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream);
 
 /* Host builder of the acceptance table (cosine-waveform temperature, the
  * MRAnnealer's waveform used as the IM temperature schedule):
@@ -217,7 +254,8 @@ qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t 
 /* Rank-k local-field update H[p] += Q dX[p] for all p (the O(n) move-value
  * update of the Tabu section generalised to many flipped variables).
  * variant: 0 = automatic, 1 = VALU gather over the changed columns,
- * 2 = int8 MFMA dense contraction (int8_ok problems only).  Exact (int32). */
+ * 2 = int8 MFMA dense contraction (int8_ok problems only), 3 = ELL sparse
+ * product (the only variant of a sparse problem).  Exact (int32). */
 qb_status qb_rankk(qb_problem P, int32_t z, const int8_t *dX_d, int32_t *H_d, int32_t variant,
                    void *stream);
 /* Fill an int8 buffer with zeros (a kernel, safe under graph capture). */
@@ -307,6 +345,15 @@ void qb_graph_destroy(void *graph_exec);
  * allocates scratch and synchronises `stream`. */
 qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX_d, const int32_t *H_d, int32_t reps,
                             int32_t *variant_out, float *ms_out, void *stream);
+/* Autotuner for qb_anneal_ell's replicas per workgroup: times rw in
+ * {1, 2, 4, 8, 16} (those <= R that fit LDS) `reps` times each on the given
+ * jobs, checks that every rw gives the same Y and e (else QB_E_STATE), and
+ * returns the fastest in *rw_out (its mean time in *ms_out if not NULL).  Not
+ * a hot call: it allocates scratch and synchronises `stream`. */
+qb_status qb_autotune_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d,
+                                 const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                                 uint64_t seed, uint32_t inst_base, int32_t reps, int32_t *rw_out, float *ms_out,
+                                 void *stream);
 
 #ifdef __cplusplus
 }

@@ -292,6 +292,7 @@ extern "C" qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, co
 {
     if (!P || !b || !X_d || !H_d || !tile_d || !F0_d || !y0_d) return QB_E_ARG;
     if (b->n != P->n) return QB_E_ARG;
+    if (P->sparse) return QB_E_UNSUPPORTED;
     if ((uintptr_t)tile_d & 15) return QB_E_ARG;
     hipStream_t s = qb_stream(stream);
     if (P->int8_ok)

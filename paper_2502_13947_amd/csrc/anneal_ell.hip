@@ -1,0 +1,284 @@
+// Sparse sub-QUBOs: extraction into a per-job ELL (eq. 4, Alg. 3 lines 3-5)
+// and the batched Ising-machine stage on it (Alg. 3 line 6) on gfx950.
+//
+// The annealer is the dense kernel's ballot-block sweep with the same
+// random numbers and thresholds, so Y and e are bit-identical to it: lane L
+// owns positions 64*s + L, a block's 64 candidates are evaluated at once and
+// the lowest accepting lane k is taken (ballot + find-first-set), after
+// which only lanes past k re-evaluate.  What differs is where the fields
+// live and how an accept updates them.  Row k of a sparse tile has a handful
+// of entries, so instead of every lane adding its slice of a dense row, the
+// flip bases F of each replica live in LDS and lane t adds the t-th entry of
+// row k to F[col_t] with one LDS atomic add (the entries of a row have
+// distinct columns); the current block's F is read back before the next
+// ballot.  The job's ELL tile is staged in LDS once and shared by the rw
+// replicas (waves) of the workgroup; rw only changes the schedule.
+#include "qb_internal.h"
+
+namespace {
+
+// ------------------------------------------------------------------ extract
+// One workgroup per job, one thread per row: the entries of Q's row S_a whose
+// column is in S (binary search in the ascending index set) become the row's
+// ELL words with local column indices; c and F0 as in the dense extraction.
+__global__ void __launch_bounds__(256) k_extract_ell(const uint32_t *__restrict__ ell, int W,
+                                                     const int32_t *__restrict__ ecnt,
+                                                     const int32_t *__restrict__ diag, int n,
+                                                     const int32_t *__restrict__ sol,
+                                                     const int32_t *__restrict__ off,
+                                                     const int32_t *__restrict__ idx,
+                                                     const uint8_t *__restrict__ X,
+                                                     const int32_t *__restrict__ H, uint32_t *__restrict__ tiles,
+                                                     int32_t *__restrict__ c, int32_t *__restrict__ F0,
+                                                     uint8_t *__restrict__ y0)
+{
+    __shared__ int32_t S[1024];
+    __shared__ uint8_t ys[1024];
+    const int q = blockIdx.x, tid = threadIdx.x;
+    const int base = off[q], m = off[q + 1] - base, p = sol[q];
+    const int64_t xo = (int64_t)p * n;
+    for (int a = tid; a < m; a += 256) {
+        const int j = idx[base + a];
+        S[a] = j;
+        ys[a] = X[xo + j];
+    }
+    __syncthreads();
+    uint32_t *tile = tiles + (int64_t)base * W;
+    for (int a = tid; a < m; a += 256) {
+        const int i = S[a];
+        const int32_t qii = diag[i];
+        const int32_t f0 = qii + 2 * (H[xo + i] - qii * (int32_t)ys[a]);
+        F0[base + a] = f0;
+        y0[base + a] = ys[a];
+        const uint32_t *row = ell + (int64_t)i * W;
+        uint32_t *out = tile + (int64_t)a * W;
+        const int cnt = ecnt[i];
+        int k = 0;
+        int32_t rowsum = 0;
+        for (int t = 0; t < cnt; ++t) {
+            const uint32_t w = row[t];
+            const int col = qb_ell_col(w);
+            int lo = 0, hi = m - 1, pos = -1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int sm = S[mid];
+                if (sm == col) {
+                    pos = mid;
+                    break;
+                }
+                if (sm < col)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
+            }
+            if (pos >= 0) {
+                const int32_t v = qb_ell_val(w);
+                out[k++] = qb_ell_word(v, pos);
+                rowsum += v * (int32_t)ys[pos];
+            }
+        }
+        for (; k < W; ++k) out[k] = 0u;
+        if (c) c[base + a] = f0 - 2 * rowsum;
+    }
+}
+
+// ------------------------------------------------------------------ anneal
+template <int MS>
+__global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__ jobs, int rgroups,
+                                                     const int32_t *__restrict__ off, int W,
+                                                     const uint32_t *__restrict__ tiles,
+                                                     const int32_t *__restrict__ F0,
+                                                     const uint8_t *__restrict__ y0, int nsw, int B,
+                                                     const int32_t *__restrict__ thr, int R, int rw, uint32_t k0,
+                                                     uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
+                                                     int64_t *__restrict__ eout)
+{
+    constexpr int MP = 64 * MS;
+    extern __shared__ __align__(16) uint32_t dl[];
+    const int q = jobs[blockIdx.x / rgroups];
+    const int rg = blockIdx.x % rgroups;
+    const int base = off[q], m = off[q + 1] - base;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r = rg * rw + wid;
+
+    uint32_t *tl = dl;                                   // [m][W]
+    int32_t *F = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + wid * MP;
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(tiles + (int64_t)base * W);
+        uint4 *dst = reinterpret_cast<uint4 *>(tl);
+        const int n16 = m * W / 4;
+        for (int t = tid; t < n16; t += blockDim.x) dst[t] = src[t];
+    }
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        F[pos] = pos < m ? F0[base + pos] : 0;
+    }
+    __syncthreads();
+    if (r >= R) return;   // no barrier follows
+
+    uint32_t ybits = 0;
+    uint64_t active[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        if (pos < m && y0[base + pos]) ybits |= 1u << s;
+        const int na = min(max(m - 64 * s, 0), 64);
+        active[s] = na == 64 ? ~0ull : ((1ull << na) - 1ull);
+    }
+    int64_t e = 0;
+    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    constexpr int G = (MS + 3) / 4;
+    const int sh = 32 - B;
+
+    for (int sw = 0; sw < nsw; ++sw) {
+        uint32_t u[4 * G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint4 o = qb_philox(make_uint4(((uint32_t)g << 6) | (uint32_t)lane, (uint32_t)sw, (uint32_t)r, tag),
+                                      k0, k1);
+            u[4 * g + 0] = o.x;
+            u[4 * g + 1] = o.y;
+            u[4 * g + 2] = o.z;
+            u[4 * g + 3] = o.w;
+        }
+        const int32_t *ts = thr + ((size_t)sw << B);
+        int32_t tv[MS];
+#pragma unroll
+        for (int s = 0; s < MS; ++s) tv[s] = ts[u[s] >> sh];
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+            uint64_t pend = active[s];
+            if (pend == 0) continue;
+            int32_t fs = F[64 * s + lane];
+            while (true) {
+                const uint32_t yb = (ybits >> s) & 1u;
+                const int32_t dE = yb ? -fs : fs;
+                const uint64_t acc = __ballot(dE <= tv[s]) & pend;
+                if (acc == 0) break;
+                const int k = __builtin_ctzll(acc);
+                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
+                const int32_t ykb = __builtin_amdgcn_readlane((int32_t)yb, k);
+                e += dEk;
+                const int32_t d2 = ykb ? -2 : 2;
+                if (lane == k) ybits ^= 1u << s;
+                const uint32_t *row = tl + (size_t)(64 * s + k) * W;
+                for (int t0 = 0; t0 < W; t0 += 64) {
+                    if (t0 + lane < W) {
+                        const uint32_t wd = row[t0 + lane];
+                        if (wd != 0u) atomicAdd(&F[qb_ell_col(wd)], d2 * qb_ell_val(wd));
+                    }
+                }
+                pend &= ~((2ull << k) - 1ull);
+                fs = F[64 * s + lane];
+            }
+        }
+    }
+
+    uint8_t *Yr = Y + (size_t)base * R + (size_t)r * m;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        if (pos < m) Yr[pos] = (uint8_t)((ybits >> s) & 1u);
+    }
+    if (lane == 0) eout[(size_t)q * R + r] = e;
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+inline size_t ell_lds_bytes(int ms, int W, int rw) { return sizeof(uint32_t) * (size_t)64 * ms * (W + rw); }
+
+template <int MS>
+qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *jobs, qb_batch b, int W,
+                     const uint32_t *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr,
+                     uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
+{
+    const size_t lds = ell_lds_bytes(MS, W, rw);
+    static size_t attr = 0;
+    if (attr < lds) {
+        QB_TRY_HIP(hipFuncSetAttribute((const void *)k_anneal_ell<MS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)LDS_MAX));
+        attr = LDS_MAX;
+    }
+    const int rgroups = (R + rw - 1) / rw;
+    k_anneal_ell<MS><<<njobs * rgroups, 64 * rw, lds, s>>>(jobs, rgroups, b->off_d, W, tiles, F0, y0, nsw, B, thr, R,
+                                                           rw, (uint32_t)seed, (uint32_t)(seed >> 32), inst_base, Y,
+                                                           e);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
+qb_status dispatch_ell(int cls, int njobs, int rw, int R, hipStream_t s, const int32_t *jobs, qb_batch b, int W,
+                       const uint32_t *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B,
+                       const int32_t *thr, uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
+{
+#define QB_ARGS njobs, rw, R, s, jobs, b, W, tiles, F0, y0, nsw, B, thr, seed, inst_base, Y, e
+    switch (cls) {
+    case 0: return launch_ell<16>(QB_ARGS);
+    case 1: return launch_ell<8>(QB_ARGS);
+    case 2: return launch_ell<4>(QB_ARGS);
+    case 3: return launch_ell<2>(QB_ARGS);
+    case 4: return launch_ell<1>(QB_ARGS);
+    }
+#undef QB_ARGS
+    return QB_E_UNSUPPORTED;
+}
+
+}  // namespace
+
+extern "C" qb_status qb_extract_ell(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t *H_d,
+                                   uint32_t *tile_d, int32_t *c_d, int32_t *F0_d, uint8_t *y0_d, void *stream)
+{
+    if (!P || !b || !X_d || !H_d || !tile_d || !F0_d || !y0_d) return QB_E_ARG;
+    if (b->n != P->n) return QB_E_ARG;
+    if (!P->sparse) return QB_E_UNSUPPORTED;
+    if ((uintptr_t)tile_d & 15) return QB_E_ARG;
+    k_extract_ell<<<b->J, 256, 0, qb_stream(stream)>>>(P->ell, P->ellw, P->ecnt, P->diag, P->n, b->sol_d, b->off_d,
+                                                       b->idx_d, X_d, H_d, tile_d, c_d, F0_d, y0_d);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
+extern "C" qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d,
+                                  const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                                  int32_t rw, uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d,
+                                  void *stream)
+{
+    if (!b || !tile_d || !F0_d || !y0_d || !thr_d || !Y_d || !e_d) return QB_E_ARG;
+    if (nsw < 1 || B < 1 || B > 16 || R < 1 || R > 16 || rw < 0 || rw > 16) return QB_E_ARG;
+    if (W < 4 || (W & 3) || W > 65536) return QB_E_ARG;
+    if ((uintptr_t)tile_d & 15) return QB_E_ARG;
+    if ((uint64_t)inst_base + (uint64_t)b->J > (1ull << 28)) return QB_E_RANGE;
+    hipStream_t s = qb_stream(stream);
+    bool first = true, forked = false;
+    for (int c = 0; c < QB_NCLASS; ++c) {
+        const int nj = b->cls_end[c] - b->cls_begin[c];
+        if (nj <= 0) continue;
+        const int ms = qb_ms_of_class(c);
+        int r2 = rw;
+        if (r2 == 0) {
+            // automatic: up to 8 replicas per workgroup, fewer when LDS is short
+            r2 = R < 8 ? R : 8;
+            while (r2 > 1 && ell_lds_bytes(ms, W, r2) > LDS_MAX) r2 >>= 1;
+        }
+        if (ell_lds_bytes(ms, W, r2) > LDS_MAX) return QB_E_CAPACITY;
+        hipStream_t ls = s;
+        if (!first) {
+            if (!forked) {
+                QB_TRY_HIP(hipEventRecord(b->ev_fork, s));
+                forked = true;
+            }
+            ls = b->side[c];
+            QB_TRY_HIP(hipStreamWaitEvent(ls, b->ev_fork, 0));
+        }
+        const qb_status rc = dispatch_ell(c, nj, r2, R, ls, b->lpt_d + b->cls_begin[c], b, W, tile_d, F0_d, y0_d, nsw,
+                                          B, thr_d, seed, inst_base, Y_d, e_d);
+        if (rc != QB_OK) return rc;
+        if (!first) {
+            QB_TRY_HIP(hipEventRecord(b->ev_join[c], ls));
+            QB_TRY_HIP(hipStreamWaitEvent(s, b->ev_join[c], 0));
+        }
+        first = false;
+    }
+    return QB_OK;
+}

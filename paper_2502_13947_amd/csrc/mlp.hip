@@ -28,7 +28,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f)
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ------------------------------------------------------------------ features
-__global__ void __launch_bounds__(256) k_features(int n, int z, const int16_t *__restrict__ Q,
+__global__ void __launch_bounds__(256) k_features(int n, int z, const int32_t *__restrict__ diag,
                                                   const int64_t *__restrict__ eta, const int32_t *__restrict__ cnt,
                                                   const int32_t *__restrict__ H, const int32_t *__restrict__ T,
                                                   const int32_t *__restrict__ LF, const int32_t *__restrict__ G,
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) k_features(int n, int z, const int16_t *_
         const int32_t age = LF[at] > 0 ? alpha - LF[at] : alpha;
         float f[8];
         f[0] = (float)H[at] * s0;
-        f[1] = (float)Q[(int64_t)j * n + j] * s1;
+        f[1] = (float)diag[j] * s1;
         f[2] = (float)T[at] * s2;
         f[3] = (float)age * s3;
         f[4] = (float)G[at] * s4;
@@ -295,7 +295,7 @@ extern "C" qb_status qb_features(qb_problem P, int32_t z, const uint8_t *X_d, co
     hipStream_t s = qb_stream(stream);
     qb_status rc = qb_column_counts(P, z, X_d, stream);
     if (rc != QB_OK) return rc;
-    k_features<<<z, 256, 0, s>>>(P->n, z, P->Q, P->eta, P->colcnt, H_d, T_d, LF_d, G_d, alpha, scales_h[0],
+    k_features<<<z, 256, 0, s>>>(P->n, z, P->diag, P->eta, P->colcnt, H_d, T_d, LF_d, G_d, alpha, scales_h[0],
                                  scales_h[1], scales_h[2], scales_h[3], scales_h[4], scales_h[5], scales_h[6], F_d);
     QB_LAUNCH_CHECK();
     return QB_OK;

@@ -89,6 +89,12 @@ __global__ void k_pad_copy(const int16_t *__restrict__ Q, int n, int ld, T *__re
         out[(int64_t)i * ld + j] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
 }
 
+__global__ void k_diag(const int16_t *__restrict__ Q, int n, int32_t *__restrict__ diag)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) diag[j] = Q[(int64_t)j * n + j];
+}
+
 __global__ void k_to_int8(const int16_t *__restrict__ Q, int8_t *__restrict__ Q8, int64_t count)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
@@ -134,12 +140,14 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
         P->sigma = sqrt((double)scan_h.sumsq / (double)n);
         if (hipMalloc(&P->eta, sizeof(int64_t) * n) != hipSuccess ||
             hipMalloc(&P->colcnt, sizeof(int32_t) * n) != hipSuccess ||
+            hipMalloc(&P->diag, sizeof(int32_t) * n) != hipSuccess ||
             hipMalloc(&P->status, sizeof(int32_t)) != hipSuccess) {
             fail(QB_E_HIP);
             break;
         }
         hipMemsetAsync(P->status, 0, sizeof(int32_t), s);
         k_eta<<<(n + 255) / 256, 256, 0, s>>>(Q_d, n, P->eta);
+        k_diag<<<(n + 255) / 256, 256, 0, s>>>(Q_d, n, P->diag);
         if (P->int8_ok) {
             if (hipMalloc(&P->Q8, (size_t)n * n) != hipSuccess) { fail(QB_E_HIP); break; }
             k_to_int8<<<1024, 256, 0, s>>>(Q_d, P->Q8, (int64_t)n * n);
@@ -173,6 +181,173 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
     return QB_OK;
 }
 
+// ------------------------------------------------------------------ sparse problem
+// One thread per row: structure (columns strictly ascending and in range),
+// diagonal, off-diagonal count, eta, max |Q|, squared off-diagonal sum, and
+// symmetry (each off-diagonal entry is looked up in its mirror row by binary
+// search; a row that is itself unsorted is flagged as malformed).
+__global__ void __launch_bounds__(256) k_csr_scan(int n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col,
+                                                  const int16_t *__restrict__ val, int32_t *__restrict__ diag,
+                                                  int32_t *__restrict__ deg, int64_t *__restrict__ eta,
+                                                  int32_t *__restrict__ flags, int32_t *__restrict__ qmax,
+                                                  int32_t *__restrict__ dmax, unsigned long long *__restrict__ sumsq)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t amax = 0, bad = 0, asym = 0, d = 0;
+    unsigned long long sq = 0;
+    if (i < n) {
+        const int a = rp[i], b = rp[i + 1];
+        int prev = -1;
+        int32_t dg = 0;
+        int64_t et = 0;
+        for (int t = a; t < b; ++t) {
+            const int c = col[t];
+            if (c <= prev || c >= n) {
+                bad = 1;
+                break;
+            }
+            prev = c;
+            const int32_t v = val[t];
+            const int32_t av = v < 0 ? -v : v;
+            amax = max(amax, av);
+            et += av;
+            if (c == i) {
+                dg = v;
+                continue;
+            }
+            ++d;
+            sq += (unsigned long long)(av * av);
+            int lo = rp[c], hi = rp[c + 1] - 1;
+            bool found = false;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int cm = col[mid];
+                if (cm == i) {
+                    found = val[mid] == v;
+                    break;
+                }
+                if (cm < i)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
+            }
+            asym |= !found;
+        }
+        diag[i] = dg;
+        deg[i] = d;
+        eta[i] = et;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        amax = max(amax, __shfl_xor(amax, o, 64));
+        d = max(d, __shfl_xor(d, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+        asym |= __shfl_xor(asym, o, 64);
+        sq += __shfl_xor(sq, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(qmax, amax);
+        atomicMax(dmax, d);
+        if (bad) atomicOr(flags, 2);
+        if (asym) atomicOr(flags, 1);
+        if (sq) atomicAdd(sumsq, sq);
+    }
+}
+
+// Off-diagonal entries of row i into ELL words [i*W, i*W + deg), zeros after.
+__global__ void k_csr_to_ell(int n, int W, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const int16_t *__restrict__ val, uint32_t *__restrict__ ell,
+                             int32_t *__restrict__ ecnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t *row = ell + (int64_t)i * W;
+    int k = 0;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) {
+        const int c = col[t];
+        if (c != i) row[k++] = qb_ell_word(val[t], c);
+    }
+    ecnt[i] = k;
+    for (; k < W; ++k) row[k] = 0u;
+}
+
+extern "C" qb_status qb_problem_create_csr(qb_problem *out, int32_t n, const int32_t *rowptr_d,
+                                          const int32_t *col_d, const int16_t *val_d, void *stream)
+{
+    if (!out || !rowptr_d || n < 1 || n > 65535) return QB_E_ARG;
+    *out = nullptr;
+    hipStream_t s = qb_stream(stream);
+    std::vector<int32_t> rp(n + 1);
+    QB_TRY_HIP(hipMemcpyAsync(rp.data(), rowptr_d, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    QB_TRY_HIP(hipStreamSynchronize(s));
+    if (rp[0] != 0) return QB_E_ARG;
+    for (int i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return QB_E_ARG;
+    const int64_t nnz = rp[n];
+    if (nnz > 0 && (!col_d || !val_d)) return QB_E_ARG;
+    qb_problem P = new qb_problem_s();
+    P->n = n;
+    P->sparse = 1;
+    struct Scan {
+        int32_t flags, qmax, dmax, pad;
+        unsigned long long sumsq;
+    };
+    Scan *scan_d = nullptr;
+    int32_t *deg_d = nullptr;
+    Scan scan_h{};
+    qb_status rc = QB_OK;
+    do {
+        if (hipMalloc(&scan_d, sizeof(Scan)) != hipSuccess || hipMalloc(&deg_d, sizeof(int32_t) * n) != hipSuccess ||
+            hipMalloc(&P->eta, sizeof(int64_t) * n) != hipSuccess ||
+            hipMalloc(&P->colcnt, sizeof(int32_t) * n) != hipSuccess ||
+            hipMalloc(&P->diag, sizeof(int32_t) * n) != hipSuccess ||
+            hipMalloc(&P->ecnt, sizeof(int32_t) * n) != hipSuccess ||
+            hipMalloc(&P->status, sizeof(int32_t)) != hipSuccess) {
+            rc = QB_E_HIP;
+            break;
+        }
+        if (hipMemsetAsync(scan_d, 0, sizeof(Scan), s) != hipSuccess ||
+            hipMemsetAsync(P->status, 0, sizeof(int32_t), s) != hipSuccess) {
+            rc = QB_E_HIP;
+            break;
+        }
+        k_csr_scan<<<(n + 255) / 256, 256, 0, s>>>(n, rowptr_d, col_d, val_d, P->diag, deg_d, P->eta, &scan_d->flags,
+                                                   &scan_d->qmax, &scan_d->dmax, &scan_d->sumsq);
+        if (hipMemcpyAsync(&scan_h, scan_d, sizeof(Scan), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = QB_E_HIP;
+            break;
+        }
+        if (scan_h.flags & 2) { rc = QB_E_ARG; break; }
+        if (scan_h.flags & 1) { rc = QB_E_NOT_SYMMETRIC; break; }
+        const int64_t bound = (2 * (int64_t)n + 1) * (int64_t)scan_h.qmax;
+        if (bound >= (int64_t(1) << 31)) { rc = QB_E_RANGE; break; }
+        P->qmax = scan_h.qmax;
+        P->int8_ok = scan_h.qmax <= 127;
+        P->sigma = sqrt((double)scan_h.sumsq / (double)n);
+        P->ellw = std::max(4, (scan_h.dmax + 3) & ~3);
+        if (hipMalloc(&P->ell, sizeof(uint32_t) * (size_t)n * P->ellw) != hipSuccess) { rc = QB_E_HIP; break; }
+        k_csr_to_ell<<<(n + 255) / 256, 256, 0, s>>>(n, P->ellw, rowptr_d, col_d, val_d, P->ell, P->ecnt);
+        std::vector<int64_t> eta_h(n);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(eta_h.data(), P->eta, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = QB_E_HIP;
+            break;
+        }
+        P->eta_max = *std::max_element(eta_h.begin(), eta_h.end());
+    } while (0);
+    if (scan_d) hipFree(scan_d);
+    if (deg_d) hipFree(deg_d);
+    if (rc != QB_OK) {
+        qb_problem_destroy(P);
+        return rc;
+    }
+    *out = P;
+    return QB_OK;
+}
+
 extern "C" void qb_problem_destroy(qb_problem P)
 {
     if (!P) return;
@@ -180,6 +355,9 @@ extern "C" void qb_problem_destroy(qb_problem P)
     if (P->Qp) hipFree(P->Qp);
     if (P->eta) hipFree(P->eta);
     if (P->colcnt) hipFree(P->colcnt);
+    if (P->diag) hipFree(P->diag);
+    if (P->ell) hipFree(P->ell);
+    if (P->ecnt) hipFree(P->ecnt);
     if (P->status) hipFree(P->status);
     delete P;
 }
@@ -192,6 +370,8 @@ extern "C" qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info)
     info->qmax = P->qmax;
     info->eta_max = P->eta_max;
     info->sigma = P->sigma;
+    info->sparse = P->sparse;
+    info->ell_width = P->ellw;
     return QB_OK;
 }
 
@@ -272,10 +452,12 @@ __global__ void __launch_bounds__(256) k_field(const int16_t *__restrict__ Q, in
 }
 
 qb_status qb_rankk_mfma_launch(qb_problem P, int z, const int8_t *dX, int32_t *H, hipStream_t s);
+qb_status qb_field_ell_launch(qb_problem P, int z, const uint8_t *X, int32_t *H, hipStream_t s);
 
 extern "C" qb_status qb_field(qb_problem P, int32_t z, const uint8_t *X_d, int32_t *H_d, void *stream)
 {
     if (!P || z < 1 || z > 65535 || !X_d || !H_d) return QB_E_ARG;
+    if (P->sparse) return qb_field_ell_launch(P, z, X_d, H_d, qb_stream(stream));
     if (P->int8_ok && P->Qp && z >= 32) {
         // H = 0 + X Q on the int8 matrix cores (X in {0,1} read as int8)
         qb_status rc = qb_zero(H_d, sizeof(int32_t) * (size_t)z * P->n, stream);

@@ -24,7 +24,23 @@ struct qb_problem_s {
     int qmax = 0;
     int64_t eta_max = 0;
     double sigma = 0.0;
+    int32_t *diag = nullptr;      // owned, device [n]: Q_jj
+    // sparse problems (qb_problem_create_csr): off-diagonal entries as a
+    // row-major ELL, word [i*ellw + t] = (Q_ij << 16) | j for the t-th entry
+    // of row i (ascending j), zero words after the last; ecnt[i] entries
+    int sparse = 0;
+    int ellw = 0;                 // padded to a multiple of 4
+    uint32_t *ell = nullptr;      // owned, device [n * ellw]
+    int32_t *ecnt = nullptr;      // owned, device [n]
 };
+
+// ELL word of a sparse entry and its two halves.
+static inline __host__ __device__ uint32_t qb_ell_word(int32_t v, int col)
+{
+    return ((uint32_t)(uint16_t)(int16_t)v << 16) | (uint32_t)col;
+}
+static inline __host__ __device__ int qb_ell_col(uint32_t w) { return (int)(w & 0xffffu); }
+static inline __host__ __device__ int32_t qb_ell_val(uint32_t w) { return (int32_t)w >> 16; }
 
 // Threads of the Tabu workgroup and elements per thread for n variables;
 // the padded copy of Q has pitch QB_TABU_THREADS * EPT.  0 if n is too large.
@@ -34,6 +50,16 @@ static inline int qb_tabu_ept(int n)
     static const int opts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
     for (int e : opts)
         if (n <= QB_TABU_THREADS * e) return e;
+    return 0;
+}
+
+// Sparse Tabu: 1024 threads, EPT variables each (n <= 20480).
+#define QB_TABU_SP_THREADS 1024
+static inline int qb_tabu_sp_ept(int n)
+{
+    static const int opts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20};
+    for (int e : opts)
+        if (n <= QB_TABU_SP_THREADS * e) return e;
     return 0;
 }
 
@@ -127,4 +153,29 @@ __device__ __forceinline__ uint64_t qb_wave_min_u64(uint64_t v)
         v = w < v ? w : v;
     }
     return v;
+}
+
+constexpr int qb_ceil_log2(int v) { return v <= 1 ? 0 : 1 + qb_ceil_log2((v + 1) / 2); }
+
+// Wave minimum of an unsigned value, returned uniform: DPP quad_perm
+// [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror, then the four
+// row results by readlane.
+__device__ __forceinline__ uint32_t qb_wave_min_u32(uint32_t v)
+{
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// Tabu wave winner: (biased move << 32) | (index << 1) | x_index, so the
+// 64-bit minimum is the lowest move, then the lowest index.
+__device__ __forceinline__ uint64_t qb_tabu_winner(uint32_t dbias, int j, uint32_t x)
+{
+    return ((uint64_t)dbias << 32) | ((uint64_t)(uint32_t)j << 1) | x;
 }

@@ -152,7 +152,42 @@ __global__ void __launch_bounds__(256) k_rankk_mfma(const int8_t *__restrict__ d
             }
 }
 
+// Sparse product over the row-major ELL: H[p][i] (+)= Q_ii V[p][i] +
+// sum_t val_t V[p][col_t].  One thread per (i, p); a row's words are read as
+// 16-byte vectors (the width is a multiple of 4, and the zero words past a
+// row's last entry add 0).
+template <typename VT, bool ACC>
+__global__ void __launch_bounds__(256) k_ell_spmm(const uint32_t *__restrict__ ell, const int32_t *__restrict__ ecnt,
+                                                  const int32_t *__restrict__ diag, int n, int W,
+                                                  const VT *__restrict__ V, int32_t *__restrict__ H)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int p = blockIdx.y;
+    if (i >= n) return;
+    const VT *v = V + (int64_t)p * n;
+    int32_t acc = diag[i] * (int32_t)v[i];
+    const uint4 *row = reinterpret_cast<const uint4 *>(ell + (int64_t)i * W);
+    const int c4 = (ecnt[i] + 3) >> 2;
+    for (int t = 0; t < c4; ++t) {
+        const uint4 w = row[t];
+        acc += qb_ell_val(w.x) * (int32_t)v[qb_ell_col(w.x)];
+        acc += qb_ell_val(w.y) * (int32_t)v[qb_ell_col(w.y)];
+        acc += qb_ell_val(w.z) * (int32_t)v[qb_ell_col(w.z)];
+        acc += qb_ell_val(w.w) * (int32_t)v[qb_ell_col(w.w)];
+    }
+    int32_t *h = H + (int64_t)p * n + i;
+    *h = ACC ? *h + acc : acc;
+}
+
 }  // namespace
+
+qb_status qb_field_ell_launch(qb_problem P, int z, const uint8_t *X, int32_t *H, hipStream_t s)
+{
+    dim3 grid((P->n + 255) / 256, z);
+    k_ell_spmm<uint8_t, false><<<grid, 256, 0, s>>>(P->ell, P->ecnt, P->diag, P->n, P->ellw, X, H);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
 
 qb_status qb_rankk_mfma_launch(qb_problem P, int z, const int8_t *dX, int32_t *H, hipStream_t s)
 {
@@ -180,9 +215,16 @@ qb_status qb_rankk_mfma_launch(qb_problem P, int z, const int8_t *dX, int32_t *H
 extern "C" qb_status qb_rankk(qb_problem P, int32_t z, const int8_t *dX_d, int32_t *H_d, int32_t variant,
                              void *stream)
 {
-    if (!P || z < 1 || z > 65535 || !dX_d || !H_d || variant < 0 || variant > 2) return QB_E_ARG;
-    if (variant == 2 && !P->int8_ok) return QB_E_UNSUPPORTED;
+    if (!P || z < 1 || z > 65535 || !dX_d || !H_d || variant < 0 || variant > 3) return QB_E_ARG;
     hipStream_t s = qb_stream(stream);
+    if (P->sparse) {
+        if (variant != 0 && variant != 3) return QB_E_UNSUPPORTED;
+        dim3 g((P->n + 255) / 256, z);
+        k_ell_spmm<int8_t, true><<<g, 256, 0, s>>>(P->ell, P->ecnt, P->diag, P->n, P->ellw, dX_d, H_d);
+        QB_LAUNCH_CHECK();
+        return QB_OK;
+    }
+    if (variant == 3 || (variant == 2 && !P->int8_ok)) return QB_E_UNSUPPORTED;
     constexpr int CPT = 4;
     dim3 grid((P->n + 256 * CPT - 1) / (256 * CPT), z);
     if (variant == 0) variant = (P->int8_ok && P->Qp && z >= 32) ? 2 : 1;

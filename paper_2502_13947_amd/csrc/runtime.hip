@@ -61,9 +61,11 @@ extern "C" qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX
     int best = 1;
     float best_ms = 1e30f;
     qb_status rc = QB_OK;
-    const int cand[2] = {1, 2};
-    for (int vi = 0; vi < 2 && rc == QB_OK; ++vi) {
+    const int cand[3] = {1, 2, 3};
+    if (P->sparse) best = 3;
+    for (int vi = 0; vi < 3 && rc == QB_OK; ++vi) {
         const int v = cand[vi];
+        if (P->sparse != (v == 3)) continue;
         if (v == 2 && (!P->int8_ok || !P->Qp)) continue;
         float tot = 0.f;
         for (int r = 0; r < reps + 1 && rc == QB_OK; ++r) {
@@ -91,6 +93,77 @@ extern "C" qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX
     (void)hipFree(Hw);
     if (rc != QB_OK) return rc;
     *variant_out = best;
+    if (ms_out) *ms_out = best_ms;
+    return QB_OK;
+}
+
+// Times qb_anneal_ell for every replicas-per-workgroup choice that fits and
+// returns the fastest; every choice must give the same (Y, e) (checked on the
+// host, QB_E_STATE otherwise).  Not a hot call: allocates scratch, syncs.
+extern "C" qb_status qb_autotune_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d,
+                                           const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d,
+                                           int32_t R, uint64_t seed, uint32_t inst_base, int32_t reps,
+                                           int32_t *rw_out, float *ms_out, void *stream)
+{
+    if (!b || !rw_out || reps < 1 || R < 1 || R > 16) return QB_E_ARG;
+    hipStream_t s = qb_stream(stream);
+    const size_t ybytes = (size_t)b->total * R, ebytes = sizeof(int64_t) * (size_t)b->J * R;
+    uint8_t *Yw = nullptr;
+    int64_t *ew = nullptr;
+    if (hipMalloc(&Yw, ybytes ? ybytes : 1) != hipSuccess || hipMalloc(&ew, ebytes ? ebytes : 8) != hipSuccess) {
+        if (Yw) (void)hipFree(Yw);
+        return QB_E_HIP;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    std::vector<uint8_t> Yref, Ycur;
+    std::vector<int64_t> eref, ecur;
+    int best = 0;
+    float best_ms = 1e30f;
+    qb_status rc = QB_OK;
+    for (int rw = 1; rw <= 16 && rc == QB_OK; rw <<= 1) {
+        if (rw > R && rw > 1) break;
+        float tot = 0.f;
+        qb_status r0 = QB_OK;
+        for (int r = 0; r < reps + 1; ++r) {
+            (void)hipEventRecord(e0, s);
+            r0 = qb_anneal_ell(b, W, tile_d, F0_d, y0_d, nsw, B, thr_d, R, rw, seed, inst_base, Yw, ew, stream);
+            if (r0 != QB_OK) break;
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) { r0 = QB_E_HIP; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) tot += ms;
+        }
+        if (r0 == QB_E_CAPACITY) break;   // larger rw do not fit either
+        if (r0 != QB_OK) { rc = r0; break; }
+        Ycur.resize(ybytes);
+        ecur.resize((size_t)b->J * R);
+        if (hipMemcpy(Ycur.data(), Yw, ybytes, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(ecur.data(), ew, ebytes, hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = QB_E_HIP;
+            break;
+        }
+        if (Yref.empty() && eref.empty()) {
+            Yref = Ycur;
+            eref = ecur;
+        } else if (Yref != Ycur || eref != ecur) {
+            rc = QB_E_STATE;
+        }
+        const float avg = tot / reps;
+        if (avg < best_ms) {
+            best_ms = avg;
+            best = rw;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(Yw);
+    (void)hipFree(ew);
+    if (rc != QB_OK) return rc;
+    if (best == 0) return QB_E_CAPACITY;
+    *rw_out = best;
     if (ms_out) *ms_out = best_ms;
     return QB_OK;
 }

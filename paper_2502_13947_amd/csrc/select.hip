@@ -83,6 +83,123 @@ __global__ void __launch_bounds__(1024) k_rank(int n, int npad, const int64_t *_
     for (int r = threadIdx.x; r < n; r += 1024) order[(int64_t)p * n + r] = (int32_t)(sk[r] & 0xffffu);
 }
 
+// Larger n: an ascending-only bitonic network (each merge opens with the
+// mirrored comparison, so every comparator puts the smaller key first and
+// the virtual positions >= n act as +infinity that no comparator moves) over
+// the indices held in order[p] itself; keys are rebuilt from K when needed.
+// Strides below the LDS chunk run in LDS on whole chunks, longer strides on
+// the indices in global memory (one workgroup per solution, so a barrier
+// orders them).
+constexpr int RANK_CHUNK = 16384;
+
+__device__ __forceinline__ uint64_t rank_key(const int64_t *__restrict__ Kp, int j)
+{
+    constexpr int64_t lim = (int64_t(1) << 47) - 1;
+    const int64_t k = min(max(Kp[j], -lim), lim);
+    return ((uint64_t)(lim - k) << 16) | (uint64_t)j;
+}
+
+__device__ __forceinline__ void bitonic_positions(int i, int k, int jj, bool flip, int &lo, int &hi)
+{
+    if (flip) {
+        const int half = k >> 1, blk = i / half, w = i - blk * half;
+        lo = blk * k + w;
+        hi = blk * k + k - 1 - w;
+    } else {
+        lo = ((i & ~(jj - 1)) << 1) | (i & (jj - 1));
+        hi = lo + jj;
+    }
+}
+
+// In-LDS stages of one merge of size k on a chunk: the mirrored step (when
+// k <= chunk) then the half-cleaners of stride jj0, jj0/2, ..., 1.
+__device__ __forceinline__ void lds_merge(uint64_t *sk, int k, bool with_flip, int jj0)
+{
+    constexpr int C = RANK_CHUNK;
+    if (with_flip) {
+        for (int i = threadIdx.x; i < C / 2; i += 1024) {
+            int lo, hi;
+            bitonic_positions(i, k, 0, true, lo, hi);
+            const uint64_t a = sk[lo], b = sk[hi];
+            if (a > b) {
+                sk[lo] = b;
+                sk[hi] = a;
+            }
+        }
+        __syncthreads();
+    }
+    for (int jj = jj0; jj > 0; jj >>= 1) {
+        for (int i = threadIdx.x; i < C / 2; i += 1024) {
+            int lo, hi;
+            bitonic_positions(i, 0, jj, false, lo, hi);
+            const uint64_t a = sk[lo], b = sk[hi];
+            if (a > b) {
+                sk[lo] = b;
+                sk[hi] = a;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_rank_big(int n, int npad, const int64_t *__restrict__ K,
+                                                   int32_t *__restrict__ order)
+{
+    constexpr int C = RANK_CHUNK;
+    extern __shared__ uint64_t sk[];
+    const int p = blockIdx.x;
+    const int64_t *Kp = K + (int64_t)p * n;
+    int32_t *op = order + (int64_t)p * n;
+    const int nchunk = npad / C;
+    // every chunk sorted ascending on its own
+    for (int c = 0; c < nchunk; ++c) {
+        for (int r = threadIdx.x; r < C; r += 1024) {
+            const int g = c * C + r;
+            sk[r] = g < n ? rank_key(Kp, g) : ~0ull;
+        }
+        __syncthreads();
+        for (int k = 2; k <= C; k <<= 1) lds_merge(sk, k, true, k >> 2);
+        for (int r = threadIdx.x; r < C; r += 1024) {
+            const int g = c * C + r;
+            if (g < n) op[g] = (int32_t)(sk[r] & 0xffffu);
+        }
+        __syncthreads();
+    }
+    // merges longer than a chunk
+    for (int k = 2 * C; k <= npad; k <<= 1) {
+        // the mirrored step (jj == k), then the half-cleaners of stride >= C
+        for (int jj = k; jj >= C; jj = jj == k ? k >> 2 : jj >> 1) {
+            const bool flip = jj == k;
+            for (int i = threadIdx.x; i < npad / 2; i += 1024) {
+                int lo, hi;
+                bitonic_positions(i, k, flip ? 0 : jj, flip, lo, hi);
+                if (hi < n) {
+                    const int a = op[lo], b = op[hi];
+                    if (rank_key(Kp, a) > rank_key(Kp, b)) {
+                        op[lo] = b;
+                        op[hi] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int c = 0; c < nchunk; ++c) {
+            if (c * C >= n) break;
+            for (int r = threadIdx.x; r < C; r += 1024) {
+                const int g = c * C + r;
+                sk[r] = g < n ? rank_key(Kp, op[g]) : ~0ull;
+            }
+            __syncthreads();
+            lds_merge(sk, 0, false, C >> 1);
+            for (int r = threadIdx.x; r < C; r += 1024) {
+                const int g = c * C + r;
+                if (g < n) op[g] = (int32_t)(sk[r] & 0xffffu);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Job q: ranks [rank0, rank0+m) of its solution, sorted ascending.
 __global__ void __launch_bounds__(1024) k_select(int n, const int32_t *__restrict__ sol,
                                                  const int32_t *__restrict__ off,
@@ -231,11 +348,21 @@ extern "C" qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const 
 
 extern "C" qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *order_d, void *stream)
 {
-    if (n < 1 || z < 1 || !K_d || !order_d) return QB_E_ARG;
-    if (n > 16384) return QB_E_CAPACITY;
+    if (n < 1 || n > 65535 || z < 1 || !K_d || !order_d) return QB_E_ARG;
     int npad = 1;
     while (npad < n) npad <<= 1;
     npad = std::max(npad, 2);
+    if (n > RANK_CHUNK) {
+        static bool big_attr_set = false;
+        if (!big_attr_set) {
+            hipFuncSetAttribute((const void *)k_rank_big, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                RANK_CHUNK * (int)sizeof(uint64_t));
+            big_attr_set = true;
+        }
+        k_rank_big<<<z, 1024, RANK_CHUNK * sizeof(uint64_t), qb_stream(stream)>>>(n, npad, K_d, order_d);
+        QB_LAUNCH_CHECK();
+        return QB_OK;
+    }
     const size_t lds = sizeof(uint64_t) * npad;
     static bool attr_set = false;
     if (!attr_set) {

@@ -27,29 +27,6 @@ namespace {
 constexpr int TB = QB_TABU_THREADS;
 constexpr int NW = TB / 64;
 
-constexpr int ceil_log2(int v) { return v <= 1 ? 0 : 1 + ceil_log2((v + 1) / 2); }
-
-// Wave minimum of an unsigned value, returned uniform.
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
-{
-    // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return min(min(a, b), min(c, d));
-}
-
-// wave key: (biased move << 32) | (index << 1) | x_index
-__device__ __forceinline__ uint64_t pack_winner(uint32_t dbias, int j, uint32_t x)
-{
-    return ((uint64_t)dbias << 32) | ((uint64_t)(uint32_t)j << 1) | x;
-}
-
 template <int EPT, typename QT>
 __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp, const int16_t *__restrict__ Q16,
                                              int n, uint8_t *__restrict__ X, int32_t *__restrict__ H,
@@ -57,7 +34,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
                                              int32_t *__restrict__ Tout, int32_t *__restrict__ LFout,
                                              uint32_t bias)
 {
-    constexpr int EB = ceil_log2(EPT);           // bits of the element index
+    constexpr int EB = qb_ceil_log2(EPT);           // bits of the element index
     constexpr uint32_t EMASK = (1u << EB) - 1u;
     __shared__ uint64_t red[2][NW];
     __shared__ uint64_t red2[NW];
@@ -108,7 +85,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const uint32_t key = (Db[e] << EB) | (uint32_t)e;
             best = min(best, allowed ? key : 0xFFFFFFFFu);
         }
-        const uint32_t wmin = wave_min_u32(best);
+        const uint32_t wmin = qb_wave_min_u32(best);
         uint64_t wkey = ~0ull;
         if (wmin != 0xFFFFFFFFu) {
             // lowest index among the minimal moves: the lowest lane holding the
@@ -117,7 +94,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const int L = __builtin_ctzll(who);
             const int ew = (int)(wmin & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            wkey = pack_winner(wmin >> EB, ew * TB + wid * 64 + L, xw);
+            wkey = qb_tabu_winner(wmin >> EB, ew * TB + wid * 64 + L, xw);
         }
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
@@ -129,12 +106,12 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             uint32_t b2 = 0xFFFFFFFFu;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) b2 = min(b2, (Db[e] << EB) | (uint32_t)e);
-            const uint32_t w2 = wave_min_u32(b2);
+            const uint32_t w2 = qb_wave_min_u32(b2);
             const uint64_t who = __ballot(b2 == w2);
             const int L = __builtin_ctzll(who);
             const int ew = (int)(w2 & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            if (lane == 0) red2[wid] = pack_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
+            if (lane == 0) red2[wid] = qb_tabu_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
             __syncthreads();
             kb = red2[0];
 #pragma unroll
@@ -266,7 +243,7 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
     const uint32_t bias = (uint32_t)dmax;
 #define QB_T(K)                                                                                    \
     if (ept == K) {                                                                               \
-        if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> ceil_log2(K))) return QB_E_RANGE;             \
+        if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;             \
         launch_one<K, QT>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);             \
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
@@ -279,14 +256,19 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
 
 }  // namespace
 
+qb_status qb_tabu_sparse_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha, int tenure,
+                                int asp, int32_t *T, int32_t *LF, hipStream_t s);
+
 extern "C" qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d, int64_t *E_d,
                             int32_t alpha, int32_t tenure, int32_t aspiration, int32_t *T_d,
                             int32_t *LF_d, void *stream)
 {
     if (!P || z < 1 || !X_d || !H_d || !E_d || !T_d || !LF_d || alpha < 0 || tenure < 0)
         return QB_E_ARG;
-    if (qb_tabu_ept(P->n) == 0) return QB_E_CAPACITY;
     hipStream_t s = qb_stream(stream);
+    if (P->sparse)
+        return qb_tabu_sparse_launch(P, z, X_d, H_d, E_d, alpha, tenure, aspiration != 0, T_d, LF_d, s);
+    if (qb_tabu_ept(P->n) == 0) return QB_E_CAPACITY;
     if (P->int8_ok)
         return launch_tabu<int8_t>(P, (const int8_t *)P->Qp, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
                                    aspiration != 0, T_d, LF_d, s);

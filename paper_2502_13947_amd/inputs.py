@@ -63,6 +63,16 @@ def torus_graph_qubo(rows: int, cols: int, avg_degree: float, seed: int):
     return rowptr, dst.astype(np.int32), val.astype(np.int8)
 
 
+def dense_to_csr(Q: np.ndarray):
+    """CSR arrays (rowptr int32, col int32 ascending per row, val int16) of the
+    non-zero entries of a dense matrix."""
+    nz = Q != 0
+    rowptr = np.zeros(Q.shape[0] + 1, np.int32)
+    rowptr[1:] = np.cumsum(nz.sum(axis=1))
+    r, c = np.nonzero(nz)
+    return rowptr, c.astype(np.int32), Q[r, c].astype(np.int16)
+
+
 def csr_to_dense(n: int, rowptr, col, val) -> np.ndarray:
     Q = np.zeros((n, n), np.int16)
     for i in range(n):
@@ -111,4 +121,9 @@ WORKLOADS = {
     # n=7000 fully dense, 1024 sub-QUBOs of uneven size per launch
     "c3_n7000_d100": dict(n=7000, density=1.00, qseed=3, z=256, k=4,
                           sizes=(128, 256, 512, 1024), nsw=1000, iters=10, init_m=512, R=1),
+    # n=20000 sparse: 100 x 200 torus plus a random graph of average degree 4,
+    # +-1 couplings, CSR storage; 128 sub-QUBOs of 1024 x 16 replicas = 2048
+    # replicas per launch
+    "c5_n20000_sparse": dict(n=20000, rows=100, cols=200, avg_degree=4.0, qseed=5, z=16, k=8,
+                             sizes=(1024,), nsw=1000, iters=10, init_m=1024, R=16, sparse=True),
 }

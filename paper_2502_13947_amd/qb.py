@@ -32,7 +32,8 @@ class QBError(RuntimeError):
 
 class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("int8_ok", ctypes.c_int32), ("qmax", ctypes.c_int32),
-                ("eta_max", ctypes.c_int64), ("sigma", ctypes.c_double)]
+                ("eta_max", ctypes.c_int64), ("sigma", ctypes.c_double), ("sparse", ctypes.c_int32),
+                ("ell_width", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -50,6 +51,7 @@ SIGNATURES = {
     "qb_last_hip_error": (_I32, []),
     "qb_version": (ctypes.c_char_p, []),
     "qb_problem_create_dense": (_I32, [ctypes.POINTER(_P), _I32, _P, _P]),
+    "qb_problem_create_csr": (_I32, [ctypes.POINTER(_P), _I32, _P, _P, _P, _P]),
     "qb_problem_destroy": (None, [_P]),
     "qb_problem_get_info": (_I32, [_P, ctypes.POINTER(ProblemInfo)]),
     "qb_problem_eta": (_I32, [_P, _P, _P]),
@@ -69,6 +71,8 @@ SIGNATURES = {
     "qb_select": (_I32, [_P, _P, _P]),
     "qb_extract": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "qb_anneal": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P]),
+    "qb_extract_ell": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _U64, _U32, _P, _P, _P]),
     "qb_threshold_table": (_I32, [_I32, _I32, _F64, _F64, _P]),
     "qb_writeback": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "qb_rankk": (_I32, [_P, _I32, _P, _P, _I32, _P]),
@@ -88,6 +92,8 @@ SIGNATURES = {
     "qb_graph_launch": (_I32, [_P, _P]),
     "qb_graph_destroy": (None, [_P]),
     "qb_autotune_rankk": (_I32, [_P, _I32, _P, _P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
+    "qb_autotune_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _I32,
+                                      ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
 }
 
 
@@ -127,22 +133,45 @@ def _stream(stream=None):
 
 # --------------------------------------------------------------------------- handles
 class Problem:
-    """Dense QUBO problem (eq. 1) on the device.  Keeps a reference to Q."""
+    """QUBO problem (eq. 1) on the device: dense int16 Q (the handle keeps a
+    reference to it) or CSR (``Problem.from_csr``; the handle copies what it
+    needs)."""
 
-    def __init__(self, Q: torch.Tensor, stream=None):
-        assert Q.dtype == torch.int16 and Q.dim() == 2 and Q.shape[0] == Q.shape[1]
-        self.Q = Q.contiguous()
+    def __init__(self, Q: torch.Tensor = None, stream=None, csr=None):
         h = ctypes.c_void_p()
-        _chk(lib().qb_problem_create_dense(ctypes.byref(h), self.Q.shape[0], _ptr(self.Q),
-                                           _stream(stream)), "qb_problem_create_dense")
+        if csr is None:
+            assert Q.dtype == torch.int16 and Q.dim() == 2 and Q.shape[0] == Q.shape[1]
+            self.Q = Q.contiguous()
+            self.device = self.Q.device
+            _chk(lib().qb_problem_create_dense(ctypes.byref(h), self.Q.shape[0], _ptr(self.Q),
+                                               _stream(stream)), "qb_problem_create_dense")
+        else:
+            rowptr, col, val = csr
+            assert rowptr.dtype == torch.int32 and col.dtype == torch.int32 and val.dtype == torch.int16
+            self.Q = None
+            self.device = rowptr.device
+            _chk(lib().qb_problem_create_csr(ctypes.byref(h), rowptr.numel() - 1, _ptr(rowptr),
+                                             _ptr(col) if col.numel() else None,
+                                             _ptr(val) if val.numel() else None, _stream(stream)),
+                 "qb_problem_create_csr")
         self.h = h
         info = ProblemInfo()
         _chk(lib().qb_problem_get_info(self.h, ctypes.byref(info)), "qb_problem_get_info")
         self.n, self.int8_ok, self.qmax = info.n, bool(info.int8_ok), info.qmax
         self.eta_max, self.sigma = info.eta_max, info.sigma
+        self.sparse, self.ell_width = bool(info.sparse), int(info.ell_width)
+
+    @classmethod
+    def from_csr(cls, rowptr, col, val, device, stream=None) -> "Problem":
+        """CSR arrays (host or device; int32 rowptr and col, integer values
+        that fit int16) to a sparse problem on ``device``."""
+        def dev(a, dt):
+            return torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a).to(
+                device=device, dtype=dt).contiguous()
+        return cls(stream=stream, csr=(dev(rowptr, torch.int32), dev(col, torch.int32), dev(val, torch.int16)))
 
     def eta(self, stream=None) -> torch.Tensor:
-        out = torch.empty(self.n, dtype=torch.int64, device=self.Q.device)
+        out = torch.empty(self.n, dtype=torch.int64, device=self.device)
         _chk(lib().qb_problem_eta(self.h, _ptr(out), _stream(stream)), "qb_problem_eta")
         return out
 
@@ -242,6 +271,27 @@ def anneal(b: Batch, tile, F0, y0, thr, R, seed, inst_base, Y, e, B, stream=None
     int8_tile = 1 if tile.dtype == torch.int8 else 0
     _chk(lib().qb_anneal(b.h, _ptr(tile), int8_tile, _ptr(F0), _ptr(y0), nsw, B, _ptr(thr), R, seed,
                          inst_base, _ptr(Y), _ptr(e), _stream(stream)), "qb_anneal")
+
+
+def extract_ell(P: Problem, b: Batch, X, H, tile, F0, y0, c=None, stream=None):
+    _chk(lib().qb_extract_ell(P.h, b.h, _ptr(X), _ptr(H), _ptr(tile), _ptr(c), _ptr(F0), _ptr(y0),
+                              _stream(stream)), "qb_extract_ell")
+
+
+def anneal_ell(b: Batch, W, tile, F0, y0, thr, R, seed, inst_base, Y, e, B, rw=0, stream=None):
+    nsw = thr.shape[0]
+    assert thr.shape[1] == (1 << B) and tile.dtype == torch.int32
+    _chk(lib().qb_anneal_ell(b.h, int(W), _ptr(tile), _ptr(F0), _ptr(y0), nsw, B, _ptr(thr), R, int(rw), seed,
+                             inst_base, _ptr(Y), _ptr(e), _stream(stream)), "qb_anneal_ell")
+
+
+def autotune_anneal_ell(b: Batch, W, tile, F0, y0, thr, R, seed, inst_base, B, reps=2, stream=None):
+    rw = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _chk(lib().qb_autotune_anneal_ell(b.h, int(W), _ptr(tile), _ptr(F0), _ptr(y0), thr.shape[0], B, _ptr(thr), R,
+                                      seed, inst_base, reps, ctypes.byref(rw), ctypes.byref(ms), _stream(stream)),
+         "qb_autotune_anneal_ell")
+    return int(rw.value), float(ms.value)
 
 
 def threshold_table(nsw, B, tmax, tmin) -> np.ndarray:
@@ -372,3 +422,18 @@ def untile(tile: torch.Tensor, b: Batch, q: int) -> np.ndarray:
         off += mm * mm
     t = tile[off:off + mp * mp].cpu().numpy().astype(np.int32).reshape(mp, 64, ms)
     return np.ascontiguousarray(t.transpose(0, 2, 1).reshape(mp, mp)[:m, :m])
+
+
+def untile_ell(tile: torch.Tensor, b: Batch, q: int, W: int) -> np.ndarray:
+    """Row-major [m, m] matrix of job q's ELL tile (layout documented with
+    qb_extract_ell); tile is the int32 view of the uint32 words."""
+    m = int(b.sizes[q])
+    base = int(b.off[q])
+    w = tile[base * W:(base + m) * W].cpu().numpy().view(np.uint32).reshape(m, W)
+    T = np.zeros((m, m), np.int32)
+    col = (w & 0xFFFF).astype(np.int64)
+    val = (w.view(np.int32) >> 16).astype(np.int32)
+    rows = np.repeat(np.arange(m), W).reshape(m, W)
+    nz = w != 0
+    T[rows[nz], col[nz]] = val[nz]
+    return T

@@ -38,13 +38,22 @@ def feature_scales(P: "qb.Problem", alpha: int, z: int) -> np.ndarray:
 
 
 class Solver:
-    def __init__(self, Q: torch.Tensor, *, z: int, seed: int, job_m, init_m: int, thr_init, thr,
+    """The outer loop on one problem: dense (``Q``, int16 [n, n] on the
+    device) or sparse (``csr`` = (rowptr, col, val) with ``device``)."""
+
+    def __init__(self, Q: torch.Tensor = None, *, z: int, seed: int, job_m, init_m: int, thr_init, thr,
                  B: int, R: int, alpha: int, tenure: int, aspiration: bool = True, W=(2, 2, 1),
-                 rankk_variant: int = 0, mlp_W=None, trace_capacity: int = 0):
-        dev = Q.device
+                 rankk_variant: int = 0, mlp_W=None, trace_capacity: int = 0, csr=None, device=None,
+                 anneal_rw: int = 0):
+        dev = Q.device if csr is None else torch.device(device)
         self.dev = dev
         self.stream = torch.cuda.Stream(device=dev)
-        self.P = qb.Problem(Q, stream=self.stream)
+        if csr is None:
+            self.P = qb.Problem(Q, stream=self.stream)
+        else:
+            self.P = qb.Problem.from_csr(*csr, device=dev, stream=self.stream)
+        self.sparse = self.P.sparse
+        self.anneal_rw = anneal_rw
         n = self.n = self.P.n
         self.z, self.seed, self.B, self.R = z, int(seed), B, R
         self.alpha, self.tenure, self.aspiration, self.W = alpha, tenure, aspiration, W
@@ -55,7 +64,9 @@ class Solver:
         k = job_m.shape[1]
         self.batch = qb.Batch(n, z, np.repeat(np.arange(z, dtype=np.int32), k), job_m.reshape(-1))
         b = self.batch
-        self.tile_dtype = qb.tile_dtype(self.P)
+        # dense tiles (int8/int16) or ELL tiles (uint32 words held as int32)
+        self.tile_dtype = torch.int32 if self.sparse else qb.tile_dtype(self.P)
+        tile_len = (lambda bb: bb.total * self.P.ell_width) if self.sparse else (lambda bb: bb.tile_elems)
         self.X = torch.zeros((z, n), dtype=torch.uint8, device=dev)
         self.H = torch.zeros((z, n), dtype=torch.int32, device=dev)
         self.E = torch.zeros(z, dtype=torch.int64, device=dev)
@@ -67,7 +78,7 @@ class Solver:
         self.xbest = torch.zeros(n, dtype=torch.uint8, device=dev)
         self.ebest = torch.full((1,), 2**63 - 1, dtype=torch.int64, device=dev)
         self.kcount = torch.zeros(z, dtype=torch.int32, device=dev)
-        self.tiles = torch.zeros(max(b.tile_elems, 16), dtype=self.tile_dtype, device=dev)
+        self.tiles = torch.zeros(max(tile_len(b), 16), dtype=self.tile_dtype, device=dev)
         self.F0 = torch.zeros(b.total, dtype=torch.int32, device=dev)
         self.y0 = torch.zeros(b.total, dtype=torch.uint8, device=dev)
         self.Y = torch.zeros(b.total * R, dtype=torch.uint8, device=dev)
@@ -78,7 +89,7 @@ class Solver:
             self.thr_init = torch.as_tensor(np.ascontiguousarray(thr_init, np.int32), device=dev)
             self.ib = qb.Batch(n, z, np.arange(z, dtype=np.int32), np.full(z, init_m, np.int32))
             ib = self.ib
-            self.itiles = torch.zeros(max(ib.tile_elems, 16), dtype=self.tile_dtype, device=dev)
+            self.itiles = torch.zeros(max(tile_len(ib), 16), dtype=self.tile_dtype, device=dev)
             self.iF0 = torch.zeros(ib.total, dtype=torch.int32, device=dev)
             self.iy0 = torch.zeros(ib.total, dtype=torch.uint8, device=dev)
             self.iY = torch.zeros(ib.total * R, dtype=torch.uint8, device=dev)
@@ -102,6 +113,19 @@ class Solver:
         self.t = 0
 
     # ------------------------------------------------------------------ stages
+    def _extract(self, b, tiles, F0, y0, stream):
+        if self.sparse:
+            qb.extract_ell(self.P, b, self.X, self.H, tiles, F0, y0, stream=stream)
+        else:
+            qb.extract(self.P, b, self.X, self.H, tiles, F0, y0, stream=stream)
+
+    def _anneal(self, b, tiles, F0, y0, thr, Y, e, stream):
+        if self.sparse:
+            qb.anneal_ell(b, self.P.ell_width, tiles, F0, y0, thr, self.R, self.seed, self.inst, Y, e, self.B,
+                          rw=self.anneal_rw, stream=stream)
+        else:
+            qb.anneal(b, tiles, F0, y0, thr, self.R, self.seed, self.inst, Y, e, self.B, stream=stream)
+
     def _apply(self, stream=None):
         qb.rankk(self.P, self.dX, self.H, self.rankk_variant, stream=stream)
         qb.energy(self.X, self.H, self.E, stream=stream)
@@ -120,9 +144,8 @@ class Solver:
             m0 = self.init_m
             for l in range(n // m0):
                 self.ib.set_idx(np.tile(np.arange(l * m0, (l + 1) * m0, dtype=np.int32), z), stream=s)
-                qb.extract(self.P, self.ib, self.X, self.H, self.itiles, self.iF0, self.iy0, stream=s)
-                qb.anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.R, self.seed,
-                          self.inst, self.iY, self.ie, self.B, stream=s)
+                self._extract(self.ib, self.itiles, self.iF0, self.iy0, s)
+                self._anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.iY, self.ie, s)
                 self.inst += z
                 qb.zero(self.dX, stream=s)
                 qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, stream=s)
@@ -137,6 +160,22 @@ class Solver:
         self.stream.synchronize()
         self.rankk_variant, ms = qb.autotune_rankk(self.P, dX, self.H, reps=reps, stream=self.stream)
         return self.rankk_variant, ms
+
+    def autotune_anneal(self, reps=2):
+        """Sparse problems: pick the annealer's replicas per workgroup on the
+        current state's plain selection (results are identical for every
+        choice; the autotuner checks it).  Leaves the solver state as it was
+        apart from scratch buffers the next iteration overwrites."""
+        if not self.sparse:
+            return None
+        s, b = self.stream, self.batch
+        qb.keys(self.P, self.X, self.T, self.K, self.W, t_bound=max(self.alpha, 1), stream=s)
+        qb.rank(self.K, self.order, stream=s)
+        qb.select(b, self.order, stream=s)
+        self._extract(b, self.tiles, self.F0, self.y0, s)
+        self.anneal_rw, ms = qb.autotune_anneal_ell(b, self.P.ell_width, self.tiles, self.F0, self.y0, self.thr,
+                                                    self.R, self.seed ^ 0x5A5A, 0, self.B, reps=reps, stream=s)
+        return self.anneal_rw, ms
 
     def capture(self, iters: int) -> "qb.Graph":
         """One HIP graph holding the next `iters` outer iterations."""
@@ -170,10 +209,9 @@ class Solver:
         else:
             qb.select(b, self.order, stream=s)
         mark("extract")
-        qb.extract(self.P, b, self.X, self.H, self.tiles, self.F0, self.y0, stream=s)
+        self._extract(b, self.tiles, self.F0, self.y0, s)
         mark("anneal")
-        qb.anneal(b, self.tiles, self.F0, self.y0, self.thr, self.R, self.seed, self.inst, self.Y, self.e,
-                  self.B, stream=s)
+        self._anneal(b, self.tiles, self.F0, self.y0, self.thr, self.Y, self.e, s)
         mark("apply")
         self.inst += b.J
         qb.gain_update(b, self.R, self.Y, self.e, self.y0, self.G, stream=s)

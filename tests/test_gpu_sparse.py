@@ -1,0 +1,467 @@
+"""GPU-vs-oracle parity of the sparse (CSR / ELL) path, bit-exact.
+
+The oracle works on the dense form of each seeded sparse instance; the
+library sees only the CSR arrays.  Instances: the 2D-torus-plus-random-graph
+family of the n = 20000 workload at several sizes, and sparse matrices with
+diagonals and int16 weights drawn by the dense generator.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_13947_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2502_13947_amd import qb
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    qb.lib()
+
+
+def qb():
+    from paper_2502_13947_amd import qb as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def torus(rows, cols, seed, deg=4.0):
+    rp, col, val = inputs.torus_graph_qubo(rows, cols, deg, seed)
+    n = rows * cols
+    return n, (rp, col, val.astype(np.int16)), inputs.csr_to_dense(n, rp, col, val)
+
+
+def sparse_wide(n, density, seed, lo=-3000, hi=3000):
+    """Sparse matrix with a diagonal and int16 weights beyond int8."""
+    Q = inputs.dense_qubo(n, density, seed, lo=lo, hi=hi)
+    return n, inputs.dense_to_csr(Q), Q
+
+
+def field_csr(csr, X):
+    """H = X Q from the CSR arrays (scipy; an input, not an expected value)."""
+    import scipy.sparse as sp
+    rp, col, val = csr
+    n = rp.shape[0] - 1
+    Qs = sp.csr_matrix((np.asarray(val, np.int64), col, rp), shape=(n, n))
+    return np.ascontiguousarray((Qs @ np.atleast_2d(X).T.astype(np.int64)).T.astype(np.int32))
+
+
+def csr_problem(csr):
+    return qb().Problem.from_csr(*csr, device=DEV)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+# ----------------------------------------------------------------------------- a0
+def test_csr_problem_matches_dense_statistics():
+    for n, csr, Q in (torus(20, 30, 1), sparse_wide(700, 0.02, 2)):
+        Ps = csr_problem(csr)
+        Pd = qb().Problem(dev(Q))
+        assert Ps.sparse and not Pd.sparse
+        assert Ps.n == n and Ps.qmax == Pd.qmax and Ps.int8_ok == Pd.int8_ok
+        assert Ps.eta_max == Pd.eta_max and Ps.sigma == Pd.sigma
+        assert (Ps.eta().cpu().numpy() == oracle.eta(Q)).all()
+        deg = np.diff(csr[0]) - (Q.diagonal() != 0)
+        assert Ps.ell_width % 4 == 0 and Ps.ell_width >= max(int(deg.max()), 1)
+
+
+def test_csr_problem_rejects_bad_input():
+    n, (rp, col, val), Q = torus(6, 7, 3)
+    def status(rp2, col2, val2):
+        with pytest.raises(qb().QBError) as ei:
+            qb().Problem.from_csr(rp2, col2, val2, device=DEV)
+        return ei.value.status
+    c2 = col.copy()
+    c2[[0, 1]] = c2[[1, 0]]                      # columns out of order
+    assert status(rp, c2, val) == -1
+    c3 = col.copy()
+    c3[5] = n                                    # column out of range
+    assert status(rp, c3, val) == -1
+    rp4 = rp.copy()
+    rp4[0] = 1
+    assert status(rp4, col, val) == -1
+    v5 = val.copy()
+    v5[3] = -v5[3]                               # mirror value differs
+    assert status(rp, col, v5) == -2
+    # an entry without its mirror
+    Qa = Q.copy()
+    Qa[0, 5] = 1 if Qa[0, 5] == 0 else 0
+    rpa, cola, vala = inputs.dense_to_csr(Qa)
+    assert status(rpa, cola, vala) == -2
+    # range bound (2n+1) max|Q| < 2^31 is the dense form's
+    Qb = np.zeros((4, 4), np.int16)
+    Qb[1, 1] = 32767
+    assert csr_problem(inputs.dense_to_csr(Qb)).qmax == 32767
+    # an all-zero matrix is a valid (empty) sparse problem
+    Pz = csr_problem((np.zeros(11, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int16)))
+    assert Pz.n == 10 and Pz.ell_width == 4
+
+
+# ----------------------------------------------------------------------------- a1/a7/a8
+@pytest.mark.parametrize("case", ["torus", "wide"])
+@pytest.mark.parametrize("z", [1, 5, 40])
+def test_sparse_field_energy_rankk(case, z):
+    say("sparse field", case, z)
+    n, csr, Q = torus(25, 31, 4) if case == "torus" else sparse_wide(901, 0.03, 5)
+    P = csr_problem(csr)
+    X0 = inputs.random_solutions(z, n, 6)
+    H = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    E = torch.zeros(z, dtype=torch.int64, device=DEV)
+    qb().field(P, dev(X0), H)
+    qb().energy(dev(X0), H, E)
+    Ho = oracle.field(Q, X0)
+    assert (H.cpu().numpy() == Ho).all()
+    assert (E.cpu().numpy() == oracle.energy(X0, Ho)).all()
+    X1 = X0.copy()
+    flip = np.random.default_rng(7).random((z, n)) < 0.3
+    X1[flip] ^= 1
+    dX = (X1.astype(np.int16) - X0).astype(np.int8)
+    for v in (0, 3):
+        Hd = dev(Ho)
+        qb().rankk(P, dev(dX), Hd, v)
+        assert (Hd.cpu().numpy() == oracle.field(Q, X1)).all(), v
+    for v in (1, 2):
+        with pytest.raises(qb().QBError) as ei:
+            qb().rankk(P, dev(dX), dev(Ho), v)
+        assert ei.value.status == -8
+
+
+# ----------------------------------------------------------------------------- a2
+@pytest.mark.parametrize("case,z,alpha,tenure,asp", [
+    ("t:5x6", 2, 150, 3, True),          # n = 30, one element per thread
+    ("t:30x37", 3, 3000, 7, True),       # n = 1110, two per thread
+    ("w:2900", 2, 4000, 19, False),      # int16 weights with a diagonal
+    ("w:2900", 1, 4000, 19, True),
+    ("t:100x200", 1, 3000, 133, True),   # n = 20000, twenty per thread
+])
+def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp):
+    say("sparse tabu", case, z, alpha, tenure, asp)
+    if case.startswith("t:"):
+        r, c = (int(v) for v in case[2:].split("x"))
+        n, csr, Q = torus(r, c, 8)
+    else:
+        n, csr, Q = sparse_wide(int(case[2:]), 0.01, 9)
+    X = inputs.random_solutions(z, n, 10)
+    H = field_csr(csr, X)
+    E = oracle.energy(X, H)
+    P = csr_problem(csr)
+    Xd, Hd, Ed = dev(X), dev(H), dev(E)
+    T = torch.full((z, n), 7, dtype=torch.int32, device=DEV)     # overwritten
+    LF = torch.full((z, n), 7, dtype=torch.int32, device=DEV)
+    qb().tabu(P, Xd, Hd, Ed, alpha, tenure, asp, T, LF)
+    for p in range(z):
+        x, h, ov, To, LFo = oracle.tabu(Q, X[p], H[p], int(E[p]), alpha, tenure, asp)
+        assert (Xd[p].cpu().numpy() == x).all(), p
+        assert (Hd[p].cpu().numpy() == h).all(), p
+        assert int(Ed[p].item()) == ov
+        assert (T[p].cpu().numpy() == To).all()
+        assert (LF[p].cpu().numpy() == LFo).all()
+
+
+def test_sparse_tabu_capacity():
+    n, csr, Q = torus(103, 200, 11)             # n = 20600 > 20 x 1024
+    P = csr_problem(csr)
+    z = 1
+    X = torch.zeros((z, n), dtype=torch.uint8, device=DEV)
+    H = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    E = torch.zeros(z, dtype=torch.int64, device=DEV)
+    T = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    with pytest.raises(qb().QBError) as ei:
+        qb().tabu(P, X, H, E, 10, 3, True, T, T.clone())
+    assert ei.value.status == -5
+
+
+# ----------------------------------------------------------------------------- a3
+@pytest.mark.parametrize("n,z,spread", [(16385, 2, 1000), (20000, 3, 2**40), (40000, 2, 37), (65535, 1, 2**46)])
+def test_rank_large_n(n, z, spread):
+    """Beyond the single-LDS sort: the order equals the lexicographic sort
+    (key descending, index ascending), ties included."""
+    say("rank", n, z, spread)
+    rng = np.random.default_rng(n)
+    K = rng.integers(-spread, spread, size=(z, n)).astype(np.int64)
+    order = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().rank(dev(K), order)
+    o = order.cpu().numpy()
+    for p in range(z):
+        assert (o[p] == np.lexsort((np.arange(n), -K[p]))).all(), p
+    assert (o[0] == oracle.order(K[0])).all()
+
+
+def test_keys_rank_select_on_sparse_problem():
+    n, csr, Q = torus(100, 200, 12)
+    z = 3
+    P = csr_problem(csr)
+    X = inputs.random_solutions(z, n, 13)
+    T = np.random.default_rng(14).integers(0, 9, size=(z, n)).astype(np.int32)
+    K = torch.zeros((z, n), dtype=torch.int64, device=DEV)
+    qb().keys(P, dev(X), dev(T), K, (2, 2, 1), t_bound=10)
+    Ko = oracle.keys(oracle.eta(Q), X, T, (2, 2, 1))
+    assert (K.cpu().numpy() == Ko).all()
+    order = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().rank(K, order)
+    b = qb().Batch(n, z, np.repeat(np.arange(z), 8), np.full(8 * z, 1024))
+    qb().select(b, order)
+    idx = b.idx(DEV).cpu().numpy()
+    for p in range(z):
+        o = oracle.order(Ko[p])
+        for j in range(8):
+            s = (p * 8 + j) * 1024
+            assert (idx[s:s + 1024] == np.sort(o[j * 1024:(j + 1) * 1024])).all()
+
+
+# ----------------------------------------------------------------------------- a4/a5
+def _jobs(n, z, sizes, seed):
+    job_m = np.tile(np.array(sizes, np.int32), (z, 1))
+    sol, off, idx = inputs.random_index_sets(z, n, job_m, seed)
+    return sol, job_m.reshape(-1), idx
+
+
+def _extract_ell(P, n, z, sizes, X, H, seed):
+    sol, m, idx = _jobs(n, z, sizes, seed)
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    W = P.ell_width
+    tiles = torch.zeros(max(b.total * W, 4), dtype=torch.int32, device=DEV)
+    c = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract_ell(P, b, dev(X), dev(H), tiles, F0, y0, c=c)
+    return b, sol, idx, tiles, c, F0, y0
+
+
+@pytest.mark.parametrize("case,z,sizes", [("t:20x30", 2, [1, 7, 64]), ("t:40x50", 2, [300, 1024, 65]),
+                                          ("w:1500", 2, [512, 100]), ("t:100x200", 1, [1024] * 3)])
+def test_extract_ell_bit_exact(case, z, sizes):
+    say("extract_ell", case, z, sizes)
+    if case.startswith("t:"):
+        r, cc = (int(v) for v in case[2:].split("x"))
+        n, csr, Q = torus(r, cc, 15)
+    else:
+        n, csr, Q = sparse_wide(int(case[2:]), 0.03, 16)
+    P = csr_problem(csr)
+    X = inputs.random_solutions(z, n, 17)
+    H = field_csr(csr, X)
+    b, sol, idx, tiles, c, F0, y0 = _extract_ell(P, n, z, sizes, X, H, 18)
+    cc_, FF, yy = c.cpu().numpy(), F0.cpu().numpy(), y0.cpu().numpy()
+    for q in range(b.J):
+        S = idx[b.off[q]:b.off[q + 1]]
+        Tq, co, Fo, yo = oracle.extract(Q, X[sol[q]], H[sol[q]], S)
+        assert (qb().untile_ell(tiles, b, q, P.ell_width) == Tq).all(), q
+        sl = slice(b.off[q], b.off[q + 1])
+        assert (cc_[sl] == co).all() and (FF[sl] == Fo).all() and (yy[sl] == yo).all(), q
+
+
+ELL_CASES = [
+    # (instance, z, sizes, nsw, R, rw)
+    ("t:20x30", 2, [1, 5], 9, 1, 0),
+    ("t:30x40", 2, [64, 65, 127], 12, 3, 1),
+    ("t:40x50", 2, [128, 200, 256], 10, 4, 2),
+    ("w:1500", 1, [512, 300], 8, 5, 4),
+    ("t:60x60", 1, [1024, 700], 6, 16, 8),
+    ("t:60x60", 1, [1024], 5, 16, 16),
+    ("t:60x60", 1, [1024], 5, 16, 0),
+]
+
+
+@pytest.mark.parametrize("case,z,sizes,nsw,R,rw", ELL_CASES)
+def test_anneal_ell_bit_exact(case, z, sizes, nsw, R, rw):
+    say("anneal_ell", case, z, sizes, nsw, R, rw)
+    if case.startswith("t:"):
+        r, cc = (int(v) for v in case[2:].split("x"))
+        n, csr, Q = torus(r, cc, 21)
+    else:
+        n, csr, Q = sparse_wide(int(case[2:]), 0.03, 22)
+    P = csr_problem(csr)
+    X = inputs.random_solutions(z, n, 23)
+    H = field_csr(csr, X)
+    b, sol, idx, tiles, c, F0, y0 = _extract_ell(P, n, z, sizes, X, H, 24)
+    B = 10
+    sig = max(P.sigma, 1.0)
+    thr = oracle.threshold_table(nsw, B, 0.5 * sig, 0.002 * sig)
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    seed, inst = 0x1234ABCD5678, 1000
+    qb().anneal_ell(b, P.ell_width, tiles, F0, y0, dev(thr), R, seed, inst, Y, e, B, rw=rw)
+    Yh, eh = Y.cpu().numpy(), e.cpu().numpy()
+    for q in range(b.J):
+        S = idx[b.off[q]:b.off[q + 1]]
+        Tq, _, F, yy = oracle.extract(Q, X[sol[q]], H[sol[q]], S)
+        Yo, eo = oracle.anneal(Tq, F, yy, thr, R, seed, inst + q, B)
+        mm = len(S)
+        got = Yh[b.off[q] * R:(b.off[q] + mm) * R].reshape(R, mm)
+        assert (got == Yo).all(), (q, mm)
+        assert (eh[q * R:(q + 1) * R] == eo).all(), (q, mm)
+
+
+def test_anneal_ell_equals_dense_annealer():
+    """The same jobs annealed from the dense tiles of the dense form give the
+    same states and energies."""
+    n, csr, Q = torus(30, 40, 25)
+    z, sizes, R, nsw, B = 2, [1024, 128], 3, 8, 10
+    Ps, Pd = csr_problem(csr), qb().Problem(dev(Q))
+    X = inputs.random_solutions(z, n, 26)
+    H = oracle.field(Q, X)
+    b, sol, idx, tiles, c, F0, y0 = _extract_ell(Ps, n, z, sizes, X, H, 27)
+    tiles_d = torch.zeros(b.tile_elems, dtype=qb().tile_dtype(Pd), device=DEV)
+    F0d = torch.zeros_like(F0)
+    y0d = torch.zeros_like(y0)
+    qb().extract(Pd, b, dev(X), dev(H), tiles_d, F0d, y0d)
+    assert (F0d == F0).all() and (y0d == y0).all()
+    thr = dev(oracle.threshold_table(nsw, B, 0.5 * Ps.sigma, 0.002 * Ps.sigma))
+    Ys = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    es = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    Yd, ed = torch.zeros_like(Ys), torch.zeros_like(es)
+    qb().anneal_ell(b, Ps.ell_width, tiles, F0, y0, thr, R, 5, 0, Ys, es, B)
+    qb().anneal(b, tiles_d, F0d, y0d, thr, R, 5, 0, Yd, ed, B)
+    assert (Ys == Yd).all() and (es == ed).all()
+
+
+def test_anneal_ell_rejects_what_does_not_fit():
+    n, csr, Q = sparse_wide(1200, 0.3, 28)      # wide ELL rows
+    P = csr_problem(csr)
+    assert P.ell_width > 300
+    X = inputs.random_solutions(1, n, 29)
+    H = field_csr(csr, X)
+    b, sol, idx, tiles, c, F0, y0 = _extract_ell(P, n, 1, [1024], X, H, 30)
+    thr = dev(oracle.threshold_table(2, 10, 10.0, 1.0))
+    Y = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J, dtype=torch.int64, device=DEV)
+    with pytest.raises(qb().QBError) as ei:
+        qb().anneal_ell(b, P.ell_width, tiles, F0, y0, thr, 1, 1, 0, Y, e, 10, rw=1)
+    assert ei.value.status == -5
+
+
+# ----------------------------------------------------------------------------- a11
+def _solver_kw(n, P, z, job_m, R, nsw=20, init_m=128, B=10):
+    thr = oracle.threshold_table(nsw, B, 0.25 * max(P.sigma, 1), 0.002 * max(P.sigma, 1))
+    thr0 = oracle.threshold_table(nsw, B, 0.25 * max(P.sigma, 1), 0.002 * max(P.sigma, 1))
+    return dict(z=z, seed=7, job_m=job_m, init_m=init_m, thr_init=thr0, thr=thr, B=B, R=R,
+                alpha=5 * n, tenure=max(1, n // 150))
+
+
+def test_sparse_full_trajectory_vs_oracle():
+    """Alg. 2 end to end on a CSR problem, bit-exact with the oracle run on
+    its dense form; then the replica schedule is autotuned and a captured
+    graph of further iterations is replayed."""
+    from paper_2502_13947_amd.solver import Solver
+    n, csr, Q = torus(20, 30, 31)
+    z, iters, R = 4, 3, 4
+    job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
+    P = csr_problem(csr)
+    kw = _solver_kw(n, P, z, job_m, R)
+    S = Solver(csr=csr, device=DEV, **kw)
+    trace = S.run(iters)
+    ref = oracle.run(Q, iters=iters, **kw)
+    assert trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all()
+    assert (S.H.cpu().numpy() == ref["H"]).all()
+    assert (S.E.cpu().numpy() == ref["E"]).all()
+    assert int(S.ebest.item()) == ref["ebest"] and (S.xbest.cpu().numpy() == ref["xbest"]).all()
+
+
+def test_sparse_autotune_and_graph_replay():
+    from paper_2502_13947_amd.solver import Solver
+    n, csr, Q = torus(24, 25, 32)
+    z, R = 3, 8
+    job_m = np.tile([128, 200], (z, 1)).astype(np.int32)
+    P = csr_problem(csr)
+    kw = _solver_kw(n, P, z, job_m, R, init_m=0)
+    G = Solver(csr=csr, device=DEV, **kw)
+    G.init()
+    v, _ = G.autotune()
+    assert v == 3
+    rw, ms = G.autotune_anneal()
+    assert rw in (1, 2, 4, 8) and ms > 0
+    with torch.cuda.stream(G.stream):
+        G.init()
+    G.stream.synchronize()
+    snap = [t.clone() for t in (G.X, G.H, G.E, G.ebest, G.xbest)]
+    graph = G.capture(2)
+    ref = oracle.run(Q, iters=2, **kw)
+    for rep in range(2):
+        with torch.cuda.stream(G.stream):
+            for t, s0 in zip((G.X, G.H, G.E, G.ebest, G.xbest), snap):
+                t.copy_(s0)
+        G.stream.synchronize()
+        graph.launch()
+        G.stream.synchronize()
+        assert (G.X.cpu().numpy() == ref["X"]).all(), rep
+        assert (G.H.cpu().numpy() == ref["H"]).all(), rep
+        assert int(G.ebest.item()) == ref["ebest"], rep
+
+
+def test_full_size_sparse_workload_sampled():
+    """The n = 20000 workload at its full size, in the launch configuration
+    the benchmark times (16 solutions, 8 jobs of 1024 each, 16 replicas,
+    1000 sweeps, alpha = 5n): sampled outputs against the oracle, the rest
+    against properties that hold at any size (H = Q x, E = x.h, flips sum to
+    alpha)."""
+    import scipy.sparse as sp
+    from paper_2502_13947_amd.solver import Solver, default_thresholds
+    w = inputs.WORKLOADS["c5_n20000_sparse"]
+    rp, col, val = inputs.torus_graph_qubo(w["rows"], w["cols"], w["avg_degree"], w["qseed"])
+    n, z, R = w["n"], w["z"], w["R"]
+    csr = (rp, col, val.astype(np.int16))
+    Qs = sp.csr_matrix((val.astype(np.int64), col, rp), shape=(n, n))
+    P = csr_problem(csr)
+    thr = default_thresholds(P, w["nsw"])
+    job_m = np.full((z, w["k"]), 1024, np.int32)
+    S = Solver(csr=csr, device=DEV, z=z, seed=3, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=10, R=R,
+               alpha=5 * n, tenure=n // 150)
+    S.init()
+    S.stream.synchronize()
+    X0 = S.X.cpu().numpy()
+    H0 = S.H.cpu().numpy()
+    E0 = S.E.cpu().numpy()
+    assert (H0 == (Qs @ X0.T.astype(np.int64)).T).all()
+    assert (E0 == (X0.astype(np.int64) * H0).sum(1)).all()
+    say("c5 tabu")
+    qb().tabu(S.P, S.X, S.H, S.E, S.alpha, S.tenure, True, S.T, S.LF, stream=S.stream)
+    S.stream.synchronize()
+    Xt, Ht, Et, Tt = (t.cpu().numpy() for t in (S.X, S.H, S.E, S.T))
+    assert (Ht == (Qs @ Xt.T.astype(np.int64)).T).all()
+    assert (Et == (Xt.astype(np.int64) * Ht).sum(1)).all()
+    assert (Tt.sum(1) == S.alpha).all()
+    Qd = inputs.csr_to_dense(n, rp, col, val)
+    x, h, ov, To, LFo = oracle.tabu(Qd, X0[0], H0[0], int(E0[0]), S.alpha, S.tenure, True)
+    assert (Xt[0] == x).all() and (Ht[0] == h).all() and Et[0] == ov and (Tt[0] == To).all()
+    assert (S.LF[0].cpu().numpy() == LFo).all()
+    say("c5 select/extract/anneal")
+    b = S.batch
+    qb().keys(S.P, S.X, S.T, S.K, S.W, t_bound=S.alpha, stream=S.stream)
+    qb().rank(S.K, S.order, stream=S.stream)
+    qb().select(b, S.order, stream=S.stream)
+    S._extract(b, S.tiles, S.F0, S.y0, S.stream)
+    S._anneal(b, S.tiles, S.F0, S.y0, S.thr, S.Y, S.e, S.stream)
+    S.stream.synchronize()
+    idx = b.idx(DEV).cpu().numpy()
+    Ko = oracle.keys(oracle.eta(Qd), Xt, Tt, S.W)
+    assert (S.K.cpu().numpy() == Ko).all()
+    o0 = oracle.order(Ko[0])
+    assert (S.order[0].cpu().numpy() == o0).all()
+    Yh, eh = S.Y.cpu().numpy(), S.e.cpu().numpy()
+    for q in (0, b.J - 1):
+        Sq = idx[b.off[q]:b.off[q + 1]]
+        Tq, _, F, yy = oracle.extract(Qd, Xt[b.sol[q]], Ht[b.sol[q]], Sq)
+        Yo, eo = oracle.anneal(Tq, F, yy, S.thr.cpu().numpy(), R, S.seed, S.inst + q, S.B)
+        got = Yh[b.off[q] * R:(b.off[q] + 1024) * R].reshape(R, 1024)
+        assert (got == Yo).all(), q
+        assert (eh[q * R:(q + 1) * R] == eo).all(), q
+    say("c5 write-back/rank-k")
+    qb().zero(S.dX, stream=S.stream)
+    qb().writeback(b, R, S.Y, S.e, S.y0, S.X, S.dX, stream=S.stream)
+    S._apply(stream=S.stream)
+    S.stream.synchronize()
+    X2, H2, E2 = S.X.cpu().numpy(), S.H.cpu().numpy(), S.E.cpu().numpy()
+    assert (H2 == (Qs @ X2.T.astype(np.int64)).T).all()
+    assert (E2 == (X2.astype(np.int64) * H2).sum(1)).all()
