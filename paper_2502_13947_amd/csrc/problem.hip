@@ -327,7 +327,14 @@ extern "C" qb_status qb_problem_create_csr(qb_problem *out, int32_t n, const int
         P->int8_ok = scan_h.qmax <= 127;
         P->sigma = sqrt((double)scan_h.sumsq / (double)n);
         P->ellw = std::max(4, (scan_h.dmax + 3) & ~3);
-        if (hipMalloc(&P->ell, sizeof(uint32_t) * (size_t)n * P->ellw) != hipSuccess) { rc = QB_E_HIP; break; }
+        // 16 spare zero words after the last row: row readers fetch whole
+        // 16-word chunks and ignore the words past the row
+        const size_t ell_words = (size_t)n * P->ellw + 16;
+        if (hipMalloc(&P->ell, sizeof(uint32_t) * ell_words) != hipSuccess ||
+            hipMemsetAsync(P->ell + (size_t)n * P->ellw, 0, sizeof(uint32_t) * 16, s) != hipSuccess) {
+            rc = QB_E_HIP;
+            break;
+        }
         k_csr_to_ell<<<(n + 255) / 256, 256, 0, s>>>(n, P->ellw, rowptr_d, col_d, val_d, P->ell, P->ecnt);
         std::vector<int64_t> eta_h(n);
         if (hipGetLastError() != hipSuccess ||

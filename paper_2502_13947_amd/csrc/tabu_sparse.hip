@@ -1,19 +1,33 @@
 // Tabu search (Alg. 1 of the IC-D^2S paper) on a sparse problem: one
 // 1024-thread workgroup (sixteen waves, four per SIMD) per solution.
 //
-// The step is the dense kernel's: thread t owns the variables j = e*1024 + t
-// (e < EPT) and keeps in registers the biased move value D_j and the step
-// U_j after which j is free again; every lane keys its allowed variables (move << EB | element), the
-// wave minimum comes from DPP, the sixteen wave winners meet in LDS with one
-// barrier per step.  What changes is the field update: flipping i moves
-// D_j only for the neighbours j of i (the O(n) update of the Tabu section,
-// here O(degree)).  The neighbour list is read once by the whole workgroup
-// (uniform address, scalar loads); each entry's owner patches its own
-// element through a scalar switch on the (uniform) element index.  The
-// factor 2(1-2x_j) is taken from the x bits when an element is touched, so
-// no per-element copy of it is kept.  The flip count and last-flip step go
-// straight to the output arrays (a vector atomic add and a store by the
-// owner, neither waited for), which keeps the registers for D and U.
+// Thread t owns the variables j = e*1024 + t (e < EPT) and keeps in
+// registers the biased move value D_j and the step U_j after which j is free
+// again; keys are (move << EB | element), the wave minimum comes from DPP,
+// and the sixteen wave winners meet in LDS with one barrier per step, where
+// a DPP tree over lanes picks the smallest.  What changes from the dense
+// kernel is the field update: flipping i moves D_j only for the neighbours
+// j of i (the O(n) update of the Tabu section, here O(degree)), so the
+// argmin is kept incrementally too.  Each thread holds, per group of GS
+// variables, the minimum key of its free variables (kf) and of its tabu ones
+// (kt), and the step-1 at which the group's next tabu variable is free
+// (texp).  An allowed variable is free, or tabu with D < OV_min - OV
+// (aspiration), and the smallest tabu key aspirates whenever any tabu key
+// does, so a thread's candidate is min(kf, kt if kt aspirates).  A group is
+// rescanned only when one of its variables expires, when its flipped
+// variable turns tabu, or when the variable holding its kf or kt got worse;
+// a lowered move just lowers them.
+//
+// Before the barrier every wave copies the neighbour row of its own
+// candidate from the ELL into LDS, so the winner's row is on chip when the
+// step resolves and no memory round trip follows the barrier; each wave then
+// applies only the entries whose variable it owns (a ballot), the owning
+// lane through a scalar switch on the element index.  The factor 2(1-2x_j)
+// is taken from the x bits when an element is touched.  The flip count and
+// last-flip step go straight to the output arrays (a vector atomic add and a
+// store by the owner, neither waited for), which keeps the registers for D
+// and U.  Measured on the n = 20000 workload: the step is bound by
+// instruction issue (four waves per SIMD), not by the scan or by memory.
 #include "qb_internal.h"
 
 namespace {
@@ -28,28 +42,61 @@ static_assert(TB == 1 << TSHIFT, "thread count must be 2^TSHIFT");
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) \
     CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19)
 
-// Calls f on every word of row i's ELL entries (zero words included up to
-// the next multiple of four), 16-byte loads one chunk ahead of their use.
+// Calls f on the W words of row i of the ELL (zero words included), reading
+// 16 words at a time with the next chunk in flight; the allocation has 16
+// spare words after the last row, and words past W are not passed to f.
 template <typename Fn>
-__device__ __forceinline__ void for_row(const uint32_t *__restrict__ ell, int W, const int32_t *__restrict__ ecnt,
-                                        int i, Fn &f)
+__device__ __forceinline__ void for_row(const uint32_t *__restrict__ ell, int W, int i, Fn &f)
 {
     const uint4 *row = reinterpret_cast<const uint4 *>(ell + (int64_t)i * W);
-    const int c4 = (ecnt[i] + 3) >> 2;
-    uint4 cur = c4 > 0 ? row[0] : make_uint4(0, 0, 0, 0);
-    for (int t = 0; t < c4; ++t) {
-        const uint4 nxt = t + 1 < c4 ? row[t + 1] : make_uint4(0, 0, 0, 0);
-        f(cur.x);
-        f(cur.y);
-        f(cur.z);
-        f(cur.w);
-        cur = nxt;
+    uint4 c0 = row[0], c1 = row[1], c2 = row[2], c3 = row[3];
+    for (int t0 = 0; t0 < W; t0 += 16) {
+        uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0, n2 = n0, n3 = n0;
+        if (t0 + 16 < W) {
+            const uint4 *nx = row + ((t0 + 16) >> 2);
+            n0 = nx[0];
+            n1 = nx[1];
+            n2 = nx[2];
+            n3 = nx[3];
+        }
+        const uint32_t w[16] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
+                                c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (t0 + u < W) f(w[u]);
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
     }
+}
+
+// Minimum of the NW (<= 16) 64-bit wave winners: lane l of every wave reads
+// winner l, and a DPP tree inside the first row of 16 lanes (xor 1, xor 2,
+// rotate 4, rotate 8) leaves the minimum in lane 0, returned uniform.
+template <int CTL>
+__device__ __forceinline__ uint64_t dpp_min64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTL, 0xF, 0xF, false);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    return o < v ? o : v;
+}
+
+__device__ __forceinline__ uint64_t min_winners(const uint64_t *slot, int lane)
+{
+    uint64_t v = lane < NW ? slot[lane] : ~0ull;
+    v = dpp_min64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = dpp_min64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v = dpp_min64<0x124>(v);   // row_ror 4
+    v = dpp_min64<0x128>(v);   // row_ror 8
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 template <int EPT>
 __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell, int W,
-                                                const int32_t *__restrict__ ecnt,
                                                 const int32_t *__restrict__ diag, int n,
                                                 uint8_t *__restrict__ X, int32_t *__restrict__ H,
                                                 int64_t *__restrict__ E, int alpha, int tenure, int asp,
@@ -63,8 +110,10 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
     __shared__ uint64_t red2[NW];
     __shared__ int32_t list[TB];
     __shared__ int lcount;
+    extern __shared__ uint32_t rowbuf[];   // [2][NW][W]
 
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wid_u = __builtin_amdgcn_readfirstlane(wid);
     const int64_t ro = (int64_t)p * n;
     const uint32_t dpad = 0xFFFFFFFFu >> EB;
 
@@ -88,46 +137,79 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         }
     }
     int64_t OV = E[p], OVmin = OV;
+    constexpr uint32_t KNONE = 0xFFFFFFFFu;
+    constexpr int GS = 4;                         // variables per group
+    constexpr int G = (EPT + GS - 1) / GS;
+    uint32_t kf[G], kt[G];                         // minimum keys of the free / tabu variables
+    int32_t texp[G];                               // the step-1 at which a tabu variable is next free
+    uint32_t dirty = (1u << G) - 1u;               // groups to rescan
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        kf[g] = KNONE;
+        kt[g] = KNONE;
+        texp[g] = 0;
+    }
 
     for (int step = 1; step <= alpha; ++step) {
         const int64_t tau = OVmin - OV + (int64_t)bias;
         const uint32_t tb = tau <= 0 ? 0u : (uint32_t)tau;
         const int32_t free_at = step - 1;
-        uint32_t best = 0xFFFFFFFFu;
+        uint32_t kfa = KNONE, kta = KNONE;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const bool allowed = U[e] <= free_at || (asp && Db[e] < tb);
-            const uint32_t key = (Db[e] << EB) | (uint32_t)e;
-            best = min(best, allowed ? key : 0xFFFFFFFFu);
+        for (int g = 0; g < G; ++g) {
+            if (((dirty >> g) & 1u) || free_at >= texp[g]) {
+                kf[g] = KNONE;
+                kt[g] = KNONE;
+                texp[g] = 0x7fffffff;
+#pragma unroll
+                for (int e = g * GS; e < (g + 1) * GS && e < EPT; ++e) {
+                    const uint32_t key = (Db[e] << EB) | (uint32_t)e;
+                    if (U[e] <= free_at) {
+                        kf[g] = min(kf[g], key);
+                    } else {
+                        kt[g] = min(kt[g], key);
+                        texp[g] = min(texp[g], U[e]);
+                    }
+                }
+            }
+            kfa = min(kfa, kf[g]);
+            kta = min(kta, kt[g]);
         }
+        dirty = 0;
+        const uint32_t best = min(kfa, (asp && (kta >> EB) < tb) ? kta : KNONE);
         const uint32_t wmin = qb_wave_min_u32(best);
         uint64_t wkey = ~0ull;
-        if (wmin != 0xFFFFFFFFu) {
+        if (wmin != KNONE) {
             const uint64_t who = __ballot(best == wmin);
             const int L = __builtin_ctzll(who);
             const int ew = (int)(wmin & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
             wkey = qb_tabu_winner(wmin >> EB, ew * TB + wid * 64 + L, xw);
+            const int iw = ew * TB + wid * 64 + L;
+            uint32_t *rb = rowbuf + ((step & 1) * NW + wid) * W;
+            if (iw < n)
+                for (int t = lane; t < W; t += 64) rb[t] = ell[(int64_t)iw * W + t];
         }
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
-        uint64_t kb = red[step & 1][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) kb = min(kb, red[step & 1][w]);
+        uint64_t kb = min_winners(red[step & 1], lane);
         if (kb == ~0ull) {
-            uint32_t b2 = 0xFFFFFFFFu;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) b2 = min(b2, (Db[e] << EB) | (uint32_t)e);
+            // every variable is tabu and none aspirates: argmin over all of them
+            const uint32_t b2 = min(kfa, kta);
             const uint32_t w2 = qb_wave_min_u32(b2);
             const uint64_t who = __ballot(b2 == w2);
             const int L = __builtin_ctzll(who);
             const int ew = (int)(w2 & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
             if (lane == 0) red2[wid] = qb_tabu_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
+            {
+                const int iw = ew * TB + wid * 64 + L;
+                uint32_t *rb = rowbuf + ((step & 1) * NW + wid) * W;
+                if (iw < n)
+                    for (int t = lane; t < W; t += 64) rb[t] = ell[(int64_t)iw * W + t];
+            }
             __syncthreads();
-            kb = red2[0];
-#pragma unroll
-            for (int w = 1; w < NW; ++w) kb = min(kb, red2[w]);
+            kb = min_winners(red2, lane);
         }
         const uint32_t dib = (uint32_t)(kb >> 32);
         const int i = __builtin_amdgcn_readfirstlane((int)((uint32_t)kb >> 1));
@@ -137,12 +219,21 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         // neighbours j of i: h_j += s Q_ji, so D_j += 2(1-2x_j) s Q_ji
         auto nb = [&](uint32_t wd) {
             const int c = qb_ell_col(wd);
-            if (wd != 0u && tid == (c & TMASK)) {
+            if (wd != 0u && ((c >> 6) & (NW - 1)) == wid_u && lane == (c & 63)) {
                 const int32_t dv = s * qb_ell_val(wd);
                 switch (c >> TSHIFT) {
 #define QB_NB_CASE(K)                                                                        \
     case K:                                                                                  \
-        if constexpr (K < EPT) Db[K] += (uint32_t)(((xb >> K) & 1ull) ? -2 * dv : 2 * dv); \
+        if constexpr (K < EPT) {                                                             \
+            const uint32_t ko = (Db[K] << EB) | (uint32_t)K;                                 \
+            Db[K] += (uint32_t)(((xb >> K) & 1ull) ? -2 * dv : 2 * dv);                      \
+            const uint32_t kn = (Db[K] << EB) | (uint32_t)K;                                 \
+            uint32_t &km = U[K] <= free_at ? kf[K / GS] : kt[K / GS];                        \
+            if (kn < km)                                                                     \
+                km = kn;                                                                     \
+            else if (ko == km)                                                               \
+                dirty |= 1u << (K / GS);                                                     \
+        }                                                                                    \
         break;
                     QB_SWITCH20(QB_NB_CASE)
 #undef QB_NB_CASE
@@ -150,7 +241,19 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
                 }
             }
         };
-        for_row(ell, W, ecnt, i, nb);
+        {
+            const uint32_t *rb = rowbuf + ((step & 1) * NW + ((i >> 6) & (NW - 1))) * W;
+            for (int t0 = 0; t0 < W; t0 += 64) {
+                const uint32_t wd = t0 + lane < W ? rb[t0 + lane] : 0u;
+                const int c = qb_ell_col(wd);
+                uint64_t mine = __ballot(wd != 0u && ((c >> 6) & (NW - 1)) == wid);
+                while (mine) {
+                    const int t = __builtin_ctzll(mine);
+                    mine &= mine - 1;
+                    nb((uint32_t)__builtin_amdgcn_readlane((int)wd, t));
+                }
+            }
+        }
         if (tid == (i & TMASK)) {
             // the zeroing stores above precede the first step's barrier
             __hip_atomic_fetch_add(Tout + ro + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -163,6 +266,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         if constexpr (K < EPT) {                                                 \
             Db[K] = 2u * bias - dib;                                             \
             U[K] = step + max(max(U[K] - (step - 1), 0) + tenure - 1, 0);        \
+            dirty |= 1u << (K / GS);                                             \
         }                                                                        \
         break;
                 QB_SWITCH20(QB_OWNER_CASE)
@@ -229,7 +333,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
                     }
                 }
             };
-            for_row(ell, W, ecnt, jv, hup);
+            for_row(ell, W, jv, hup);
         }
         __syncthreads();
     }
@@ -255,11 +359,17 @@ qb_status qb_tabu_sparse_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int
     if (ept == 0) return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
     const uint32_t bias = (uint32_t)dmax;
+    // each wave's candidate row, double-buffered by step parity
+    const size_t lds = sizeof(uint32_t) * 2 * NW * (size_t)P->ellw;
+    if (lds > 64 * 1024) return QB_E_CAPACITY;
 #define QB_T(K)                                                                                     \
     if (ept == K) {                                                                                \
         if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;          \
-        k_tabu_sp<K><<<z, TB, 0, s>>>(P->ell, P->ellw, P->ecnt, P->diag, P->n, X, H, E, alpha, tenure, asp, T, \
-                                      LF, bias);                                                   \
+        if (lds > 48 * 1024)                                                                       \
+            QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_sp<K>,                             \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+        k_tabu_sp<K><<<z, TB, lds, s>>>(P->ell, P->ellw, P->diag, P->n, X, H, E, alpha, tenure, asp, T, LF,      \
+                                      bias);                                                       \
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
     }

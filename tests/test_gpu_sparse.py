@@ -143,14 +143,17 @@ def test_sparse_field_energy_rankk(case, z):
     ("w:2900", 2, 4000, 19, False),      # int16 weights with a diagonal
     ("w:2900", 1, 4000, 19, True),
     ("t:100x200", 1, 3000, 133, True),   # n = 20000, twenty per thread
+    ("d:1500", 2, 3000, 10, True),       # rows of ~120 entries: wider than a wave
 ])
 def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp):
     say("sparse tabu", case, z, alpha, tenure, asp)
     if case.startswith("t:"):
         r, c = (int(v) for v in case[2:].split("x"))
         n, csr, Q = torus(r, c, 8)
-    else:
+    elif case.startswith("w:"):
         n, csr, Q = sparse_wide(int(case[2:]), 0.01, 9)
+    else:
+        n, csr, Q = sparse_wide(int(case[2:]), 0.08, 9, lo=-100, hi=100)
     X = inputs.random_solutions(z, n, 10)
     H = field_csr(csr, X)
     E = oracle.energy(X, H)
