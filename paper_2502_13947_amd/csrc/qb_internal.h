@@ -179,3 +179,32 @@ __device__ __forceinline__ uint64_t qb_tabu_winner(uint32_t dbias, int j, uint32
 {
     return ((uint64_t)dbias << 32) | ((uint64_t)(uint32_t)j << 1) | x;
 }
+
+template <int CTL>
+__device__ __forceinline__ uint64_t qb_dpp_min64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTL, 0xF, 0xF, false);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    return o < v ? o : v;
+}
+
+// Minimum of NW (<= 16) 64-bit values slot[0..NW), returned uniform: lane l
+// of the calling wave reads slot[l] (lanes >= NW take the largest value) and
+// a DPP tree inside the first row of 16 lanes (xor 1, xor 2, rotate 4,
+// rotate 8) leaves the minimum in lane 0.  Must be called by a full wave.
+template <int NW>
+__device__ __forceinline__ uint64_t qb_min_winners(const uint64_t *slot, int lane)
+{
+    static_assert(NW >= 1 && NW <= 16, "one row of 16 lanes");
+    uint64_t v = lane < NW ? slot[lane] : ~0ull;
+    v = qb_dpp_min64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = qb_dpp_min64<0x4E>(v);    // quad_perm [2,3,0,1]
+    if constexpr (NW > 4) {
+        v = qb_dpp_min64<0x124>(v);   // row_ror 4
+        v = qb_dpp_min64<0x128>(v);   // row_ror 8
+    }
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}

@@ -14,7 +14,8 @@
 // the minimum; the wave minimum comes from DPP row operations plus four
 // readlanes; index order inside a wave is (element, lane), so the lowest
 // lane holding the minimal key gives the lowest index; the eight wave
-// winners meet in LDS (one barrier per step, double-buffered slots).  The
+// winners meet in LDS (one barrier per step, double-buffered slots), where a
+// DPP tree over lanes picks the smallest.  The
 // chosen variable's row of the padded copy of Q is read (coalesced) and
 // every D is updated by one multiply-add; the owner of the flipped variable
 // patches its own element through a scalar switch.  x_min is never copied:
@@ -98,9 +99,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         }
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
-        uint64_t kb = red[step & 1][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) kb = min(kb, red[step & 1][w]);
+        uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
         if (kb == ~0ull) {
             // every variable is tabu and none aspirates: argmin over all of them
             uint32_t b2 = 0xFFFFFFFFu;
@@ -113,9 +112,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
             if (lane == 0) red2[wid] = qb_tabu_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
             __syncthreads();
-            kb = red2[0];
-#pragma unroll
-            for (int w = 1; w < NW; ++w) kb = min(kb, red2[w]);
+            kb = qb_min_winners<NW>(red2, lane);
         }
         const uint32_t dib = (uint32_t)(kb >> 32);
         const int i = (int)((uint32_t)kb >> 1);

@@ -74,27 +74,6 @@ __device__ __forceinline__ void for_row(const uint32_t *__restrict__ ell, int W,
 // Minimum of the NW (<= 16) 64-bit wave winners: lane l of every wave reads
 // winner l, and a DPP tree inside the first row of 16 lanes (xor 1, xor 2,
 // rotate 4, rotate 8) leaves the minimum in lane 0, returned uniform.
-template <int CTL>
-__device__ __forceinline__ uint64_t dpp_min64(uint64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTL, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTL, 0xF, 0xF, false);
-    const uint64_t o = ((uint64_t)hi << 32) | lo;
-    return o < v ? o : v;
-}
-
-__device__ __forceinline__ uint64_t min_winners(const uint64_t *slot, int lane)
-{
-    uint64_t v = lane < NW ? slot[lane] : ~0ull;
-    v = dpp_min64<0xB1>(v);    // quad_perm [1,0,3,2]
-    v = dpp_min64<0x4E>(v);    // quad_perm [2,3,0,1]
-    v = dpp_min64<0x124>(v);   // row_ror 4
-    v = dpp_min64<0x128>(v);   // row_ror 8
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 template <int EPT>
 __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell, int W,
                                                 const int32_t *__restrict__ diag, int n,
@@ -192,7 +171,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         }
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
-        uint64_t kb = min_winners(red[step & 1], lane);
+        uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
         if (kb == ~0ull) {
             // every variable is tabu and none aspirates: argmin over all of them
             const uint32_t b2 = min(kfa, kta);
@@ -209,7 +188,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
                     for (int t = lane; t < W; t += 64) rb[t] = ell[(int64_t)iw * W + t];
             }
             __syncthreads();
-            kb = min_winners(red2, lane);
+            kb = qb_min_winners<NW>(red2, lane);
         }
         const uint32_t dib = (uint32_t)(kb >> 32);
         const int i = __builtin_amdgcn_readfirstlane((int)((uint32_t)kb >> 1));
