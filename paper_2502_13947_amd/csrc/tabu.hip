@@ -46,14 +46,17 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t ro = (int64_t)p * n;
-    // padding elements carry the largest possible key and are never chosen
-    const uint32_t dpad = 0xFFFFFFFFu >> EB;
+    constexpr uint32_t TBIT = 0x80000000u;       // set in a key while the variable is tabu
+    constexpr uint32_t KNONE = 0xFFFFFFFFu;
+    // padding elements carry the largest possible key, tabu for ever
+    const uint32_t dpad = 0x7FFFFFFFu >> EB;
 
-    uint32_t Db[EPT];      // D + bias
-    int32_t S[EPT];        // 2 (1 - 2 x)
+    uint32_t Kb[EPT];      // ((D + bias) << EB | e) | TBIT if tabu
+    int32_t S[EPT];        // 2 (1 - 2 x) << EB
     int32_t U[EPT];        // tabu through step U
     uint64_t xb = 0;       // x bits of the owned variables
     uint64_t pb = 0;       // flipped since the last improvement
+    int32_t nexp = 0x7fffffff;   // smallest U among the thread's tabu variables
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int j = e * TB + tid;
@@ -61,14 +64,14 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         if (j < n) {
             const int32_t x = X[ro + j] & 1;
             const int32_t qjj = Q16[(int64_t)j * n + j];
-            S[e] = x ? -2 : 2;
+            S[e] = (x ? -2 : 2) << EB;
             xb |= (uint64_t)x << e;
-            Db[e] = (uint32_t)(qjj + S[e] * H[ro + j]) + bias;
+            Kb[e] = (((uint32_t)(qjj + (x ? -2 : 2) * H[ro + j]) + bias) << EB) | (uint32_t)e;
             Ts[j] = 0;
             Ls[j] = 0;
         } else {
-            S[e] = 2;
-            Db[e] = dpad;
+            S[e] = 2 << EB;
+            Kb[e] = (dpad << EB) | (uint32_t)e | TBIT;
             U[e] = 0x7fffffff;                   // never allowed
         }
     }
@@ -79,13 +82,30 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         const int64_t tau = OVmin - OV + (int64_t)bias;
         const uint32_t tb = tau <= 0 ? 0u : (uint32_t)tau;
         const int32_t free_at = step - 1;
-        uint32_t best = 0xFFFFFFFFu;
+        if (free_at >= nexp) {
+            // a tabu variable of this thread is free again
+            nexp = 0x7fffffff;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                if (Kb[e] & TBIT) {
+                    if (U[e] <= free_at)
+                        Kb[e] &= ~TBIT;
+                    else
+                        nexp = min(nexp, U[e]);
+                }
+            }
+        }
+        // smallest free key and smallest tabu key: the smallest tabu key
+        // aspirates (D < OV_min - OV) whenever any tabu key does
+        uint32_t m1 = KNONE, m2 = KNONE;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const bool allowed = U[e] <= free_at || (asp && Db[e] < tb);
-            const uint32_t key = (Db[e] << EB) | (uint32_t)e;
-            best = min(best, allowed ? key : 0xFFFFFFFFu);
+            m1 = min(m1, Kb[e]);
+            m2 = min(m2, Kb[e] ^ TBIT);
         }
+        const uint32_t fk = m1 < TBIT ? m1 : KNONE;
+        const uint32_t tk = m2 < TBIT ? m2 : KNONE;
+        const uint32_t best = min(fk, (asp && (tk >> EB) < tb) ? tk : KNONE);
         const uint32_t wmin = qb_wave_min_u32(best);
         uint64_t wkey = ~0ull;
         if (wmin != 0xFFFFFFFFu) {
@@ -102,9 +122,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
         if (kb == ~0ull) {
             // every variable is tabu and none aspirates: argmin over all of them
-            uint32_t b2 = 0xFFFFFFFFu;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) b2 = min(b2, (Db[e] << EB) | (uint32_t)e);
+            const uint32_t b2 = min(fk, tk);
             const uint32_t w2 = qb_wave_min_u32(b2);
             const uint64_t who = __ballot(b2 == w2);
             const int L = __builtin_ctzll(who);
@@ -124,13 +142,14 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 #pragma unroll
             for (int e = 0; e < EPT; ++e) q[e] = rowp[e * TB];
         }
-        // h_j += s Q_ji  =>  D_j += S_j s Q_ji (the owner is patched below)
+        // h_j += s Q_ji  =>  D_j += S_j s Q_ji, applied to the key above its
+        // element bits (the owner is patched below)
         if (s > 0) {
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) Db[e] += (uint32_t)__mul24(q[e], S[e]);
+            for (int e = 0; e < EPT; ++e) Kb[e] += (uint32_t)__mul24(q[e], S[e]);
         } else {
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) Db[e] -= (uint32_t)__mul24(q[e], S[e]);
+            for (int e = 0; e < EPT; ++e) Kb[e] -= (uint32_t)__mul24(q[e], S[e]);
         }
         const int ti = i % TB;
         if (tid == ti) {
@@ -143,9 +162,13 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 #define QB_OWNER_CASE(K)                                                         \
     case K:                                                                      \
         if constexpr (K < EPT) {                                                 \
-            Db[K] = 2u * bias - dib;                                             \
+            Kb[K] = ((2u * bias - dib) << EB) | (uint32_t)K;                     \
             S[K] = -S[K];                                                        \
             U[K] = step + max(max(U[K] - (step - 1), 0) + tenure - 1, 0);        \
+            if (U[K] > step) {                                                   \
+                Kb[K] |= TBIT;                                                   \
+                nexp = min(nexp, U[K]);                                          \
+            }                                                                    \
         }                                                                        \
         break;
                 QB_OWNER_CASE(0) QB_OWNER_CASE(1) QB_OWNER_CASE(2) QB_OWNER_CASE(3)
@@ -182,7 +205,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         h[e] = 0;
         if (j < n) {
             const int32_t qjj = Q16[(int64_t)j * n + j];
-            h[e] = ((int32_t)(Db[e] - bias) - qjj) * S[e] / 4;
+            h[e] = ((int32_t)(((Kb[e] & ~TBIT) >> EB) - bias) - qjj) * (S[e] >> EB) / 4;
         }
     }
 #pragma unroll
@@ -240,7 +263,7 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
     const uint32_t bias = (uint32_t)dmax;
 #define QB_T(K)                                                                                    \
     if (ept == K) {                                                                               \
-        if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;             \
+        if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;             \
         launch_one<K, QT>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);             \
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
