@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2_n5000_d50")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="solutions in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="solutions in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-init-pass", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="also time a captured HIP graph of the same steps")
     ap.add_argument("--ttt", action="store_true",
@@ -59,10 +59,11 @@ def workload(name):
     return w
 
 
-def cpu_baseline(Q, w, thr, nsol):
+def cpu_baseline(Q, w, thr, nsol, max_jobs=None):
     """The oracle, untuned, on a bounded sample: `nsol` solutions through one
     full outer iteration (Tabu, keys, selection, extraction, annealing,
-    write-back, field, mutation) on one host thread."""
+    write-back, field, mutation) on one host thread; with `max_jobs`, only
+    that many of each solution's sub-QUBOs are annealed."""
     import oracle
     n = w["n"]
     X = oracle.init_x(n, nsol, w["seed"])
@@ -80,7 +81,7 @@ def cpu_baseline(Q, w, thr, nsol):
         o = oracle.order(K[p])
         off = 0
         inU = np.zeros(n, np.uint8)
-        for m in w["job_m"][p]:
+        for m in w["job_m"][p][:max_jobs]:
             S = np.sort(o[off:off + m]).astype(np.int32)
             off += m
             Tq, c, F0, y0 = oracle.extract(Q, X[p], H[p], S)
@@ -93,8 +94,9 @@ def cpu_baseline(Q, w, thr, nsol):
     E = oracle.energy(X, H)
     dt = time.perf_counter() - t0
     return dict(value=attempts / dt, unit="spin-flip attempts/s", cores=1, kind="oracle",
-                sample=f"{nsol} of {w['z']} solutions through one outer iteration "
-                       f"({attempts} attempts, {dt:.1f} s, single thread)")
+                sample=f"{nsol} of {w['z']} solutions through one outer iteration"
+                       + (f", {max_jobs} of {len(w['job_m'][0])} sub-QUBOs each" if max_jobs else "")
+                       + f" ({attempts} attempts, {dt:.1f} s, single thread)")
 
 
 def measured_traffic(workload_name, kernel):
@@ -213,15 +215,24 @@ def main():
 
     w = workload(a.workload)
     n, z = w["n"], w["z"]
-    Q = inputs.dense_qubo(n, w["density"], w["qseed"])
     dev = torch.device("cuda:0")
-    Qd = torch.as_tensor(Q, device=dev)
-    sigma = qb.Problem(Qd).sigma
-    thr = default_thresholds(qb.Problem(Qd), w["nsw"], w["B"])
-    S = Solver(Qd, z=z, seed=w["seed"], job_m=w["job_m"], init_m=0 if a.no_init_pass else w["init_m"],
-               thr_init=thr, thr=thr, B=w["B"], R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
+    sparse = bool(w.get("sparse"))
+    kw = dict(z=z, seed=w["seed"], job_m=w["job_m"], init_m=0 if a.no_init_pass else w["init_m"], B=w["B"],
+              R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
+    if sparse:
+        rp, col, val = inputs.torus_graph_qubo(w["rows"], w["cols"], w["avg_degree"], w["qseed"])
+        csr = (rp, col, val.astype(np.int16))
+        thr = default_thresholds(qb.Problem.from_csr(*csr, device=dev), w["nsw"], w["B"])
+        S = Solver(csr=csr, device=dev, thr_init=thr, thr=thr, **kw)
+        Q = None
+    else:
+        Q = inputs.dense_qubo(n, w["density"], w["qseed"])
+        Qd = torch.as_tensor(Q, device=dev)
+        thr = default_thresholds(qb.Problem(Qd), w["nsw"], w["B"])
+        S = Solver(Qd, thr_init=thr, thr=thr, **kw)
     S.init()
     tuned_variant, tuned_ms = S.autotune()
+    tuned_rw = S.autotune_anneal() if sparse else None
     with torch.cuda.stream(S.stream):
         for _ in range(a.warmup):
             S.iterate()
@@ -277,13 +288,27 @@ def main():
 
     # roofline of the dominant kernel (Tabu and the annealer are single launches)
     qbytes = 1 if S.P.int8_ok else 2
-    tabu_bytes = z * w["alpha"] * n * qbytes + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
+    if sparse:
+        # one ELL row (ell_width 4-byte words) per step, plus the state in and out
+        tabu_bytes = z * w["alpha"] * S.P.ell_width * 4 + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
+        tabu_what = f"{z} solutions x {w['alpha']} steps x one {S.P.ell_width}-word ELL row"
+    else:
+        tabu_bytes = z * w["alpha"] * n * qbytes + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
+        tabu_what = f"{z} solutions x {w['alpha']} steps x one {n}-entry int{8 * qbytes} row of Q"
     t_tabu, t_ann = stages["tabu"] / 1e3, stages["anneal"] / 1e3
-    if t_tabu >= t_ann:
+    # sparse Tabu: the method's step is an argmin over all n move values (one
+    # compare-select each); the row it reads is a few dozen bytes
+    tabu_ops = z * w["alpha"] * n
+    if t_tabu >= t_ann and sparse:
+        ach = tabu_ops / t_tabu / 1e12
+        roof = dict(kernel="k_tabu_sp", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
+                    frac=ach / ALU_PEAK_TOPS, traffic=None,
+                    algorithmic=f"{z} solutions x {w['alpha']} steps x an argmin over {n} move values")
+    elif t_tabu >= t_ann:
         ach = tabu_bytes / t_tabu / 1e9
         roof = dict(kernel="k_tabu", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(a.workload, "k_tabu"),
-                    algorithmic=f"{z} solutions x {w['alpha']} steps x one {n}-entry int{8 * qbytes} row of Q")
+                    algorithmic=tabu_what)
     else:
         ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
         ach = ops / t_ann / 1e12
@@ -294,8 +319,13 @@ def main():
     ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
     other["k_anneal"] = dict(ms=stages["anneal"], attempts_per_s=attempts_per_step / t_ann,
                              alu_frac=ops / t_ann / 1e12 / ALU_PEAK_TOPS)
-    other["k_tabu"] = dict(ms=stages["tabu"], GBps=tabu_bytes / t_tabu / 1e9,
-                           hbm_frac=tabu_bytes / t_tabu / 1e9 / HBM_PEAK_GBS)
+    if sparse:
+        other["k_tabu_sp"] = dict(ms=stages["tabu"], ns_per_step=t_tabu * 1e9 / w["alpha"],
+                                  alu_frac=tabu_ops / t_tabu / 1e12 / ALU_PEAK_TOPS)
+    else:
+        other["k_tabu"] = dict(ms=stages["tabu"], GBps=tabu_bytes / t_tabu / 1e9,
+                               hbm_frac=tabu_bytes / t_tabu / 1e9 / HBM_PEAK_GBS,
+                               ns_per_step=t_tabu * 1e9 / w["alpha"])
 
     if a.copy_probe > 0:
         nb = a.copy_probe << 20
@@ -309,7 +339,9 @@ def main():
 
     cpu = None
     if a.cpu_sample > 0:
-        cpu = cpu_baseline(Q, w, thr, a.cpu_sample)
+        if sparse:
+            Q = inputs.csr_to_dense(n, rp, col, val)
+        cpu = cpu_baseline(Q, w, thr, 1, max_jobs=2) if sparse else cpu_baseline(Q, w, thr, a.cpu_sample)
 
     out = {
         "metric": "spin-flip attempts/sec",
@@ -324,7 +356,10 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": a.workload, "n": n, "density": w["density"], "z": z,
+        "config": {"workload": a.workload, "n": n,
+                   **({"graph": f"{w['rows']}x{w['cols']} torus + random graph of average degree "
+                               f"{w['avg_degree']}, +-1 couplings, CSR", "ell_width": S.P.ell_width}
+                      if sparse else {"density": w["density"]}), "z": z,
                    "subqubos_per_step": b.J, "m": sorted(set(int(v) for v in np.ravel(w["job_m"]))),
                    "sweeps": w["nsw"], "replicas": w["R"], "tabu_alpha": w["alpha"],
                    "attempts_per_step": attempts_per_step},
@@ -335,6 +370,8 @@ def main():
         "kernels": other,
         "graph_ms_per_step": graph_ms,
         "rankk_variant": {"chosen": tuned_variant, "ms": tuned_ms, "by": "autotuner"},
+        **({"anneal_replicas_per_workgroup": {"chosen": tuned_rw[0], "ms": tuned_rw[1], "by": "autotuner"}}
+           if tuned_rw else {}),
         "wall_s": t_wall,
     }
     print(json.dumps(out), flush=True)
