@@ -138,6 +138,12 @@ qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d, int64_t *
  * if (W1+W2+W3) eta_max z max(t_bound,1) >= 2^47 (the rank packing). */
 qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const int32_t *T_d, int32_t W1,
                   int32_t W2, int32_t W3, int32_t t_bound, int64_t *K_d, void *stream);
+/* Random keys for the ablation that omits the control parameters (No_SM of
+ * the Discussion section): K[p][j] = word (j mod 4) of Philox4x32-10 at
+ * counter (j/4, t, p, 4<<28), key (seed lo, seed hi), as int64 in [0, 2^32).
+ * Ranked by qb_rank like the plain keys, they pick the sub-QUBO variables
+ * and order the mutation candidates at random. */
+qb_status qb_random_keys(int32_t n, int32_t z, int32_t t, uint64_t seed, int64_t *K_d, void *stream);
 /* order[p][r] = variable of rank r when sorting solution p by (K desc, index
  * asc) (Alg. 3 "highest values in A"; ties to the lower index).  Keys must
  * satisfy |K| < 2^47 (guaranteed by qb_keys).  n <= 16384 sorts in LDS;
@@ -155,7 +161,9 @@ qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *order_d, vo
  * 0 per solution, in job order).  The handle OWNS its device metadata (sol,
  * off, rank0, idx, tile offsets, dispatch order) and the side streams used to
  * run the annealer's size classes concurrently; create/destroy are not hot
- * calls.  Capacity: 1 <= m_q <= 1024, sum of a solution's sizes <= n. */
+ * calls.  Capacity: 1 <= m_q <= 1024, sum of a solution's sizes <= n.
+ * J = 0 makes an empty batch (sol_h and size_h may be NULL): every per-job
+ * call returns at once, and qb_mutate sees no IM variables (U_p empty). */
 typedef struct qb_batch_s *qb_batch;
 typedef struct {
     int32_t J;
@@ -244,13 +252,16 @@ qb_status qb_threshold_table(int32_t nsw, int32_t B, double tmax, double tmin, i
 /* ---------------------------------------------------------------- a6/a7/a8
  * Write-back (Alg. 3 line 7): per job the replica with the lowest e (lowest
  * r on ties) is written into X[sol][S] unconditionally, and dX[sol][S] =
- * Y - y0 (int8 in {-1,0,1}).  dX_d (int8 [z][n]) must be all zero on entry
- * outside the jobs' variables.  ebest_job_d (optional, int64 [J]) receives
- * the chosen e.  Jobs of one solution are disjoint (qb_select builds them
- * so; qb_batch_set_idx checks it). */
+ * Y - y0 (int8 in {-1,0,1}).  flags bit 0 (QB_WB_NOT_WORSE): write a job
+ * back only if that e <= 0 (the "only if not worse" variant; otherwise X
+ * and dX of the job are left untouched).  dX_d (int8 [z][n]) must be all
+ * zero on entry outside the jobs' variables.  ebest_job_d (optional, int64
+ * [J]) receives the chosen e.  Jobs of one solution are disjoint (qb_select
+ * builds them so; qb_batch_set_idx checks it). */
+#define QB_WB_NOT_WORSE 1
 qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d,
                        const uint8_t *y0_d, uint8_t *X_d, int8_t *dX_d, int64_t *ebest_job_d,
-                       void *stream);
+                       int32_t flags, void *stream);
 /* Rank-k local-field update H[p] += Q dX[p] for all p (the O(n) move-value
  * update of the Tabu section generalised to many flipped variables).
  * variant: 0 = automatic, 1 = VALU gather over the changed columns,

@@ -65,6 +65,9 @@ def lib():
         L.qbo_anneal.argtypes = [i32, P, P, P, i32, i32, P, i32, u64, u32, P, P]
         L.qbo_mutate.argtypes = [i32, P, P, P, i32, i32, u64, P]
         L.qbo_mutate.restype = i32
+        L.qbo_mutate2.argtypes = [i32, P, P, P, P, i32, i32, u64, P]
+        L.qbo_mutate2.restype = i32
+        L.qbo_random_keys.argtypes = [i32, i32, i32, u64, P]
         L.qbo_run.argtypes = [P, P, P, P, P, P, P, P]
         L.qbo_run.restype = i32
         f32 = ctypes.c_float
@@ -240,6 +243,27 @@ def mutate(x, K, inU, t, p, seed):
     return x, flip, int(k)
 
 
+def mutate2(x, Korder, Kprob, inU, t, p, seed):
+    """Mutation with the candidate order from Korder and the flip
+    probabilities from Kprob.  Returns (x after mutation, flip mask, k)."""
+    x = _c(x, np.uint8).copy()
+    Korder = _c(Korder, np.int64)
+    Kprob = _c(Kprob, np.int64)
+    inU = _c(inU, np.uint8)
+    n = x.shape[0]
+    flip = np.zeros(n, np.uint8)
+    k = lib().qbo_mutate2(n, _p(x), _p(Korder), _p(Kprob), _p(inU), int(t), int(p), int(seed), _p(flip))
+    return x, flip, int(k)
+
+
+def random_keys(n, z, t, seed) -> np.ndarray:
+    """Random keys of the ablation without control parameters: Philox
+    stream 4, one 32-bit word per (solution, variable) at iteration t."""
+    K = np.zeros((z, n), np.int64)
+    lib().qbo_random_keys(int(n), int(z), int(t), int(seed), _p(K))
+    return K
+
+
 class _RunCfg(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("z", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("iters", ctypes.c_int32), ("alpha", ctypes.c_int32), ("tenure", ctypes.c_int32),
@@ -248,13 +272,21 @@ class _RunCfg(ctypes.Structure):
                 ("job_m", ctypes.c_void_p), ("init_m", ctypes.c_int32),
                 ("nsw_init", ctypes.c_int32), ("thr_init", ctypes.c_void_p),
                 ("nsw", ctypes.c_int32), ("B", ctypes.c_int32), ("thr", ctypes.c_void_p),
-                ("R", ctypes.c_int32), ("mlp_W", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+                ("R", ctypes.c_int32), ("mlp_W", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("random_select", ctypes.c_int32), ("no_im", ctypes.c_int32), ("init_jacobi", ctypes.c_int32),
+                ("wb_not_worse", ctypes.c_int32), ("patience", ctypes.c_int32)]
 
 
 def run(Q, *, z, seed, iters, alpha, tenure, job_m, init_m, thr_init, thr, B, R,
-        aspiration=True, W=(2, 2, 1), mlp_W=None, scales=None):
+        aspiration=True, W=(2, 2, 1), mlp_W=None, scales=None, random_select=False, no_im=False,
+        init_jacobi=False, wb_not_worse=False, patience=0):
     """Full Alg. 2 run.  job_m: [z, k] sub-QUBO sizes.  Returns a dict with the
-    final X, H, E, the best solution/energy, and E_best after each iteration."""
+    final X, H, E, the best solution/energy, E_best after each iteration run and
+    the number of iterations run (fewer than ``iters`` when ``patience`` stops
+    it).  random_select / no_im are the ablations without the control
+    parameters and without the Ising machine; init_jacobi runs the initial
+    pass concurrently; wb_not_worse writes a sub-solution back only if it is
+    not worse."""
     Q = _c(Q, np.int16)
     n = Q.shape[0]
     job_m = _c(np.atleast_2d(job_m), np.int32)
@@ -265,7 +297,10 @@ def run(Q, *, z, seed, iters, alpha, tenure, job_m, init_m, thr_init, thr, B, R,
                   aspiration=int(bool(aspiration)), W1=W[0], W2=W[1], W3=W[2],
                   jobs_per_sol=job_m.shape[1], job_m=_p(job_m).value, init_m=init_m,
                   nsw_init=thr_init.shape[0], thr_init=_p(thr_init).value,
-                  nsw=thr.shape[0], B=B, thr=_p(thr).value, R=R, mlp_W=None, scales=None)
+                  nsw=thr.shape[0], B=B, thr=_p(thr).value, R=R, mlp_W=None, scales=None,
+                  random_select=int(bool(random_select)), no_im=int(bool(no_im)),
+                  init_jacobi=int(bool(init_jacobi)), wb_not_worse=int(bool(wb_not_worse)),
+                  patience=int(patience))
     if mlp_W is not None:
         mlp_W = _c(mlp_W, np.uint16)
         scales = _c(scales, np.float32)
@@ -278,9 +313,9 @@ def run(Q, *, z, seed, iters, alpha, tenure, job_m, init_m, thr_init, thr, B, R,
     eb = np.zeros(1, np.int64)
     tr = np.zeros(max(iters, 1), np.int64)
     rc = lib().qbo_run(_p(Q), ctypes.byref(cfg), _p(X), _p(H), _p(E), _p(xb), _p(eb), _p(tr))
-    if rc != 0:
+    if rc < 0:
         raise ValueError("oracle run rejected its configuration")
-    return dict(X=X, H=H, E=E, xbest=xb, ebest=int(eb[0]), trace=tr[:iters])
+    return dict(X=X, H=H, E=E, xbest=xb, ebest=int(eb[0]), trace=tr[:rc], iters_run=int(rc))
 
 
 # --------------------------------------------------------------------------- learned selector

@@ -380,6 +380,13 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
 int qbo_mutate(int n, uint8_t *x, const int64_t *K, const uint8_t *inU, int t, int p,
                uint64_t seed, uint8_t *flip)
 {
+    return qbo_mutate2(n, x, K, K, inU, t, p, seed, flip);
+}
+
+int qbo_mutate2(int n, uint8_t *x, const int64_t *Korder, const int64_t *Kprob, const uint8_t *inU, int t,
+                int p, uint64_t seed, uint8_t *flip)
+{
+    const int64_t *K = Kprob;
     int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int nc = 0;
     for (int j = 0; j < n; ++j) {
@@ -389,7 +396,7 @@ int qbo_mutate(int n, uint8_t *x, const int64_t *K, const uint8_t *inU, int t, i
     double r = qbo_mutation_rate(t);
     int k = (int)floor((double)nc * r);
     if (k > nc) k = nc;
-    g_sort_keys = K;
+    g_sort_keys = Korder;
     qsort(cand, (size_t)nc, sizeof(int32_t), cmp_key_desc_index_asc);
     int64_t klo = K[0], khi = K[0];
     for (int j = 1; j < n; ++j) {
@@ -416,6 +423,19 @@ int qbo_mutate(int n, uint8_t *x, const int64_t *K, const uint8_t *inU, int t, i
     return k;
 }
 
+/* Reading for the ablation without the control parameters (No_SM, the
+ * Discussion section): every place where the method ranks variables by A
+ * ranks them by a fresh uniform random key instead, one 32-bit Philox word
+ * per variable and iteration (stream tag 4), and the mutation flips each of
+ * its candidates with probability 1/2. */
+void qbo_random_keys(int n, int z, int t, uint64_t seed, int64_t *K)
+{
+    for (int p = 0; p < z; ++p)
+        for (int j = 0; j < n; ++j)
+            K[(int64_t)p * n + j] =
+                (int64_t)philox_word((uint32_t)(j >> 2), (uint32_t)t, (uint32_t)p, 4u << 28, seed, j & 3);
+}
+
 /* ------------------------------------------------------------------------ */
 uint16_t qbo_bf16_rne(float f);
 void qbo_features(int n, int z, const int16_t *Q, const int64_t *eta, const uint8_t *X, const int32_t *H,
@@ -432,13 +452,18 @@ static void best_update(int n, int z, const uint8_t *X, const int64_t *E,
         }
 }
 
-static void pick_and_write(int m, const int32_t *S, const uint8_t *Y, const int64_t *e, int R,
-                           uint8_t *x)
+/* Write-back (Alg. 3 line 7): the replica with the lowest e (lowest r on
+ * ties) replaces x_S -- unconditionally as in the listing, or, in the
+ * "only if not worse" variant, only when its e <= 0.  Returns 1 if written. */
+static int pick_and_write(int m, const int32_t *S, const uint8_t *Y, const int64_t *e, int R,
+                          int not_worse, uint8_t *x)
 {
     int rb = 0;
     for (int r = 1; r < R; ++r)
         if (e[r] < e[rb]) rb = r;
+    if (not_worse && e[rb] > 0) return 0;
     for (int a = 0; a < m; ++a) x[S[a]] = Y[(int64_t)rb * m + a];
+    return 1;
 }
 
 /* Alg. 2 with Call_IM_Solution_Set and Call_IM_Partial_Solution_Set (Alg. 3):
@@ -460,7 +485,15 @@ static void pick_and_write(int m, const int32_t *S, const uint8_t *Y, const int6
  *   Learned selection (cfg->mlp_W != NULL): the IM variables are the top
  *   MLP scores of the eight features instead of the top A; mutation still
  *   uses A.  G (gain of the last IM job that changed a variable) feeds
- *   feature 4. */
+ *   feature 4.
+ *   Variants: random_select (No_SM: random keys rank the IM variables and
+ *   order the mutation candidates, each flipped with probability 1/2);
+ *   no_im (No_IM: no sub-QUBOs, so every variable is a mutation candidate);
+ *   init_jacobi (all initial blocks of a solution extracted against the
+ *   same state and written back together, the concurrent option of the
+ *   initial pass); wb_not_worse (a sub-solution is written back only if its
+ *   e <= 0); patience (stall termination: stop once E_best has not improved
+ *   for that many consecutive iterations). */
 int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, int64_t *E,
             uint8_t *xbest, int64_t *ebest, int64_t *trace_best)
 {
@@ -474,7 +507,10 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
         if (tot > n) return -1;
     }
     const int learned = cfg->mlp_W != NULL;
+    if (learned && (cfg->random_select || cfg->no_im || cfg->wb_not_worse)) return -1;
     int64_t *eta = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *K0 = (int64_t *)calloc((size_t)n * z, sizeof(int64_t));
+    int64_t *KR = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * z);
     int32_t *T = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * z);
     int32_t *LF = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * z);
     int32_t *G = (int32_t *)calloc((size_t)n * z, sizeof(int32_t));
@@ -505,7 +541,7 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
     best_update(n, z, X, E, xbest, ebest);
     uint32_t inst = 0;
 
-    if (cfg->init_m > 0) {
+    if (cfg->init_m > 0 && !cfg->init_jacobi) {
         int m0 = cfg->init_m, L0 = n / m0;
         for (int l = 0; l < L0; ++l) {
             for (int a = 0; a < m0; ++a) S[a] = l * m0 + a;
@@ -514,28 +550,49 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
                 qbo_extract(n, Q, x, H + (int64_t)p * n, m0, S, Tq, c, F0, y0);
                 qbo_anneal(m0, Tq, F0, y0, cfg->nsw_init, cfg->B, cfg->thr_init, cfg->R,
                            cfg->seed, inst + (uint32_t)p, Y, e);
-                pick_and_write(m0, S, Y, e, cfg->R, x);
+                pick_and_write(m0, S, Y, e, cfg->R, cfg->wb_not_worse, x);
             }
             inst += (uint32_t)z;
             qbo_field(n, Q, z, X, H);
             qbo_energy(n, z, X, H, E);
             best_update(n, z, X, E, xbest, ebest);
         }
+    } else if (cfg->init_m > 0) {
+        /* the concurrent option: every block of solution p against the
+         * state before the pass, job (p, l) numbered p * L0 + l */
+        int m0 = cfg->init_m, L0 = n / m0;
+        memcpy(X0, X, (size_t)n * z);
+        for (int p = 0; p < z; ++p) {
+            for (int l = 0; l < L0; ++l) {
+                for (int a = 0; a < m0; ++a) S[a] = l * m0 + a;
+                qbo_extract(n, Q, X0 + (int64_t)p * n, H + (int64_t)p * n, m0, S, Tq, c, F0, y0);
+                qbo_anneal(m0, Tq, F0, y0, cfg->nsw_init, cfg->B, cfg->thr_init, cfg->R, cfg->seed,
+                           inst + (uint32_t)(p * L0 + l), Y, e);
+                pick_and_write(m0, S, Y, e, cfg->R, cfg->wb_not_worse, X + (int64_t)p * n);
+            }
+        }
+        inst += (uint32_t)(z * L0);
+        qbo_field(n, Q, z, X, H);
+        qbo_energy(n, z, X, H, E);
+        best_update(n, z, X, E, xbest, ebest);
     }
 
+    int t_run = 0, stall = 0;
     for (int t = 0; t < cfg->iters; ++t) {
+        const int64_t eprev = *ebest;
         for (int p = 0; p < z; ++p)
             qbo_tabu(n, Q, X + (int64_t)p * n, H + (int64_t)p * n, E + p, cfg->alpha,
                      cfg->tenure, cfg->aspiration, T + (int64_t)p * n, LF + (int64_t)p * n);
         best_update(n, z, X, E, xbest, ebest);
 
         qbo_keys(n, z, eta, X, T, cfg->W1, cfg->W2, cfg->W3, K);
+        if (cfg->random_select) qbo_random_keys(n, z, t, cfg->seed, KR);
         if (learned) {
             qbo_features(n, z, Q, eta, X, H, T, LF, G, cfg->alpha, cfg->scales, F);
             qbo_mlp_scores(n * z, cfg->mlp_W, F, NULL, KL);
         }
         for (int p = 0; p < z; ++p) {
-            qbo_order(n, (learned ? KL : K) + (int64_t)p * n, order);
+            qbo_order(n, (learned ? KL : cfg->random_select ? KR : K) + (int64_t)p * n, order);
             int off = 0;
             for (int q = 0; q < kj; ++q) {
                 int m = cfg->job_m[p * kj + q];
@@ -546,7 +603,7 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
             }
         }
         memcpy(X0, X, (size_t)n * z);
-        for (int p = 0; p < z; ++p) {
+        for (int p = 0; p < z && !cfg->no_im; ++p) {
             int off = 0;
             for (int q = 0; q < kj; ++q) {
                 int m = cfg->job_m[p * kj + q];
@@ -554,7 +611,10 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
                 qbo_extract(n, Q, X0 + (int64_t)p * n, H + (int64_t)p * n, m, Sq, Tq, c, F0, y0);
                 qbo_anneal(m, Tq, F0, y0, cfg->nsw, cfg->B, cfg->thr, cfg->R, cfg->seed,
                            inst + (uint32_t)(p * kj + q), Y, e);
-                pick_and_write(m, Sq, Y, e, cfg->R, X + (int64_t)p * n);
+                if (!pick_and_write(m, Sq, Y, e, cfg->R, cfg->wb_not_worse, X + (int64_t)p * n)) {
+                    off += m;
+                    continue;
+                }
                 /* last-improvement gain of every variable this job changed */
                 int rb = 0;
                 for (int r = 1; r < cfg->R; ++r)
@@ -567,26 +627,36 @@ int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, in
                 off += m;
             }
         }
-        inst += (uint32_t)(z * kj);
-        qbo_field(n, Q, z, X, H);
-        qbo_energy(n, z, X, H, E);
-        best_update(n, z, X, E, xbest, ebest);
+        if (!cfg->no_im) {
+            inst += (uint32_t)(z * kj);
+            qbo_field(n, Q, z, X, H);
+            qbo_energy(n, z, X, H, E);
+            best_update(n, z, X, E, xbest, ebest);
+        }
 
         for (int p = 0; p < z; ++p) {
             memset(inU, 0, (size_t)n);
             int tot = 0;
             for (int q = 0; q < kj; ++q) tot += cfg->job_m[p * kj + q];
-            for (int a = 0; a < tot; ++a) inU[S[(int64_t)p * n + a]] = 1;
-            qbo_mutate(n, X + (int64_t)p * n, K + (int64_t)p * n, inU, t, p, cfg->seed, flip);
+            if (!cfg->no_im)
+                for (int a = 0; a < tot; ++a) inU[S[(int64_t)p * n + a]] = 1;
+            if (cfg->random_select)
+                qbo_mutate2(n, X + (int64_t)p * n, KR + (int64_t)p * n, K0 + (int64_t)p * n, inU, t, p,
+                            cfg->seed, flip);
+            else
+                qbo_mutate(n, X + (int64_t)p * n, K + (int64_t)p * n, inU, t, p, cfg->seed, flip);
         }
         qbo_field(n, Q, z, X, H);
         qbo_energy(n, z, X, H, E);
         best_update(n, z, X, E, xbest, ebest);
         if (trace_best) trace_best[t] = *ebest;
+        t_run = t + 1;
+        stall = *ebest < eprev ? 0 : stall + 1;
+        if (cfg->patience > 0 && stall >= cfg->patience) break;
     }
-    free(eta); free(T); free(LF); free(G); free(K); free(KL); free(F); free(order); free(X0); free(S);
-    free(Tq); free(c); free(F0); free(y0); free(Y); free(e); free(inU); free(flip);
-    return 0;
+    free(eta); free(K0); free(KR); free(T); free(LF); free(G); free(K); free(KL); free(F); free(order); free(X0);
+    free(S); free(Tq); free(c); free(F0); free(y0); free(Y); free(e); free(inU); free(flip);
+    return t_run;
 }
 
 /* ======================================================================== */

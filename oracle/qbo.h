@@ -82,6 +82,13 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
  * writes flip[n] (1 where flipped).  Returns the number of candidates k. */
 int qbo_mutate(int n, uint8_t *x, const int64_t *K, const uint8_t *inU, int t, int p,
                uint64_t seed, uint8_t *flip);
+/* The same with the candidate order taken from Korder and the flip
+ * probabilities from the min-max of Kprob (qbo_mutate uses K for both). */
+int qbo_mutate2(int n, uint8_t *x, const int64_t *Korder, const int64_t *Kprob, const uint8_t *inU, int t,
+                int p, uint64_t seed, uint8_t *flip);
+/* Random keys of the ablation without control parameters (No_SM):
+ * K[p][j] = word (j mod 4) of Philox4x32-10 at counter (j/4, t, p, 4<<28). */
+void qbo_random_keys(int n, int z, int t, uint64_t seed, int64_t *K);
 
 /* Learned selector (see qbo.c). */
 uint16_t qbo_bf16_rne(float f);
@@ -110,10 +117,16 @@ typedef struct {
     int nsw; int B; const int32_t *thr; int R;
     const uint16_t *mlp_W;     /* NULL: plain selection; else the BF16 MLP picks the IM variables */
     const float *scales;       /* 7 feature scales (learned selection) */
+    int random_select;         /* ablation No_SM: random keys instead of the control parameters */
+    int no_im;                 /* ablation No_IM: no Ising-machine stage */
+    int init_jacobi;           /* initial pass: all blocks against the same state (else one after another) */
+    int wb_not_worse;          /* write a sub-solution back only if its energy change is <= 0 */
+    int patience;              /* > 0: stop after this many iterations without a better E_best */
 } qbo_run_cfg;
 
 /* Outputs: X,H,E final state; xbest[n], *ebest; trace_best[iters] = E_best
- * after each outer iteration (may be NULL). */
+ * after each outer iteration run (may be NULL).  Returns the number of outer
+ * iterations run, or -1 for an invalid configuration. */
 int qbo_run(const int16_t *Q, const qbo_run_cfg *cfg, uint8_t *X, int32_t *H, int64_t *E,
             uint8_t *xbest, int64_t *ebest, int64_t *trace_best);
 

@@ -268,13 +268,16 @@ __global__ void __launch_bounds__(256) k_writeback(int n, int R, const int32_t *
                                                    const int32_t *__restrict__ off, const int32_t *__restrict__ idx,
                                                    const uint8_t *__restrict__ Y, const int64_t *__restrict__ e,
                                                    const uint8_t *__restrict__ y0, uint8_t *__restrict__ X,
-                                                   int8_t *__restrict__ dX, int64_t *__restrict__ ebest)
+                                                   int8_t *__restrict__ dX, int64_t *__restrict__ ebest,
+                                                   int not_worse)
 {
     const int q = blockIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
     int rb = 0;
     for (int r = 1; r < R; ++r)
         if (e[(size_t)q * R + r] < e[(size_t)q * R + rb]) rb = r;
+    if (ebest && threadIdx.x == 0) ebest[q] = e[(size_t)q * R + rb];
+    if (not_worse && e[(size_t)q * R + rb] > 0) return;   // x_S and dX stay as they are
     const uint8_t *Yr = Y + (size_t)base * R + (size_t)rb * m;
     for (int a = threadIdx.x; a < m; a += 256) {
         const int j = idx[base + a];
@@ -282,7 +285,6 @@ __global__ void __launch_bounds__(256) k_writeback(int n, int R, const int32_t *
         X[(int64_t)p * n + j] = y;
         dX[(int64_t)p * n + j] = (int8_t)((int)y - (int)y0[base + a]);
     }
-    if (ebest && threadIdx.x == 0) ebest[q] = e[(size_t)q * R + rb];
 }
 
 }  // namespace
@@ -294,6 +296,7 @@ extern "C" qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, co
     if (b->n != P->n) return QB_E_ARG;
     if (P->sparse) return QB_E_UNSUPPORTED;
     if ((uintptr_t)tile_d & 15) return QB_E_ARG;
+    if (b->J == 0) return QB_OK;
     hipStream_t s = qb_stream(stream);
     if (P->int8_ok)
         k_extract<int8_t><<<b->J, 256, 0, s>>>(P->Q, P->Q8, P->n, b->sol_d, b->off_d, b->tile_off_d, b->idx_d,
@@ -342,11 +345,12 @@ extern "C" qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile
 
 extern "C" qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d,
                                  const uint8_t *y0_d, uint8_t *X_d, int8_t *dX_d, int64_t *ebest_job_d,
-                                 void *stream)
+                                 int32_t flags, void *stream)
 {
-    if (!b || R < 1 || R > 16 || !Y_d || !e_d || !y0_d || !X_d || !dX_d) return QB_E_ARG;
+    if (!b || R < 1 || R > 16 || !Y_d || !e_d || !y0_d || !X_d || !dX_d || (flags & ~1)) return QB_E_ARG;
+    if (b->J == 0) return QB_OK;
     k_writeback<<<b->J, 256, 0, qb_stream(stream)>>>(b->n, R, b->sol_d, b->off_d, b->idx_d, Y_d, e_d, y0_d, X_d,
-                                                     dX_d, ebest_job_d);
+                                                     dX_d, ebest_job_d, flags & 1);
     QB_LAUNCH_CHECK();
     return QB_OK;
 }

@@ -233,6 +233,7 @@ extern "C" qb_status qb_extract_ell(qb_problem P, qb_batch b, const uint8_t *X_d
     if (b->n != P->n) return QB_E_ARG;
     if (!P->sparse) return QB_E_UNSUPPORTED;
     if ((uintptr_t)tile_d & 15) return QB_E_ARG;
+    if (b->J == 0) return QB_OK;
     k_extract_ell<<<b->J, 256, 0, qb_stream(stream)>>>(P->ell, P->ellw, P->ecnt, P->diag, P->n, b->sol_d, b->off_d,
                                                        b->idx_d, X_d, H_d, tile_d, c_d, F0_d, y0_d);
     QB_LAUNCH_CHECK();

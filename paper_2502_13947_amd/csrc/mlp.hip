@@ -316,6 +316,7 @@ extern "C" qb_status qb_trace(qb_batch b, int32_t R, const uint16_t *F_d, const 
 {
     if (!b || R < 1 || R > 16 || !F_d || !Y_d || !e_d || !y0_d || !outF_d || !outL_d) return QB_E_ARG;
     if (((uintptr_t)F_d & 15) || ((uintptr_t)outF_d & 15)) return QB_E_ARG;
+    if (b->J == 0) return QB_OK;
     k_trace<<<b->J, 256, 0, qb_stream(stream)>>>(b->n, R, b->sol_d, b->off_d, b->idx_d, F_d, Y_d, e_d, y0_d, outF_d,
                                                  outL_d);
     QB_LAUNCH_CHECK();
@@ -326,6 +327,7 @@ extern "C" qb_status qb_gain_update(qb_batch b, int32_t R, const uint8_t *Y_d, c
                                    const uint8_t *y0_d, int32_t *G_d, void *stream)
 {
     if (!b || R < 1 || R > 16 || !Y_d || !e_d || !y0_d || !G_d) return QB_E_ARG;
+    if (b->J == 0) return QB_OK;
     k_gain<<<b->J, 256, 0, qb_stream(stream)>>>(b->n, R, b->sol_d, b->off_d, b->idx_d, Y_d, e_d, y0_d, G_d);
     QB_LAUNCH_CHECK();
     return QB_OK;

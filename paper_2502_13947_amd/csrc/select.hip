@@ -50,6 +50,20 @@ __global__ void __launch_bounds__(256) k_keys(int n, int z, const int64_t *__res
     }
 }
 
+// Random keys of the ablation without control parameters: one Philox word
+// per (solution, variable), stream tag 4 in counter word 3.
+__global__ void k_random_keys(int n, int t, uint32_t k0, uint32_t k1, int64_t *__restrict__ K)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;   // group of 4 variables
+    const int p = blockIdx.y;
+    if (4 * g >= n) return;
+    const uint4 o = qb_philox(make_uint4((uint32_t)g, (uint32_t)t, (uint32_t)p, 4u << 28), k0, k1);
+    int64_t *row = K + (int64_t)p * n;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        if (4 * g + w < n) row[4 * g + w] = (int64_t)qb_word(o, w);
+}
+
 // Bitonic sort of (K desc, index asc) packed into one 64-bit key per element.
 __global__ void __launch_bounds__(1024) k_rank(int n, int npad, const int64_t *__restrict__ K,
                                                int32_t *__restrict__ order)
@@ -346,6 +360,15 @@ extern "C" qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const 
     return QB_OK;
 }
 
+extern "C" qb_status qb_random_keys(int32_t n, int32_t z, int32_t t, uint64_t seed, int64_t *K_d, void *stream)
+{
+    if (n < 1 || z < 1 || z > 65535 || t < 0 || !K_d) return QB_E_ARG;
+    dim3 grid(((n + 3) / 4 + 255) / 256, z);
+    k_random_keys<<<grid, 256, 0, qb_stream(stream)>>>(n, t, (uint32_t)seed, (uint32_t)(seed >> 32), K_d);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
 extern "C" qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *order_d, void *stream)
 {
     if (n < 1 || n > 65535 || z < 1 || !K_d || !order_d) return QB_E_ARG;
@@ -394,7 +417,7 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
                                     const int32_t *sol_h, const int32_t *size_h,
                                     const int32_t *rank0_h)
 {
-    if (!out || n < 1 || n > 65535 || z < 1 || J < 1 || !sol_h || !size_h) return QB_E_ARG;
+    if (!out || n < 1 || n > 65535 || z < 1 || J < 0 || (J > 0 && (!sol_h || !size_h))) return QB_E_ARG;
     *out = nullptr;
     std::vector<int64_t> per_sol(z, 0);
     for (int q = 0; q < J; ++q) {
@@ -414,7 +437,7 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
     b->off_h.assign(J + 1, 0);
     for (int q = 0; q < J; ++q) b->off_h[q + 1] = b->off_h[q] + size_h[q];
     b->total = b->off_h[J];
-    b->m_max = *std::max_element(size_h, size_h + J);
+    b->m_max = J ? *std::max_element(size_h, size_h + J) : 0;
     b->rank0_h.assign(J, 0);
     {
         int cur = -1, r = 0;
@@ -454,7 +477,8 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
     qb_status rc = QB_OK;
     auto up = [&](void **dst, const void *src, size_t bytes) {
         if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
-        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+        if (hipMemset(*dst, 0, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+        return bytes == 0 || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
     };
     if (!up((void **)&b->sol_d, b->sol_h.data(), sizeof(int32_t) * J) ||
         !up((void **)&b->off_d, b->off_h.data(), sizeof(int32_t) * (J + 1)) ||
@@ -529,6 +553,7 @@ extern "C" qb_status qb_batch_copy_idx(qb_batch b, int32_t *idx_d, void *stream)
 extern "C" qb_status qb_select(qb_batch b, const int32_t *order_d, void *stream)
 {
     if (!b || !order_d) return QB_E_ARG;
+    if (b->J == 0) return QB_OK;
     k_select<<<b->J, 1024, 0, qb_stream(stream)>>>(b->n, b->sol_d, b->off_d, b->rank0_d, order_d,
                                                   b->idx_d);
     QB_LAUNCH_CHECK();

@@ -74,7 +74,8 @@ SIGNATURES = {
     "qb_extract_ell": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "qb_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _U64, _U32, _P, _P, _P]),
     "qb_threshold_table": (_I32, [_I32, _I32, _F64, _F64, _P]),
-    "qb_writeback": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_writeback": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
+    "qb_random_keys": (_I32, [_I32, _I32, _I32, _U64, _P, _P]),
     "qb_rankk": (_I32, [_P, _I32, _P, _P, _I32, _P]),
     "qb_zero": (_I32, [_P, _SZ, _P]),
     "qb_mutate": (_I32, [_P, _P, _P, _F64, _I32, _U64, _P, _P, _P, _P]),
@@ -194,7 +195,8 @@ class Batch:
         self.rank0 = None if rank0 is None else np.ascontiguousarray(rank0, np.int32)
         h = ctypes.c_void_p()
         _chk(lib().qb_batch_create(ctypes.byref(h), n, z, len(self.sol),
-                                   self.sol.ctypes.data, self.sizes.ctypes.data,
+                                   self.sol.ctypes.data if len(self.sol) else None,
+                                   self.sizes.ctypes.data if len(self.sizes) else None,
                                    None if self.rank0 is None else self.rank0.ctypes.data),
              "qb_batch_create")
         self.h = h
@@ -300,9 +302,17 @@ def threshold_table(nsw, B, tmax, tmin) -> np.ndarray:
     return thr
 
 
-def writeback(b: Batch, R, Y, e, y0, X, dX, ebest_job=None, stream=None):
+WB_NOT_WORSE = 1
+
+
+def writeback(b: Batch, R, Y, e, y0, X, dX, ebest_job=None, flags=0, stream=None):
     _chk(lib().qb_writeback(b.h, R, _ptr(Y), _ptr(e), _ptr(y0), _ptr(X), _ptr(dX), _ptr(ebest_job),
-                            _stream(stream)), "qb_writeback")
+                            int(flags), _stream(stream)), "qb_writeback")
+
+
+def random_keys(t, seed, K, stream=None):
+    z, n = K.shape
+    _chk(lib().qb_random_keys(n, z, int(t), int(seed), _ptr(K), _stream(stream)), "qb_random_keys")
 
 
 def rankk(P: Problem, dX, H, variant=0, stream=None):

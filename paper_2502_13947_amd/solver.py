@@ -39,12 +39,25 @@ def feature_scales(P: "qb.Problem", alpha: int, z: int) -> np.ndarray:
 
 class Solver:
     """The outer loop on one problem: dense (``Q``, int16 [n, n] on the
-    device) or sparse (``csr`` = (rowptr, col, val) with ``device``)."""
+    device) or sparse (``csr`` = (rowptr, col, val) with ``device``).
+
+    Variants of the method (all off by default, i.e. the paper's method):
+    ``random_select`` and ``no_im`` are the two ablations of the Discussion
+    section (sub-QUBO variables and mutation candidates ranked by random keys,
+    each candidate flipped with probability 1/2; no Ising-machine stage, so
+    every variable is a mutation candidate); ``init_jacobi`` runs the initial
+    pass's blocks concurrently against one state; ``wb_not_worse`` writes a
+    sub-solution back only if its energy change is <= 0.  ``run(iters,
+    patience)`` stops early once E_best has not improved for ``patience``
+    iterations."""
 
     def __init__(self, Q: torch.Tensor = None, *, z: int, seed: int, job_m, init_m: int, thr_init, thr,
                  B: int, R: int, alpha: int, tenure: int, aspiration: bool = True, W=(2, 2, 1),
                  rankk_variant: int = 0, mlp_W=None, trace_capacity: int = 0, csr=None, device=None,
-                 anneal_rw: int = 0):
+                 anneal_rw: int = 0, random_select: bool = False, no_im: bool = False,
+                 init_jacobi: bool = False, wb_not_worse: bool = False):
+        if mlp_W is not None and (random_select or no_im or wb_not_worse):
+            raise ValueError("the learned selector runs with the plain method only")
         dev = Q.device if csr is None else torch.device(device)
         self.dev = dev
         self.stream = torch.cuda.Stream(device=dev)
@@ -54,6 +67,9 @@ class Solver:
             self.P = qb.Problem.from_csr(*csr, device=dev, stream=self.stream)
         self.sparse = self.P.sparse
         self.anneal_rw = anneal_rw
+        self.random_select, self.no_im = bool(random_select), bool(no_im)
+        self.init_jacobi = bool(init_jacobi)
+        self.wb_flags = qb.WB_NOT_WORSE if wb_not_worse else 0
         n = self.n = self.P.n
         self.z, self.seed, self.B, self.R = z, int(seed), B, R
         self.alpha, self.tenure, self.aspiration, self.W = alpha, tenure, aspiration, W
@@ -85,9 +101,21 @@ class Solver:
         self.e = torch.zeros(b.J * R, dtype=torch.int64, device=dev)
         self.thr = torch.as_tensor(np.ascontiguousarray(thr, np.int32), device=dev)
         self.init_m = init_m
+        if self.random_select:
+            self.KR = torch.zeros((z, n), dtype=torch.int64, device=dev)
+            self.orderR = torch.zeros((z, n), dtype=torch.int32, device=dev)
+            self.K0 = torch.zeros((z, n), dtype=torch.int64, device=dev)   # equal keys: P = 1/2
+        if self.no_im:
+            self.empty = qb.Batch(n, z, np.zeros(0, np.int32), np.zeros(0, np.int32))
         if init_m:
             self.thr_init = torch.as_tensor(np.ascontiguousarray(thr_init, np.int32), device=dev)
-            self.ib = qb.Batch(n, z, np.arange(z, dtype=np.int32), np.full(z, init_m, np.int32))
+            L0 = n // init_m
+            if self.init_jacobi:
+                # every block of every solution in one batch, jobs solution-major
+                self.ib = qb.Batch(n, z, np.repeat(np.arange(z, dtype=np.int32), L0),
+                                   np.full(z * L0, init_m, np.int32))
+            else:
+                self.ib = qb.Batch(n, z, np.arange(z, dtype=np.int32), np.full(z, init_m, np.int32))
             ib = self.ib
             self.itiles = torch.zeros(max(tile_len(ib), 16), dtype=self.tile_dtype, device=dev)
             self.iF0 = torch.zeros(ib.total, dtype=torch.int32, device=dev)
@@ -140,7 +168,18 @@ class Solver:
         with torch.cuda.stream(s):
             self.ebest.fill_(2**63 - 1)
         qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
-        if self.init_m:
+        if self.init_m and self.init_jacobi:
+            m0 = self.init_m
+            L0 = n // m0
+            self.ib.set_idx(np.tile(np.arange(L0 * m0, dtype=np.int32), z), stream=s)
+            self._extract(self.ib, self.itiles, self.iF0, self.iy0, s)
+            self._anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.iY, self.ie, s)
+            self.inst += z * L0
+            qb.zero(self.dX, stream=s)
+            qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, flags=self.wb_flags,
+                         stream=s)
+            self._apply(stream=s)
+        elif self.init_m:
             m0 = self.init_m
             for l in range(n // m0):
                 self.ib.set_idx(np.tile(np.arange(l * m0, (l + 1) * m0, dtype=np.int32), z), stream=s)
@@ -148,7 +187,8 @@ class Solver:
                 self._anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.iY, self.ie, s)
                 self.inst += z
                 qb.zero(self.dX, stream=s)
-                qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, stream=s)
+                qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, flags=self.wb_flags,
+                             stream=s)
                 self._apply(stream=s)
 
     def autotune(self, reps=3, density=0.3, seed=0):
@@ -206,36 +246,61 @@ class Solver:
             qb.mlp_score(self.F, self.mlp_W, self.KL, stream=s)
             qb.rank(self.KL, self.orderL, stream=s)
             qb.select(b, self.orderL, stream=s)
+        elif self.random_select:
+            qb.random_keys(self.t, self.seed, self.KR, stream=s)
+            qb.rank(self.KR, self.orderR, stream=s)
+            qb.select(b, self.orderR, stream=s)
         else:
             qb.select(b, self.order, stream=s)
-        mark("extract")
-        self._extract(b, self.tiles, self.F0, self.y0, s)
-        mark("anneal")
-        self._anneal(b, self.tiles, self.F0, self.y0, self.thr, self.Y, self.e, s)
-        mark("apply")
-        self.inst += b.J
-        qb.gain_update(b, self.R, self.Y, self.e, self.y0, self.G, stream=s)
-        if self.tracing and self.trN + b.total <= self.trF.shape[0]:
-            qb.trace(b, self.R, self.F, self.Y, self.e, self.y0, self.trF[self.trN:], self.trL[self.trN:],
-                     stream=s)
-            self.trN += b.total
-        qb.zero(self.dX, stream=s)
-        qb.writeback(b, self.R, self.Y, self.e, self.y0, self.X, self.dX, stream=s)
-        self._apply(stream=s)
+        if not self.no_im:
+            mark("extract")
+            self._extract(b, self.tiles, self.F0, self.y0, s)
+            mark("anneal")
+            self._anneal(b, self.tiles, self.F0, self.y0, self.thr, self.Y, self.e, s)
+            mark("apply")
+            self.inst += b.J
+            if self.learned or self.tracing:
+                qb.gain_update(b, self.R, self.Y, self.e, self.y0, self.G, stream=s)
+            if self.tracing and self.trN + b.total <= self.trF.shape[0]:
+                qb.trace(b, self.R, self.F, self.Y, self.e, self.y0, self.trF[self.trN:], self.trL[self.trN:],
+                         stream=s)
+                self.trN += b.total
+            qb.zero(self.dX, stream=s)
+            qb.writeback(b, self.R, self.Y, self.e, self.y0, self.X, self.dX, flags=self.wb_flags, stream=s)
+            self._apply(stream=s)
         mark("mutate")
         qb.zero(self.dX, stream=s)
-        qb.mutate(b, self.K, self.order, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
-                  self.kcount, stream=s)
+        mb = self.empty if self.no_im else b
+        if self.random_select:
+            qb.mutate(mb, self.K0, self.orderR, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
+                      self.kcount, stream=s)
+        else:
+            qb.mutate(mb, self.K, self.order, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
+                      self.kcount, stream=s)
         self._apply(stream=s)
         mark("end")
         self.t += 1
 
-    def run(self, iters: int):
+    def run(self, iters: int, patience: int = 0):
+        """init() and up to ``iters`` outer iterations; E_best after each.
+        With ``patience`` > 0 the loop stops once E_best has not improved for
+        that many consecutive iterations (read back after every iteration)."""
         self.init()
         trace = []
         with torch.cuda.stream(self.stream):
-            for _ in range(iters):
-                self.iterate()
-                trace.append(self.ebest.clone())
+            if patience <= 0:
+                for _ in range(iters):
+                    self.iterate()
+                    trace.append(self.ebest.clone())
+            else:
+                best, stall = int(self.ebest.item()), 0
+                for _ in range(iters):
+                    self.iterate()
+                    eb = int(self.ebest.item())
+                    trace.append(eb)
+                    stall = 0 if eb < best else stall + 1
+                    best = eb   # E_best never increases
+                    if stall >= patience:
+                        break
         self.stream.synchronize()
-        return [int(v.item()) for v in trace]
+        return [int(v.item()) if torch.is_tensor(v) else v for v in trace]

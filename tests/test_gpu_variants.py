@@ -1,0 +1,166 @@
+"""GPU-vs-oracle parity of the method's variants (bit-exact): the two
+ablations of the Discussion section (random selection instead of the control
+parameters; no Ising-machine stage), the concurrent initial pass, the "only
+if not worse" write-back and stall termination."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_13947_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2502_13947_amd import qb
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    qb.lib()
+
+
+def qb():
+    from paper_2502_13947_amd import qb as m
+    return m
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("n,z,t", [(1, 1, 0), (13, 3, 5), (5000, 4, 29)])
+def test_random_keys_bit_exact(n, z, t):
+    seed = 0xABCDEF0123
+    K = torch.zeros((z, n), dtype=torch.int64, device=DEV)
+    qb().random_keys(t, seed, K)
+    assert (K.cpu().numpy() == oracle.random_keys(n, z, t, seed)).all()
+
+
+def test_empty_batch_is_a_no_op_and_mutates_over_all_variables():
+    n, z = 700, 3
+    Q = inputs.dense_qubo(n, 0.3, 1)
+    P = qb().Problem(dev(Q))
+    b = qb().Batch(n, z, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert b.J == 0 and b.total == 0
+    X = inputs.random_solutions(z, n, 2)
+    H = oracle.field(Q, X)
+    Xd, Hd = dev(X), dev(H)
+    t16 = torch.zeros(16, dtype=torch.int8, device=DEV)
+    i16 = torch.zeros(16, dtype=torch.int32, device=DEV)
+    u16 = torch.zeros(16, dtype=torch.uint8, device=DEV)
+    e16 = torch.zeros(16, dtype=torch.int64, device=DEV)
+    dX = torch.zeros((z, n), dtype=torch.int8, device=DEV)
+    qb().select(b, torch.zeros((z, n), dtype=torch.int32, device=DEV))
+    qb().extract(P, b, Xd, Hd, t16, i16, u16)
+    thr = dev(oracle.threshold_table(3, 10, 50.0, 1.0))
+    qb().anneal(b, t16, i16, u16, thr, 1, 1, 0, u16, e16, 10)
+    qb().writeback(b, 1, u16, e16, u16, Xd, dX)
+    assert (Xd.cpu().numpy() == X).all() and (dX == 0).all()
+    T = np.random.default_rng(3).integers(0, 5, size=(z, n)).astype(np.int32)
+    K = torch.zeros((z, n), dtype=torch.int64, device=DEV)
+    qb().keys(P, Xd, dev(T), K, (2, 2, 1), t_bound=10)
+    order = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().rank(K, order)
+    kc = torch.zeros(z, dtype=torch.int32, device=DEV)
+    qb().mutate(b, K, order, qb().mutation_rate(2), 2, 7, Xd, dX, kc)
+    Kh = K.cpu().numpy()
+    for p in range(z):
+        xo, _, k = oracle.mutate(X[p], Kh[p], np.zeros(n, np.uint8), 2, p, 7)
+        assert int(kc[p].item()) == k == int(np.floor(n * oracle.mutation_rate(2)))
+        assert (Xd[p].cpu().numpy() == xo).all()
+
+
+def test_write_back_only_if_not_worse():
+    n, z, R = 900, 3, 3
+    Q = inputs.dense_qubo(n, 0.5, 4)
+    X = inputs.random_solutions(z, n, 5)
+    sol, off, idx = inputs.random_index_sets(z, n, np.tile([100, 200], (z, 1)), 6)
+    b = qb().Batch(n, z, sol, np.tile([100, 200], z))
+    b.set_idx(idx)
+    rng = np.random.default_rng(7)
+    Y = rng.integers(0, 2, size=b.total * R).astype(np.uint8)
+    e = rng.integers(-50, 50, size=b.J * R).astype(np.int64)
+    e[0:R] = [5, 3, 9]                         # job 0: best replica is worse -> kept
+    e[R:2 * R] = [4, 0, 7]                     # job 1: best is 0 -> written
+    y0 = np.concatenate([X[sol[q], idx[off[q]:off[q + 1]]] for q in range(b.J)]).astype(np.uint8)
+    Xd = dev(X)
+    dX = torch.zeros((z, n), dtype=torch.int8, device=DEV)
+    eb = torch.zeros(b.J, dtype=torch.int64, device=DEV)
+    qb().writeback(b, R, dev(Y), dev(e), dev(y0), Xd, dX, eb, flags=qb().WB_NOT_WORSE)
+    Xo = X.copy()
+    for q in range(b.J):
+        es = e[q * R:(q + 1) * R]
+        rb = int(np.argmin(es))
+        assert int(eb[q].item()) == es[rb]
+        if es[rb] > 0:
+            continue
+        m = off[q + 1] - off[q]
+        Xo[sol[q], idx[off[q]:off[q + 1]]] = Y[off[q] * R + rb * m: off[q] * R + (rb + 1) * m]
+    assert (Xd.cpu().numpy() == Xo).all()
+    assert (dX.cpu().numpy() == (Xo.astype(np.int16) - X).astype(np.int8)).all()
+
+
+def _kw(n, P, z, job_m, R, nsw=20, init_m=128, B=10):
+    sg = max(P.sigma, 1.0)
+    thr = oracle.threshold_table(nsw, B, 0.25 * sg, 0.002 * sg)
+    return dict(z=z, seed=5, job_m=job_m, init_m=init_m, thr_init=thr, thr=thr, B=B, R=R,
+                alpha=5 * n, tenure=max(1, n // 150))
+
+
+VARIANTS = [
+    dict(random_select=True),
+    dict(no_im=True),
+    dict(init_jacobi=True),
+    dict(wb_not_worse=True),
+    dict(random_select=True, init_jacobi=True, wb_not_worse=True),
+]
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: "+".join(sorted(v)))
+@pytest.mark.parametrize("sparse", [False, True])
+def test_variant_trajectory_vs_oracle(variant, sparse):
+    from paper_2502_13947_amd.solver import Solver
+    say("variant", variant, "sparse" if sparse else "dense")
+    z, iters, R = 4, 3, 2
+    if sparse:
+        rp, col, val = inputs.torus_graph_qubo(20, 30, 4.0, 41)
+        n = 600
+        Q = inputs.csr_to_dense(n, rp, col, val)
+        P = qb().Problem.from_csr(rp, col, val.astype(np.int16), device=DEV)
+    else:
+        n = 600
+        Q = inputs.dense_qubo(n, 0.1, 42)
+        P = qb().Problem(dev(Q))
+    job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
+    kw = _kw(n, P, z, job_m, R)
+    if sparse:
+        S = Solver(csr=(rp, col, val.astype(np.int16)), device=DEV, **kw, **variant)
+    else:
+        S = Solver(dev(Q), **kw, **variant)
+    trace = S.run(iters)
+    ref = oracle.run(Q, iters=iters, **kw, **variant)
+    assert trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all()
+    assert (S.H.cpu().numpy() == ref["H"]).all()
+    assert (S.E.cpu().numpy() == ref["E"]).all()
+    assert int(S.ebest.item()) == ref["ebest"] and (S.xbest.cpu().numpy() == ref["xbest"]).all()
+
+
+@pytest.mark.parametrize("patience", [1, 2])
+def test_stall_termination_vs_oracle(patience):
+    from paper_2502_13947_amd.solver import Solver
+    n, z, R = 400, 3, 1
+    Q = inputs.dense_qubo(n, 0.1, 43)
+    P = qb().Problem(dev(Q))
+    kw = _kw(n, P, z, np.tile([64], (z, 1)).astype(np.int32), R, init_m=0)
+    S = Solver(dev(Q), **kw)
+    trace = S.run(25, patience=patience)
+    ref = oracle.run(Q, iters=25, patience=patience, **kw)
+    assert len(trace) == ref["iters_run"] and trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all()

@@ -503,3 +503,138 @@ def test_features_closed_forms():
     assert F[:, :, 5].max() == 1.0
     assert F[0, 4, 3] == 1.0                       # never flipped: age = alpha
     assert F[0, 2, 1] == float(Q[2, 2])
+
+
+# --------------------------------------------------------------------------- method variants
+def test_random_keys_are_the_philox_stream_four_words():
+    n, z, t, seed = 13, 3, 5, 0x1234_5678_9ABC
+    K = oracle.random_keys(n, z, t, seed)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for p in range(z):
+        for j in range(n):
+            w = oracle.philox([j >> 2, t, p, 4 << 28], key)[j & 3]
+            assert K[p, j] == int(w)
+    assert K.min() >= 0 and K.max() < 2**32
+
+
+def test_mutation_with_separate_order_and_probability_keys():
+    n, t, p, seed = 300, 0, 2, 17
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 2, n).astype(np.uint8)
+    inU = (rng.random(n) < 0.2).astype(np.uint8)
+    Ko = rng.integers(0, 2**32, n).astype(np.int64)
+    x1, flip, k = oracle.mutate2(x, Ko, np.zeros(n, np.int64), inU, t, p, seed)
+    cand = np.flatnonzero(inU == 0)
+    assert k == math.floor(len(cand) * 0.6)
+    top = cand[np.lexsort((cand, -Ko[cand]))][:k]
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    want = np.zeros(n, np.uint8)
+    for j in top:                                   # equal Kprob: P = 2^31
+        want[j] = oracle.philox([j >> 2, t, p, 2 << 28], key)[j & 3] < 2**31
+    assert (flip == want).all() and (x1 ^ x == flip).all()
+    # the one-key form is the two-key form with the same keys
+    xa, fa, ka = oracle.mutate(x, Ko, inU, t, p, seed)
+    xb, fb, kb = oracle.mutate2(x, Ko, Ko, inU, t, p, seed)
+    assert ka == kb and (fa == fb).all()
+
+
+def _variant_run(Q, **kw):
+    n = Q.shape[0]
+    thr = oracle.threshold_table(12, 8, 40.0, 0.5)
+    z = kw.get("z", 3)
+    base = dict(z=z, seed=4, iters=3, alpha=4 * n, tenure=2, job_m=np.full((z, 2), 6, np.int32),
+                init_m=8, thr_init=thr, thr=thr, B=8, R=2)
+    base.update(kw)
+    return oracle.run(Q, **base)
+
+
+def test_jacobi_initial_pass_equals_sequential_pass_on_decoupled_blocks():
+    # block-diagonal Q on the pass's blocks: no block sees another's result,
+    # so the concurrent and the sequential passes coincide (one solution, so
+    # both number their jobs 0, 1, 2, ...)
+    n, m0 = 24, 8
+    Q = np.zeros((n, n), np.int16)
+    for b in range(n // m0):
+        s = slice(b * m0, (b + 1) * m0)
+        Q[s, s] = rand_sym(m0, 40 + b, -20, 20)
+    kw = dict(z=1, job_m=np.full((1, 1), 6, np.int32), iters=0, init_m=m0)
+    a = _variant_run(Q, **kw)
+    j = _variant_run(Q, init_jacobi=True, **kw)
+    assert (a["X"] == j["X"]).all() and a["ebest"] == j["ebest"]
+    # coupled blocks: the two passes differ in general, both stay consistent
+    Qc = rand_sym(n, 50, -20, 20)
+    jc = _variant_run(Qc, init_jacobi=True, z=3, iters=2)
+    assert (jc["H"] == oracle.field(Qc, jc["X"])).all()
+
+
+def test_not_worse_write_back_never_raises_the_energy_of_the_pass():
+    n = 40
+    Q = rand_sym(n, 60, -30, 30)
+    hot = oracle.threshold_table(3, 8, 1e6, 1e6)          # accepts every move: odd sweeps flip all
+    z, seed = 4, 8
+    X0 = oracle.init_x(n, z, seed)
+    E0 = oracle.energy(X0, oracle.field(Q, X0))
+    kw = dict(z=z, seed=seed, iters=0, init_m=8, thr_init=hot, thr=hot)
+    guarded = _variant_run(Q, wb_not_worse=True, **kw)
+    assert (guarded["E"] <= E0).all()
+    plain = _variant_run(Q, **kw)
+    assert (plain["E"] > E0).any()                        # the guard is what holds it
+
+
+def test_stall_termination_stops_after_patience_flat_iterations():
+    n = 30
+    Q = rand_sym(n, 70, -30, 30)
+    full = _variant_run(Q, iters=12)
+    for patience in (1, 2, 3):
+        r = _variant_run(Q, iters=12, patience=patience)
+        tr = list(r["trace"])
+        assert tr == list(full["trace"][:len(tr)])        # same trajectory up to the stop
+        eb0 = _variant_run(Q, iters=0)["ebest"]
+        prev, stall, stop = eb0, 0, 12
+        for i, e in enumerate(full["trace"]):
+            stall = 0 if e < prev else stall + 1
+            prev = e
+            if stall >= patience:
+                stop = i + 1
+                break
+        assert r["iters_run"] == stop == len(tr)
+
+
+def test_no_im_run_is_tabu_then_mutation_over_all_variables():
+    n, z, seed = 25, 2, 11
+    Q = rand_sym(n, 80, -30, 30)
+    r = _variant_run(Q, z=z, seed=seed, iters=1, init_m=0, no_im=True, job_m=np.full((z, 1), 5, np.int32))
+    X = oracle.init_x(n, z, seed)
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    T = np.zeros((z, n), np.int32)
+    for p in range(z):
+        X[p], H[p], E[p], T[p], _ = oracle.tabu(Q, X[p], H[p], int(E[p]), 4 * n, 2, True)
+    K = oracle.keys(oracle.eta(Q), X, T)
+    for p in range(z):
+        X[p], _, _ = oracle.mutate(X[p], K[p], np.zeros(n, np.uint8), 0, p, seed)
+    assert (r["X"] == X).all()
+
+
+def test_random_selection_run_is_the_plain_run_with_random_keys():
+    n, z, seed, m, R = 25, 2, 12, 6, 2
+    Q = rand_sym(n, 90, -30, 30)
+    thr = oracle.threshold_table(12, 8, 40.0, 0.5)
+    r = _variant_run(Q, z=z, seed=seed, iters=1, init_m=0, random_select=True, R=R,
+                     job_m=np.full((z, 1), m, np.int32))
+    X = oracle.init_x(n, z, seed)
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    for p in range(z):
+        X[p], H[p], E[p], _, _ = oracle.tabu(Q, X[p], H[p], int(E[p]), 4 * n, 2, True)
+    KR = oracle.random_keys(n, z, 0, seed)
+    X0 = X.copy()
+    for p in range(z):
+        S = np.sort(oracle.order(KR[p])[:m]).astype(np.int32)
+        Tq, c, F0, y0 = oracle.extract(Q, X0[p], H[p], S)
+        Y, e = oracle.anneal(Tq, F0, y0, thr, R, seed, p, 8)
+        X[p, S] = Y[int(np.argmin(e))]
+        inU = np.zeros(n, np.uint8)
+        inU[S] = 1
+        X[p], _, _ = oracle.mutate2(X[p], KR[p], np.zeros(n, np.int64), inU, 0, p, seed)
+    assert (r["X"] == X).all()
