@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--ttt", action="store_true",
                     help="time-to-target: learned vs plain selection (trains the selector first)")
     ap.add_argument("--ttt-seeds", type=int, default=5)
+    ap.add_argument("--ablation", action="store_true",
+                    help="the paper's ablations (full / random selection / no IM) and hyperparameter sweeps "
+                         "on n=2500 10%%-dense stand-in instances")
+    ap.add_argument("--ablation-seeds", type=int, default=5)
+    ap.add_argument("--ablation-epochs", type=int, default=40)
     ap.add_argument("--ttt-iters", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (counter calibration)")
@@ -201,6 +206,79 @@ def ttt_main(a):
     print(json.dumps(out), flush=True)
 
 
+def ablation_main(a):
+    """The ablations of the Discussion section and the hyperparameter sweeps
+    of the Impact-of-Hyperparameters section, on seeded n=2500 instances with
+    10% density (stand-ins for the sparse benchmark set).  Table 1's values:
+    z=4, alpha=5n, c=n/150, weights (1, 1, 0.5); four sub-QUBOs of 128 per
+    solution, 200 sweeps.  Every variant runs the same number of epochs."""
+    import torch
+
+    from paper_2502_13947_amd import inputs, qb
+    from paper_2502_13947_amd.solver import Solver, default_thresholds
+    dev = torch.device("cuda:0")
+    n = 2500
+    E = a.ablation_epochs
+
+    def solve(Qd, thr, z=4, alpha=5 * n, tenure=n // 150, seed=1, iters=E, budget_s=None, **variant):
+        S = Solver(Qd, z=z, seed=seed, job_m=np.full((z, 4), 128, np.int32), init_m=128, thr_init=thr,
+                   thr=thr, B=10, R=1, alpha=alpha, tenure=max(1, tenure), **variant)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.init()
+        trace = []
+        with torch.cuda.stream(S.stream):
+            for _ in range(iters):
+                S.iterate()
+                trace.append(S.ebest.clone())
+                if budget_s is not None:
+                    S.stream.synchronize()
+                    if time.perf_counter() - t0 >= budget_s:
+                        break
+        S.stream.synchronize()
+        dt = time.perf_counter() - t0
+        tr = [int(v.item()) for v in trace]
+        first = next(i for i, v in enumerate(tr) if v == tr[-1]) + 1
+        return dict(ebest=tr[-1], epochs=len(tr), epoch_of_best=first, seconds=round(dt, 3))
+
+    rows = []
+    for sd in range(1, a.ablation_seeds + 1):
+        Q = inputs.dense_qubo(n, 0.10, 3000 + sd)
+        Qd = torch.as_tensor(Q, device=dev)
+        thr = default_thresholds(qb.Problem(Qd), 200)
+        row = {"instance": sd}
+        for name, var in (("full", {}), ("no_sm", dict(random_select=True)), ("no_im", dict(no_im=True)),
+                          ("full_not_worse", dict(wb_not_worse=True))):
+            row[name] = solve(Qd, thr, **var)
+        rows.append(row)
+    diff = {v: [r[v]["ebest"] - r["full"]["ebest"] for r in rows] for v in ("no_sm", "no_im", "full_not_worse")}
+
+    # sweeps on the second instance, one parameter at a time around Table 1's values
+    Q = inputs.dense_qubo(n, 0.10, 3002)
+    Qd = torch.as_tensor(Q, device=dev)
+    thr = default_thresholds(qb.Problem(Qd), 200)
+    sweeps = {
+        "c": {str(c): solve(Qd, thr, tenure=c) for c in (n // 600, n // 300, n // 150, n // 75, n // 30)},
+        "z": {str(z): solve(Qd, thr, z=z) for z in (1, 2, 4, 8, 16)},
+        "alpha": {f"{k}n": solve(Qd, thr, alpha=k * n) for k in (1, 2, 5, 10, 20)},
+    }
+    budget = 0.5
+    zfixed = {str(z): solve(Qd, thr, z=z, iters=10000, budget_s=budget) for z in (1, 2, 4, 8, 16, 64)}
+    out = {
+        "metric": "ablations and hyperparameter sweeps (E_best after a fixed number of epochs)",
+        "instances": f"{a.ablation_seeds} seeded n=2500, 10% dense, weights in [-100, 100]",
+        "config": "z=4, alpha=5n, c=n/150, w=(1,1,0.5), 4 sub-QUBOs of 128, 200 sweeps, R=1",
+        "epochs": E,
+        "ablation": rows,
+        "ablation_mean_gap": {v: float(np.mean(d)) for v, d in diff.items()},
+        "ablation_worse_count": {v: int(sum(x > 0 for x in d)) for v, d in diff.items()},
+        "sweeps_instance": 2,
+        "sweeps": sweeps,
+        "z_at_fixed_wall_clock": {"budget_s": budget, "runs": zfixed},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -208,6 +286,8 @@ def main():
         sys.exit(2)
     if a.ttt:
         return ttt_main(a)
+    if a.ablation:
+        return ablation_main(a)
     import torch
 
     from paper_2502_13947_amd import inputs, qb

@@ -242,6 +242,30 @@ qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int
                         int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R, int32_t rw, uint64_t seed,
                         uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream);
 
+/* The IM stage in Ising form (eq. 2, eq. 3), the native input of hardware
+ * Ising machines.  Job q is given as couplings J_q in the tile layout of
+ * qb_extract (element [tile_off[q] + a*mp + L*MS + s] = J[a][64s+L], J
+ * symmetric; diagonal and padding ignored; int8 or int16 as int8_tile
+ * says), fields h_d (int32 [total]) and start spins s0_d (int8 [total], -1
+ * or +1), and annealed on E'(s) = -sum_{a != b} J_ab s_a s_b - sum_a h_a s_a
+ * with the sweep, uniforms and replica layout of qb_anneal: the move of
+ * spin k is E'(s with s_k flipped) - E'(s), accepted iff <= thr[s][u >>
+ * (32-B)] (thr_d in E' units).  Outputs S_d (int8 [total*R], spins, layout
+ * of Y) and e_d (int64 [J*R]) = E'(S_r) - E'(s0).  For the Ising form of a
+ * QUBO (J = -Q off the diagonal, h_i = -2 (Q_ii + sum_{j != i} Q_ij): then
+ * 4 f(x) = E'(2x - 1) + const) and thresholds 4 thr, the result is
+ * qb_anneal's (S = 2Y - 1, e' = 4e).  A job with an asymmetric J, |J| >
+ * 8191, a spin not in {-1, +1} or a start field |2 sum_b J_ab s0_b + h_a| >=
+ * 2^30 is not
+ * annealed: its spins stay s0 and every e of it is INT64_MIN.  work_d:
+ * qb_anneal_ising_workspace(b, R) bytes, 256-byte aligned, owned by the
+ * caller.  Capacity as qb_anneal. */
+size_t qb_anneal_ising_workspace(qb_batch b, int32_t R);
+qb_status qb_anneal_ising(qb_batch b, const void *J_tile_d, int32_t int8_tile, const int32_t *h_d,
+                          const int8_t *s0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                          uint64_t seed, uint32_t inst_base, void *work_d, int8_t *S_d, int64_t *e_d,
+                          void *stream);
+
 /* Host builder of the acceptance table (cosine-waveform temperature, the
  * MRAnnealer's waveform used as the IM temperature schedule):
  *   T_s = tmin + 0.5 (tmax - tmin)(1 + cos(pi s / (nsw - 1)))   (T_0 = tmax

@@ -68,6 +68,11 @@ def lib():
         L.qbo_mutate2.argtypes = [i32, P, P, P, P, i32, i32, u64, P]
         L.qbo_mutate2.restype = i32
         L.qbo_random_keys.argtypes = [i32, i32, i32, u64, P]
+        L.qbo_ising_from_qubo.argtypes = [i32, P, P, P]
+        L.qbo_ising_from_qubo.restype = i64
+        L.qbo_ising_energy.argtypes = [i32, P, P, P]
+        L.qbo_ising_energy.restype = i64
+        L.qbo_anneal_ising.argtypes = [i32, P, P, P, i32, i32, P, i32, u64, u32, P, P]
         L.qbo_run.argtypes = [P, P, P, P, P, P, P, P]
         L.qbo_run.restype = i32
         f32 = ctypes.c_float
@@ -262,6 +267,40 @@ def random_keys(n, z, t, seed) -> np.ndarray:
     K = np.zeros((z, n), np.int64)
     lib().qbo_random_keys(int(n), int(z), int(t), int(seed), _p(K))
     return K
+
+
+def ising_from_qubo(Q):
+    """Ising form of eq. 2/3 in quarter units: (J int32 [n][n], h int64 [n],
+    const4) with 4 f(x) = E'(2x - 1) + const4."""
+    Q = _c(Q, np.int16)
+    n = Q.shape[0]
+    J = np.zeros((n, n), np.int32)
+    h = np.zeros(n, np.int64)
+    c4 = lib().qbo_ising_from_qubo(n, _p(Q), _p(J), _p(h))
+    return J, h, int(c4)
+
+
+def ising_energy(J, h, s) -> int:
+    J = _c(J, np.int32)
+    h = _c(h, np.int64)
+    s = _c(s, np.int8)
+    return int(lib().qbo_ising_energy(J.shape[0], _p(J), _p(h), _p(s)))
+
+
+def anneal_ising(J, h, s0, thr4, R, seed, inst, B):
+    """Spin-form annealer.  Returns (S [R, m] int8 spins, e [R] int64 = E'
+    change)."""
+    J = _c(J, np.int32)
+    h = _c(h, np.int64)
+    s0 = _c(s0, np.int8)
+    thr4 = _c(thr4, np.int64)
+    m = s0.shape[0]
+    assert thr4.shape[1] == (1 << B)
+    S = np.zeros((R, m), np.int8)
+    e = np.zeros(R, np.int64)
+    lib().qbo_anneal_ising(m, _p(J), _p(h), _p(s0), thr4.shape[0], int(B), _p(thr4), int(R), int(seed),
+                           int(inst), _p(S), _p(e))
+    return S, e
 
 
 class _RunCfg(ctypes.Structure):

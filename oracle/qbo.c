@@ -367,6 +367,85 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ising form (eq. 2 and eq. 3).  With s = 2x - 1, x_i x_j = (1 + s_i + s_j +
+ * s_i s_j) / 4, so for symmetric Q
+ *   4 f(x) = E'(s) + const4,   E'(s) = -sum_{i != j} J_ij s_i s_j - sum_i h_i s_i,
+ *   J_ij = -Q_ij (i != j),  h_i = -2 (Q_ii + sum_{j != i} Q_ij),
+ *   const4 = 2 sum_i Q_ii + sum_{i != j} Q_ij,
+ * i.e. eq. 2 in units of a quarter (every coefficient an integer).
+ * Reading: eq. 2's double sum runs over i != j (s_i^2 = 1 is a constant). */
+int64_t qbo_ising_from_qubo(int n, const int16_t *Q, int32_t *J, int64_t *h)
+{
+    int64_t c4 = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t r = Q[(int64_t)i * n + i];
+        c4 += 2 * (int64_t)Q[(int64_t)i * n + i];
+        for (int j = 0; j < n; ++j) {
+            J[(int64_t)i * n + j] = i == j ? 0 : -(int32_t)Q[(int64_t)i * n + j];
+            if (j != i) {
+                r += Q[(int64_t)i * n + j];
+                c4 += Q[(int64_t)i * n + j];
+            }
+        }
+        h[i] = -2 * r;
+    }
+    return c4;
+}
+
+/* E'(s) of eq. 2 (i != j), s_i in {-1, +1}. */
+int64_t qbo_ising_energy(int n, const int32_t *J, const int64_t *h, const int8_t *s)
+{
+    int64_t E = 0;
+    for (int i = 0; i < n; ++i) {
+        E -= h[i] * s[i];
+        for (int j = 0; j < n; ++j)
+            if (j != i) E -= (int64_t)J[(int64_t)i * n + j] * s[i] * s[j];
+    }
+    return E;
+}
+
+/* The Ising-machine stage in spin form: R replicas of the sequential
+ * Metropolis sweep on E'(s) of eq. 2 (symmetric J, zero diagonal), spins in
+ * order, the same uniforms as qbo_anneal (position k, sweep, replica,
+ * instance), accept iff the change E'(s with s_k flipped) - E'(s) <= thr'.
+ * The change is 2 s_k g_k with the local field g_k = 2 sum_{j != k} J_kj s_j
+ * + h_k.  S[R][m] final spins, e[R] = E'(S_r) - E'(s0).  For an Ising form
+ * made from a sub-QUBO, thr' = 4 thr gives qbo_anneal's trajectory. */
+void qbo_anneal_ising(int m, const int32_t *J, const int64_t *h, const int8_t *s0, int nsw, int B,
+                      const int64_t *thr4, int R, uint64_t seed, uint32_t inst, int8_t *S, int64_t *e)
+{
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    for (int r = 0; r < R; ++r) {
+        int8_t *s = S + (int64_t)r * m;
+        memcpy(s, s0, (size_t)m);
+        for (int k = 0; k < m; ++k) {
+            int64_t acc = h[k];
+            for (int j = 0; j < m; ++j)
+                if (j != k) acc += 2 * (int64_t)J[(int64_t)k * m + j] * s[j];
+            g[k] = acc;
+        }
+        int64_t tot = 0;
+        for (int sw = 0; sw < nsw; ++sw) {
+            for (int k = 0; k < m; ++k) {
+                const int64_t dE = 2 * (int64_t)s[k] * g[k];
+                uint32_t cw = (uint32_t)(((k >> 8) << 6) | (k & 63));
+                uint32_t u = philox_word(cw, (uint32_t)sw, (uint32_t)r, (1u << 28) | inst, seed, (k >> 6) & 3);
+                if (dE <= thr4[((int64_t)sw << B) + (u >> (32 - B))]) {
+                    const int sk = s[k];
+                    s[k] = (int8_t)-sk;
+                    tot += dE;
+                    /* g_j changes by 2 J_jk (s_k new - s_k old) = -4 J_jk s_k old */
+                    for (int j = 0; j < m; ++j)
+                        if (j != k) g[j] -= 4 * (int64_t)J[(int64_t)j * m + k] * sk;
+                }
+            }
+        }
+        e[r] = tot;
+    }
+    free(g);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Mutation (end of the proposed-heuristic section):
  *   candidates = variables the IM did not solve (not in U);
  *   subset = the floor((n - |U|) * r_t) candidates with the highest A

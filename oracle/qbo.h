@@ -77,6 +77,15 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
                 int nsw, int B, const int32_t *thr, int R, uint64_t seed, uint32_t inst,
                 uint8_t *Y, int64_t *e);
 
+/* Ising form (eq. 2, eq. 3) in quarter units: 4 f(x) = E'(2x - 1) + const4
+ * with J = -Q off the diagonal (J[n][n], zero diagonal) and h[n]; returns
+ * const4.  qbo_ising_energy: E'(s).  qbo_anneal_ising: the spin-form
+ * Metropolis sweep (see qbo.c), thr4 in E' units [nsw][2^B]. */
+int64_t qbo_ising_from_qubo(int n, const int16_t *Q, int32_t *J, int64_t *h);
+int64_t qbo_ising_energy(int n, const int32_t *J, const int64_t *h, const int8_t *s);
+void qbo_anneal_ising(int m, const int32_t *J, const int64_t *h, const int8_t *s0, int nsw, int B,
+                      const int64_t *thr4, int R, uint64_t seed, uint32_t inst, int8_t *S, int64_t *e);
+
 /* Mutation of one solution p at outer iteration t.  inU[n] marks the
  * variables the IM solved; K the aggregated keys of p.  Flips x in place and
  * writes flip[n] (1 where flipped).  Returns the number of candidates k. */

@@ -73,6 +73,8 @@ SIGNATURES = {
     "qb_anneal": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P]),
     "qb_extract_ell": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "qb_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _U64, _U32, _P, _P, _P]),
+    "qb_anneal_ising_workspace": (_SZ, [_P, _I32]),
+    "qb_anneal_ising": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P, _P]),
     "qb_threshold_table": (_I32, [_I32, _I32, _F64, _F64, _P]),
     "qb_writeback": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "qb_random_keys": (_I32, [_I32, _I32, _I32, _U64, _P, _P]),
@@ -296,6 +298,18 @@ def autotune_anneal_ell(b: Batch, W, tile, F0, y0, thr, R, seed, inst_base, B, r
     return int(rw.value), float(ms.value)
 
 
+def anneal_ising(b: Batch, J_tile, h, s0, thr, R, seed, inst_base, S, e, B, work=None, stream=None):
+    """Ising-form IM stage; ``work`` (uint8, qb_anneal_ising_workspace bytes)
+    is allocated here when not given."""
+    nsw = thr.shape[0]
+    assert thr.shape[1] == (1 << B)
+    if work is None:
+        work = torch.empty(int(lib().qb_anneal_ising_workspace(b.h, R)), dtype=torch.uint8, device=h.device)
+    int8_tile = 1 if J_tile.dtype == torch.int8 else 0
+    _chk(lib().qb_anneal_ising(b.h, _ptr(J_tile), int8_tile, _ptr(h), _ptr(s0), nsw, B, _ptr(thr), R, seed,
+                               inst_base, _ptr(work), _ptr(S), _ptr(e), _stream(stream)), "qb_anneal_ising")
+
+
 def threshold_table(nsw, B, tmax, tmin) -> np.ndarray:
     thr = np.zeros((nsw, 1 << B), np.int32)
     _chk(lib().qb_threshold_table(nsw, B, float(tmax), float(tmin), thr.ctypes.data), "qb_threshold_table")
@@ -447,3 +461,17 @@ def untile_ell(tile: torch.Tensor, b: Batch, q: int, W: int) -> np.ndarray:
     nz = w != 0
     T[rows[nz], col[nz]] = val[nz]
     return T
+
+
+def tile_pack(b: Batch, mats, dtype) -> np.ndarray:
+    """The tile layout of qb_extract (element [a*mp + L*MS + s] = M[a][64s+L],
+    zero padding) of one [m_q, m_q] matrix per job, as one host array."""
+    parts = []
+    for q, M in enumerate(mats):
+        m = int(b.sizes[q])
+        ms = tile_ms(m)
+        mp = 64 * ms
+        P = np.zeros((mp, mp), np.int64)
+        P[:m, :m] = M
+        parts.append(P.reshape(mp, ms, 64).transpose(0, 2, 1).reshape(-1))
+    return np.concatenate(parts).astype(dtype)

@@ -638,3 +638,49 @@ def test_random_selection_run_is_the_plain_run_with_random_keys():
         inU[S] = 1
         X[p], _, _ = oracle.mutate2(X[p], KR[p], np.zeros(n, np.int64), inU, 0, p, seed)
     assert (r["X"] == X).all()
+
+
+# --------------------------------------------------------------------------- Ising form
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ising_form_is_the_qubo_energy_plus_a_constant_by_brute_force(seed):
+    n = 9
+    Q = rand_sym(n, 500 + seed, -40, 40)
+    J, h, c4 = oracle.ising_from_qubo(Q)
+    assert (J == J.T).all() and (np.diag(J) == 0).all()
+    for x in all_states(n):
+        s = (2 * x.astype(np.int16) - 1).astype(np.int8)
+        assert 4 * oracle.energy_def(Q, x) == oracle.ising_energy(J, h, s) + c4
+
+
+def test_spin_annealer_closed_forms():
+    m = 11
+    Q = rand_sym(m, 600, -30, 30)
+    J, h, _ = oracle.ising_from_qubo(Q)
+    s0 = np.where(np.random.default_rng(1).random(m) < 0.5, -1, 1).astype(np.int8)
+    for nsw in (1, 2, 5):
+        allacc = np.full((nsw, 256), 2**40, np.int64)
+        S, e = oracle.anneal_ising(J, h, s0, allacc, 2, 3, 7, 8)
+        want = s0 * (-1) ** nsw
+        assert (S == want).all()
+        assert (e == oracle.ising_energy(J, h, want) - oracle.ising_energy(J, h, s0)).all()
+    none = np.full((3, 256), -2**40, np.int64)
+    S, e = oracle.anneal_ising(J, h, s0, none, 1, 3, 7, 8)
+    assert (S == s0).all() and e[0] == 0
+
+
+def test_spin_annealer_follows_the_qubo_annealer_on_a_qubo_derived_form():
+    # same uniforms, thresholds scaled by 4: spins 2Y-1 and E' change 4e
+    n, m, R, seed, inst = 40, 17, 3, 9, 11
+    Q = rand_sym(n, 700, -30, 30)
+    x = np.random.default_rng(2).integers(0, 2, n).astype(np.uint8)
+    S_idx = np.sort(np.random.default_rng(3).choice(n, m, replace=False)).astype(np.int32)
+    Tq, c, F0, y0 = oracle.extract(Q, x, oracle.field(Q, x[None])[0], S_idx)
+    sub = Tq.astype(np.int64).copy()
+    sub[np.arange(m), np.arange(m)] = c                   # the sub-QUBO as one matrix
+    J, h, _ = oracle.ising_from_qubo(sub.astype(np.int16))
+    thr = oracle.threshold_table(6, 8, 60.0, 1.0)
+    Y, e = oracle.anneal(Tq, F0, y0, thr, R, seed, inst, 8)
+    S, e4 = oracle.anneal_ising(J, h, (2 * y0.astype(np.int16) - 1).astype(np.int8), 4 * thr.astype(np.int64),
+                                R, seed, inst, 8)
+    assert (S == 2 * Y.astype(np.int16) - 1).all()
+    assert (e4 == 4 * e).all()
