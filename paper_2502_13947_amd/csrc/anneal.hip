@@ -237,11 +237,303 @@ void launch_anneal(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_ba
                                                       inst_base, Y, e);
 }
 
+// ------------------------------------------------------------ anneal, waves
+// The same sweep with the blocks of a replica spread over NW = min(MS, 4)
+// waves (one per SIMD): wave w owns the NB = MS/NW consecutive blocks
+// s = w NB .. w NB + NB - 1 -- their F in VGPRs, their spins as sign masks,
+// and the diagonal 64x64 block of each packed in VGPRs -- and runs the
+// accept loops of its blocks when its turn comes.  Every accept is published
+// as one word in an LDS list (the list of block sequence number
+// G = sw MS + s), and the other waves fold the accepted rows into their own
+// F while the owner is still sweeping.  A wave starts its turn once it has
+// applied every list before it, so each decision sees exactly the fields of
+// the sequential sweep (integer sums do not depend on the order of the
+// additions): Y and e are bit-identical to the one-wave kernel.  The owner's
+// per-accept chain reads the flipped row's element in its own block from
+// registers (an indexed register move), with no memory access on it.
+//
+// Lists: MS per replica, list G in slot G % MS, 65 words (64 accepts and an
+// end mark), word = (G+1) << 8 | k << 1 | (y_k before the flip).  When the
+// owner of G writes its list, every other wave has started a turn after
+// G - MS and so has read list G - MS to its end: the ring never overwrites
+// an unread list.  Every wait is bounded; a replica whose wait runs out
+// reports e = INT64_MIN.
+constexpr int MW_SLOTS = 65;
+constexpr int MW_SPIN_LIMIT = 1 << 24;
+constexpr int MW_LDS_LIMIT = 163840;
+
+template <int MS, typename TT, int MODE>
+struct AnnealMw {
+    static constexpr int NW = MS < 4 ? MS : 4;                 // waves per replica
+    static constexpr int NB = MS / NW;                         // blocks per wave
+    static constexpr int DW = 64 * (int)sizeof(TT) / 4;        // dwords of a packed diagonal column
+    static constexpr size_t tile = MODE == 0 ? (size_t)64 * MS * 64 * MS * sizeof(TT) : SYM_BYTES;
+    static constexpr size_t list_bytes = (size_t)MS * MW_SLOTS * 4;
+    static constexpr int RWAVES = 16 / NW;                     // replicas of 1024 threads
+    static constexpr int RLDS = (int)((MW_LDS_LIMIT - tile - 256) / list_bytes);
+    static constexpr int RMAX = RWAVES < RLDS ? RWAVES : RLDS;
+};
+
+// Address of T[64 a + k][64 cb + lane] in the staged tile as
+// base + k * ks + lane * ls: base and the strides depend only on the row
+// block a and the column block cb, so they are formed once per list and
+// block, leaving one multiply-add per element.
+struct ElemAddr {
+    int base, ks, ls;
+};
+
+template <int MS, typename TT, int MODE>
+__device__ __forceinline__ ElemAddr elem_addr(int a, int cb)
+{
+    if constexpr (MODE == 1) {
+        if (cb >= a) return ElemAddr{sym_block_index(a, cb) * SYM_BLOCK, SYM_STRIDE, 1};
+        return ElemAddr{sym_block_index(cb, a) * SYM_BLOCK, 1, SYM_STRIDE};
+    } else {
+        constexpr int MP = 64 * MS;
+        return ElemAddr{64 * a * MP + cb, MP, MS};
+    }
+}
+
+template <typename TT, int MODE>
+__device__ __forceinline__ int32_t elem_at(const uint8_t *lds, const ElemAddr &ea, int k, int lane)
+{
+    const int o = ea.base + k * ea.ks + lane * ea.ls;
+    if constexpr (MODE == 1)
+        return (int32_t)(int8_t)lds[o];
+    else
+        return (int32_t)reinterpret_cast<const TT *>(lds)[o];
+}
+
+// element k of a packed diagonal column (k uniform: an indexed register move)
+template <typename TT, int DW>
+__device__ __forceinline__ int32_t diag_at(const uint32_t (&d)[DW], int k)
+{
+    if constexpr (sizeof(TT) == 1)
+        return (int32_t)(int8_t)(d[k >> 2] >> ((k & 3) * 8));
+    else
+        return (int32_t)(int16_t)(d[k >> 1] >> ((k & 1) * 16));
+}
+
+template <int MS, typename TT, int MODE>
+__global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+                                                    const int64_t *__restrict__ tile_off,
+                                                    const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                    const uint8_t *__restrict__ y0, int nsw, int B,
+                                                    const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                    uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
+                                                    int64_t *__restrict__ eout)
+{
+    using C = AnnealMw<MS, TT, MODE>;
+    constexpr int NW = C::NW, NB = C::NB, DW = C::DW, MP = 64 * MS;
+    constexpr int PER = 4 / (int)sizeof(TT);
+    __shared__ __align__(16) uint8_t lds[C::tile];
+    __shared__ uint32_t lists[C::RMAX][MS][MW_SLOTS];
+    __shared__ int64_t esum[16];
+    __shared__ int32_t bad[C::RMAX];
+    const int q = jobs[blockIdx.x];
+    const int base = off[q], m = off[q + 1] - base;
+    const TT *gtile = tiles + tile_off[q];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wg = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = wg / NW, w = wg - r * NW;
+    const int s0 = w * NB;                       // first own block
+
+    if constexpr (MODE == 0) {
+        constexpr int n16 = (int)(C::tile / 16);
+        const uint4 *src = reinterpret_cast<const uint4 *>(gtile);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds);
+        for (int t = tid; t < n16; t += blockDim.x) dst[t] = src[t];
+    } else {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(gtile);
+        for (int t = tid; t < MP * 64; t += blockDim.x) {
+            const int x = t >> 6, cc = t & 63;
+            const uint64_t v = src[t];
+            const int a = x >> 6, rr = x & 63;
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (b >= a) lds[sym_block_index(a, b) * SYM_BLOCK + rr * SYM_STRIDE + cc] = (uint8_t)(v >> (8 * b));
+        }
+    }
+    for (int t = tid; t < C::RMAX * MS * MW_SLOTS; t += blockDim.x) (&lists[0][0][0])[t] = 0u;
+    if (tid < C::RMAX) bad[tid] = 0;
+    __syncthreads();
+
+    uint32_t(*L)[MW_SLOTS] = lists[r];
+    int32_t F[NB], M[NB];      // M: 0 or -1 (= -y) for position 64 (s0 + j) + lane
+    uint64_t active[NB];
+    uint32_t dcol[NB][DW];     // T[64 s + k][64 s + lane] for k = 0..63, packed
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int pos = 64 * (s0 + j) + lane;
+        F[j] = pos < m ? F0[base + pos] : 0;
+        M[j] = (pos < m && y0[base + pos]) ? -1 : 0;
+        const int na = min(max(m - 64 * (s0 + j), 0), 64);
+        active[j] = na == 64 ? ~0ull : ((1ull << na) - 1ull);
+        const ElemAddr ed = elem_addr<MS, TT, MODE>(s0 + j, s0 + j);
+#pragma unroll
+        for (int i = 0; i < DW; ++i) {
+            uint32_t wv = 0;
+#pragma unroll
+            for (int t = 0; t < PER; ++t)
+                wv |= ((uint32_t)elem_at<TT, MODE>(lds, ed, i * PER + t, lane) & (0xFFFFFFFFu >> (32 - 32 / PER)))
+                      << (t * (32 / PER));
+            dcol[j][i] = wv;
+        }
+    }
+    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    const int sh = 32 - B;
+    // thresholds of one sweep for the own blocks: they lie in one Philox
+    // group (s0 >> 2), the uniform of block s being word s & 3
+    auto thresholds = [&](int sw, int32_t (&tv)[NB]) {
+        const uint4 o = qb_philox(make_uint4(((uint32_t)(s0 >> 2) << 6) | (uint32_t)lane, (uint32_t)sw, (uint32_t)r, tag),
+                                  k0, k1);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int sq = (s0 + j) & 3;
+            const uint32_t uw = sq == 0 ? o.x : sq == 1 ? o.y : sq == 2 ? o.z : o.w;
+            tv[j] = thr[((size_t)sw << B) + (uw >> sh)];
+        }
+    };
+    // fetched one sweep ahead, right after the turn
+    int32_t tvn[NB];
+    thresholds(0, tvn);
+    int64_t e = 0;
+    int Gc = 0;                // next list this wave has to apply
+    bool ok = true;
+
+    for (int sw = 0; sw < nsw && ok; ++sw) {
+        const int G0 = sw * MS + s0;
+        for (; Gc < G0; ++Gc) {
+            const int sc = Gc & (MS - 1);
+            if (sc >= s0 && sc < s0 + NB) continue;       // own list: applied while produced
+            const uint32_t want = (uint32_t)(Gc + 1);
+            const uint32_t *lst = L[sc];
+            ElemAddr ea[NB];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) ea[jj] = elem_addr<MS, TT, MODE>(sc, s0 + jj);
+            int idx = 0;
+            uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane(
+                (int)__hip_atomic_load(&lst[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            while (true) {
+                int spins = 0;
+                while ((v >> 8) != want) {
+                    if (++spins > MW_SPIN_LIMIT) {
+                        ok = false;
+                        break;
+                    }
+                    if (spins > 16) __builtin_amdgcn_s_sleep(1);
+                    v = (uint32_t)__builtin_amdgcn_readfirstlane(
+                        (int)__hip_atomic_load(&lst[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                }
+                if (!ok) break;
+                const int k = (int)((v >> 1) & 127u);
+                if (k == 64) break;                         // end of list
+                const int32_t d2 = (v & 1u) ? -2 : 2;
+                int32_t t[NB];
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) t[jj] = elem_at<TT, MODE>(lds, ea[jj], k, lane);
+                // the next word is read together with the row elements
+                ++idx;
+                v = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    (int)__hip_atomic_load(&lst[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) F[jj] += d2 * t[jj];
+            }
+            if (!ok) break;
+        }
+        if (!ok) break;
+
+        int32_t tv[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) tv[j] = tvn[j];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int s = s0 + j;
+            const int G = G0 + j;
+            uint32_t *out = L[s];
+            const uint32_t gt = (uint32_t)(G + 1) << 8;
+            ElemAddr ea[NB];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) ea[jj] = elem_addr<MS, TT, MODE>(s, s0 + jj);
+            uint64_t pend = active[j];
+            int32_t ej = 0;            // at most 64 moves of |dE| < 2^24
+            int c = 0;
+            int32_t dE = (F[j] ^ M[j]) - M[j];
+            uint64_t acc = __ballot(dE <= tv[j]) & pend;
+            while (acc) {
+                const int k = __builtin_ctzll(acc);
+                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
+                const int32_t mk = __builtin_amdgcn_readlane(M[j], k);
+                ej += dEk;
+                const int32_t d2 = mk ? -2 : 2;                // y_k = 0: +2, y_k = 1: -2
+                F[j] += d2 * diag_at<TT, DW>(dcol[j], k);
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj)
+                    if (jj != j) F[jj] += d2 * elem_at<TT, MODE>(lds, ea[jj], k, lane);
+                M[j] ^= lane == k ? -1 : 0;
+                // every lane stores the same word
+                __hip_atomic_store(&out[c], gt | ((uint32_t)k << 1) | (uint32_t)(mk & 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                ++c;
+                pend &= (~0ull << k) << 1;
+                dE = (F[j] ^ M[j]) - M[j];
+                acc = __ballot(dE <= tv[j]) & pend;
+            }
+            __hip_atomic_store(&out[c], gt | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            e += ej;
+        }
+        Gc = G0 + NB;
+        if (sw + 1 < nsw) thresholds(sw + 1, tvn);
+    }
+
+    if (!ok && lane == 0) __hip_atomic_store(&bad[r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (lane == 0) esum[wg] = e;
+    uint8_t *Yr = Y + (size_t)base * R + (size_t)r * m;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int pos = 64 * (s0 + j) + lane;
+        if (pos < m) Yr[pos] = (uint8_t)(M[j] & 1);
+    }
+    __syncthreads();
+    if (w == 0 && lane == 0) {
+        int64_t t = 0;
+        for (int v = 0; v < NW; ++v) t += esum[r * NW + v];
+        eout[(size_t)q * R + r] = bad[r] ? INT64_MIN : t;
+    }
+}
+
+template <int MS, typename TT, int MODE>
+bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
+                      const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
+                      uint32_t inst_base, uint8_t *Y, int64_t *e)
+{
+    using C = AnnealMw<MS, TT, MODE>;
+    // replicas per workgroup, and list tags G + 1 < 2^24 that cannot wrap
+    if (R > C::RMAX || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
+    k_anneal_mw<MS, TT, MODE><<<nblocks, 64 * C::NW * R, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles,
+                                                                 F0, y0, nsw, B, thr, R, (uint32_t)seed,
+                                                                 (uint32_t)(seed >> 32), inst_base, Y, e);
+    return true;
+}
+
 bool dispatch_anneal(int cls, bool int8_tile, int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b,
                      const void *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr,
                      uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
 {
 #define QB_ARGS nblocks, R, s, jobs, b, tiles, F0, y0, nsw, B, thr, seed, inst_base, Y, e
+    // the multi-wave kernel where its replicas fit one workgroup
+    if (int8_tile) {
+        switch (cls) {
+        case 1: if (launch_anneal_mw<8, int8_t, 1>(QB_ARGS)) return true; break;
+        case 2: if (launch_anneal_mw<4, int8_t, 0>(QB_ARGS)) return true; break;
+        case 3: if (launch_anneal_mw<2, int8_t, 0>(QB_ARGS)) return true; break;
+        }
+    } else {
+        switch (cls) {
+        case 2: if (launch_anneal_mw<4, int16_t, 0>(QB_ARGS)) return true; break;
+        case 3: if (launch_anneal_mw<2, int16_t, 0>(QB_ARGS)) return true; break;
+        }
+    }
     if (int8_tile) {
         switch (cls) {
         case 0: launch_anneal<16, int8_t, 2>(QB_ARGS); return true;

@@ -238,6 +238,11 @@ ANNEAL_CASES = [
     (900, 2, [100, 256], 10, 2, False),
     (1500, 1, [512, 400], 6, 1, False),
     (1100, 1, [1024], 4, 2, False),
+    # replicas at the multi-wave kernel's limit (4 per workgroup for m <= 512)
+    # and past it (the one-wave kernel for m > 128, the multi-wave one below)
+    (1500, 2, [300, 512], 12, 4, True),
+    (1500, 1, [512, 200, 100, 64], 8, 5, True),
+    (1300, 1, [256, 120], 9, 5, False),
 ]
 
 
