@@ -516,6 +516,254 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
     return true;
 }
 
+// ------------------------------------------------ anneal, waves, rows in HBM
+// The multi-wave sweep for tiles that do not fit LDS (mp = 1024 int8,
+// mp = 512 int16; 16 bytes of every row per lane).  Wave w owns the NB
+// consecutive blocks s0 = w NB ..; it keeps their diagonal 64x64 blocks in
+// VGPRs and the off-diagonal blocks of its own NB x NB square in LDS, so
+// the owner's accept loop touches no global memory.  The other waves fetch,
+// for each published accept, the one dword of the accepted row that holds
+// their NB column blocks (row k, bytes 16 lane + 4 w), up to P loads in
+// flight per batch of list words.  Lists, ring and bounded waits as in the
+// in-LDS multi-wave kernel.
+template <int MS, typename TT>
+struct AnnealMwG {
+    static constexpr int NW = 4;
+    static constexpr int NB = MS / NW;
+    static constexpr int DW = 64 * (int)sizeof(TT) / 4;
+    static constexpr int PER = 4 / (int)sizeof(TT);
+    static constexpr int OSTR = 64 * (int)sizeof(TT) + 4;      // bytes per row of a stored block
+    static constexpr int OBLK = 64 * OSTR;
+    static constexpr int NOFF = NB * (NB - 1) / 2;             // own off-diagonal blocks
+    static constexpr int P = 8;                                // list words per consumer batch
+    static constexpr int SLOTS = 65 + P - 1;
+    static_assert(MS * sizeof(TT) == 16 && NB * sizeof(TT) == 4, "16 bytes per lane, one dword per consumer row");
+};
+
+__device__ __forceinline__ int own_pair(int a, int b, int nb)   // a < b < nb
+{
+    return a * nb - (a * (a + 1)) / 2 + (b - a - 1);
+}
+
+template <int MS, typename TT>
+__global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__ jobs,
+                                                     const int32_t *__restrict__ off,
+                                                     const int64_t *__restrict__ tile_off,
+                                                     const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                     const uint8_t *__restrict__ y0, int nsw, int B,
+                                                     const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                     uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
+                                                     int64_t *__restrict__ eout)
+{
+    using C = AnnealMwG<MS, TT>;
+    constexpr int NW = C::NW, NB = C::NB, DW = C::DW, PER = C::PER, P = C::P, SLOTS = C::SLOTS;
+    constexpr int MP = 64 * MS;
+    constexpr int ROWB = MP * (int)sizeof(TT);                 // bytes per tile row
+    constexpr int EB = 8 * (int)sizeof(TT);                    // bits per element
+    __shared__ __align__(16) uint8_t own[NW][C::NOFF > 0 ? C::NOFF : 1][C::OBLK];
+    __shared__ uint32_t lists[MS][SLOTS];
+    __shared__ int64_t esum[NW];
+    __shared__ int32_t bad;
+    const int q = jobs[blockIdx.x];
+    const int base = off[q], m = off[q + 1] - base;
+    const uint8_t *gt8 = reinterpret_cast<const uint8_t *>(tiles + tile_off[q]);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int s0 = w * NB;
+    const int r = 0;                                           // one replica per workgroup
+    uint8_t *ow = &own[w][0][0];
+
+    // this wave's columns of row x: dword 16 lane + 4 w of the row
+    const uint8_t *colp = gt8 + 16 * lane + 4 * w;
+    auto elem_of = [&](uint32_t x, int t) -> int32_t {
+        return sizeof(TT) == 1 ? (int32_t)(int8_t)(x >> (8 * t)) : (int32_t)(int16_t)(x >> (16 * t));
+    };
+
+    // own rows: diagonal blocks into VGPRs, the upper off-diagonal blocks of
+    // the own square into LDS (the lower ones are their transposes)
+    // one array per block, so that each is promoted to VGPRs on its own
+    uint32_t dc0[DW], dc1[DW], dc2[DW], dc3[DW];
+    auto dcol = [&](int j) -> uint32_t (&)[DW] { return j == 0 ? dc0 : j == 1 ? dc1 : j == 2 ? dc2 : dc3; };
+    static_assert(NB <= 4, "at most four blocks per wave");
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+#pragma unroll 2
+        for (int i = 0; i < DW; ++i) {
+            uint32_t wv = 0;
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int rr = i * PER + p;
+                const uint32_t x = *reinterpret_cast<const uint32_t *>(colp + (size_t)(64 * (s0 + a) + rr) * ROWB);
+                wv |= ((uint32_t)elem_of(x, a) & (0xFFFFFFFFu >> (32 - EB))) << (p * EB);
+#pragma unroll
+                for (int t = a + 1; t < NB; ++t) {
+                    const TT v = (TT)elem_of(x, t);
+                    *reinterpret_cast<TT *>(ow + own_pair(a, t, NB) * C::OBLK + rr * C::OSTR + lane * (int)sizeof(TT)) = v;
+                }
+            }
+            dcol(a)[i] = wv;
+        }
+    }
+    for (int t = tid; t < MS * SLOTS; t += blockDim.x) (&lists[0][0])[t] = 0u;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+
+    int32_t F[NB], M[NB];
+    uint64_t active[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int pos = 64 * (s0 + j) + lane;
+        F[j] = pos < m ? F0[base + pos] : 0;
+        M[j] = (pos < m && y0[base + pos]) ? -1 : 0;
+        const int na = min(max(m - 64 * (s0 + j), 0), 64);
+        active[j] = na == 64 ? ~0ull : ((1ull << na) - 1ull);
+    }
+    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    const int sh = 32 - B;
+    auto thresholds = [&](int sw, int32_t (&tv)[NB]) {
+        const uint4 o = qb_philox(make_uint4(((uint32_t)(s0 >> 2) << 6) | (uint32_t)lane, (uint32_t)sw, (uint32_t)r, tag),
+                                  k0, k1);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int sq = (s0 + j) & 3;
+            const uint32_t uw = sq == 0 ? o.x : sq == 1 ? o.y : sq == 2 ? o.z : o.w;
+            tv[j] = thr[((size_t)sw << B) + (uw >> sh)];
+        }
+    };
+    int32_t tvn[NB];
+    thresholds(0, tvn);
+    int64_t e = 0;
+    int Gc = 0;
+    bool ok = true;
+
+    for (int sw = 0; sw < nsw && ok; ++sw) {
+        const int G0 = sw * MS + s0;
+        for (; Gc < G0; ++Gc) {
+            const int sc = Gc & (MS - 1);
+            if (sc >= s0 && sc < s0 + NB) continue;       // own list: applied while produced
+            const uint32_t want = (uint32_t)(Gc + 1);
+            const uint32_t *lst = lists[sc];
+            const uint8_t *rowp = colp + (size_t)(64 * sc) * ROWB;
+            int idx = 0, spins = 0;
+            while (true) {
+                uint32_t vv[P];
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    vv[i] = (uint32_t)__builtin_amdgcn_readfirstlane(
+                        (int)__hip_atomic_load(&lst[idx + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                int n = 0;
+                bool stop = false, end = false;
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    if (!stop) {
+                        if ((vv[i] >> 8) != want)
+                            stop = true;
+                        else if (((vv[i] >> 1) & 127u) == 64u)
+                            stop = end = true;
+                        else
+                            ++n;
+                    }
+                }
+                if (n == 0 && !end) {
+                    if (++spins > MW_SPIN_LIMIT) {
+                        ok = false;
+                        break;
+                    }
+                    if (spins > 16) __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                spins = 0;
+                uint32_t x[P];
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    if (i < n) x[i] = *reinterpret_cast<const uint32_t *>(rowp + (size_t)((vv[i] >> 1) & 63u) * ROWB);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    if (i < n) {
+                        const int32_t d2 = (vv[i] & 1u) ? -2 : 2;
+#pragma unroll
+                        for (int t = 0; t < NB; ++t) F[t] += d2 * elem_of(x[i], t);
+                    }
+                }
+                idx += n;
+                if (end) break;
+            }
+            if (!ok) break;
+        }
+        if (!ok) break;
+
+        int32_t tv[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) tv[j] = tvn[j];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int s = s0 + j;
+            const int G = G0 + j;
+            uint32_t *out = lists[s];
+            const uint32_t gtag = (uint32_t)(G + 1) << 8;
+            uint64_t pend = active[j];
+            int32_t ej = 0;
+            int c = 0;
+            int32_t dE = (F[j] ^ M[j]) - M[j];
+            uint64_t acc = __ballot(dE <= tv[j]) & pend;
+            while (acc) {
+                const int k = __builtin_ctzll(acc);
+                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
+                const int32_t mk = __builtin_amdgcn_readlane(M[j], k);
+                ej += dEk;
+                const int32_t d2 = mk ? -2 : 2;
+                F[j] += d2 * diag_at<TT, DW>(dcol(j), k);
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) {
+                    if (jj == j) continue;
+                    const int o = jj > j ? own_pair(j, jj, NB) * C::OBLK + k * C::OSTR + lane * (int)sizeof(TT)
+                                         : own_pair(jj, j, NB) * C::OBLK + lane * C::OSTR + k * (int)sizeof(TT);
+                    F[jj] += d2 * (int32_t)*reinterpret_cast<const TT *>(ow + o);
+                }
+                M[j] ^= lane == k ? -1 : 0;
+                __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (uint32_t)(mk & 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                ++c;
+                pend &= (~0ull << k) << 1;
+                dE = (F[j] ^ M[j]) - M[j];
+                acc = __ballot(dE <= tv[j]) & pend;
+            }
+            __hip_atomic_store(&out[c], gtag | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            e += ej;
+        }
+        Gc = G0 + NB;
+        if (sw + 1 < nsw) thresholds(sw + 1, tvn);
+    }
+
+    if (!ok && lane == 0) __hip_atomic_store(&bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (lane == 0) esum[w] = e;
+    uint8_t *Yr = Y + (size_t)base * R;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int pos = 64 * (s0 + j) + lane;
+        if (pos < m) Yr[pos] = (uint8_t)(M[j] & 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t t = 0;
+        for (int v = 0; v < NW; ++v) t += esum[v];
+        eout[(size_t)q * R] = bad ? INT64_MIN : t;
+    }
+}
+
+template <int MS, typename TT>
+bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
+                        const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
+                        uint32_t inst_base, uint8_t *Y, int64_t *e)
+{
+    if (R != 1 || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
+    k_anneal_mw_g<MS, TT><<<nblocks, 64 * AnnealMwG<MS, TT>::NW, 0, s>>>(jobs, b->off_d, b->tile_off_d,
+                                                                      (const TT *)tiles, F0, y0, nsw, B, thr, R,
+                                                                      (uint32_t)seed, (uint32_t)(seed >> 32),
+                                                                      inst_base, Y, e);
+    return true;
+}
+
 bool dispatch_anneal(int cls, bool int8_tile, int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b,
                      const void *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr,
                      uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
@@ -524,12 +772,14 @@ bool dispatch_anneal(int cls, bool int8_tile, int nblocks, int R, hipStream_t s,
     // the multi-wave kernel where its replicas fit one workgroup
     if (int8_tile) {
         switch (cls) {
+        case 0: if (launch_anneal_mw_g<16, int8_t>(QB_ARGS)) return true; break;
         case 1: if (launch_anneal_mw<8, int8_t, 1>(QB_ARGS)) return true; break;
         case 2: if (launch_anneal_mw<4, int8_t, 0>(QB_ARGS)) return true; break;
         case 3: if (launch_anneal_mw<2, int8_t, 0>(QB_ARGS)) return true; break;
         }
     } else {
         switch (cls) {
+        case 1: if (launch_anneal_mw_g<8, int16_t>(QB_ARGS)) return true; break;
         case 2: if (launch_anneal_mw<4, int16_t, 0>(QB_ARGS)) return true; break;
         case 3: if (launch_anneal_mw<2, int16_t, 0>(QB_ARGS)) return true; break;
         }

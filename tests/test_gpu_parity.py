@@ -243,6 +243,11 @@ ANNEAL_CASES = [
     (1500, 2, [300, 512], 12, 4, True),
     (1500, 1, [512, 200, 100, 64], 8, 5, True),
     (1300, 1, [256, 120], 9, 5, False),
+    # one replica: the multi-wave kernel with rows in HBM (m = 1024 int8,
+    # m = 512 int16), many sweeps
+    (2200, 1, [700, 1024], 6, 1, True),
+    (3200, 1, [1024, 1000, 999], 40, 1, True),
+    (1500, 1, [512, 257], 30, 1, False),
 ]
 
 
