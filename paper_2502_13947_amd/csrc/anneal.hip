@@ -1,22 +1,24 @@
 // Sub-QUBO extraction (eq. 4, Alg. 3 lines 3-5), the batched Ising-machine
 // stage (Alg. 3 line 6) and the write-back (Alg. 3 line 7) on gfx950.
 //
-// Annealer layout: one replica per wave64, the R replicas of a job share a
-// workgroup and its tile.  Lane L owns positions 64*s + L (s < MS = mp/64):
-// their flip bases F live in VGPRs and their spins in a per-lane bit mask.
-// A sweep visits blocks of 64 positions; all 64 uniforms and thresholds of a
-// block are ready before the block starts, the accept predicate is evaluated
-// by every pending lane at once, and the lowest accepting lane k is taken
-// (ballot + find-first-set).  After flipping k every lane adds 2 d T[k][own]
-// to its F (one row read per accept) and only lanes after k re-evaluate:
-// lanes before k were rejected with exactly the fields the sequential sweep
-// would have shown them, so the result is the sequential sweep's, bit for
-// bit, with #accepts + MS ballot rounds per sweep instead of m steps.
+// Annealer layout (the one-wave kernel; the multi-wave kernels below spread
+// the same sweep over several waves): one replica per wave64, the R
+// replicas of a job share a workgroup and its tile.  Lane L owns positions
+// 64*s + L (s < MS = mp/64): their flip bases F live in VGPRs and their
+// spins in a per-lane bit mask.  A sweep visits blocks of 64 positions; all
+// 64 uniforms and thresholds of a block are ready before the block starts,
+// the accept predicate is evaluated by every pending lane at once, and the
+// lowest accepting lane k is taken (ballot + find-first-set).  After
+// flipping k every lane adds 2 d T[k][own] to its F (one row read per
+// accept) and only lanes after k re-evaluate: lanes before k were rejected
+// with exactly the fields the sequential sweep would have shown them, so the
+// result is the sequential sweep's, bit for bit, with #accepts + MS ballot
+// rounds per sweep instead of m steps.
 //
-// Tile placement by size class: mp <= 256 (int8) or <= 256 (int16): whole
-// tile in LDS; mp = 512 int8: the 36 upper 64x64 blocks of the symmetric tile
-// in LDS (156,672 bytes, rows padded to 68 bytes so that both row and column
-// reads of a block are bank-conflict free); otherwise rows stream from L2/HBM.
+// Tile placement by size class: mp <= 256 (int8 or int16): whole tile in
+// LDS; mp = 512 int8: the 36 upper 64x64 blocks of the symmetric tile in LDS
+// (156,672 bytes, rows padded to 68 bytes so that both row and column reads
+// of a block are bank-conflict free); otherwise rows stay in L2/HBM.
 #include "qb_internal.h"
 
 namespace {
