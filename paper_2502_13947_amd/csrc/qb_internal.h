@@ -44,10 +44,11 @@ static inline __host__ __device__ int32_t qb_ell_val(uint32_t w) { return (int32
 
 // Threads of the Tabu workgroup and elements per thread for n variables;
 // the padded copy of Q has pitch QB_TABU_THREADS * EPT.  0 if n is too large.
-#define QB_TABU_THREADS 512
+#define QB_TABU_THREADS 1024
 static inline int qb_tabu_ept(int n)
 {
-    static const int opts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32};
+    // beyond 16 elements per thread the state no longer fits 128 VGPRs
+    static const int opts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16};
     for (int e : opts)
         if (n <= QB_TABU_THREADS * e) return e;
     return 0;

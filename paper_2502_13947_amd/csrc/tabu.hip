@@ -1,8 +1,9 @@
-// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 512-thread
-// workgroup (eight waves, two per SIMD, so one wave's latency overlaps the
-// other's work) per solution.
+// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 1024-thread
+// workgroup (sixteen waves, four per SIMD, so the per-step element work is
+// spread thin and one wave's latency overlaps the others' work) per
+// solution.
 //
-// Thread t owns the variables j = e*512 + t (e < EPT; every row chunk read is
+// Thread t owns the variables j = e*1024 + t (e < EPT; every row chunk read is
 // coalesced across the workgroup) and keeps in registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
 // to be non-negative), the factor S_j = 2(1-2x_j), and the step U_j after
 // which the variable is free again.  U replaces the tenure vector of the
@@ -269,7 +270,6 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
         return QB_OK;                                                                              \
     }
     QB_T(1) QB_T(2) QB_T(3) QB_T(4) QB_T(5) QB_T(6) QB_T(7) QB_T(8) QB_T(10) QB_T(12) QB_T(14) QB_T(16)
-    QB_T(20) QB_T(24) QB_T(28) QB_T(32)
 #undef QB_T
     return QB_E_CAPACITY;
 }
