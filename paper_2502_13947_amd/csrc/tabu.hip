@@ -29,7 +29,34 @@ namespace {
 constexpr int TB = QB_TABU_THREADS;
 constexpr int NW = TB / 64;
 
-template <int EPT, typename QT>
+// Cross-wave winner in 32 bits (K32): the slot's low word is
+// (wave minimum key << WB) | wave and its high word (lane << 1) | x.  Within
+// a wave the ballot already took the lowest lane among equal keys, and
+// across waves (move, element, wave) orders exactly as (move, index) since
+// index = element * TB + wave * 64 + lane; so a 32-bit DPP minimum over the
+// slots picks the winner and one readlane of the winning slot's high word
+// gives its lane and x.  Used when every real key fits 31 - WB bits.
+constexpr int WB = qb_ceil_log2(NW);
+
+template <int NWV>
+__device__ __forceinline__ bool qb_pick32(const uint64_t *slot, int lane, uint32_t &key, uint32_t &hi)
+{
+    static_assert(NWV >= 1 && NWV <= 16, "one row of 16 lanes");
+    const uint64_t v = lane < NWV ? slot[lane] : ~0ull;
+    uint32_t lo = (uint32_t)v;
+    lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    if constexpr (NWV > 4) {
+        lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x124, 0xF, 0xF, false));  // row_ror 4
+        lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x128, 0xF, 0xF, false));  // row_ror 8
+    }
+    key = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+    if (key == 0xFFFFFFFFu) return false;
+    hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)(key & (NWV - 1)));
+    return true;
+}
+
+template <int EPT, typename QT, bool K32>
 __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp, const int16_t *__restrict__ Q16,
                                              int n, uint8_t *__restrict__ X, int32_t *__restrict__ H,
                                              int64_t *__restrict__ E, int alpha, int tenure, int asp,
@@ -108,34 +135,59 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         const uint32_t tk = m2 < TBIT ? m2 : KNONE;
         const uint32_t best = min(fk, (asp && (tk >> EB) < tb) ? tk : KNONE);
         const uint32_t wmin = qb_wave_min_u32(best);
-        uint64_t wkey = ~0ull;
-        if (wmin != 0xFFFFFFFFu) {
+        // the wave's winner slot for minimum key wm among the lanes' keys bsel
+        // (a whole-wave call); padding keys never win a K32 slot
+        auto slot_of = [&](uint32_t wm, uint32_t bsel) -> uint64_t {
             // lowest index among the minimal moves: the lowest lane holding the
             // minimal move value, then that lane's own lowest element
-            const uint64_t who = __ballot(best == wmin);
+            const uint64_t who = __ballot(bsel == wm);
             const int L = __builtin_ctzll(who);
-            const int ew = (int)(wmin & EMASK);
+            const int ew = (int)(wm & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            wkey = qb_tabu_winner(wmin >> EB, ew * TB + wid * 64 + L, xw);
-        }
+            if constexpr (K32) {
+                if (wm >= (1u << (31 - WB))) return ~0ull;
+                return ((uint64_t)(((uint32_t)L << 1) | xw) << 32) | ((wm << WB) | (uint32_t)wid);
+            } else {
+                return qb_tabu_winner(wm >> EB, ew * TB + wid * 64 + L, xw);
+            }
+        };
+        uint64_t wkey = ~0ull;
+        if (wmin != 0xFFFFFFFFu) wkey = slot_of(wmin, best);
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
-        uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
-        if (kb == ~0ull) {
-            // every variable is tabu and none aspirates: argmin over all of them
-            const uint32_t b2 = min(fk, tk);
-            const uint32_t w2 = qb_wave_min_u32(b2);
-            const uint64_t who = __ballot(b2 == w2);
-            const int L = __builtin_ctzll(who);
-            const int ew = (int)(w2 & EMASK);
-            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            if (lane == 0) red2[wid] = qb_tabu_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
-            __syncthreads();
-            kb = qb_min_winners<NW>(red2, lane);
+        uint32_t dib;
+        int i;
+        int32_t s;                                 // direction of x_i
+        if constexpr (K32) {
+            uint32_t key = 0, hi = 0;
+            if (!qb_pick32<NW>(red[step & 1], lane, key, hi)) {
+                // every variable is tabu and none aspirates: argmin over all of them
+                const uint32_t b2 = min(fk, tk);
+                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint64_t k2 = slot_of(w2, b2);
+                if (lane == 0) red2[wid] = k2;
+                __syncthreads();
+                qb_pick32<NW>(red2, lane, key, hi);
+            }
+            const uint32_t wm = key >> WB;
+            dib = wm >> EB;
+            i = (int)(wm & EMASK) * TB + (int)(key & (NW - 1)) * 64 + (int)(hi >> 1);
+            s = (hi & 1u) ? -1 : 1;
+        } else {
+            uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
+            if (kb == ~0ull) {
+                // every variable is tabu and none aspirates: argmin over all of them
+                const uint32_t b2 = min(fk, tk);
+                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint64_t k2 = slot_of(w2, b2);
+                if (lane == 0) red2[wid] = k2;
+                __syncthreads();
+                kb = qb_min_winners<NW>(red2, lane);
+            }
+            dib = (uint32_t)(kb >> 32);
+            i = (int)((uint32_t)kb >> 1);
+            s = (kb & 1) ? -1 : 1;
         }
-        const uint32_t dib = (uint32_t)(kb >> 32);
-        const int i = (int)((uint32_t)kb >> 1);
-        const int32_t s = (kb & 1) ? -1 : 1;       // direction of x_i
         OV += (int64_t)(int32_t)(dib - bias);
         int32_t q[EPT];
         {
@@ -245,13 +297,14 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     if (tid == 0) E[p] = OVmin;
 }
 
-template <int EPT, typename QT>
+template <int EPT, typename QT, bool K32>
 void launch_one(const QT *Qp, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
                 int tenure, int asp, int32_t *T, int32_t *LF, uint32_t bias, hipStream_t s)
 {
     const size_t lds = sizeof(int32_t) * 2 * (size_t)P->n;
-    (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_tabu<EPT, QT><<<z, TB, lds, s>>>(Qp, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
+    (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT, K32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    k_tabu<EPT, QT, K32><<<z, TB, lds, s>>>(Qp, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
 }
 
 template <typename QT>
@@ -265,7 +318,10 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
 #define QB_T(K)                                                                                    \
     if (ept == K) {                                                                               \
         if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;             \
-        launch_one<K, QT>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);             \
+        if (((2 * dmax + 1) << qb_ceil_log2(K)) < (int64_t(1) << (31 - WB)))                         \
+            launch_one<K, QT, true>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);     \
+        else                                                                                       \
+            launch_one<K, QT, false>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);    \
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
     }

@@ -96,7 +96,9 @@ def test_field_energy_best(n, z, int8):
 @pytest.mark.parametrize("int8", [True, False])
 @pytest.mark.parametrize("n,z,alpha,tenure,asp", [(3, 1, 7, 2, True), (50, 3, 250, 4, True),
                                                   (1100, 4, 2000, 7, True), (2500, 2, 3000, 16, False),
-                                                  (5000, 2, 800, 33, True)])
+                                                  (5000, 2, 800, 33, True),
+                                                  # tenure beyond n: every variable tabu, none aspirating
+                                                  (70, 2, 300, 90, False), (1500, 1, 2000, 1600, True)])
 def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
     say("tabu", n, z, alpha, tenure, asp, int8)
     Q = inputs.dense_qubo(n, 0.3, 5) if int8 else wide_qubo(n, 5)
@@ -115,6 +117,28 @@ def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
         assert int(Ed[p].item()) == ov
         assert (T[p].cpu().numpy() == To).all()
         assert (LF[p].cpu().numpy() == LFo).all()
+
+
+def test_tabu_bit_exact_wide_moves():
+    """Move values too wide for the 32-bit cross-wave winner key (int16
+    weights of +-30000 at n = 5000): the 64-bit winner path."""
+    n, z, alpha, tenure = 5000, 2, 600, 33
+    say("tabu wide moves", n, z, alpha, tenure)
+    Q = inputs.dense_qubo(n, 0.5, 27, lo=-30000, hi=30000)
+    X = inputs.random_solutions(z, n, 28)
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    P = qb().Problem(dq(Q))
+    assert not P.int8_ok
+    Xd, Hd, Ed = (torch.as_tensor(a, device=DEV) for a in (X, H, E))
+    T = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    LF = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().tabu(P, Xd, Hd, Ed, alpha, tenure, True, T, LF)
+    for p in range(z):
+        x, h, ov, To, LFo = oracle.tabu(Q, X[p], H[p], int(E[p]), alpha, tenure, True)
+        assert (Xd[p].cpu().numpy() == x).all() and (Hd[p].cpu().numpy() == h).all()
+        assert int(Ed[p].item()) == ov
+        assert (T[p].cpu().numpy() == To).all() and (LF[p].cpu().numpy() == LFo).all()
 
 
 def test_tabu_golden_fixtures_on_gpu():
