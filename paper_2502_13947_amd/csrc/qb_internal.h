@@ -190,6 +190,29 @@ __device__ __forceinline__ uint64_t qb_dpp_min64(uint64_t v)
     return o < v ? o : v;
 }
 
+// Tabu cross-wave winner in 32 bits: slot[w] holds, in its low word,
+// (wave w's minimum key << log2 NW) | w and, in its high word,
+// (lane << 1) | x.  A 32-bit DPP minimum over the first row of lanes picks
+// the winning key and one readlane of that slot's high word gives its lane
+// and x.  False when every slot is empty.
+template <int NWV>
+__device__ __forceinline__ bool qb_pick32(const uint64_t *slot, int lane, uint32_t &key, uint32_t &hi)
+{
+    static_assert(NWV >= 1 && NWV <= 16, "one row of 16 lanes");
+    const uint64_t v = lane < NWV ? slot[lane] : ~0ull;
+    uint32_t lo = (uint32_t)v;
+    lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    if constexpr (NWV > 4) {
+        lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x124, 0xF, 0xF, false));  // row_ror 4
+        lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x128, 0xF, 0xF, false));  // row_ror 8
+    }
+    key = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+    if (key == 0xFFFFFFFFu) return false;
+    hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)(key & (NWV - 1)));
+    return true;
+}
+
 // Minimum of NW (<= 16) 64-bit values slot[0..NW), returned uniform: lane l
 // of the calling wave reads slot[l] (lanes >= NW take the largest value) and
 // a DPP tree inside the first row of 16 lanes (xor 1, xor 2, rotate 4,

@@ -14,12 +14,13 @@
 // its allowed variables (not tabu, or aspirating: OV + D < OV_min) and keeps
 // the minimum; the wave minimum comes from DPP row operations plus four
 // readlanes; index order inside a wave is (element, lane), so the lowest
-// lane holding the minimal key gives the lowest index; the eight wave
+// lane holding the minimal key gives the lowest index; the sixteen wave
 // winners meet in LDS (one barrier per step, double-buffered slots), where a
-// DPP tree over lanes picks the smallest.  The
-// chosen variable's row of the padded copy of Q is read (coalesced) and
-// every D is updated by one multiply-add; the owner of the flipped variable
-// patches its own element through a scalar switch.  x_min is never copied:
+// DPP minimum over lanes picks the smallest (32-bit (key, wave) when the
+// move values allow, else 64-bit (move, index, x)).  The chosen variable's
+// row of the padded copy of Q is read (coalesced) and every D is updated by
+// one multiply-add; the owner of the flipped variable patches its own
+// element (a uniform index into its registers).  x_min is never copied:
 // per-variable "flipped since the last improvement" bits recover it, and the
 // field is moved to x_min with the rows of the differing variables.
 #include "qb_internal.h"
@@ -37,24 +38,6 @@ constexpr int NW = TB / 64;
 // slots picks the winner and one readlane of the winning slot's high word
 // gives its lane and x.  Used when every real key fits 31 - WB bits.
 constexpr int WB = qb_ceil_log2(NW);
-
-template <int NWV>
-__device__ __forceinline__ bool qb_pick32(const uint64_t *slot, int lane, uint32_t &key, uint32_t &hi)
-{
-    static_assert(NWV >= 1 && NWV <= 16, "one row of 16 lanes");
-    const uint64_t v = lane < NWV ? slot[lane] : ~0ull;
-    uint32_t lo = (uint32_t)v;
-    lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-    lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    if constexpr (NWV > 4) {
-        lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x124, 0xF, 0xF, false));  // row_ror 4
-        lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x128, 0xF, 0xF, false));  // row_ror 8
-    }
-    key = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
-    if (key == 0xFFFFFFFFu) return false;
-    hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)(key & (NWV - 1)));
-    return true;
-}
 
 template <int EPT, typename QT, bool K32>
 __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp, const int16_t *__restrict__ Q16,
@@ -204,45 +187,25 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 #pragma unroll
             for (int e = 0; e < EPT; ++e) Kb[e] -= (uint32_t)__mul24(q[e], S[e]);
         }
-        const int ti = i % TB;
+        const int ti = i & (TB - 1);
         if (tid == ti) {
+            // the owner patches its element ei (uniform, so the register
+            // arrays are indexed directly) and bumps the counters without
+            // waiting on LDS
             const int ei = i / TB;
             xb ^= 1ull << ei;
             pb ^= 1ull << ei;
-            Ts[i] += 1;
+            atomicAdd(&Ts[i], 1);
             Ls[i] = step;
-            switch (ei) {
-#define QB_OWNER_CASE(K)                                                         \
-    case K:                                                                      \
-        if constexpr (K < EPT) {                                                 \
-            Kb[K] = ((2u * bias - dib) << EB) | (uint32_t)K;                     \
-            S[K] = -S[K];                                                        \
-            U[K] = step + max(max(U[K] - (step - 1), 0) + tenure - 1, 0);        \
-            if (U[K] > step) {                                                   \
-                Kb[K] |= TBIT;                                                   \
-                nexp = min(nexp, U[K]);                                          \
-            }                                                                    \
-        }                                                                        \
-        break;
-                QB_OWNER_CASE(0) QB_OWNER_CASE(1) QB_OWNER_CASE(2) QB_OWNER_CASE(3)
-                QB_OWNER_CASE(4) QB_OWNER_CASE(5) QB_OWNER_CASE(6) QB_OWNER_CASE(7)
-                QB_OWNER_CASE(8) QB_OWNER_CASE(9) QB_OWNER_CASE(10) QB_OWNER_CASE(11)
-                QB_OWNER_CASE(12) QB_OWNER_CASE(13) QB_OWNER_CASE(14) QB_OWNER_CASE(15)
-                QB_OWNER_CASE(16) QB_OWNER_CASE(17) QB_OWNER_CASE(18) QB_OWNER_CASE(19)
-                QB_OWNER_CASE(20) QB_OWNER_CASE(21) QB_OWNER_CASE(22) QB_OWNER_CASE(23)
-                QB_OWNER_CASE(24) QB_OWNER_CASE(25) QB_OWNER_CASE(26) QB_OWNER_CASE(27)
-                QB_OWNER_CASE(28) QB_OWNER_CASE(29) QB_OWNER_CASE(30) QB_OWNER_CASE(31)
-                QB_OWNER_CASE(32) QB_OWNER_CASE(33) QB_OWNER_CASE(34) QB_OWNER_CASE(35)
-                QB_OWNER_CASE(36) QB_OWNER_CASE(37) QB_OWNER_CASE(38) QB_OWNER_CASE(39)
-                QB_OWNER_CASE(40) QB_OWNER_CASE(41) QB_OWNER_CASE(42) QB_OWNER_CASE(43)
-                QB_OWNER_CASE(44) QB_OWNER_CASE(45) QB_OWNER_CASE(46) QB_OWNER_CASE(47)
-                QB_OWNER_CASE(48) QB_OWNER_CASE(49) QB_OWNER_CASE(50) QB_OWNER_CASE(51)
-                QB_OWNER_CASE(52) QB_OWNER_CASE(53) QB_OWNER_CASE(54) QB_OWNER_CASE(55)
-                QB_OWNER_CASE(56) QB_OWNER_CASE(57) QB_OWNER_CASE(58) QB_OWNER_CASE(59)
-                QB_OWNER_CASE(60) QB_OWNER_CASE(61) QB_OWNER_CASE(62) QB_OWNER_CASE(63)
-#undef QB_OWNER_CASE
-            default: break;
+            const int32_t Un = step + max(max(U[ei] - (step - 1), 0) + tenure - 1, 0);
+            U[ei] = Un;
+            S[ei] = -S[ei];
+            uint32_t kn = ((2u * bias - dib) << EB) | (uint32_t)ei;
+            if (Un > step) {
+                kn |= TBIT;
+                nexp = min(nexp, Un);
             }
+            Kb[ei] = kn;
         }
         if (OV < OVmin) {
             OVmin = OV;

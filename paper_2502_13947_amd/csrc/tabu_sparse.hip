@@ -5,7 +5,8 @@
 // registers the biased move value D_j and the step U_j after which j is free
 // again; keys are (move << EB | element), the wave minimum comes from DPP,
 // and the sixteen wave winners meet in LDS with one barrier per step, where
-// a DPP tree over lanes picks the smallest.  What changes from the dense
+// a DPP minimum over lanes picks the smallest (32-bit (key, wave) when the
+// move values allow, else 64-bit (move, index, x)).  What changes from the dense
 // kernel is the field update: flipping i moves D_j only for the neighbours
 // j of i (the O(n) update of the Tabu section, here O(degree)), so the
 // argmin is kept incrementally too.  Each thread holds, per group of GS
@@ -71,10 +72,9 @@ __device__ __forceinline__ void for_row(const uint32_t *__restrict__ ell, int W,
     }
 }
 
-// Minimum of the NW (<= 16) 64-bit wave winners: lane l of every wave reads
-// winner l, and a DPP tree inside the first row of 16 lanes (xor 1, xor 2,
-// rotate 4, rotate 8) leaves the minimum in lane 0, returned uniform.
-template <int EPT>
+constexpr int WB = qb_ceil_log2(NW);
+
+template <int EPT, bool K32>
 __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell, int W,
                                                 const int32_t *__restrict__ diag, int n,
                                                 uint8_t *__restrict__ X, int32_t *__restrict__ H,
@@ -157,42 +157,62 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         dirty = 0;
         const uint32_t best = min(kfa, (asp && (kta >> EB) < tb) ? kta : KNONE);
         const uint32_t wmin = qb_wave_min_u32(best);
-        uint64_t wkey = ~0ull;
-        if (wmin != KNONE) {
-            const uint64_t who = __ballot(best == wmin);
+        // the wave's winner slot for minimum key wm among the lanes' keys
+        // bsel (a whole-wave call), and the copy of its candidate row;
+        // padding keys never win a 32-bit slot
+        auto slot_of = [&](uint32_t wm, uint32_t bsel) -> uint64_t {
+            const uint64_t who = __ballot(bsel == wm);
             const int L = __builtin_ctzll(who);
-            const int ew = (int)(wmin & EMASK);
+            const int ew = (int)(wm & EMASK);
             const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            wkey = qb_tabu_winner(wmin >> EB, ew * TB + wid * 64 + L, xw);
             const int iw = ew * TB + wid * 64 + L;
             uint32_t *rb = rowbuf + ((step & 1) * NW + wid) * W;
             if (iw < n)
                 for (int t = lane; t < W; t += 64) rb[t] = ell[(int64_t)iw * W + t];
-        }
+            if constexpr (K32) {
+                if (wm >= (1u << (31 - WB))) return ~0ull;
+                return ((uint64_t)(((uint32_t)L << 1) | xw) << 32) | ((wm << WB) | (uint32_t)wid);
+            } else {
+                return qb_tabu_winner(wm >> EB, iw, xw);
+            }
+        };
+        uint64_t wkey = ~0ull;
+        if (wmin != KNONE) wkey = slot_of(wmin, best);
         if (lane == 0) red[step & 1][wid] = wkey;
         __syncthreads();
-        uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
-        if (kb == ~0ull) {
-            // every variable is tabu and none aspirates: argmin over all of them
-            const uint32_t b2 = min(kfa, kta);
-            const uint32_t w2 = qb_wave_min_u32(b2);
-            const uint64_t who = __ballot(b2 == w2);
-            const int L = __builtin_ctzll(who);
-            const int ew = (int)(w2 & EMASK);
-            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
-            if (lane == 0) red2[wid] = qb_tabu_winner(w2 >> EB, ew * TB + wid * 64 + L, xw);
-            {
-                const int iw = ew * TB + wid * 64 + L;
-                uint32_t *rb = rowbuf + ((step & 1) * NW + wid) * W;
-                if (iw < n)
-                    for (int t = lane; t < W; t += 64) rb[t] = ell[(int64_t)iw * W + t];
+        uint32_t dib;
+        int i;
+        int32_t s;                                 // direction of x_i
+        if constexpr (K32) {
+            uint32_t key = 0, hi = 0;
+            if (!qb_pick32<NW>(red[step & 1], lane, key, hi)) {
+                // every variable is tabu and none aspirates: argmin over all of them
+                const uint32_t b2 = min(kfa, kta);
+                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint64_t k2 = slot_of(w2, b2);
+                if (lane == 0) red2[wid] = k2;
+                __syncthreads();
+                qb_pick32<NW>(red2, lane, key, hi);
             }
-            __syncthreads();
-            kb = qb_min_winners<NW>(red2, lane);
+            const uint32_t wm = key >> WB;
+            dib = wm >> EB;
+            i = (int)(wm & EMASK) * TB + (int)(key & (NW - 1)) * 64 + (int)(hi >> 1);
+            s = (hi & 1u) ? -1 : 1;
+        } else {
+            uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
+            if (kb == ~0ull) {
+                // every variable is tabu and none aspirates: argmin over all of them
+                const uint32_t b2 = min(kfa, kta);
+                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint64_t k2 = slot_of(w2, b2);
+                if (lane == 0) red2[wid] = k2;
+                __syncthreads();
+                kb = qb_min_winners<NW>(red2, lane);
+            }
+            dib = (uint32_t)(kb >> 32);
+            i = __builtin_amdgcn_readfirstlane((int)((uint32_t)kb >> 1));
+            s = (kb & 1) ? -1 : 1;
         }
-        const uint32_t dib = (uint32_t)(kb >> 32);
-        const int i = __builtin_amdgcn_readfirstlane((int)((uint32_t)kb >> 1));
-        const int32_t s = (kb & 1) ? -1 : 1;   // direction of x_i
         OV += (int64_t)(int32_t)(dib - bias);
 
         // neighbours j of i: h_j += s Q_ji, so D_j += 2(1-2x_j) s Q_ji
@@ -344,11 +364,18 @@ qb_status qb_tabu_sparse_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int
 #define QB_T(K)                                                                                     \
     if (ept == K) {                                                                                \
         if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;          \
-        if (lds > 48 * 1024)                                                                       \
-            QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_sp<K>,                             \
+        if (lds > 48 * 1024) {                                                                     \
+            QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_sp<K, true>,                       \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-        k_tabu_sp<K><<<z, TB, lds, s>>>(P->ell, P->ellw, P->diag, P->n, X, H, E, alpha, tenure, asp, T, LF,      \
-                                      bias);                                                       \
+            QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_sp<K, false>,                      \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+        }                                                                                          \
+        if (((2 * dmax + 1) << qb_ceil_log2(K)) < (int64_t(1) << (31 - WB)))                         \
+            k_tabu_sp<K, true><<<z, TB, lds, s>>>(P->ell, P->ellw, P->diag, P->n, X, H, E, alpha, tenure, \
+                                                  asp, T, LF, bias);                                 \
+        else                                                                                       \
+            k_tabu_sp<K, false><<<z, TB, lds, s>>>(P->ell, P->ellw, P->diag, P->n, X, H, E, alpha,      \
+                                                   tenure, asp, T, LF, bias);                        \
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
     }
