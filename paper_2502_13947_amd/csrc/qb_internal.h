@@ -163,15 +163,18 @@ constexpr int qb_ceil_log2(int v) { return v <= 1 ? 0 : 1 + qb_ceil_log2((v + 1)
 // row results by readlane.
 __device__ __forceinline__ uint32_t qb_wave_min_u32(uint32_t v)
 {
+    // row minimum in every lane (xor 1, xor 2, half-row mirror, row mirror),
+    // then the rows meet through the gfx950 row-swap moves: no readlane and
+    // no scalar round trip
     v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
     v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
     v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
     v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return min(min(a, b), min(c, d));
+    const auto p16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min(v, min((uint32_t)p16[0], (uint32_t)p16[1]));
+    const auto p32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    v = min(v, min((uint32_t)p32[0], (uint32_t)p32[1]));
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
 // Tabu wave winner: (biased move << 32) | (index << 1) | x_index, so the
