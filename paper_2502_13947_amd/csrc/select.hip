@@ -491,10 +491,20 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
         rc = QB_E_HIP;
     if (rc == QB_OK) {
         if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) rc = QB_E_HIP;
-        for (int c = 0; c < QB_NCLASS && rc == QB_OK; ++c)
+        // side streams only for the size classes after the first one present
+        // (the first runs on the caller's stream): fewer streams share the
+        // process's hardware queues, so the classes really run concurrently
+        bool first = true;
+        for (int c = 0; c < QB_NCLASS && rc == QB_OK; ++c) {
+            if (b->cls_end[c] <= b->cls_begin[c]) continue;
+            if (first) {
+                first = false;
+                continue;
+            }
             if (hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) != hipSuccess)
                 rc = QB_E_HIP;
+        }
     }
     if (rc != QB_OK) {
         qb_set_hip_error(hipGetLastError());
