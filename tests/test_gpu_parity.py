@@ -272,6 +272,9 @@ ANNEAL_CASES = [
     (2200, 1, [700, 1024], 6, 1, True),
     (3200, 1, [1024, 1000, 999], 40, 1, True),
     (1500, 1, [512, 257], 30, 1, False),
+    # several size classes with one replica, launched concurrently
+    (3000, 1, [1024, 512, 256, 128, 40], 20, 1, True),
+    (2000, 1, [512, 256, 200], 12, 1, False),
 ]
 
 
