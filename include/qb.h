@@ -219,8 +219,11 @@ qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t
  * thr_d: int32 [nsw][2^B] (see qb_threshold_table).  tile as qb_extract;
  * int8_tile selects its element type.  Jobs are grouped by padded size and
  * the groups run concurrently (side streams joined back into `stream`),
- * largest first.  Capacity: 1 <= R <= 16, 1 <= B <= 16, nsw >= 1,
- * inst_base + J <= 2^28. */
+ * largest first.  The tile must be symmetric (as qb_extract writes it).
+ * Capacity: 1 <= R <= 16, 1 <= B <= 16, nsw >= 1, inst_base + J <= 2^28.
+ * Where a replica's sweep is spread over several waves of a workgroup, the
+ * waves wait on each other with bounded waits; a replica whose wait runs out
+ * (never seen) reports e = INT64_MIN, so every launch completes. */
 qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
                     const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
                     uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream);
