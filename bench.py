@@ -8,7 +8,7 @@ exact energy, best tracking, mutation and its field update.  The metric is
 spin-flip attempts per second of the whole step (attempts = sum over jobs of
 replicas x sub-QUBO size x sweeps), with every input resident in HBM.
 
-Prints one JSON line.  --gpus above 1 is rejected: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is rejected: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -282,7 +282,7 @@ def ablation_main(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if a.ttt:
         return ttt_main(a)
