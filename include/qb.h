@@ -222,11 +222,19 @@ qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t
  * largest first.  The tile must be symmetric (as qb_extract writes it).
  * Capacity: 1 <= R <= 16, 1 <= B <= 16, nsw >= 1, inst_base + J <= 2^28.
  * Where a replica's sweep is spread over several waves of a workgroup, the
- * waves wait on each other with bounded waits; a replica whose wait runs out
- * (never seen) reports e = INT64_MIN, so every launch completes. */
+ * waves wait on each other with bounded waits (qb_set_anneal_wait_limit); a
+ * replica whose wait runs out (never seen at the default limit) reports
+ * e = INT64_MIN, so every launch completes. */
 qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
                     const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
                     uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream);
+/* Bounds the waits between the waves of one replica in the multi-wave
+ * annealers (qb_anneal): a wave that reads a list word `polls` times without
+ * finding it written gives up, and its replica reports e = INT64_MIN (Y then
+ * holds an unfinished state).  Default 2^24 polls (about a second); 0 makes
+ * every wait that does not succeed at once give up.  Process-wide, takes
+ * effect at the next launch; for tests of that path.  QB_E_ARG if polls < 0. */
+qb_status qb_set_anneal_wait_limit(int32_t polls);
 
 /* Sparse sub-QUBOs (eq. 4 on a problem made by qb_problem_create_csr).  Same
  * c, F0 and y0 as qb_extract; the tile is an ELL of width W = ell_width:

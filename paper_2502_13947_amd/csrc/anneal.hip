@@ -19,6 +19,8 @@
 // LDS; mp = 512 int8: the 36 upper 64x64 blocks of the symmetric tile in LDS
 // (156,672 bytes, rows padded to 68 bytes so that both row and column reads
 // of a block are bank-conflict free); otherwise rows stay in L2/HBM.
+#include <atomic>
+
 #include "qb_internal.h"
 
 namespace {
@@ -258,11 +260,12 @@ void launch_anneal(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_ba
 // end mark), word = (G+1) << 8 | k << 1 | (y_k before the flip).  When the
 // owner of G writes its list, every other wave has started a turn after
 // G - MS and so has read list G - MS to its end: the ring never overwrites
-// an unread list.  Every wait is bounded; a replica whose wait runs out
-// reports e = INT64_MIN.
+// an unread list.  Every wait is bounded (qb_set_anneal_wait_limit polls,
+// 2^24 by default); a replica whose wait runs out reports e = INT64_MIN.
 constexpr int MW_SLOTS = 65;
-constexpr int MW_SPIN_LIMIT = 1 << 24;
 constexpr int MW_LDS_LIMIT = 163840;
+// polls of one word before a wave gives up (qb_set_anneal_wait_limit)
+std::atomic<int32_t> g_wait_limit{1 << 24};
 
 template <int MS, typename TT, int MODE>
 struct AnnealMw {
@@ -323,7 +326,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
                                                     const uint8_t *__restrict__ y0, int nsw, int B,
                                                     const int32_t *__restrict__ thr, int R, uint32_t k0,
                                                     uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
-                                                    int64_t *__restrict__ eout)
+                                                    int64_t *__restrict__ eout, int wait_limit)
 {
     using C = AnnealMw<MS, TT, MODE>;
     constexpr int NW = C::NW, NB = C::NB, DW = C::DW, MP = 64 * MS;
@@ -419,7 +422,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
             while (true) {
                 int spins = 0;
                 while ((v >> 8) != want) {
-                    if (++spins > MW_SPIN_LIMIT) {
+                    if (++spins > wait_limit) {
                         ok = false;
                         break;
                     }
@@ -514,7 +517,8 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
     if (R > C::RMAX || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
     k_anneal_mw<MS, TT, MODE><<<nblocks, 64 * C::NW * R, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles,
                                                                  F0, y0, nsw, B, thr, R, (uint32_t)seed,
-                                                                 (uint32_t)(seed >> 32), inst_base, Y, e);
+                                                                 (uint32_t)(seed >> 32), inst_base, Y, e,
+                                                                 g_wait_limit.load(std::memory_order_relaxed));
     return true;
 }
 
@@ -555,7 +559,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                                                      const uint8_t *__restrict__ y0, int nsw, int B,
                                                      const int32_t *__restrict__ thr, int R, uint32_t k0,
                                                      uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
-                                                     int64_t *__restrict__ eout)
+                                                     int64_t *__restrict__ eout, int wait_limit)
 {
     using C = AnnealMwG<MS, TT>;
     constexpr int NW = C::NW, NB = C::NB, DW = C::DW, PER = C::PER, P = C::P, SLOTS = C::SLOTS;
@@ -667,7 +671,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                     }
                 }
                 if (n == 0 && !end) {
-                    if (++spins > MW_SPIN_LIMIT) {
+                    if (++spins > wait_limit) {
                         ok = false;
                         break;
                     }
@@ -762,7 +766,8 @@ bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, 
     k_anneal_mw_g<MS, TT><<<nblocks, 64 * AnnealMwG<MS, TT>::NW, 0, s>>>(jobs, b->off_d, b->tile_off_d,
                                                                       (const TT *)tiles, F0, y0, nsw, B, thr, R,
                                                                       (uint32_t)seed, (uint32_t)(seed >> 32),
-                                                                      inst_base, Y, e);
+                                                                      inst_base, Y, e,
+                                                                      g_wait_limit.load(std::memory_order_relaxed));
     return true;
 }
 
@@ -896,5 +901,12 @@ extern "C" qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, con
     k_writeback<<<b->J, 256, 0, qb_stream(stream)>>>(b->n, R, b->sol_d, b->off_d, b->idx_d, Y_d, e_d, y0_d, X_d,
                                                      dX_d, ebest_job_d, flags & 1);
     QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
+extern "C" qb_status qb_set_anneal_wait_limit(int32_t polls)
+{
+    if (polls < 0) return QB_E_ARG;
+    g_wait_limit.store(polls, std::memory_order_relaxed);
     return QB_OK;
 }

@@ -74,6 +74,7 @@ SIGNATURES = {
     "qb_extract_ell": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "qb_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _I32, _U64, _U32, _P, _P, _P]),
     "qb_anneal_ising_workspace": (_SZ, [_P, _I32]),
+    "qb_set_anneal_wait_limit": (_I32, [_I32]),
     "qb_anneal_ising": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P, _P]),
     "qb_threshold_table": (_I32, [_I32, _I32, _F64, _F64, _P]),
     "qb_writeback": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
@@ -314,6 +315,15 @@ def threshold_table(nsw, B, tmax, tmin) -> np.ndarray:
     thr = np.zeros((nsw, 1 << B), np.int32)
     _chk(lib().qb_threshold_table(nsw, B, float(tmax), float(tmin), thr.ctypes.data), "qb_threshold_table")
     return thr
+
+
+DEFAULT_ANNEAL_WAIT_LIMIT = 1 << 24
+
+
+def set_anneal_wait_limit(polls: int):
+    """Polls of one list word after which a wave of the multi-wave annealers
+    gives up (its replica then reports e = INT64_MIN); for failure-path tests."""
+    _chk(lib().qb_set_anneal_wait_limit(int(polls)), "qb_set_anneal_wait_limit")
 
 
 WB_NOT_WORSE = 1

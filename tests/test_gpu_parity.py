@@ -311,6 +311,64 @@ def test_anneal_bit_exact(n, z, sizes, nsw, R, int8):
         assert (eh[q * R:(q + 1) * R] == eo).all(), (q, mm)
 
 
+def test_anneal_wait_limit_bails_out_cleanly():
+    """With a zero wait limit every wait between the waves of a replica that
+    does not succeed at once gives up: every launch still completes, each
+    replica reports either e = INT64_MIN or the oracle's exact result, and
+    the default limit restores full parity on the same batch."""
+    n, z, sizes, nsw, R = 3000, 2, [1024, 512, 256, 100], 6, 1
+    say("anneal wait limit", n, z, sizes, nsw, R)
+    Q = inputs.dense_qubo(n, 0.5, 41)
+    X = inputs.random_solutions(z, n, 42)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, sizes, 43)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    tiles = torch.zeros(b.tile_elems, dtype=qb().tile_dtype(P), device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
+    B = 10
+    thr = oracle.threshold_table(nsw, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr_d = torch.as_tensor(thr, device=DEV)
+    seed, inst = 0x51, 300
+    ref = []
+    for q in range(b.J):
+        Sq = idx[b.off[q]:b.off[q + 1]]
+        Tq, c, F, yy = oracle.extract(Q, X[sol[q]], H[sol[q]], Sq)
+        ref.append(oracle.anneal(Tq, F, yy, thr, R, seed, inst + q, B))
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    qb().set_anneal_wait_limit(0)
+    try:
+        qb().anneal(b, tiles, F0, y0, thr_d, R, seed, inst, Y, e, B)
+        torch.cuda.synchronize()
+    finally:
+        qb().set_anneal_wait_limit(qb().DEFAULT_ANNEAL_WAIT_LIMIT)
+    Yh, eh = Y.cpu().numpy(), e.cpu().numpy()
+    gave_up = 0
+    for q in range(b.J):
+        mm = int(b.off[q + 1] - b.off[q])
+        Yo, eo = ref[q]
+        got = Yh[b.off[q] * R:(b.off[q] + mm) * R].reshape(R, mm)
+        for r in range(R):
+            if eh[q * R + r] == np.iinfo(np.int64).min:
+                gave_up += 1
+            else:
+                assert eh[q * R + r] == eo[r] and (got[r] == Yo[r]).all(), (q, r)
+    assert gave_up >= 1
+    with pytest.raises(qb().QBError):
+        qb().set_anneal_wait_limit(-1)
+    qb().anneal(b, tiles, F0, y0, thr_d, R, seed, inst, Y, e, B)
+    Yh, eh = Y.cpu().numpy(), e.cpu().numpy()
+    for q in range(b.J):
+        mm = int(b.off[q + 1] - b.off[q])
+        Yo, eo = ref[q]
+        assert (Yh[b.off[q] * R:(b.off[q] + mm) * R].reshape(R, mm) == Yo).all(), q
+        assert (eh[q * R:(q + 1) * R] == eo).all(), q
+
+
 def test_threshold_table_matches_oracle():
     for nsw, B, tmax, tmin in [(1, 10, 100.0, 1.0), (200, 10, 2047.3, 8.2), (37, 4, 5.0, 0.0),
                                (3, 16, 1e9, 1e8)]:
