@@ -264,8 +264,10 @@ void launch_anneal(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_ba
 // 2^24 by default); a replica whose wait runs out reports e = INT64_MIN.
 constexpr int MW_SLOTS = 65;
 constexpr int MW_LDS_LIMIT = 163840;
-// polls of one word before a wave gives up (qb_set_anneal_wait_limit)
-std::atomic<int32_t> g_wait_limit{1 << 24};
+// polls of one word before a wave gives up (qb_set_anneal_wait_limit); the
+// kernels take it as a constant unless it was changed from the default
+constexpr int32_t MW_WAIT_DEFAULT = 1 << 24;
+std::atomic<int32_t> g_wait_limit{MW_WAIT_DEFAULT};
 
 template <int MS, typename TT, int MODE>
 struct AnnealMw {
@@ -319,7 +321,7 @@ __device__ __forceinline__ int32_t diag_at(const uint32_t (&d)[DW], int k)
         return (int32_t)(int16_t)(d[k >> 1] >> ((k & 1) * 16));
 }
 
-template <int MS, typename TT, int MODE>
+template <int MS, typename TT, int MODE, bool LIM>
 __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
                                                     const int64_t *__restrict__ tile_off,
                                                     const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
@@ -422,7 +424,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
             while (true) {
                 int spins = 0;
                 while ((v >> 8) != want) {
-                    if (++spins > wait_limit) {
+                    if (++spins > (LIM ? wait_limit : MW_WAIT_DEFAULT)) {
                         ok = false;
                         break;
                     }
@@ -515,10 +517,15 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
     using C = AnnealMw<MS, TT, MODE>;
     // replicas per workgroup, and list tags G + 1 < 2^24 that cannot wrap
     if (R > C::RMAX || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
-    k_anneal_mw<MS, TT, MODE><<<nblocks, 64 * C::NW * R, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles,
-                                                                 F0, y0, nsw, B, thr, R, (uint32_t)seed,
-                                                                 (uint32_t)(seed >> 32), inst_base, Y, e,
-                                                                 g_wait_limit.load(std::memory_order_relaxed));
+    const int32_t lim = g_wait_limit.load(std::memory_order_relaxed);
+    if (lim == MW_WAIT_DEFAULT)
+        k_anneal_mw<MS, TT, MODE, false><<<nblocks, 64 * C::NW * R, 0, s>>>(
+            jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
+            (uint32_t)(seed >> 32), inst_base, Y, e, lim);
+    else
+        k_anneal_mw<MS, TT, MODE, true><<<nblocks, 64 * C::NW * R, 0, s>>>(
+            jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
+            (uint32_t)(seed >> 32), inst_base, Y, e, lim);
     return true;
 }
 
@@ -551,7 +558,7 @@ __device__ __forceinline__ int own_pair(int a, int b, int nb)   // a < b < nb
     return a * nb - (a * (a + 1)) / 2 + (b - a - 1);
 }
 
-template <int MS, typename TT>
+template <int MS, typename TT, bool LIM>
 __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__ jobs,
                                                      const int32_t *__restrict__ off,
                                                      const int64_t *__restrict__ tile_off,
@@ -671,7 +678,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                     }
                 }
                 if (n == 0 && !end) {
-                    if (++spins > wait_limit) {
+                    if (++spins > (LIM ? wait_limit : MW_WAIT_DEFAULT)) {
                         ok = false;
                         break;
                     }
@@ -763,11 +770,16 @@ bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, 
                         uint32_t inst_base, uint8_t *Y, int64_t *e)
 {
     if (R != 1 || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
-    k_anneal_mw_g<MS, TT><<<nblocks, 64 * AnnealMwG<MS, TT>::NW, 0, s>>>(jobs, b->off_d, b->tile_off_d,
-                                                                      (const TT *)tiles, F0, y0, nsw, B, thr, R,
-                                                                      (uint32_t)seed, (uint32_t)(seed >> 32),
-                                                                      inst_base, Y, e,
-                                                                      g_wait_limit.load(std::memory_order_relaxed));
+    const int32_t lim = g_wait_limit.load(std::memory_order_relaxed);
+    constexpr int NT = 64 * AnnealMwG<MS, TT>::NW;
+    if (lim == MW_WAIT_DEFAULT)
+        k_anneal_mw_g<MS, TT, false><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
+                                                            y0, nsw, B, thr, R, (uint32_t)seed,
+                                                            (uint32_t)(seed >> 32), inst_base, Y, e, lim);
+    else
+        k_anneal_mw_g<MS, TT, true><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
+                                                           y0, nsw, B, thr, R, (uint32_t)seed,
+                                                           (uint32_t)(seed >> 32), inst_base, Y, e, lim);
     return true;
 }
 
