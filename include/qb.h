@@ -186,13 +186,13 @@ qb_status qb_batch_set_idx(qb_batch b, const int32_t *idx_h, void *stream);
 /* Copies the handle's index sets (int32 [total]) into idx_d. */
 qb_status qb_batch_copy_idx(qb_batch b, int32_t *idx_d, void *stream);
 
-/* Plain selection (Alg. 3 line 2): job q takes the ranks [rank0[q],
+/* Plain selection (the selection step of Alg. 3): job q takes the ranks [rank0[q],
  * rank0[q] + m_q) of its solution in order_d and stores their indices
  * ascending in the handle's idx. */
 qb_status qb_select(qb_batch b, const int32_t *order_d, void *stream);
 
 /* ---------------------------------------------------------------- a4
- * Sub-QUBO extraction, eq. 4 / Alg. 3 lines 3-5, against the state (X, H).
+ * Sub-QUBO extraction, eq. 4 / the sub-QUBO construction of Alg. 3, against the state (X, H).
  * For job q with S = idx of q, m = m_q, MS = the power of two >= ceil(m/64)
  * (1, 2, 4, 8 or 16) and mp = 64 MS:
  *   tile  (int8 if the problem is int8_ok, else int16), element
@@ -285,7 +285,7 @@ qb_status qb_anneal_ising(qb_batch b, const void *J_tile_d, int32_t int8_tile, c
 qb_status qb_threshold_table(int32_t nsw, int32_t B, double tmax, double tmin, int32_t *thr_h);
 
 /* ---------------------------------------------------------------- a6/a7/a8
- * Write-back (Alg. 3 line 7): per job the replica with the lowest e (lowest
+ * Write-back (the last step of Alg. 3): per job the replica with the lowest e (lowest
  * r on ties) is written into X[sol][S] unconditionally, and dX[sol][S] =
  * Y - y0 (int8 in {-1,0,1}).  flags bit 0 (QB_WB_NOT_WORSE): write a job
  * back only if that e <= 0 (the "only if not worse" variant; otherwise X
@@ -328,7 +328,7 @@ double qb_mutation_rate(int32_t t);
  * Learned selection.  An MLP scores every (solution, variable) and the top
  * scores go to the annealer instead of the top control-parameter values;
  * the plain keys still drive the mutation, and the exact integer energy still
- * judges every result, so the network only changes which variables are
+ * decides every result, so the network only changes which variables are
  * chosen, never the arithmetic.
  *
  * qb_features: eight features per (p, j), each an FP32 product of an integer

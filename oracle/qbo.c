@@ -531,7 +531,7 @@ static void best_update(int n, int z, const uint8_t *X, const int64_t *E,
         }
 }
 
-/* Write-back (Alg. 3 line 7): the replica with the lowest e (lowest r on
+/* Write-back (the last step of Alg. 3): the replica with the lowest e (lowest r on
  * ties) replaces x_S -- unconditionally as in the listing, or, in the
  * "only if not worse" variant, only when its e <= 0.  Returns 1 if written. */
 static int pick_and_write(int m, const int32_t *S, const uint8_t *Y, const int64_t *e, int R,

@@ -1,5 +1,5 @@
-// Sub-QUBO extraction (eq. 4, Alg. 3 lines 3-5), the batched Ising-machine
-// stage (Alg. 3 line 6) and the write-back (Alg. 3 line 7) on gfx950.
+// Sub-QUBO extraction (eq. 4, sub-QUBO construction in Alg. 3), the batched
+// Ising-machine stage and the write-back of Alg. 3 on gfx950.
 //
 // Annealer layout (the one-wave kernel; the multi-wave kernels below spread
 // the same sweep over several waves): one replica per wave64, the R

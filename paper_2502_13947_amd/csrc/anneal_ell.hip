@@ -1,5 +1,6 @@
-// Sparse sub-QUBOs: extraction into a per-job ELL (eq. 4, Alg. 3 lines 3-5)
-// and the batched Ising-machine stage on it (Alg. 3 line 6) on gfx950.
+// Sparse sub-QUBOs: extraction into a per-job ELL (eq. 4, sub-QUBO
+// construction in Alg. 3) and the batched Ising-machine stage of Alg. 3 on it,
+// on gfx950.
 //
 // The annealer is the dense kernel's ballot-block sweep with the same
 // random numbers and thresholds, so Y and e are bit-identical to it: lane L

@@ -1,5 +1,5 @@
-// Control-parameter keys (Alg. 4), rank order, plain selection (Alg. 3
-// line 2), the job batch handle, and mutation (end of the heuristic section).
+// Control-parameter keys (Alg. 4), rank order, plain selection (the
+// selection step of Alg. 3), the job batch handle, and mutation (end of the heuristic section).
 #include <math.h>
 
 #include <algorithm>

@@ -160,7 +160,7 @@ class Solver:
         qb.best(self.X, self.E, self.ebest, self.xbest, stream=stream)
 
     def init(self):
-        """Alg. 2 lines 1-2: random set, field, energy, then the initial pass."""
+        """Start of Alg. 2: random set, field, energy, then the initial pass."""
         n, z, s = self.n, self.z, self.stream
         qb.init_solutions(n, z, self.seed, self.X, stream=s)
         qb.field(self.P, self.X, self.H, stream=s)
@@ -226,7 +226,7 @@ class Solver:
         return g
 
     def iterate(self, stream=None, marks=None):
-        """One outer iteration of Alg. 2 (lines 6-11).  ``marks`` (optional) is
+        """One outer iteration of the main loop of Alg. 2.  ``marks`` (optional) is
         a callable invoked with a stage name between launches, e.g. to record
         timing events on the stream."""
         s = stream if stream is not None else self.stream
