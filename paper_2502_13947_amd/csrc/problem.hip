@@ -89,6 +89,18 @@ __global__ void k_pad_copy(const int16_t *__restrict__ Q, int n, int ld, T *__re
         out[(int64_t)i * ld + j] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
 }
 
+// Rows of Q in the dense Tabu kernel's thread-chunk order (qb_tabu_pos),
+// zero past column n.
+template <typename T>
+__global__ void k_tabu_copy(const int16_t *__restrict__ Q, int n, int ld, int ept, T *__restrict__ out)
+{
+    const int i = blockIdx.y;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ld; j += gridDim.x * blockDim.x) {
+        const int pos = qb_tabu_pos(j / QB_TABU_THREADS, j % QB_TABU_THREADS, ept, (int)sizeof(T));
+        out[(int64_t)i * ld + pos] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
+    }
+}
+
 __global__ void k_diag(const int16_t *__restrict__ Q, int n, int32_t *__restrict__ diag)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -156,12 +168,19 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
         if (ept) {
             P->ldp = QB_TABU_THREADS * ept;
             const size_t esz = P->int8_ok ? 1 : 2;
-            if (hipMalloc(&P->Qp, esz * (size_t)n * P->ldp) != hipSuccess) { fail(QB_E_HIP); break; }
+            if (hipMalloc(&P->Qp, esz * (size_t)n * P->ldp) != hipSuccess ||
+                hipMalloc(&P->Qt, esz * (size_t)n * P->ldp) != hipSuccess) {
+                fail(QB_E_HIP);
+                break;
+            }
             dim3 g((P->ldp + 255) / 256, n);
-            if (P->int8_ok)
+            if (P->int8_ok) {
                 k_pad_copy<int8_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, (int8_t *)P->Qp);
-            else
+                k_tabu_copy<int8_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, ept, (int8_t *)P->Qt);
+            } else {
                 k_pad_copy<int16_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, (int16_t *)P->Qp);
+                k_tabu_copy<int16_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, ept, (int16_t *)P->Qt);
+            }
         }
         std::vector<int64_t> eta_h(n);
         if (hipMemcpyAsync(eta_h.data(), P->eta, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s) !=
@@ -360,6 +379,7 @@ extern "C" void qb_problem_destroy(qb_problem P)
     if (!P) return;
     if (P->Q8) hipFree(P->Q8);
     if (P->Qp) hipFree(P->Qp);
+    if (P->Qt) hipFree(P->Qt);
     if (P->eta) hipFree(P->eta);
     if (P->colcnt) hipFree(P->colcnt);
     if (P->diag) hipFree(P->diag);

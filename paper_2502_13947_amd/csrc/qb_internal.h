@@ -19,7 +19,9 @@ struct qb_problem_s {
     int32_t *colcnt = nullptr;    // owned, device [n] scratch for qb_keys
     int32_t *status = nullptr;    // owned, device status word
     void *Qp = nullptr;           // owned, device: Q with rows padded to ldp (int8 if int8_ok)
-    int ldp = 0;                  // row pitch of Qp in elements
+    void *Qt = nullptr;           // owned, device: the same rows in the dense Tabu kernel's
+                                  // thread-chunk order (qb_tabu_pos), same type and pitch
+    int ldp = 0;                  // row pitch of Qp and Qt in elements
     int int8_ok = 0;
     int qmax = 0;
     int64_t eta_max = 0;
@@ -52,6 +54,25 @@ static inline int qb_tabu_ept(int n)
     for (int e : opts)
         if (n <= QB_TABU_THREADS * e) return e;
     return 0;
+}
+
+// The dense Tabu kernel's copy of Q.  Thread t of the workgroup owns the
+// variables e * QB_TABU_THREADS + t (e < ept); in a row of the copy its ept
+// elements are split into chunks of 16, 8, 4, 2 and 1 bytes (largest first,
+// the largest repeated as often as it fits), and each chunk is stored for
+// all threads in turn, so one naturally aligned vector load per chunk reads
+// a thread's elements (two loads instead of five at ept = 5, one instead of
+// sixteen at ept = 16 with int8).  Returns the element offset of (e, t)
+// within the row.
+static inline __host__ __device__ int qb_tabu_pos(int e, int t, int ept, int esz)
+{
+    int start = 0;
+    for (int sz = 16 / esz; sz >= 1; sz >>= 1)
+        while (ept - start >= sz) {
+            if (e < start + sz) return start * QB_TABU_THREADS + t * sz + (e - start);
+            start += sz;
+        }
+    return -1;
 }
 
 // Sparse Tabu: 1024 threads, EPT variables each (n <= 20480).
@@ -177,6 +198,22 @@ __device__ __forceinline__ uint32_t qb_wave_min_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Wave minimum, returned uniform: the row minimum in every lane (xor 1,
+// xor 2, half-row mirror, row mirror), then the row broadcasts (lane 15 of
+// each row into the next row, lane 31 into rows 2 and 3) leave the minimum
+// of the whole wave in lane 63.  Six DPP minima and one readlane.
+__device__ __forceinline__ uint32_t qb_wave_min_u32_b(uint32_t v)
+{
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    // rows outside the row mask see the identity of the minimum
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xA, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Tabu wave winner: (biased move << 32) | (index << 1) | x_index, so the
 // 64-bit minimum is the lowest move, then the lowest index.
 __device__ __forceinline__ uint64_t qb_tabu_winner(uint32_t dbias, int j, uint32_t x)
@@ -201,8 +238,10 @@ __device__ __forceinline__ uint64_t qb_dpp_min64(uint64_t v)
 template <int NWV>
 __device__ __forceinline__ bool qb_pick32(const uint64_t *slot, int lane, uint32_t &key, uint32_t &hi)
 {
-    static_assert(NWV >= 1 && NWV <= 16, "one row of 16 lanes");
-    const uint64_t v = lane < NWV ? slot[lane] : ~0ull;
+    static_assert(NWV >= 1 && NWV <= 16 && (NWV & (NWV - 1)) == 0, "a power of two, one row of 16 lanes");
+    // every lane reads a slot (lanes past NWV repeat them), so no lane needs
+    // a fill value and the read needs no exec mask
+    const uint64_t v = slot[lane & (NWV - 1)];
     uint32_t lo = (uint32_t)v;
     lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
     lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]

@@ -3,8 +3,8 @@
 // spread thin and one wave's latency overlaps the others' work) per
 // solution.
 //
-// Thread t owns the variables j = e*1024 + t (e < EPT; every row chunk read is
-// coalesced across the workgroup) and keeps in registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
+// Thread t owns the variables j = e*1024 + t (e < EPT) and keeps in
+// registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
 // to be non-negative), the factor S_j = 2(1-2x_j), and the step U_j after
 // which the variable is free again.  U replaces the tenure vector of the
 // listing: "C_j <= 0 at step t" is exactly "U_j <= t-1" when U is updated
@@ -12,18 +12,23 @@
 //
 // One step: every lane forms a 32-bit key (move value, element) for each of
 // its allowed variables (not tabu, or aspirating: OV + D < OV_min) and keeps
-// the minimum; the wave minimum comes from DPP row operations plus four
-// readlanes; index order inside a wave is (element, lane), so the lowest
+// the minimum; the wave minimum comes from DPP row operations and the row
+// broadcasts; index order inside a wave is (element, lane), so the lowest
 // lane holding the minimal key gives the lowest index; the sixteen wave
-// winners meet in LDS (one barrier per step, double-buffered slots), where a
-// DPP minimum over lanes picks the smallest (32-bit (key, wave) when the
-// move values allow, else 64-bit (move, index, x)).  The chosen variable's
-// row of the padded copy of Q is read (coalesced) and every D is updated by
-// one multiply-add; the owner of the flipped variable patches its own
-// element (a uniform index into its registers).  x_min is never copied:
-// per-variable "flipped since the last improvement" bits recover it, and the
-// field is moved to x_min with the rows of the differing variables.
+// winners meet in LDS (one barrier per step, double-buffered slots, the
+// step loop run in pairs so every slot address is fixed), where a DPP
+// minimum over lanes picks the smallest (32-bit (key, wave) when the move
+// values allow, else 64-bit (move, index, x)).  The chosen variable's row is
+// read from the Tabu copy of Q, where each thread's elements lie in a few
+// naturally aligned chunks (qb_tabu_pos), so a wave issues one vector load
+// per chunk rather than one byte load per element; every D is updated by
+// one multiply-add and the owner of the flipped variable patches its own
+// element.  x_min is never copied: per-variable "flipped since the last
+// improvement" bits recover it, and the field is moved to x_min with the
+// rows of the differing variables.
 #include "qb_internal.h"
+
+#include <type_traits>
 
 namespace {
 
@@ -39,8 +44,45 @@ constexpr int NW = TB / 64;
 // gives its lane and x.  Used when every real key fits 31 - WB bits.
 constexpr int WB = qb_ceil_log2(NW);
 
+// Thread tid's elements of one row of the Tabu copy of Q (the chunk order of
+// qb_tabu_pos): one naturally aligned vector load per chunk, chunks of SZ
+// elements from element START on, then the elements sign-extended.
+template <typename QT, int EPT, int START = 0, int SZ = 16 / (int)sizeof(QT)>
+__device__ __forceinline__ void tabu_row(const QT *row, uint32_t tid, int32_t (&q)[EPT])
+{
+    if constexpr (SZ >= 1 && START < EPT) {
+        if constexpr (EPT - START >= SZ) {
+            constexpr int BYTES = SZ * (int)sizeof(QT);
+            const uint8_t *p = reinterpret_cast<const uint8_t *>(row + START * TB) + tid * (uint32_t)BYTES;
+            uint32_t w[(BYTES + 3) / 4];
+            if constexpr (BYTES == 16) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(p);
+                w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            } else if constexpr (BYTES == 8) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(p);
+                w[0] = v.x; w[1] = v.y;
+            } else if constexpr (BYTES == 4) {
+                w[0] = *reinterpret_cast<const uint32_t *>(p);
+            } else if constexpr (BYTES == 2) {
+                w[0] = *reinterpret_cast<const uint16_t *>(p);
+            } else {
+                w[0] = *p;
+            }
+#pragma unroll
+            for (int k = 0; k < SZ; ++k) {
+                const uint32_t word = w[(k * (int)sizeof(QT)) / 4];
+                const int sh = ((k * (int)sizeof(QT)) % 4) * 8;
+                q[START + k] = sizeof(QT) == 1 ? (int32_t)(int8_t)(word >> sh) : (int32_t)(int16_t)(word >> sh);
+            }
+            tabu_row<QT, EPT, START + SZ, SZ>(row, tid, q);
+        } else {
+            tabu_row<QT, EPT, START, SZ / 2>(row, tid, q);
+        }
+    }
+}
+
 template <int EPT, typename QT, bool K32>
-__global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp, const int16_t *__restrict__ Q16,
+__global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qt, int ldp, const int16_t *__restrict__ Q16,
                                              int n, uint8_t *__restrict__ X, int32_t *__restrict__ H,
                                              int64_t *__restrict__ E, int alpha, int tenure, int asp,
                                              int32_t *__restrict__ Tout, int32_t *__restrict__ LFout,
@@ -65,8 +107,8 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     uint32_t Kb[EPT];      // ((D + bias) << EB | e) | TBIT if tabu
     int32_t S[EPT];        // 2 (1 - 2 x) << EB
     int32_t U[EPT];        // tabu through step U
-    uint64_t xb = 0;       // x bits of the owned variables
-    uint64_t pb = 0;       // flipped since the last improvement
+    uint32_t xb = 0;       // x bits of the owned variables (EPT <= 16)
+    uint32_t pb = 0;       // flipped since the last improvement
     int32_t nexp = 0x7fffffff;   // smallest U among the thread's tabu variables
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -76,7 +118,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const int32_t x = X[ro + j] & 1;
             const int32_t qjj = Q16[(int64_t)j * n + j];
             S[e] = (x ? -2 : 2) << EB;
-            xb |= (uint64_t)x << e;
+            xb |= (uint32_t)x << e;
             Kb[e] = (((uint32_t)(qjj + (x ? -2 : 2) * H[ro + j]) + bias) << EB) | (uint32_t)e;
             Ts[j] = 0;
             Ls[j] = 0;
@@ -86,38 +128,48 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             U[e] = 0x7fffffff;                   // never allowed
         }
     }
-    int64_t OV = E[p], OVmin = OV;
+    int64_t OV = E[p];
+    int64_t gap = 0;       // OV - OV_min, never negative
+    const int wu = __builtin_amdgcn_readfirstlane(wid);
 
-    for (int step = 1; step <= alpha; ++step) {
-        // aspiration in the biased domain: D + bias < (OVmin - OV) + bias
-        const int64_t tau = OVmin - OV + (int64_t)bias;
-        const uint32_t tb = tau <= 0 ? 0u : (uint32_t)tau;
+    // One step; consecutive steps alternate the two slot buffers, so the loop
+    // runs in pairs and every LDS address is fixed.
+    auto one_step = [&](const int step, uint64_t *slots) {
+        // aspiration: a tabu key k aspirates when (k >> EB) < OV_min - OV + bias,
+        // that is k < tbk (zero when nothing can aspirate)
+        uint32_t tbk = 0;
+        {
+            const uint32_t gh = (uint32_t)((uint64_t)gap >> 32), gl = (uint32_t)gap;
+            if (asp && gh == 0u && gl < bias) tbk = (bias - gl) << EB;
+        }
         const int32_t free_at = step - 1;
         if (free_at >= nexp) {
-            // a tabu variable of this thread is free again
+            // a tabu variable of this thread is free again.  Every variable
+            // that is not tabu has U <= free_at already (clearing its bit is a
+            // no-op), and padding never frees (U = INT_MAX), so no per-element
+            // branch is needed
             nexp = 0x7fffffff;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                if (Kb[e] & TBIT) {
-                    if (U[e] <= free_at)
-                        Kb[e] &= ~TBIT;
-                    else
-                        nexp = min(nexp, U[e]);
-                }
+                const bool freed = U[e] <= free_at;
+                Kb[e] &= freed ? ~TBIT : ~0u;
+                nexp = min(nexp, freed ? 0x7fffffff : U[e]);
             }
         }
-        // smallest free key and smallest tabu key: the smallest tabu key
-        // aspirates (D < OV_min - OV) whenever any tabu key does
-        uint32_t m1 = KNONE, m2 = KNONE;
+        // smallest free key (tabu keys carry bit 31, so they lose the
+        // unsigned minimum) and smallest tabu key (they win the signed one);
+        // the smallest tabu key aspirates whenever any does
+        uint32_t m1 = KNONE;
+        int32_t m2 = 0x7fffffff;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             m1 = min(m1, Kb[e]);
-            m2 = min(m2, Kb[e] ^ TBIT);
+            m2 = min(m2, (int32_t)Kb[e]);
         }
-        const uint32_t fk = m1 < TBIT ? m1 : KNONE;
-        const uint32_t tk = m2 < TBIT ? m2 : KNONE;
-        const uint32_t best = min(fk, (asp && (tk >> EB) < tb) ? tk : KNONE);
-        const uint32_t wmin = qb_wave_min_u32(best);
+        const uint32_t fk = (uint32_t)max((int32_t)m1, -1);    // KNONE when every key is tabu
+        const uint32_t tk = (uint32_t)m2 ^ TBIT;               // >= TBIT (never aspirates) when none is
+        const uint32_t best = min(fk, tk < tbk ? tk : KNONE);
+        const uint32_t wmin = qb_wave_min_u32_b(best);
         // the wave's winner slot for minimum key wm among the lanes' keys bsel
         // (a whole-wave call); padding keys never win a K32 slot
         auto slot_of = [&](uint32_t wm, uint32_t bsel) -> uint64_t {
@@ -126,27 +178,27 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const uint64_t who = __ballot(bsel == wm);
             const int L = __builtin_ctzll(who);
             const int ew = (int)(wm & EMASK);
-            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
+            const uint32_t xw = ((uint32_t)__builtin_amdgcn_readlane((int)xb, L) >> ew) & 1u;
             if constexpr (K32) {
                 if (wm >= (1u << (31 - WB))) return ~0ull;
-                return ((uint64_t)(((uint32_t)L << 1) | xw) << 32) | ((wm << WB) | (uint32_t)wid);
+                return ((uint64_t)(((uint32_t)L << 1) | xw) << 32) | ((wm << WB) | (uint32_t)wu);
             } else {
-                return qb_tabu_winner(wm >> EB, ew * TB + wid * 64 + L, xw);
+                return qb_tabu_winner(wm >> EB, ew * TB + wu * 64 + L, xw);
             }
         };
         uint64_t wkey = ~0ull;
-        if (wmin != 0xFFFFFFFFu) wkey = slot_of(wmin, best);
-        if (lane == 0) red[step & 1][wid] = wkey;
+        if (wmin != KNONE) wkey = slot_of(wmin, best);
+        if (lane == 0) slots[wid] = wkey;
         __syncthreads();
         uint32_t dib;
         int i;
         int32_t s;                                 // direction of x_i
         if constexpr (K32) {
             uint32_t key = 0, hi = 0;
-            if (!qb_pick32<NW>(red[step & 1], lane, key, hi)) {
+            if (!qb_pick32<NW>(slots, lane, key, hi)) {
                 // every variable is tabu and none aspirates: argmin over all of them
                 const uint32_t b2 = min(fk, tk);
-                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint32_t w2 = qb_wave_min_u32_b(b2);
                 const uint64_t k2 = slot_of(w2, b2);
                 if (lane == 0) red2[wid] = k2;
                 __syncthreads();
@@ -157,11 +209,11 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             i = (int)(wm & EMASK) * TB + (int)(key & (NW - 1)) * 64 + (int)(hi >> 1);
             s = (hi & 1u) ? -1 : 1;
         } else {
-            uint64_t kb = qb_min_winners<NW>(red[step & 1], lane);
+            uint64_t kb = qb_min_winners<NW>(slots, lane);
             if (kb == ~0ull) {
                 // every variable is tabu and none aspirates: argmin over all of them
                 const uint32_t b2 = min(fk, tk);
-                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint32_t w2 = qb_wave_min_u32_b(b2);
                 const uint64_t k2 = slot_of(w2, b2);
                 if (lane == 0) red2[wid] = k2;
                 __syncthreads();
@@ -171,13 +223,13 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             i = (int)((uint32_t)kb >> 1);
             s = (kb & 1) ? -1 : 1;
         }
-        OV += (int64_t)(int32_t)(dib - bias);
+        const int32_t dmove = (int32_t)(dib - bias);
+        OV += dmove;
+        gap += dmove;
+        // the row base is uniform (scalar registers); each lane adds its own
+        // 32-bit chunk offsets
         int32_t q[EPT];
-        {
-            const QT *rowp = Qp + (int64_t)i * ldp + tid;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) q[e] = rowp[e * TB];
-        }
+        tabu_row<QT, EPT>(Qt + (uint32_t)i * (uint32_t)ldp, (uint32_t)tid, q);
         // h_j += s Q_ji  =>  D_j += S_j s Q_ji, applied to the key above its
         // element bits (the owner is patched below)
         if (s > 0) {
@@ -189,29 +241,68 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
         }
         const int ti = i & (TB - 1);
         if (tid == ti) {
-            // the owner patches its element ei (uniform, so the register
-            // arrays are indexed directly) and bumps the counters without
+            // the owner patches its element ei and bumps the counters without
             // waiting on LDS
             const int ei = i / TB;
-            xb ^= 1ull << ei;
-            pb ^= 1ull << ei;
+            xb ^= 1u << ei;
+            pb ^= 1u << ei;
             atomicAdd(&Ts[i], 1);
             Ls[i] = step;
-            const int32_t Un = step + max(max(U[ei] - (step - 1), 0) + tenure - 1, 0);
-            U[ei] = Un;
-            S[ei] = -S[ei];
-            uint32_t kn = ((2u * bias - dib) << EB) | (uint32_t)ei;
-            if (Un > step) {
-                kn |= TBIT;
-                nexp = min(nexp, Un);
+            // tenure from this step on (the remaining tenure of an aspirated
+            // variable carries over), and the new key: minus the old move value
+            auto tabu_until = [&](int32_t u) { return step + max(max(u - (step - 1), 0) + tenure - 1, 0); };
+            auto new_key = [&](int32_t un, uint32_t e) {
+                uint32_t kn = ((2u * bias - dib) << EB) | e;
+                if (un > step) {
+                    kn |= TBIT;
+                    nexp = min(nexp, un);
+                }
+                return kn;
+            };
+            auto patch = [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                if constexpr (e < EPT) {
+                    const int32_t Un = tabu_until(U[e]);
+                    U[e] = Un;
+                    S[e] = -S[e];
+                    Kb[e] = new_key(Un, (uint32_t)e);
+                }
+            };
+            static_assert(EPT <= 16, "sixteen cases");
+            if constexpr (EPT <= 10) {
+                // the uniform ei indexes the register arrays (selects over
+                // the few elements)
+                const int32_t Un = tabu_until(U[ei]);
+                U[ei] = Un;
+                S[ei] = -S[ei];
+                Kb[ei] = new_key(Un, (uint32_t)ei);
+            } else switch (ei) {
+                // a scalar branch per element: an index into the larger
+                // arrays would send them to scratch memory
+#define QB_TABU_CASE(c) \
+    case c: patch(std::integral_constant<int, c>{}); break;
+                QB_TABU_CASE(0) QB_TABU_CASE(1) QB_TABU_CASE(2) QB_TABU_CASE(3)
+                QB_TABU_CASE(4) QB_TABU_CASE(5) QB_TABU_CASE(6) QB_TABU_CASE(7)
+                QB_TABU_CASE(8) QB_TABU_CASE(9) QB_TABU_CASE(10) QB_TABU_CASE(11)
+                QB_TABU_CASE(12) QB_TABU_CASE(13) QB_TABU_CASE(14) QB_TABU_CASE(15)
+#undef QB_TABU_CASE
+            default: break;
             }
-            Kb[ei] = kn;
         }
-        if (OV < OVmin) {
-            OVmin = OV;
+        if ((int32_t)((uint64_t)gap >> 32) < 0) {
+            // a new best: x_min is the current x
+            gap = 0;
             pb = 0;
         }
+    };
+
+    int step = 1;
+    for (; step < alpha; step += 2) {
+        one_step(step, red[1]);
+        one_step(step + 1, red[0]);
     }
+    if (step == alpha) one_step(step, red[1]);
+    const int64_t OVmin = OV - gap;
 
     // field of the final x from D, then moved to x_min = x ^ pb row by row
     int32_t h[EPT];
@@ -228,10 +319,10 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     for (int e = 0; e < EPT; ++e) {
         if (tid == 0) lcount = 0;
         __syncthreads();
-        if (e * TB + tid < n && ((pb >> e) & 1ull)) {
+        if (e * TB + tid < n && ((pb >> e) & 1u)) {
             const int pos = atomicAdd(&lcount, 1);
             const int jj = e * TB + tid;
-            list[pos] = ((xb >> e) & 1ull) ? -(jj + 1) : (jj + 1);
+            list[pos] = ((xb >> e) & 1u) ? -(jj + 1) : (jj + 1);
         }
         __syncthreads();
         const int cnt = lcount;
@@ -239,9 +330,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
             const int32_t v = list[u];
             const int32_t sg = v < 0 ? -1 : 1;
             int32_t q[EPT];
-            const QT *rowp = Qp + (int64_t)(v < 0 ? -v - 1 : v - 1) * ldp + tid;
-#pragma unroll
-            for (int e2 = 0; e2 < EPT; ++e2) q[e2] = rowp[e2 * TB];
+            tabu_row<QT, EPT>(Qt + (uint32_t)(v < 0 ? -v - 1 : v - 1) * (uint32_t)ldp, (uint32_t)tid, q);
 #pragma unroll
             for (int e2 = 0; e2 < EPT; ++e2) h[e2] += sg * q[e2];
         }
@@ -251,7 +340,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
     for (int e = 0; e < EPT; ++e) {
         const int j = e * TB + tid;
         if (j < n) {
-            X[ro + j] = (uint8_t)(((xb ^ pb) >> e) & 1ull);
+            X[ro + j] = (uint8_t)(((xb ^ pb) >> e) & 1u);
             H[ro + j] = h[e];
             Tout[ro + j] = Ts[j];
             LFout[ro + j] = Ls[j];
@@ -261,17 +350,17 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qp, int ldp,
 }
 
 template <int EPT, typename QT, bool K32>
-void launch_one(const QT *Qp, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
+void launch_one(const QT *Qt, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
                 int tenure, int asp, int32_t *T, int32_t *LF, uint32_t bias, hipStream_t s)
 {
     const size_t lds = sizeof(int32_t) * 2 * (size_t)P->n;
     (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT, K32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    k_tabu<EPT, QT, K32><<<z, TB, lds, s>>>(Qp, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
+    k_tabu<EPT, QT, K32><<<z, TB, lds, s>>>(Qt, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
 }
 
 template <typename QT>
-qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
+qb_status launch_tabu(qb_problem P, const QT *Qt, int ldp, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
                       int tenure, int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
     const int ept = qb_tabu_ept(P->n);
@@ -282,9 +371,9 @@ qb_status launch_tabu(qb_problem P, const QT *Qp, int ldp, int z, uint8_t *X, in
     if (ept == K) {                                                                               \
         if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;             \
         if (((2 * dmax + 1) << qb_ceil_log2(K)) < (int64_t(1) << (31 - WB)))                         \
-            launch_one<K, QT, true>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);     \
+            launch_one<K, QT, true>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);     \
         else                                                                                       \
-            launch_one<K, QT, false>(Qp, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);    \
+            launch_one<K, QT, false>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);    \
         QB_LAUNCH_CHECK();                                                                         \
         return QB_OK;                                                                              \
     }
@@ -309,8 +398,8 @@ extern "C" qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d
         return qb_tabu_sparse_launch(P, z, X_d, H_d, E_d, alpha, tenure, aspiration != 0, T_d, LF_d, s);
     if (qb_tabu_ept(P->n) == 0) return QB_E_CAPACITY;
     if (P->int8_ok)
-        return launch_tabu<int8_t>(P, (const int8_t *)P->Qp, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
+        return launch_tabu<int8_t>(P, (const int8_t *)P->Qt, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
                                    aspiration != 0, T_d, LF_d, s);
-    return launch_tabu<int16_t>(P, (const int16_t *)P->Qp, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
+    return launch_tabu<int16_t>(P, (const int16_t *)P->Qt, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
                                 aspiration != 0, T_d, LF_d, s);
 }

@@ -98,8 +98,8 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
 
     uint32_t Db[EPT];   // D + bias
     int32_t U[EPT];     // tabu through step U
-    uint64_t xb = 0;    // x bits of the owned variables
-    uint64_t pb = 0;    // flipped since the last improvement
+    uint32_t xb = 0;    // x bits of the owned variables (EPT <= 20)
+    uint32_t pb = 0;    // flipped since the last improvement
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int j = e * TB + tid;
@@ -108,14 +108,15 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             Tout[ro + j] = 0;
             LFout[ro + j] = 0;
             const int32_t x = X[ro + j] & 1;
-            xb |= (uint64_t)x << e;
+            xb |= (uint32_t)x << e;
             Db[e] = (uint32_t)(diag[j] + (x ? -2 : 2) * H[ro + j]) + bias;
         } else {
             Db[e] = dpad;
             U[e] = 0x7fffffff;
         }
     }
-    int64_t OV = E[p], OVmin = OV;
+    int64_t OV = E[p];
+    int64_t gap = 0;    // OV - OV_min, never negative
     constexpr uint32_t KNONE = 0xFFFFFFFFu;
     constexpr int GS = 4;                         // variables per group
     constexpr int G = (EPT + GS - 1) / GS;
@@ -130,8 +131,13 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
     }
 
     for (int step = 1; step <= alpha; ++step) {
-        const int64_t tau = OVmin - OV + (int64_t)bias;
-        const uint32_t tb = tau <= 0 ? 0u : (uint32_t)tau;
+        // aspiration: a tabu key k aspirates when (k >> EB) < OV_min - OV + bias,
+        // that is k < tbk (zero when nothing can aspirate)
+        uint32_t tbk = 0;
+        {
+            const uint32_t gh = (uint32_t)((uint64_t)gap >> 32), gl = (uint32_t)gap;
+            if (asp && gh == 0u && gl < bias) tbk = (bias - gl) << EB;
+        }
         const int32_t free_at = step - 1;
         uint32_t kfa = KNONE, kta = KNONE;
 #pragma unroll
@@ -155,8 +161,8 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             kta = min(kta, kt[g]);
         }
         dirty = 0;
-        const uint32_t best = min(kfa, (asp && (kta >> EB) < tb) ? kta : KNONE);
-        const uint32_t wmin = qb_wave_min_u32(best);
+        const uint32_t best = min(kfa, kta < tbk ? kta : KNONE);
+        const uint32_t wmin = qb_wave_min_u32_b(best);
         // the wave's winner slot for minimum key wm among the lanes' keys
         // bsel (a whole-wave call), and the copy of its candidate row;
         // padding keys never win a 32-bit slot
@@ -164,7 +170,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             const uint64_t who = __ballot(bsel == wm);
             const int L = __builtin_ctzll(who);
             const int ew = (int)(wm & EMASK);
-            const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)((xb >> ew) & 1ull), L);
+            const uint32_t xw = ((uint32_t)__builtin_amdgcn_readlane((int)xb, L) >> ew) & 1u;
             const int iw = ew * TB + wid * 64 + L;
             uint32_t *rb = rowbuf + ((step & 1) * NW + wid) * W;
             if (iw < n)
@@ -188,7 +194,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             if (!qb_pick32<NW>(red[step & 1], lane, key, hi)) {
                 // every variable is tabu and none aspirates: argmin over all of them
                 const uint32_t b2 = min(kfa, kta);
-                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint32_t w2 = qb_wave_min_u32_b(b2);
                 const uint64_t k2 = slot_of(w2, b2);
                 if (lane == 0) red2[wid] = k2;
                 __syncthreads();
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             if (kb == ~0ull) {
                 // every variable is tabu and none aspirates: argmin over all of them
                 const uint32_t b2 = min(kfa, kta);
-                const uint32_t w2 = qb_wave_min_u32(b2);
+                const uint32_t w2 = qb_wave_min_u32_b(b2);
                 const uint64_t k2 = slot_of(w2, b2);
                 if (lane == 0) red2[wid] = k2;
                 __syncthreads();
@@ -213,7 +219,9 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             i = __builtin_amdgcn_readfirstlane((int)((uint32_t)kb >> 1));
             s = (kb & 1) ? -1 : 1;
         }
-        OV += (int64_t)(int32_t)(dib - bias);
+        const int32_t dmove = (int32_t)(dib - bias);
+        OV += dmove;
+        gap += dmove;
 
         // neighbours j of i: h_j += s Q_ji, so D_j += 2(1-2x_j) s Q_ji
         auto nb = [&](uint32_t wd) {
@@ -225,7 +233,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
     case K:                                                                                  \
         if constexpr (K < EPT) {                                                             \
             const uint32_t ko = (Db[K] << EB) | (uint32_t)K;                                 \
-            Db[K] += (uint32_t)(((xb >> K) & 1ull) ? -2 * dv : 2 * dv);                      \
+            Db[K] += (uint32_t)(((xb >> K) & 1u) ? -2 * dv : 2 * dv);                        \
             const uint32_t kn = (Db[K] << EB) | (uint32_t)K;                                 \
             uint32_t &km = U[K] <= free_at ? kf[K / GS] : kt[K / GS];                        \
             if (kn < km)                                                                     \
@@ -257,8 +265,8 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             // the zeroing stores above precede the first step's barrier
             __hip_atomic_fetch_add(Tout + ro + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             LFout[ro + i] = step;
-            xb ^= 1ull << (i >> TSHIFT);
-            pb ^= 1ull << (i >> TSHIFT);
+            xb ^= 1u << (i >> TSHIFT);
+            pb ^= 1u << (i >> TSHIFT);
             switch (i >> TSHIFT) {
 #define QB_OWNER_CASE(K)                                                         \
     case K:                                                                      \
@@ -273,11 +281,13 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             default: break;
             }
         }
-        if (OV < OVmin) {
-            OVmin = OV;
+        if ((int32_t)((uint64_t)gap >> 32) < 0) {
+            // a new best: x_min is the current x
+            gap = 0;
             pb = 0;
         }
     }
+    const int64_t OVmin = OV - gap;
 
     // field of the final x from D, then moved to x_min = x ^ pb by the
     // neighbour lists of the differing variables
@@ -287,17 +297,17 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         const int j = e * TB + tid;
         h[e] = 0;
         if (j < n) {
-            const int32_t sg = ((xb >> e) & 1ull) ? -2 : 2;
+            const int32_t sg = ((xb >> e) & 1u) ? -2 : 2;
             h[e] = ((int32_t)(Db[e] - bias) - diag[j]) * sg / 4;
         }
     }
     for (int e = 0; e < EPT; ++e) {
         if (tid == 0) lcount = 0;
         __syncthreads();
-        if (e * TB + tid < n && ((pb >> e) & 1ull)) {
+        if (e * TB + tid < n && ((pb >> e) & 1u)) {
             const int pos = atomicAdd(&lcount, 1);
             const int jj = e * TB + tid;
-            list[pos] = ((xb >> e) & 1ull) ? -(jj + 1) : (jj + 1);
+            list[pos] = ((xb >> e) & 1u) ? -(jj + 1) : (jj + 1);
         }
         __syncthreads();
         const int cnt = lcount;
@@ -340,7 +350,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
     for (int e = 0; e < EPT; ++e) {
         const int j = e * TB + tid;
         if (j < n) {
-            X[ro + j] = (uint8_t)(((xb ^ pb) >> e) & 1ull);
+            X[ro + j] = (uint8_t)(((xb ^ pb) >> e) & 1u);
             H[ro + j] = h[e];
         }
     }
