@@ -119,6 +119,35 @@ def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
         assert (LF[p].cpu().numpy() == LFo).all()
 
 
+@pytest.mark.parametrize("n,int8", [(4000, True), (6000, True), (8000, True), (10000, True), (12000, True),
+                                    (14000, True), (16000, True), (6000, False), (10000, False),
+                                    (16000, False)])
+def test_tabu_bit_exact_every_row_chunking(n, int8):
+    """Every elements-per-thread count the dense Tabu kernel takes from 4 to
+    16 (n up to its capacity 16384): each splits a thread's part of a row
+    into different aligned chunks (4+2 at 6000, 8 at 8000, 8+2, 8+4, 8+4+2,
+    and 16 at 16000 with int8; 8+8 with int16), and from 12 on the owner
+    patches its element through the per-element branch."""
+    z, alpha, tenure = 2, 400, n // 150
+    say("tabu chunking", n, int8)
+    Q = inputs.dense_qubo(n, 0.3, 31) if int8 else wide_qubo(n, 31)
+    X = inputs.random_solutions(z, n, 32)
+    H = oracle.field(Q, X)
+    E = oracle.energy(X, H)
+    P = qb().Problem(dq(Q))
+    assert bool(P.int8_ok) == int8
+    Xd, Hd, Ed = (torch.as_tensor(a, device=DEV) for a in (X, H, E))
+    T = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    LF = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    qb().tabu(P, Xd, Hd, Ed, alpha, tenure, True, T, LF)
+    for p in range(z):
+        x, h, ov, To, LFo = oracle.tabu(Q, X[p], H[p], int(E[p]), alpha, tenure, True)
+        assert (Xd[p].cpu().numpy() == x).all() and (Hd[p].cpu().numpy() == h).all(), p
+        assert int(Ed[p].item()) == ov, p
+        assert (T[p].cpu().numpy() == To).all() and (LF[p].cpu().numpy() == LFo).all(), p
+    del P
+
+
 def test_tabu_bit_exact_wide_moves():
     """Move values too wide for the 32-bit cross-wave winner key (int16
     weights of +-30000 at n = 5000): the 64-bit winner path."""
