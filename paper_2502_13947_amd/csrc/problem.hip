@@ -157,7 +157,10 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
             fail(QB_E_HIP);
             break;
         }
-        hipMemsetAsync(P->status, 0, sizeof(int32_t), s);
+        if (hipMemsetAsync(P->status, 0, sizeof(int32_t), s) != hipSuccess) {
+            fail(QB_E_HIP);
+            break;
+        }
         k_eta<<<(n + 255) / 256, 256, 0, s>>>(Q_d, n, P->eta);
         k_diag<<<(n + 255) / 256, 256, 0, s>>>(Q_d, n, P->diag);
         if (P->int8_ok) {
@@ -191,7 +194,7 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
         }
         P->eta_max = *std::max_element(eta_h.begin(), eta_h.end());
     } while (0);
-    if (scan_d) hipFree(scan_d);
+    if (scan_d) (void)hipFree(scan_d);
     if (rc != QB_OK) {
         qb_problem_destroy(P);
         return rc;
@@ -364,8 +367,8 @@ extern "C" qb_status qb_problem_create_csr(qb_problem *out, int32_t n, const int
         }
         P->eta_max = *std::max_element(eta_h.begin(), eta_h.end());
     } while (0);
-    if (scan_d) hipFree(scan_d);
-    if (deg_d) hipFree(deg_d);
+    if (scan_d) (void)hipFree(scan_d);
+    if (deg_d) (void)hipFree(deg_d);
     if (rc != QB_OK) {
         qb_problem_destroy(P);
         return rc;
@@ -377,15 +380,15 @@ extern "C" qb_status qb_problem_create_csr(qb_problem *out, int32_t n, const int
 extern "C" void qb_problem_destroy(qb_problem P)
 {
     if (!P) return;
-    if (P->Q8) hipFree(P->Q8);
-    if (P->Qp) hipFree(P->Qp);
-    if (P->Qt) hipFree(P->Qt);
-    if (P->eta) hipFree(P->eta);
-    if (P->colcnt) hipFree(P->colcnt);
-    if (P->diag) hipFree(P->diag);
-    if (P->ell) hipFree(P->ell);
-    if (P->ecnt) hipFree(P->ecnt);
-    if (P->status) hipFree(P->status);
+    if (P->Q8) (void)hipFree(P->Q8);
+    if (P->Qp) (void)hipFree(P->Qp);
+    if (P->Qt) (void)hipFree(P->Qt);
+    if (P->eta) (void)hipFree(P->eta);
+    if (P->colcnt) (void)hipFree(P->colcnt);
+    if (P->diag) (void)hipFree(P->diag);
+    if (P->ell) (void)hipFree(P->ell);
+    if (P->ecnt) (void)hipFree(P->ecnt);
+    if (P->status) (void)hipFree(P->status);
     delete P;
 }
 

@@ -7,6 +7,8 @@
 
 #include "qb_internal.h"
 
+#include <atomic>
+
 namespace {
 
 // c_j = sum_p X[p][j] (the column count behind gamma)
@@ -376,22 +378,22 @@ extern "C" qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *
     while (npad < n) npad <<= 1;
     npad = std::max(npad, 2);
     if (n > RANK_CHUNK) {
-        static bool big_attr_set = false;
-        if (!big_attr_set) {
-            hipFuncSetAttribute((const void *)k_rank_big, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                RANK_CHUNK * (int)sizeof(uint64_t));
-            big_attr_set = true;
+        static std::atomic<bool> big_attr_set{false};
+        if (!big_attr_set.load(std::memory_order_acquire)) {
+            QB_TRY_HIP(hipFuncSetAttribute((const void *)k_rank_big, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           RANK_CHUNK * (int)sizeof(uint64_t)));
+            big_attr_set.store(true, std::memory_order_release);
         }
         k_rank_big<<<z, 1024, RANK_CHUNK * sizeof(uint64_t), qb_stream(stream)>>>(n, npad, K_d, order_d);
         QB_LAUNCH_CHECK();
         return QB_OK;
     }
     const size_t lds = sizeof(uint64_t) * npad;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute((const void *)k_rank, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            16384 * (int)sizeof(uint64_t));
-        attr_set = true;
+    static std::atomic<bool> attr_set{false};
+    if (!attr_set.load(std::memory_order_acquire)) {
+        QB_TRY_HIP(hipFuncSetAttribute((const void *)k_rank, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       16384 * (int)sizeof(uint64_t)));
+        attr_set.store(true, std::memory_order_release);
     }
     k_rank<<<z, 1024, lds, qb_stream(stream)>>>(n, npad, K_d, order_d);
     QB_LAUNCH_CHECK();
@@ -404,12 +406,12 @@ extern "C" void qb_batch_destroy(qb_batch b)
     if (!b) return;
     for (void *ptr : {(void *)b->sol_d, (void *)b->off_d, (void *)b->rank0_d, (void *)b->idx_d,
                       (void *)b->sol_begin_d, (void *)b->tile_off_d, (void *)b->lpt_d})
-        if (ptr) hipFree(ptr);
+        if (ptr) (void)hipFree(ptr);
     for (int c = 0; c < QB_NCLASS; ++c) {
-        if (b->side[c]) hipStreamDestroy(b->side[c]);
-        if (b->ev_join[c]) hipEventDestroy(b->ev_join[c]);
+        if (b->side[c]) (void)hipStreamDestroy(b->side[c]);
+        if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
     }
-    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     delete b;
 }
 
