@@ -92,11 +92,11 @@ __global__ void k_pad_copy(const int16_t *__restrict__ Q, int n, int ld, T *__re
 // Rows of Q in the dense Tabu kernel's thread-chunk order (qb_tabu_pos),
 // zero past column n.
 template <typename T>
-__global__ void k_tabu_copy(const int16_t *__restrict__ Q, int n, int ld, int ept, T *__restrict__ out)
+__global__ void k_tabu_copy(const int16_t *__restrict__ Q, int n, int ld, int ept, int tb, T *__restrict__ out)
 {
     const int i = blockIdx.y;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ld; j += gridDim.x * blockDim.x) {
-        const int pos = qb_tabu_pos(j / QB_TABU_THREADS, j % QB_TABU_THREADS, ept, (int)sizeof(T));
+        const int pos = qb_tabu_pos(j / tb, j % tb, ept, (int)sizeof(T), tb);
         out[(int64_t)i * ld + pos] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
     }
 }
@@ -167,9 +167,28 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
             if (hipMalloc(&P->Q8, (size_t)n * n) != hipSuccess) { fail(QB_E_HIP); break; }
             k_to_int8<<<1024, 256, 0, s>>>(Q_d, P->Q8, (int64_t)n * n);
         }
-        const int ept = qb_tabu_ept(n);
+        std::vector<int64_t> eta_h(n);
+        if (hipMemcpyAsync(eta_h.data(), P->eta, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            fail(QB_E_HIP);
+            break;
+        }
+        P->eta_max = *std::max_element(eta_h.begin(), eta_h.end());
+        // the dense Tabu kernel's workgroup: the preferred size, unless its
+        // wider element field leaves too few key bits for these move values
+        // (the 1024-thread kernel then takes the range it always had)
+        int tb = qb_tabu_threads(n);
+        int ept = qb_tabu_ept(n, tb);
+        const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
+        if (tb != QB_TABU_THREADS && ept && 2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(ept))) {
+            tb = QB_TABU_THREADS;
+            ept = qb_tabu_ept(n, tb);
+        }
         if (ept) {
-            P->ldp = QB_TABU_THREADS * ept;
+            P->tabu_tb = tb;
+            P->tabu_ept = ept;
+            P->ldp = tb * ept;
             const size_t esz = P->int8_ok ? 1 : 2;
             if (hipMalloc(&P->Qp, esz * (size_t)n * P->ldp) != hipSuccess ||
                 hipMalloc(&P->Qt, esz * (size_t)n * P->ldp) != hipSuccess) {
@@ -179,20 +198,16 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
             dim3 g((P->ldp + 255) / 256, n);
             if (P->int8_ok) {
                 k_pad_copy<int8_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, (int8_t *)P->Qp);
-                k_tabu_copy<int8_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, ept, (int8_t *)P->Qt);
+                k_tabu_copy<int8_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, ept, tb, (int8_t *)P->Qt);
             } else {
                 k_pad_copy<int16_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, (int16_t *)P->Qp);
-                k_tabu_copy<int16_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, ept, (int16_t *)P->Qt);
+                k_tabu_copy<int16_t><<<g, 256, 0, s>>>(Q_d, n, P->ldp, ept, tb, (int16_t *)P->Qt);
+            }
+            if (hipGetLastError() != hipSuccess) {
+                fail(QB_E_HIP);
+                break;
             }
         }
-        std::vector<int64_t> eta_h(n);
-        if (hipMemcpyAsync(eta_h.data(), P->eta, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            fail(QB_E_HIP);
-            break;
-        }
-        P->eta_max = *std::max_element(eta_h.begin(), eta_h.end());
     } while (0);
     if (scan_d) (void)hipFree(scan_d);
     if (rc != QB_OK) {

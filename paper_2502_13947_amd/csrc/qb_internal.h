@@ -21,7 +21,9 @@ struct qb_problem_s {
     void *Qp = nullptr;           // owned, device: Q with rows padded to ldp (int8 if int8_ok)
     void *Qt = nullptr;           // owned, device: the same rows in the dense Tabu kernel's
                                   // thread-chunk order (qb_tabu_pos), same type and pitch
-    int ldp = 0;                  // row pitch of Qp and Qt in elements
+    int ldp = 0;                  // row pitch of Qp and Qt in elements: tabu_tb * tabu_ept
+    int tabu_tb = 0;              // dense Tabu workgroup size (0: n beyond its capacity)
+    int tabu_ept = 0;             // dense Tabu variables per thread
     int int8_ok = 0;
     int qmax = 0;
     int64_t eta_max = 0;
@@ -44,32 +46,43 @@ static inline __host__ __device__ uint32_t qb_ell_word(int32_t v, int col)
 static inline __host__ __device__ int qb_ell_col(uint32_t w) { return (int)(w & 0xffffu); }
 static inline __host__ __device__ int32_t qb_ell_val(uint32_t w) { return (int32_t)w >> 16; }
 
-// Threads of the Tabu workgroup and elements per thread for n variables;
-// the padded copy of Q has pitch QB_TABU_THREADS * EPT.  0 if n is too large.
+// Threads of the dense Tabu workgroup for n variables: 1024 (sixteen waves),
+// or 512 where that measured faster on MI355X.  With 1024 threads, n in
+// (2048, 3072] or (4096, 5120] gives each thread 3 or 5 variables, which it
+// reads in two chunks; eight waves with 5, 6 or 10 variables each then do
+// the step 5-6 % faster (at n = 2500 and 5000), while elsewhere sixteen
+// waves are as fast or faster (n = 1000, 4000, 6000, 7000, 8000 measured).
 #define QB_TABU_THREADS 1024
-static inline int qb_tabu_ept(int n)
+static inline __host__ __device__ int qb_tabu_threads(int n)
+{
+    return ((n > 2048 && n <= 3072) || (n > 4096 && n <= 5120)) ? 512 : QB_TABU_THREADS;
+}
+
+// Elements per thread of the dense Tabu kernel with tb threads; the padded
+// copies of Q have pitch tb * EPT.  0 if n is too large.
+static inline int qb_tabu_ept(int n, int tb)
 {
     // beyond 16 elements per thread the state no longer fits 128 VGPRs
     static const int opts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16};
     for (int e : opts)
-        if (n <= QB_TABU_THREADS * e) return e;
+        if (n <= tb * e) return e;
     return 0;
 }
 
-// The dense Tabu kernel's copy of Q.  Thread t of the workgroup owns the
-// variables e * QB_TABU_THREADS + t (e < ept); in a row of the copy its ept
+// The dense Tabu kernel's copy of Q.  Thread t of the tb-thread workgroup
+// owns the variables e * tb + t (e < ept); in a row of the copy its ept
 // elements are split into chunks of 16, 8, 4, 2 and 1 bytes (largest first,
 // the largest repeated as often as it fits), and each chunk is stored for
 // all threads in turn, so one naturally aligned vector load per chunk reads
 // a thread's elements (two loads instead of five at ept = 5, one instead of
 // sixteen at ept = 16 with int8).  Returns the element offset of (e, t)
 // within the row.
-static inline __host__ __device__ int qb_tabu_pos(int e, int t, int ept, int esz)
+static inline __host__ __device__ int qb_tabu_pos(int e, int t, int ept, int esz, int tb)
 {
     int start = 0;
     for (int sz = 16 / esz; sz >= 1; sz >>= 1)
         while (ept - start >= sz) {
-            if (e < start + sz) return start * QB_TABU_THREADS + t * sz + (e - start);
+            if (e < start + sz) return start * tb + t * sz + (e - start);
             start += sz;
         }
     return -1;

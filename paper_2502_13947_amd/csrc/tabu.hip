@@ -1,9 +1,10 @@
-// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one 1024-thread
-// workgroup (sixteen waves, four per SIMD, so the per-step element work is
-// spread thin and one wave's latency overlaps the others' work) per
-// solution.
+// Tabu search (Alg. 1 of the IC-D^2S paper) on gfx950: one workgroup per
+// solution, of 1024 threads (sixteen waves, four per SIMD, so the per-step
+// element work is spread thin and one wave's latency overlaps the others'
+// work), or of 512 threads at the sizes where eight waves measured faster
+// (qb_tabu_threads).
 //
-// Thread t owns the variables j = e*1024 + t (e < EPT) and keeps in
+// Thread t owns the variables j = e*TB + t (e < EPT) and keeps in
 // registers, per variable: the move value D_j = Q_jj + 2(1-2x_j)h_j (biased
 // to be non-negative), the factor S_j = 2(1-2x_j), and the step U_j after
 // which the variable is free again.  U replaces the tenure vector of the
@@ -32,22 +33,25 @@
 
 namespace {
 
-constexpr int TB = QB_TABU_THREADS;
-constexpr int NW = TB / 64;
-
 // Cross-wave winner in 32 bits (K32): the slot's low word is
-// (wave minimum key << WB) | wave and its high word (lane << 1) | x.  Within
-// a wave the ballot already took the lowest lane among equal keys, and
-// across waves (move, element, wave) orders exactly as (move, index) since
-// index = element * TB + wave * 64 + lane; so a 32-bit DPP minimum over the
-// slots picks the winner and one readlane of the winning slot's high word
-// gives its lane and x.  Used when every real key fits 31 - WB bits.
-constexpr int WB = qb_ceil_log2(NW);
+// (wave minimum key << WB) | wave and its high word (lane << 1) | x, with
+// NW = TB / 64 waves and WB = log2 NW.  Within a wave the ballot already
+// took the lowest lane among equal keys, and across waves (move, element,
+// wave) orders exactly as (move, index) since index = element * TB + wave *
+// 64 + lane; so a 32-bit DPP minimum over the slots picks the winner and one
+// readlane of the winning slot's high word gives its lane and x.  Used when
+// every real key fits 31 - WB bits.
+template <int TB>
+struct TabuShape {
+    static constexpr int NW = TB / 64;
+    static constexpr int WB = qb_ceil_log2(NW);
+    static_assert(TB == 512 || TB == 1024, "eight or sixteen waves");
+};
 
 // Thread tid's elements of one row of the Tabu copy of Q (the chunk order of
 // qb_tabu_pos): one naturally aligned vector load per chunk, chunks of SZ
 // elements from element START on, then the elements sign-extended.
-template <typename QT, int EPT, int START = 0, int SZ = 16 / (int)sizeof(QT)>
+template <typename QT, int EPT, int TB, int START = 0, int SZ = 16 / (int)sizeof(QT)>
 __device__ __forceinline__ void tabu_row(const QT *row, uint32_t tid, int32_t (&q)[EPT])
 {
     if constexpr (SZ >= 1 && START < EPT) {
@@ -74,20 +78,21 @@ __device__ __forceinline__ void tabu_row(const QT *row, uint32_t tid, int32_t (&
                 const int sh = ((k * (int)sizeof(QT)) % 4) * 8;
                 q[START + k] = sizeof(QT) == 1 ? (int32_t)(int8_t)(word >> sh) : (int32_t)(int16_t)(word >> sh);
             }
-            tabu_row<QT, EPT, START + SZ, SZ>(row, tid, q);
+            tabu_row<QT, EPT, TB, START + SZ, SZ>(row, tid, q);
         } else {
-            tabu_row<QT, EPT, START, SZ / 2>(row, tid, q);
+            tabu_row<QT, EPT, TB, START, SZ / 2>(row, tid, q);
         }
     }
 }
 
-template <int EPT, typename QT, bool K32>
+template <int EPT, typename QT, bool K32, int TB>
 __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qt, int ldp, const int16_t *__restrict__ Q16,
                                              int n, uint8_t *__restrict__ X, int32_t *__restrict__ H,
                                              int64_t *__restrict__ E, int alpha, int tenure, int asp,
                                              int32_t *__restrict__ Tout, int32_t *__restrict__ LFout,
                                              uint32_t bias)
 {
+    constexpr int NW = TabuShape<TB>::NW, WB = TabuShape<TB>::WB;
     constexpr int EB = qb_ceil_log2(EPT);           // bits of the element index
     constexpr uint32_t EMASK = (1u << EB) - 1u;
     __shared__ uint64_t red[2][NW];
@@ -229,7 +234,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qt, int ldp,
         // the row base is uniform (scalar registers); each lane adds its own
         // 32-bit chunk offsets
         int32_t q[EPT];
-        tabu_row<QT, EPT>(Qt + (uint32_t)i * (uint32_t)ldp, (uint32_t)tid, q);
+        tabu_row<QT, EPT, TB>(Qt + (uint32_t)i * (uint32_t)ldp, (uint32_t)tid, q);
         // h_j += s Q_ji  =>  D_j += S_j s Q_ji, applied to the key above its
         // element bits (the owner is patched below)
         if (s > 0) {
@@ -330,7 +335,7 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qt, int ldp,
             const int32_t v = list[u];
             const int32_t sg = v < 0 ? -1 : 1;
             int32_t q[EPT];
-            tabu_row<QT, EPT>(Qt + (uint32_t)(v < 0 ? -v - 1 : v - 1) * (uint32_t)ldp, (uint32_t)tid, q);
+            tabu_row<QT, EPT, TB>(Qt + (uint32_t)(v < 0 ? -v - 1 : v - 1) * (uint32_t)ldp, (uint32_t)tid, q);
 #pragma unroll
             for (int e2 = 0; e2 < EPT; ++e2) h[e2] += sg * q[e2];
         }
@@ -349,35 +354,45 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qt, int ldp,
     if (tid == 0) E[p] = OVmin;
 }
 
-template <int EPT, typename QT, bool K32>
+template <int EPT, typename QT, bool K32, int TB>
 void launch_one(const QT *Qt, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
                 int tenure, int asp, int32_t *T, int32_t *LF, uint32_t bias, hipStream_t s)
 {
     const size_t lds = sizeof(int32_t) * 2 * (size_t)P->n;
-    (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT, K32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT, K32, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    k_tabu<EPT, QT, K32><<<z, TB, lds, s>>>(Qt, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
+    k_tabu<EPT, QT, K32, TB><<<z, TB, lds, s>>>(Qt, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
+}
+
+// The 32-bit winner key when every real key fits 31 - WB bits, else 64 bits.
+template <int EPT, typename QT, int TB>
+qb_status launch_keyed(const QT *Qt, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E,
+                       int alpha, int tenure, int asp, int32_t *T, int32_t *LF, int64_t dmax, hipStream_t s)
+{
+    if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(EPT))) return QB_E_RANGE;
+    const uint32_t bias = (uint32_t)dmax;
+    if (((2 * dmax + 1) << qb_ceil_log2(EPT)) < (int64_t(1) << (31 - TabuShape<TB>::WB)))
+        launch_one<EPT, QT, true, TB>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);
+    else
+        launch_one<EPT, QT, false, TB>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
 }
 
 template <typename QT>
 qb_status launch_tabu(qb_problem P, const QT *Qt, int ldp, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
                       int tenure, int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
-    const int ept = qb_tabu_ept(P->n);
-    if (ept == 0 || ldp != TB * ept) return QB_E_CAPACITY;
+    const int ept = P->tabu_ept, tb = P->tabu_tb;
+    if (ept == 0 || ldp != tb * ept) return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
-    const uint32_t bias = (uint32_t)dmax;
-#define QB_T(K)                                                                                    \
-    if (ept == K) {                                                                               \
-        if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;             \
-        if (((2 * dmax + 1) << qb_ceil_log2(K)) < (int64_t(1) << (31 - WB)))                         \
-            launch_one<K, QT, true>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);     \
-        else                                                                                       \
-            launch_one<K, QT, false>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);    \
-        QB_LAUNCH_CHECK();                                                                         \
-        return QB_OK;                                                                              \
-    }
-    QB_T(1) QB_T(2) QB_T(3) QB_T(4) QB_T(5) QB_T(6) QB_T(7) QB_T(8) QB_T(10) QB_T(12) QB_T(14) QB_T(16)
+#define QB_T(K, W)                                                                                 \
+    if (ept == K && tb == W)                                                                      \
+        return launch_keyed<K, QT, W>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, dmax, s);
+    // eight waves only where qb_tabu_threads picks them (5, 6 or 10 elements)
+    QB_T(5, 512) QB_T(6, 512) QB_T(10, 512)
+    QB_T(1, 1024) QB_T(2, 1024) QB_T(3, 1024) QB_T(4, 1024) QB_T(5, 1024) QB_T(6, 1024)
+    QB_T(7, 1024) QB_T(8, 1024) QB_T(10, 1024) QB_T(12, 1024) QB_T(14, 1024) QB_T(16, 1024)
 #undef QB_T
     return QB_E_CAPACITY;
 }
@@ -396,7 +411,7 @@ extern "C" qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d
     hipStream_t s = qb_stream(stream);
     if (P->sparse)
         return qb_tabu_sparse_launch(P, z, X_d, H_d, E_d, alpha, tenure, aspiration != 0, T_d, LF_d, s);
-    if (qb_tabu_ept(P->n) == 0) return QB_E_CAPACITY;
+    if (P->tabu_ept == 0) return QB_E_CAPACITY;
     if (P->int8_ok)
         return launch_tabu<int8_t>(P, (const int8_t *)P->Qt, P->ldp, z, X_d, H_d, E_d, alpha, tenure,
                                    aspiration != 0, T_d, LF_d, s);

@@ -98,7 +98,9 @@ def test_field_energy_best(n, z, int8):
                                                   (1100, 4, 2000, 7, True), (2500, 2, 3000, 16, False),
                                                   (5000, 2, 800, 33, True),
                                                   # tenure beyond n: every variable tabu, none aspirating
-                                                  (70, 2, 300, 90, False), (1500, 1, 2000, 1600, True)])
+                                                  (70, 2, 300, 90, False), (1500, 1, 2000, 1600, True),
+                                                  # the same with eight-wave workgroups
+                                                  (2200, 1, 1500, 2300, True)])
 def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
     say("tabu", n, z, alpha, tenure, asp, int8)
     Q = inputs.dense_qubo(n, 0.3, 5) if int8 else wide_qubo(n, 5)
@@ -119,15 +121,16 @@ def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
         assert (LF[p].cpu().numpy() == LFo).all()
 
 
-@pytest.mark.parametrize("n,int8", [(4000, True), (6000, True), (8000, True), (10000, True), (12000, True),
-                                    (14000, True), (16000, True), (6000, False), (10000, False),
-                                    (16000, False)])
+@pytest.mark.parametrize("n,int8", [(3000, True), (4000, True), (6000, True), (8000, True), (10000, True),
+                                    (12000, True), (14000, True), (16000, True), (3000, False), (6000, False),
+                                    (10000, False), (16000, False)])
 def test_tabu_bit_exact_every_row_chunking(n, int8):
     """Every elements-per-thread count the dense Tabu kernel takes from 4 to
-    16 (n up to its capacity 16384): each splits a thread's part of a row
-    into different aligned chunks (4+2 at 6000, 8 at 8000, 8+2, 8+4, 8+4+2,
-    and 16 at 16000 with int8; 8+8 with int16), and from 12 on the owner
-    patches its element through the per-element branch."""
+    16 (n up to its capacity 16384), and 6 on eight waves (n = 3000): each
+    splits a thread's part of a row into different aligned chunks (4+2 at
+    6000, 8 at 8000, 8+2, 8+4, 8+4+2, and 16 at 16000 with int8; 8+8 with
+    int16), and from 12 on the owner patches its element through the
+    per-element branch."""
     z, alpha, tenure = 2, 400, n // 150
     say("tabu chunking", n, int8)
     Q = inputs.dense_qubo(n, 0.3, 31) if int8 else wide_qubo(n, 31)
