@@ -258,10 +258,12 @@ __device__ __forceinline__ bool qb_pick32(const uint64_t *slot, int lane, uint32
     uint32_t lo = (uint32_t)v;
     lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
     lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    if constexpr (NWV > 4) {
+    // with NWV = 8 the upper half of the row repeats the lower half, so one
+    // rotation by four already meets all eight slots in lane 0
+    if constexpr (NWV > 4)
         lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x124, 0xF, 0xF, false));  // row_ror 4
+    if constexpr (NWV > 8)
         lo = min(lo, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x128, 0xF, 0xF, false));  // row_ror 8
-    }
     key = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
     if (key == 0xFFFFFFFFu) return false;
     hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)(key & (NWV - 1)));
