@@ -26,8 +26,75 @@
 namespace {
 
 // ------------------------------------------------------------------ extract
+constexpr int EXTRACT_THREADS = 512;
+
+// The lane's MS elements of tile row a (columns 64 s + lane, s < MS, stored
+// contiguously at a MP + lane MS) in one naturally aligned vector store.
+template <typename TT, int MS>
+__device__ __forceinline__ void store_lane_row(TT *dst, const TT (&v)[MS])
+{
+    constexpr int BYTES = MS * (int)sizeof(TT);
+    if constexpr (BYTES >= 16) {
+        uint4 w[BYTES / 16];
+        __builtin_memcpy(w, v, BYTES);
+#pragma unroll
+        for (int t = 0; t < BYTES / 16; ++t) reinterpret_cast<uint4 *>(dst)[t] = w[t];
+    } else if constexpr (BYTES == 8) {
+        uint2 w;
+        __builtin_memcpy(&w, v, 8);
+        *reinterpret_cast<uint2 *>(dst) = w;
+    } else if constexpr (BYTES == 4) {
+        uint32_t w;
+        __builtin_memcpy(&w, v, 4);
+        *reinterpret_cast<uint32_t *>(dst) = w;
+    } else if constexpr (BYTES == 2) {
+        uint16_t w;
+        __builtin_memcpy(&w, v, 2);
+        *reinterpret_cast<uint16_t *>(dst) = w;
+    } else {
+        *dst = v[0];
+    }
+}
+
+// Rows of one job's tile (eq. 4's T = Q[S][S] with a zero diagonal, padded
+// to MP = 64 MS) and, when c is given, the linear term: wave w takes rows
+// w, w + 8, ...; each lane gathers its MS columns of the row and stores them
+// at once.
+template <typename TT, int MS>
+__device__ __forceinline__ void extract_rows(const int16_t *__restrict__ Q16, const TT *__restrict__ Qt, int n,
+                                             int m, int base, int64_t xo, const int32_t *S, const uint8_t *ys,
+                                             const int32_t *__restrict__ H, TT *tile, int32_t *__restrict__ c)
+{
+    constexpr int MP = 64 * MS, NWV = EXTRACT_THREADS / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int a = wid; a < MP; a += NWV) {
+        const bool arow = a < m;
+        const TT *qrow = Qt + (arow ? (int64_t)S[a] * n : 0);
+        int32_t rowsum = 0;
+        TT v[MS];
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+            const int b = 64 * s + lane;
+            int32_t x = 0;
+            if (arow && b < m && b != a) x = qrow[S[b]];
+            v[s] = (TT)x;
+            if (b < m) rowsum += x * (int32_t)ys[b];
+        }
+        store_lane_row<TT, MS>(tile + (int64_t)a * MP + lane * MS, v);
+        if (c && arow) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) rowsum += __shfl_xor(rowsum, o, 64);
+            if (lane == 0) {
+                const int i = S[a];
+                const int32_t qii = Q16[(int64_t)i * n + i];
+                c[base + a] = qii + 2 * (H[xo + i] - qii * (int32_t)ys[a]) - 2 * rowsum;
+            }
+        }
+    }
+}
+
 template <typename TT>
-__global__ void __launch_bounds__(256) k_extract(const int16_t *__restrict__ Q16, const TT *__restrict__ Qt,
+__global__ void __launch_bounds__(EXTRACT_THREADS) k_extract(const int16_t *__restrict__ Q16, const TT *__restrict__ Qt,
                                                  int n, const int32_t *__restrict__ sol,
                                                  const int32_t *__restrict__ off,
                                                  const int64_t *__restrict__ tile_off,
@@ -39,43 +106,28 @@ __global__ void __launch_bounds__(256) k_extract(const int16_t *__restrict__ Q16
 {
     __shared__ int32_t S[1024];
     __shared__ uint8_t ys[1024];
-    const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int q = blockIdx.x, tid = threadIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
-    const int MS = qb_tile_ms(m), MP = MS * 64;
     const int64_t xo = (int64_t)p * n;
-    for (int a = tid; a < m; a += 256) {
+    for (int a = tid; a < m; a += EXTRACT_THREADS) {
         const int j = idx[base + a];
         S[a] = j;
         ys[a] = X[xo + j];
     }
     __syncthreads();
-    for (int a = tid; a < m; a += 256) {
+    for (int a = tid; a < m; a += EXTRACT_THREADS) {
         const int i = S[a];
         const int32_t qii = Q16[(int64_t)i * n + i];
         F0[base + a] = qii + 2 * (H[xo + i] - qii * (int32_t)ys[a]);
         y0[base + a] = ys[a];
     }
     TT *tile = tiles + tile_off[q];
-    for (int a = wid; a < MP; a += 4) {
-        const bool arow = a < m;
-        const TT *qrow = Qt + (arow ? (int64_t)S[a] * n : 0);
-        int32_t rowsum = 0;
-        for (int s = 0; s < MS; ++s) {
-            const int b = 64 * s + lane;
-            int32_t v = 0;
-            if (arow && b < m && b != a) v = qrow[S[b]];
-            tile[(int64_t)a * MP + lane * MS + s] = (TT)v;
-            if (b < m) rowsum += v * (int32_t)ys[b];
-        }
-        if (c && arow) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) rowsum += __shfl_xor(rowsum, o, 64);
-            if (lane == 0) {
-                const int i = S[a];
-                const int32_t qii = Q16[(int64_t)i * n + i];
-                c[base + a] = qii + 2 * (H[xo + i] - qii * (int32_t)ys[a]) - 2 * rowsum;
-            }
-        }
+    switch (qb_tile_ms(m)) {
+    case 1: extract_rows<TT, 1>(Q16, Qt, n, m, base, xo, S, ys, H, tile, c); break;
+    case 2: extract_rows<TT, 2>(Q16, Qt, n, m, base, xo, S, ys, H, tile, c); break;
+    case 4: extract_rows<TT, 4>(Q16, Qt, n, m, base, xo, S, ys, H, tile, c); break;
+    case 8: extract_rows<TT, 8>(Q16, Qt, n, m, base, xo, S, ys, H, tile, c); break;
+    default: extract_rows<TT, 16>(Q16, Qt, n, m, base, xo, S, ys, H, tile, c); break;
     }
 }
 
@@ -860,10 +912,10 @@ extern "C" qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, co
     if (b->J == 0) return QB_OK;
     hipStream_t s = qb_stream(stream);
     if (P->int8_ok)
-        k_extract<int8_t><<<b->J, 256, 0, s>>>(P->Q, P->Q8, P->n, b->sol_d, b->off_d, b->tile_off_d, b->idx_d,
+        k_extract<int8_t><<<b->J, EXTRACT_THREADS, 0, s>>>(P->Q, P->Q8, P->n, b->sol_d, b->off_d, b->tile_off_d, b->idx_d,
                                                X_d, H_d, (int8_t *)tile_d, c_d, F0_d, y0_d);
     else
-        k_extract<int16_t><<<b->J, 256, 0, s>>>(P->Q, P->Q, P->n, b->sol_d, b->off_d, b->tile_off_d, b->idx_d,
+        k_extract<int16_t><<<b->J, EXTRACT_THREADS, 0, s>>>(P->Q, P->Q, P->n, b->sol_d, b->off_d, b->tile_off_d, b->idx_d,
                                                 X_d, H_d, (int16_t *)tile_d, c_d, F0_d, y0_d);
     QB_LAUNCH_CHECK();
     return QB_OK;
