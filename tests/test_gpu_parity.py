@@ -449,7 +449,9 @@ def test_writeback_rankk(variant):
 
 @pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("n,z,int8", [(37, 5, True), (1000, 70, True), (1003, 129, True), (5000, 256, True),
-                                      (300, 40, False)])
+                                      (300, 40, False),
+                                      # padded-copy pitch 2560 (eight-wave Tabu sizing)
+                                      (2500, 64, True)])
 def test_rankk_variants(n, z, int8, variant):
     """H(X_old) + Q (X_new - X_old) must equal the field of X_new."""
     say("rankk", n, z, int8, variant)
