@@ -100,7 +100,10 @@ def test_field_energy_best(n, z, int8):
                                                   # tenure beyond n: every variable tabu, none aspirating
                                                   (70, 2, 300, 90, False), (1500, 1, 2000, 1600, True),
                                                   # the same with eight-wave workgroups
-                                                  (2200, 1, 1500, 2300, True)])
+                                                  (2200, 1, 1500, 2300, True),
+                                                  # the ends of the eight-wave sizes: the first one,
+                                                  # and a row with no padding at all
+                                                  (2049, 2, 900, 13, True), (5120, 2, 700, 34, True)])
 def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
     say("tabu", n, z, alpha, tenure, asp, int8)
     Q = inputs.dense_qubo(n, 0.3, 5) if int8 else wide_qubo(n, 5)
