@@ -368,9 +368,9 @@ template <typename TT, int DW>
 __device__ __forceinline__ int32_t diag_at(const uint32_t (&d)[DW], int k)
 {
     if constexpr (sizeof(TT) == 1)
-        return (int32_t)(int8_t)(d[k >> 2] >> ((k & 3) * 8));
+        return __builtin_amdgcn_sbfe((int)d[k >> 2], (uint32_t)(k & 3) * 8u, 8u);
     else
-        return (int32_t)(int16_t)(d[k >> 1] >> ((k & 1) * 16));
+        return __builtin_amdgcn_sbfe((int)d[k >> 1], (uint32_t)(k & 1) * 16u, 16u);
 }
 
 template <int MS, typename TT, int MODE, bool LIM>
@@ -519,10 +519,12 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
             int c = 0;
             int32_t dE = (F[j] ^ M[j]) - M[j];
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
+            uint64_t ym = __ballot(M[j] != 0);     // y of the block's lanes, in scalar registers
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
-                const int32_t mk = __builtin_amdgcn_readlane(M[j], k);
+                const int32_t mk = (int32_t)((ym >> k) & 1ull);
+                ym ^= 1ull << k;
                 ej += dEk;
                 const int32_t d2 = mk ? -2 : 2;                // y_k = 0: +2, y_k = 1: -2
                 F[j] += d2 * diag_at<TT, DW>(dcol[j], k);
@@ -771,10 +773,12 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
             int c = 0;
             int32_t dE = (F[j] ^ M[j]) - M[j];
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
+            uint64_t ym = __ballot(M[j] != 0);     // y of the block's lanes, in scalar registers
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
-                const int32_t mk = __builtin_amdgcn_readlane(M[j], k);
+                const int32_t mk = (int32_t)((ym >> k) & 1ull);
+                ym ^= 1ull << k;
                 ej += dEk;
                 const int32_t d2 = mk ? -2 : 2;
                 F[j] += d2 * diag_at<TT, DW>(dcol(j), k);
