@@ -517,9 +517,17 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
             uint64_t pend = active[j];
             int32_t ej = 0;            // at most 64 moves of |dE| < 2^24
             int c = 0;
-            int32_t dE = (F[j] ^ M[j]) - M[j];
+            // the turn works on dE = sigma F (sigma = 1 - 2y) itself.  A lane
+            // that flips has its sigma negated, but its dE is not read again
+            // in the turn (pend) and the negation commutes with the later
+            // updates, so every flip is applied at the end: there F = sigma dE
+            // with the sigma of the turn's start, for every lane, and y comes
+            // from the scalar mask
+            const int32_t M0 = M[j];
+            const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;    // 2 sigma
+            int32_t dE = (F[j] ^ M0) - M0;
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
-            uint64_t ym = __ballot(M[j] != 0);     // y of the block's lanes, in scalar registers
+            uint64_t ym = __ballot(M0 != 0);             // y of the block's lanes, in scalar registers
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
@@ -527,19 +535,19 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
                 ym ^= 1ull << k;
                 ej += dEk;
                 const int32_t d2 = mk ? -2 : 2;                // y_k = 0: +2, y_k = 1: -2
-                F[j] += d2 * diag_at<TT, DW>(dcol[j], k);
+                dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol[j], k);
 #pragma unroll
                 for (int jj = 0; jj < NB; ++jj)
                     if (jj != j) F[jj] += d2 * elem_at<TT, MODE>(lds, ea[jj], k, lane);
-                M[j] ^= lane == k ? -1 : 0;
                 // every lane stores the same word
                 __hip_atomic_store(&out[c], gt | ((uint32_t)k << 1) | (uint32_t)(mk & 1), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
                 pend &= (~0ull << k) << 1;
-                dE = (F[j] ^ M[j]) - M[j];
                 acc = __ballot(dE <= tv[j]) & pend;
             }
+            F[j] = (dE ^ M0) - M0;
+            M[j] = ((ym >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gt | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             e += ej;
         }
@@ -771,9 +779,13 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
             uint64_t pend = active[j];
             int32_t ej = 0;
             int c = 0;
-            int32_t dE = (F[j] ^ M[j]) - M[j];
+            // dE = sigma F itself, the flips applied at the end of the turn, as
+            // in the in-LDS kernel
+            const int32_t M0 = M[j];
+            const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;    // 2 sigma
+            int32_t dE = (F[j] ^ M0) - M0;
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
-            uint64_t ym = __ballot(M[j] != 0);     // y of the block's lanes, in scalar registers
+            uint64_t ym = __ballot(M0 != 0);             // y of the block's lanes, in scalar registers
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
@@ -781,7 +793,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                 ym ^= 1ull << k;
                 ej += dEk;
                 const int32_t d2 = mk ? -2 : 2;
-                F[j] += d2 * diag_at<TT, DW>(dcol(j), k);
+                dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol(j), k);
 #pragma unroll
                 for (int jj = 0; jj < NB; ++jj) {
                     if (jj == j) continue;
@@ -789,14 +801,14 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                                          : own_pair(jj, j, NB) * C::OBLK + lane * C::OSTR + k * (int)sizeof(TT);
                     F[jj] += d2 * (int32_t)*reinterpret_cast<const TT *>(ow + o);
                 }
-                M[j] ^= lane == k ? -1 : 0;
                 __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (uint32_t)(mk & 1), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
                 pend &= (~0ull << k) << 1;
-                dE = (F[j] ^ M[j]) - M[j];
                 acc = __ballot(dE <= tv[j]) & pend;
             }
+            F[j] = (dE ^ M0) - M0;
+            M[j] = ((ym >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gtag | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             e += ej;
         }
