@@ -546,23 +546,36 @@ __global__ void __launch_bounds__(256) k_best(int n, int z, const uint8_t *__res
                                               const int64_t *__restrict__ E, int64_t *__restrict__ ebest,
                                               uint8_t *__restrict__ xbest)
 {
-    __shared__ int64_t se[256];
-    __shared__ int sp[256];
+    __shared__ int64_t se[4];
+    __shared__ int sp[4];
     __shared__ int winner;
     int64_t be = INT64_MAX;
     int bp = -1;
     for (int p = threadIdx.x; p < z; p += 256)
         if (E[p] < be) { be = E[p]; bp = p; }   // ascending p: first minimum kept
-    se[threadIdx.x] = be;
-    sp[threadIdx.x] = bp;
+    // the smallest (E, p) of the block: shuffles within each wave, then the
+    // four wave results
+    auto take = [&](int64_t oe, int op) {
+        if (op >= 0 && (bp < 0 || oe < be || (oe == be && op < bp))) {
+            be = oe;
+            bp = op;
+        }
+    };
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t oe = __shfl_xor(be, o, 64);
+        const int op = __shfl_xor(bp, o, 64);
+        take(oe, op);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        se[threadIdx.x >> 6] = be;
+        sp[threadIdx.x >> 6] = bp;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t e0 = INT64_MAX;
-        int p0 = -1;
-        for (int t = 0; t < 256; ++t)
-            if (sp[t] >= 0 && (se[t] < e0 || (se[t] == e0 && sp[t] < p0))) { e0 = se[t]; p0 = sp[t]; }
-        winner = (p0 >= 0 && e0 < *ebest) ? p0 : -1;
-        if (winner >= 0) *ebest = e0;
+        for (int t = 1; t < 4; ++t) take(se[t], sp[t]);
+        winner = (bp >= 0 && be < *ebest) ? bp : -1;
+        if (winner >= 0) *ebest = be;
     }
     __syncthreads();
     const int w = winner;

@@ -17,6 +17,8 @@ __global__ void k_colcount(const uint8_t *__restrict__ X, int n, int z, int32_t 
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     int32_t c = 0;
+    // independent loads: unrolled so that many are in flight
+#pragma unroll 16
     for (int p = 0; p < z; ++p) c += X[(int64_t)p * n + j];
     cnt[j] = c;
 }
