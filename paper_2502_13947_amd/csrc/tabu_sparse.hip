@@ -2,22 +2,17 @@
 // 1024-thread workgroup (sixteen waves, four per SIMD) per solution.
 //
 // Thread t owns the variables j = e*1024 + t (e < EPT) and keeps in
-// registers the biased move value D_j and the step U_j after which j is free
-// again; keys are (move << EB | element), the wave minimum comes from DPP,
-// and the sixteen wave winners meet in LDS with one barrier per step, where
-// a DPP minimum over lanes picks the smallest (32-bit (key, wave) when the
-// move values allow, else 64-bit (move, index, x)).  What changes from the dense
-// kernel is the field update: flipping i moves D_j only for the neighbours
-// j of i (the O(n) update of the Tabu section, here O(degree)), so the
-// argmin is kept incrementally too.  Each thread holds, per group of GS
-// variables, the minimum key of its free variables (kf) and of its tabu ones
-// (kt), and the step-1 at which the group's next tabu variable is free
-// (texp).  An allowed variable is free, or tabu with D < OV_min - OV
-// (aspiration), and the smallest tabu key aspirates whenever any tabu key
-// does, so a thread's candidate is min(kf, kt if kt aspirates).  A group is
-// rescanned only when one of its variables expires, when its flipped
-// variable turns tabu, or when the variable holding its kf or kt got worse;
-// a lowered move just lowers them.
+// registers, per variable, the key ((D_j + bias) << EB | element), with bit
+// 31 set while j is tabu, and the step U_j after which j is free again, as
+// the dense kernel does: each step takes the unsigned minimum of the keys
+// (the smallest free key) and the signed one (the smallest tabu key, which
+// aspirates whenever any does), the wave minimum comes from DPP, and the
+// wave winners meet in LDS with one barrier per step, where a DPP minimum
+// over lanes picks the smallest (32-bit (key, wave) when the move values
+// allow, else 64-bit (move, index, x)).  What changes from the dense kernel
+// is the field update: flipping i moves D_j only for the neighbours j of i
+// (the O(n) update of the Tabu section, here O(degree)), each a shift-add
+// into the key.
 //
 // Before the barrier every wave copies the neighbour row of its own
 // candidate from the ELL into LDS, so the winner's row is on chip when the
@@ -26,9 +21,8 @@
 // lane through a scalar switch on the element index.  The factor 2(1-2x_j)
 // is taken from the x bits when an element is touched.  The flip count and
 // last-flip step go straight to the output arrays (a vector atomic add and a
-// store by the owner, neither waited for), which keeps the registers for D
-// and U.  Measured on the n = 20000 workload: the step is bound by
-// instruction issue (four waves per SIMD), not by the scan or by memory.
+// store by the owner, neither waited for), which keeps the registers for the
+// keys and U.
 #include "qb_internal.h"
 
 namespace {
@@ -94,10 +88,13 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wid_u = __builtin_amdgcn_readfirstlane(wid);
     const int64_t ro = (int64_t)p * n;
-    const uint32_t dpad = 0xFFFFFFFFu >> EB;
+    constexpr uint32_t TBIT = 0x80000000u;       // set in a key while the variable is tabu
+    // padding elements carry the largest possible key, tabu for ever
+    const uint32_t dpad = 0x7FFFFFFFu >> EB;
 
-    uint32_t Db[EPT];   // D + bias
+    uint32_t Kb[EPT];   // ((D + bias) << EB | e) | TBIT if tabu
     int32_t U[EPT];     // tabu through step U
+    int32_t nexp = 0x7fffffff;   // smallest U among the thread's tabu variables
     uint32_t xb = 0;    // x bits of the owned variables (EPT <= 20)
     uint32_t pb = 0;    // flipped since the last improvement
 #pragma unroll
@@ -109,26 +106,15 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             LFout[ro + j] = 0;
             const int32_t x = X[ro + j] & 1;
             xb |= (uint32_t)x << e;
-            Db[e] = (uint32_t)(diag[j] + (x ? -2 : 2) * H[ro + j]) + bias;
+            Kb[e] = (((uint32_t)(diag[j] + (x ? -2 : 2) * H[ro + j]) + bias) << EB) | (uint32_t)e;
         } else {
-            Db[e] = dpad;
+            Kb[e] = (dpad << EB) | (uint32_t)e | TBIT;
             U[e] = 0x7fffffff;
         }
     }
     int64_t OV = E[p];
     int64_t gap = 0;    // OV - OV_min, never negative
     constexpr uint32_t KNONE = 0xFFFFFFFFu;
-    constexpr int GS = 4;                         // variables per group
-    constexpr int G = (EPT + GS - 1) / GS;
-    uint32_t kf[G], kt[G];                         // minimum keys of the free / tabu variables
-    int32_t texp[G];                               // the step-1 at which a tabu variable is next free
-    uint32_t dirty = (1u << G) - 1u;               // groups to rescan
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        kf[g] = KNONE;
-        kt[g] = KNONE;
-        texp[g] = 0;
-    }
 
     for (int step = 1; step <= alpha; ++step) {
         // aspiration: a tabu key k aspirates when (k >> EB) < OV_min - OV + bias,
@@ -139,28 +125,29 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
             if (asp && gh == 0u && gl < bias) tbk = (bias - gl) << EB;
         }
         const int32_t free_at = step - 1;
-        uint32_t kfa = KNONE, kta = KNONE;
+        if (free_at >= nexp) {
+            // a tabu variable of this thread is free again (every variable
+            // that is not tabu has U <= free_at already, padding never frees)
+            nexp = 0x7fffffff;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if (((dirty >> g) & 1u) || free_at >= texp[g]) {
-                kf[g] = KNONE;
-                kt[g] = KNONE;
-                texp[g] = 0x7fffffff;
-#pragma unroll
-                for (int e = g * GS; e < (g + 1) * GS && e < EPT; ++e) {
-                    const uint32_t key = (Db[e] << EB) | (uint32_t)e;
-                    if (U[e] <= free_at) {
-                        kf[g] = min(kf[g], key);
-                    } else {
-                        kt[g] = min(kt[g], key);
-                        texp[g] = min(texp[g], U[e]);
-                    }
-                }
+            for (int e = 0; e < EPT; ++e) {
+                const bool freed = U[e] <= free_at;
+                Kb[e] &= freed ? ~TBIT : ~0u;
+                nexp = min(nexp, freed ? 0x7fffffff : U[e]);
             }
-            kfa = min(kfa, kf[g]);
-            kta = min(kta, kt[g]);
         }
-        dirty = 0;
+        // smallest free key (unsigned minimum: tabu keys carry bit 31) and
+        // smallest tabu key (signed minimum); the smallest tabu key
+        // aspirates whenever any does
+        uint32_t m1 = KNONE;
+        int32_t m2 = 0x7fffffff;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            m1 = min(m1, Kb[e]);
+            m2 = min(m2, (int32_t)Kb[e]);
+        }
+        const uint32_t kfa = (uint32_t)max((int32_t)m1, -1);   // KNONE when every key is tabu
+        const uint32_t kta = (uint32_t)m2 ^ TBIT;              // >= TBIT (never aspirates) when none is
         const uint32_t best = min(kfa, kta < tbk ? kta : KNONE);
         const uint32_t wmin = qb_wave_min_u32_b(best);
         // the wave's winner slot for minimum key wm among the lanes' keys
@@ -231,16 +218,8 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
                 switch (c >> TSHIFT) {
 #define QB_NB_CASE(K)                                                                        \
     case K:                                                                                  \
-        if constexpr (K < EPT) {                                                             \
-            const uint32_t ko = (Db[K] << EB) | (uint32_t)K;                                 \
-            Db[K] += (uint32_t)(((xb >> K) & 1u) ? -2 * dv : 2 * dv);                        \
-            const uint32_t kn = (Db[K] << EB) | (uint32_t)K;                                 \
-            uint32_t &km = U[K] <= free_at ? kf[K / GS] : kt[K / GS];                        \
-            if (kn < km)                                                                     \
-                km = kn;                                                                     \
-            else if (ko == km)                                                               \
-                dirty |= 1u << (K / GS);                                                     \
-        }                                                                                    \
+        if constexpr (K < EPT)                                                               \
+            Kb[K] += (uint32_t)(((xb >> K) & 1u) ? -2 * dv : 2 * dv) << EB;                  \
         break;
                     QB_SWITCH20(QB_NB_CASE)
 #undef QB_NB_CASE
@@ -271,9 +250,13 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
 #define QB_OWNER_CASE(K)                                                         \
     case K:                                                                      \
         if constexpr (K < EPT) {                                                 \
-            Db[K] = 2u * bias - dib;                                             \
-            U[K] = step + max(max(U[K] - (step - 1), 0) + tenure - 1, 0);        \
-            dirty |= 1u << (K / GS);                                             \
+            const int32_t Un = step + max(max(U[K] - (step - 1), 0) + tenure - 1, 0); \
+            U[K] = Un;                                                           \
+            Kb[K] = ((2u * bias - dib) << EB) | (uint32_t)K;                     \
+            if (Un > step) {                                                     \
+                Kb[K] |= TBIT;                                                   \
+                nexp = min(nexp, Un);                                            \
+            }                                                                    \
         }                                                                        \
         break;
                 QB_SWITCH20(QB_OWNER_CASE)
@@ -298,7 +281,7 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
         h[e] = 0;
         if (j < n) {
             const int32_t sg = ((xb >> e) & 1u) ? -2 : 2;
-            h[e] = ((int32_t)(Db[e] - bias) - diag[j]) * sg / 4;
+            h[e] = ((int32_t)(((Kb[e] & ~TBIT) >> EB) - bias) - diag[j]) * sg / 4;
         }
     }
     for (int e = 0; e < EPT; ++e) {
@@ -373,7 +356,7 @@ qb_status qb_tabu_sparse_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int
     if (lds > 64 * 1024) return QB_E_CAPACITY;
 #define QB_T(K)                                                                                     \
     if (ept == K) {                                                                                \
-        if (2 * dmax + 1 >= (int64_t)(0xFFFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;          \
+        if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(K))) return QB_E_RANGE;          \
         if (lds > 48 * 1024) {                                                                     \
             QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_sp<K, true>,                       \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
