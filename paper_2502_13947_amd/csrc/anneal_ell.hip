@@ -12,8 +12,10 @@
 // flip bases F of each replica live in LDS and lane t adds the t-th entry of
 // row k to F[col_t] with one LDS atomic add (the entries of a row have
 // distinct columns); the current block's F is read back before the next
-// ballot.  The job's ELL tile is staged in LDS once and shared by the rw
-// replicas (waves) of the workgroup; rw only changes the schedule.
+// ballot, together with the row of the next lane that accepted in the
+// current ballot (most often the next accept).  The job's ELL tile is staged
+// in LDS once and shared by the rw replicas (waves) of the workgroup; rw only
+// changes the schedule.
 #include "qb_internal.h"
 
 namespace {
@@ -152,6 +154,12 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
             uint64_t pend = active[s];
             if (pend == 0) continue;
             int32_t fs = F[64 * s + lane];
+            // the first 64 words of the row of lane kp, read one accept ahead:
+            // kp is the next accepting lane of the current ballot, which is
+            // most often the next accept, and its row read then overlaps the
+            // current update instead of following it
+            int kp = -1;
+            uint32_t wp = 0u;
             while (true) {
                 const uint32_t yb = (ybits >> s) & 1u;
                 const int32_t dE = yb ? -fs : fs;
@@ -164,12 +172,22 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
                 const int32_t d2 = ykb ? -2 : 2;
                 if (lane == k) ybits ^= 1u << s;
                 const uint32_t *row = tl + (size_t)(64 * s + k) * W;
-                for (int t0 = 0; t0 < W; t0 += 64) {
+                // (word lane of a row is inside the LDS allocation for every
+                // lane: the fields of the replicas follow the tile)
+                uint32_t w0 = wp;
+                if (kp != k) w0 = row[lane];
+                if (lane < W && w0 != 0u) atomicAdd(&F[qb_ell_col(w0)], d2 * qb_ell_val(w0));
+                for (int t0 = 64; t0 < W; t0 += 64) {
                     if (t0 + lane < W) {
                         const uint32_t wd = row[t0 + lane];
                         if (wd != 0u) atomicAdd(&F[qb_ell_col(wd)], d2 * qb_ell_val(wd));
                     }
                 }
+                // issued after the adds (which return nothing), so only the
+                // read of the fields below waits for it
+                const uint64_t rest = acc & ~((2ull << k) - 1ull);
+                kp = rest ? __builtin_ctzll(rest) : -1;
+                if (kp >= 0) wp = tl[(size_t)(64 * s + kp) * W + lane];
                 pend &= ~((2ull << k) - 1ull);
                 fs = F[64 * s + lane];
             }
