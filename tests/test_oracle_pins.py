@@ -321,6 +321,40 @@ def test_anneal_single_variable_acceptance_frequency_matches_table():
     assert abs(acc / N - p_exact) < 5 * se
 
 
+def test_anneal_fixed_temperature_samples_the_boltzmann_distribution():
+    # A single-spin Metropolis update leaves exp(-E/T) invariant, so at a
+    # fixed temperature many independent replicas of a 3-variable job end in
+    # the Boltzmann distribution of the full energy x^T Q x (eq. 1) over the
+    # 8 completions of x on S, here computed by brute force from Q.  A wrong
+    # sign of dE, a dropped boundary field or coupling, or a misread threshold
+    # moves the histogram far outside the tolerance; quantising u to 2^-12
+    # moves each acceptance probability by less than 2.5e-4.
+    n, T, B = 10, 40.0, 12
+    Q = rand_sym(n, 71, -30, 30)
+    x = inputs.random_solutions(1, n, 72)[0]
+    S = np.array([1, 4, 8], np.int32)
+    m = len(S)
+    Tq, c, F0, y0 = oracle.extract(Q, x, oracle.field(Q, x)[0], S)
+    assert (y0 == x[S]).all()
+    nsw, R = 60, 20000
+    thr = oracle.threshold_table(nsw, B, T, T)
+    Y, e = oracle.anneal(Tq, F0, y0, thr, R, seed=11, inst=3, B=B)
+    states = all_states(m)
+    Qi = Q.astype(np.int64)
+    E = np.empty(len(states))
+    for i, y in enumerate(states):
+        xx = x.astype(np.int64)
+        xx[S] = y
+        E[i] = xx @ Qi @ xx
+    p = np.exp(-(E - E.min()) / T)
+    p /= p.sum()
+    assert p.min() > 0.01 and p.max() < 0.6          # a spread-out target
+    code = Y.astype(np.int64) @ (1 << np.arange(m)[::-1])   # row order of all_states
+    freq = np.bincount(code, minlength=1 << m) / R
+    se = np.sqrt(p * (1 - p) / R)
+    assert (np.abs(freq - p) < 5 * se + 1e-3).all(), (freq, p)
+
+
 # --------------------------------------------------------------------------- mutation
 def _mut_case(n=200, seed=0):
     rng = np.random.default_rng(seed)
