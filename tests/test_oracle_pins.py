@@ -153,6 +153,46 @@ def test_tabu_reaches_brute_force_optimum_on_tiny_instances():
     assert hits >= 8
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_tabu_every_move_replayed_by_brute_force(seed):
+    # With a tenure longer than the run and no aspiration a flipped variable
+    # stays tabu to the end, so no variable flips twice and the last-flip
+    # steps give the whole trajectory.  Replayed with energies brute-forced
+    # from eq. 1: every step takes the smallest move value among the
+    # variables not yet flipped (lowest index on ties), and the result is the
+    # first strictly best state of the run, x0 included (Alg. 1).
+    n = 12 + seed
+    Q = rand_sym(n, 300 + seed, -60, 60, 0.6)
+    x0 = inputs.random_solutions(1, n, 400 + seed)[0]
+    alpha = n - 2
+    x, h, ov, T, LF = oracle.tabu(Q, x0, oracle.field(Q, x0)[0], oracle.energy_def(Q, x0), alpha,
+                                  alpha + 5, False)
+    assert set(np.unique(T)) <= {0, 1} and T.sum() == alpha
+    order = np.argsort(LF + (T == 0) * (alpha + 1), kind="stable")[:alpha]
+    assert sorted(LF[order]) == list(range(1, alpha + 1))
+    cur = x0.copy()
+    e_cur = oracle.energy_def(Q, cur)
+    best_x, best_e = cur.copy(), e_cur
+    done = set()
+    for i in order:
+        moves = {}
+        for j in range(n):
+            if j in done:
+                continue
+            y = cur.copy()
+            y[j] ^= 1
+            moves[j] = oracle.energy_def(Q, y) - e_cur
+        dmin = min(moves.values())
+        assert i == min(j for j, d in moves.items() if d == dmin)
+        cur[i] ^= 1
+        e_cur += dmin
+        done.add(int(i))
+        if e_cur < best_e:
+            best_x, best_e = cur.copy(), e_cur
+    assert ov == best_e and (x == best_x).all()
+    assert (h == Q.astype(np.int64) @ x).all()
+
+
 # --------------------------------------------------------------------------- Alg. 4 keys
 def test_keys_equal_exact_rational_aggregation():
     n, z = 17, 5
