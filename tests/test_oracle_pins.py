@@ -193,6 +193,69 @@ def test_tabu_every_move_replayed_by_brute_force(seed):
     assert (h == Q.astype(np.int64) @ x).all()
 
 
+def _replay_tabu(n, alpha, tenure, asp, seed):
+    # Alg. 1 is deterministic, so the runs of 1, 2, ..., alpha steps share
+    # their prefixes and the flip counts of consecutive runs differ in the
+    # variable moved at that step.  Each move is replayed with move values
+    # brute-forced from eq. 1 under the tenure and aspiration readings: a
+    # flip adds the tenure to the variable's counter, every positive counter
+    # then drops by one, and a variable is blocked while its counter is
+    # positive (so a fresh flip blocks it for tenure - 1 steps, and a blocked
+    # variable flipped again keeps what was left); a blocked move is allowed
+    # when it would give a new best (OV + move < OV_min), and when no move is
+    # allowed the smallest of all is taken; lowest index on ties.
+    Q = rand_sym(n, 500 + seed, -60, 60, 0.6)
+    x0 = inputs.random_solutions(1, n, 600 + seed)[0]
+    h0 = oracle.field(Q, x0)[0]
+    e0 = oracle.energy_def(Q, x0)
+    prev = np.zeros(n, np.int32)
+    cur = x0.copy()
+    e_cur = e0
+    best_x, best_e = cur.copy(), e_cur
+    left = np.zeros(n, np.int64)                     # tenure counters
+    aspirated = blocked = 0
+    for step in range(1, alpha + 1):
+        x, h, ov, T, LF = oracle.tabu(Q, x0, h0, e0, step, tenure, asp)
+        diff = T - prev
+        assert diff.min() == 0 and diff.sum() == 1
+        i = int(np.argmax(diff))
+        prev = T
+        moves = []
+        for j in range(n):
+            y = cur.copy()
+            y[j] ^= 1
+            moves.append(oracle.energy_def(Q, y) - e_cur)
+        ok = [j for j in range(n) if left[j] == 0 or (asp and e_cur + moves[j] < best_e)]
+        aspirated += sum(1 for j in ok if left[j] > 0)
+        if not ok:
+            ok = list(range(n))
+            blocked += 1
+        dmin = min(moves[j] for j in ok)
+        assert i == min(j for j in ok if moves[j] == dmin), step
+        cur[i] ^= 1
+        e_cur += dmin
+        left[i] += tenure
+        left = np.maximum(left - 1, 0)
+        if e_cur < best_e:
+            best_x, best_e = cur.copy(), e_cur
+        assert ov == best_e and (x == best_x).all(), step
+        assert (h == Q.astype(np.int64) @ x).all()
+    return aspirated, blocked
+
+
+@pytest.mark.parametrize("n,alpha,tenure,asp,seed,need", [
+    (12, 40, 2, False, 0, ""), (10, 30, 1, False, 3, ""),
+    (6, 20, 8, False, 4, "blocked"), (6, 20, 8, True, 5, "blocked"),   # every variable blocked now and then
+    (10, 40, 6, True, 9, "aspirated"), (12, 40, 4, True, 9, "aspirated"),   # a blocked move aspirates
+])
+def test_tabu_short_tenure_replayed_by_brute_force(n, alpha, tenure, asp, seed, need):
+    aspirated, blocked = _replay_tabu(n, alpha, tenure, asp, seed)
+    if need == "blocked":
+        assert blocked > 0
+    if need == "aspirated":
+        assert aspirated > 0
+
+
 # --------------------------------------------------------------------------- Alg. 4 keys
 def test_keys_equal_exact_rational_aggregation():
     n, z = 17, 5
