@@ -138,8 +138,9 @@ void qbo_init_x(int n, int z, uint64_t seed, uint8_t *X)
  *    entry is decremented (so a flipped variable is blocked c-1 steps);
  *  - the call returns x_min (the best seen) and its field; T counts flips.
  * Parity status: pinned by the hand-worked fixture in tests/golden, by the
- * incremental-vs-recomputed field and energy invariants, and by reaching the
- * brute-force optimum on tiny instances. */
+ * incremental-vs-recomputed field and energy invariants, by reaching the
+ * brute-force optimum on tiny instances, and by move-by-move replays of
+ * whole runs against move values brute-forced from eq. 1. */
 void qbo_tabu(int n, const int16_t *Q, uint8_t *x, int32_t *h, int64_t *ov,
               int alpha, int tenure, int aspiration, int32_t *T, int32_t *lastflip)
 {
@@ -335,7 +336,9 @@ double qbo_mutation_rate(int t)
  *   accept iff (1 - 2 y_k) F_k <= thr[s][u >> (32 - B)].
  * Parity status: pinned by closed forms (all-accept / none-accept tables),
  * e == f_S(y) - f_S(y0), 1-flip local optimality under a strict-descent
- * table, and the acceptance frequency of a single-variable job. */
+ * table, the acceptance frequency of a single-variable job, and the
+ * Boltzmann distribution of x^T Q x reached by many replicas at a fixed
+ * temperature. */
 void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
                 int nsw, int B, const int32_t *thr, int R, uint64_t seed, uint32_t inst,
                 uint8_t *Y, int64_t *e)
