@@ -213,12 +213,9 @@ qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *job
                      uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
 {
     const size_t lds = ell_lds_bytes(MS, W, rw);
-    static size_t attr = 0;
-    if (attr < lds) {
-        QB_TRY_HIP(hipFuncSetAttribute((const void *)k_anneal_ell<MS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)LDS_MAX));
-        attr = LDS_MAX;
-    }
+    // set on every launch (no cached flag shared between devices or threads)
+    QB_TRY_HIP(hipFuncSetAttribute((const void *)k_anneal_ell<MS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)LDS_MAX));
     const int rgroups = (R + rw - 1) / rw;
     k_anneal_ell<MS><<<njobs * rgroups, 64 * rw, lds, s>>>(jobs, rgroups, b->off_d, W, tiles, F0, y0, nsw, B, thr, R,
                                                            rw, (uint32_t)seed, (uint32_t)(seed >> 32), inst_base, Y,

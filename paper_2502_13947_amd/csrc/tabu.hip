@@ -355,13 +355,15 @@ __global__ void __launch_bounds__(TB) k_tabu(const QT *__restrict__ Qt, int ldp,
 }
 
 template <int EPT, typename QT, bool K32, int TB>
-void launch_one(const QT *Qt, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
-                int tenure, int asp, int32_t *T, int32_t *LF, uint32_t bias, hipStream_t s)
+qb_status launch_one(const QT *Qt, int ldp, qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha,
+                     int tenure, int asp, int32_t *T, int32_t *LF, uint32_t bias, hipStream_t s)
 {
     const size_t lds = sizeof(int32_t) * 2 * (size_t)P->n;
-    (void)hipFuncSetAttribute((const void *)k_tabu<EPT, QT, K32, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu<EPT, QT, K32, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
     k_tabu<EPT, QT, K32, TB><<<z, TB, lds, s>>>(Qt, ldp, P->Q, P->n, X, H, E, alpha, tenure, asp, T, LF, bias);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
 }
 
 // The 32-bit winner key when every real key fits 31 - WB bits, else 64 bits.
@@ -372,11 +374,8 @@ qb_status launch_keyed(const QT *Qt, int ldp, qb_problem P, int z, uint8_t *X, i
     if (2 * dmax + 1 >= (int64_t)(0x7FFFFFFFu >> qb_ceil_log2(EPT))) return QB_E_RANGE;
     const uint32_t bias = (uint32_t)dmax;
     if (((2 * dmax + 1) << qb_ceil_log2(EPT)) < (int64_t(1) << (31 - TabuShape<TB>::WB)))
-        launch_one<EPT, QT, true, TB>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);
-    else
-        launch_one<EPT, QT, false, TB>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);
-    QB_LAUNCH_CHECK();
-    return QB_OK;
+        return launch_one<EPT, QT, true, TB>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);
+    return launch_one<EPT, QT, false, TB>(Qt, ldp, P, z, X, H, E, alpha, tenure, asp, T, LF, bias, s);
 }
 
 template <typename QT>
