@@ -54,9 +54,12 @@ extern "C" qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX
     const size_t bytes = sizeof(int32_t) * (size_t)z * P->n;
     int32_t *Hw = nullptr;
     QB_TRY_HIP(hipMalloc(&Hw, bytes));
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(Hw);
+        return QB_E_HIP;
+    }
     std::vector<int32_t> ref, cur;
     int best = 1;
     float best_ms = 1e30f;
@@ -70,12 +73,15 @@ extern "C" qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX
         float tot = 0.f;
         for (int r = 0; r < reps + 1 && rc == QB_OK; ++r) {
             if (hipMemcpyAsync(Hw, H_d, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = QB_E_HIP; break; }
-            (void)hipEventRecord(e0, s);
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = QB_E_HIP; break; }
             rc = qb_rankk(P, z, dX_d, Hw, v, stream);
-            (void)hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess) { rc = QB_E_HIP; break; }
+            if (rc != QB_OK) break;
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = QB_E_HIP;
+                break;
+            }
             if (r > 0) tot += ms;   // first run is a warm-up
         }
         if (rc != QB_OK) break;
@@ -114,9 +120,13 @@ extern "C" qb_status qb_autotune_anneal_ell(qb_batch b, int32_t W, const uint32_
         if (Yw) (void)hipFree(Yw);
         return QB_E_HIP;
     }
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(Yw);
+        (void)hipFree(ew);
+        return QB_E_HIP;
+    }
     std::vector<uint8_t> Yref, Ycur;
     std::vector<int64_t> eref, ecur;
     int best = 0;
@@ -127,13 +137,15 @@ extern "C" qb_status qb_autotune_anneal_ell(qb_batch b, int32_t W, const uint32_
         float tot = 0.f;
         qb_status r0 = QB_OK;
         for (int r = 0; r < reps + 1; ++r) {
-            (void)hipEventRecord(e0, s);
+            if (hipEventRecord(e0, s) != hipSuccess) { r0 = QB_E_HIP; break; }
             r0 = qb_anneal_ell(b, W, tile_d, F0_d, y0_d, nsw, B, thr_d, R, rw, seed, inst_base, Yw, ew, stream);
             if (r0 != QB_OK) break;
-            (void)hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess) { r0 = QB_E_HIP; break; }
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                r0 = QB_E_HIP;
+                break;
+            }
             if (r > 0) tot += ms;
         }
         if (r0 == QB_E_CAPACITY) break;   // larger rw do not fit either
