@@ -89,13 +89,14 @@ __global__ void k_pad_copy(const int16_t *__restrict__ Q, int n, int ld, T *__re
         out[(int64_t)i * ld + j] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
 }
 
-// Rows of Q in the dense Tabu kernel's thread-chunk order (qb_tabu_pos),
-// zero past column n.
+// Rows of Q in the dense Tabu kernel's thread order (qb_tabu_pos), zero
+// past column n.
 template <typename T>
 __global__ void k_tabu_copy(const int16_t *__restrict__ Q, int n, int ld, int ept, int tb, T *__restrict__ out)
 {
     const int i = blockIdx.y;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ld; j += gridDim.x * blockDim.x) {
+    // the ept * tb elements of a row; a slot's padding is left as it is
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ept * tb; j += gridDim.x * blockDim.x) {
         const int pos = qb_tabu_pos(j / tb, j % tb, ept, (int)sizeof(T), tb);
         out[(int64_t)i * ld + pos] = j < n ? (T)Q[(int64_t)i * n + j] : (T)0;
     }
@@ -188,10 +189,15 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
         if (ept) {
             P->tabu_tb = tb;
             P->tabu_ept = ept;
-            P->ldp = tb * ept;
             const size_t esz = P->int8_ok ? 1 : 2;
+            P->ldp = qb_tabu_pitch(tb, ept, (int)esz);
             if (hipMalloc(&P->Qp, esz * (size_t)n * P->ldp) != hipSuccess ||
                 hipMalloc(&P->Qt, esz * (size_t)n * P->ldp) != hipSuccess) {
+                fail(QB_E_HIP);
+                break;
+            }
+            // zero first: the copy kernel leaves the slots' padding alone
+            if (hipMemsetAsync(P->Qt, 0, esz * (size_t)n * P->ldp, s) != hipSuccess) {
                 fail(QB_E_HIP);
                 break;
             }

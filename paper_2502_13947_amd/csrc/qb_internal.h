@@ -21,7 +21,7 @@ struct qb_problem_s {
     void *Qp = nullptr;           // owned, device: Q with rows padded to ldp (int8 if int8_ok)
     void *Qt = nullptr;           // owned, device: the same rows in the dense Tabu kernel's
                                   // thread-chunk order (qb_tabu_pos), same type and pitch
-    int ldp = 0;                  // row pitch of Qp and Qt in elements: tabu_tb * tabu_ept
+    int ldp = 0;                  // row pitch of Qp and Qt in elements (qb_tabu_pitch)
     int tabu_tb = 0;              // dense Tabu workgroup size (0: n beyond its capacity)
     int tabu_ept = 0;             // dense Tabu variables per thread
     int int8_ok = 0;
@@ -69,16 +69,37 @@ static inline int qb_tabu_ept(int n, int tb)
     return 0;
 }
 
+// Elements of a thread's slot in a row of the dense Tabu kernel's copy of
+// Q: when its ept elements take at most 16 bytes, the slot is rounded up to
+// a power-of-two byte count, so one aligned vector load reads them (one load
+// instead of 8 + 2 bytes at ept = 10, or 4 + 2 + 1 at ept = 7, with int8;
+// the padding is never read into a key); beyond 16 bytes the slot is ept.
+static inline __host__ __device__ int qb_tabu_slot(int ept, int esz)
+{
+    const int bytes = ept * esz;
+    if (bytes > 16) return ept;
+    int p = 1;
+    while (p < bytes) p <<= 1;
+    return p / esz;
+}
+
+// Row pitch of the dense Tabu copy (and of the padded copy) in elements.
+static inline __host__ __device__ int qb_tabu_pitch(int tb, int ept, int esz)
+{
+    return tb * qb_tabu_slot(ept, esz);
+}
+
 // The dense Tabu kernel's copy of Q.  Thread t of the tb-thread workgroup
-// owns the variables e * tb + t (e < ept); in a row of the copy its ept
-// elements are split into chunks of 16, 8, 4, 2 and 1 bytes (largest first,
-// the largest repeated as often as it fits), and each chunk is stored for
-// all threads in turn, so one naturally aligned vector load per chunk reads
-// a thread's elements (two loads instead of five at ept = 5, one instead of
-// sixteen at ept = 16 with int8).  Returns the element offset of (e, t)
-// within the row.
+// owns the variables e * tb + t (e < ept).  Up to 16 bytes, its elements
+// fill the front of its padded slot (slots in thread order).  Beyond, they
+// are split into chunks of 16, 8, 4, 2 and 1 bytes (largest first, the
+// largest repeated as often as it fits), and each chunk is stored for all
+// threads in turn, so one naturally aligned vector load per chunk reads a
+// thread's elements (one load instead of sixteen at ept = 16 with int8).
+// Returns the element offset of (e, t) within the row.
 static inline __host__ __device__ int qb_tabu_pos(int e, int t, int ept, int esz, int tb)
 {
+    if (ept * esz <= 16) return t * qb_tabu_slot(ept, esz) + e;
     int start = 0;
     for (int sz = 16 / esz; sz >= 1; sz >>= 1)
         while (ept - start >= sz) {

@@ -20,9 +20,10 @@
 // step loop run in pairs so every slot address is fixed), where a DPP
 // minimum over lanes picks the smallest (32-bit (key, wave) when the move
 // values allow, else 64-bit (move, index, x)).  The chosen variable's row is
-// read from the Tabu copy of Q, where each thread's elements lie in a few
-// naturally aligned chunks (qb_tabu_pos), so a wave issues one vector load
-// per chunk rather than one byte load per element; every D is updated by
+// read from the Tabu copy of Q, where each thread's elements lie in one
+// padded, naturally aligned slot of up to 16 bytes, or in a few aligned
+// chunks beyond that (qb_tabu_pos), so a wave issues one vector load per
+// slot or chunk rather than one byte load per element; every D is updated by
 // one multiply-add and the owner of the flipped variable patches its own
 // element.  x_min is never copied: per-variable "flipped since the last
 // improvement" bits recover it, and the field is moved to x_min with the
@@ -48,13 +49,36 @@ struct TabuShape {
     static_assert(TB == 512 || TB == 1024, "eight or sixteen waves");
 };
 
-// Thread tid's elements of one row of the Tabu copy of Q (the chunk order of
-// qb_tabu_pos): one naturally aligned vector load per chunk, chunks of SZ
-// elements from element START on, then the elements sign-extended.
+constexpr int qb_pow2_at_least(int v) { return v <= 1 ? 1 : 2 * qb_pow2_at_least((v + 1) / 2); }
+
+// Thread tid's elements of one row of the Tabu copy of Q (the order of
+// qb_tabu_pos), sign-extended: up to 16 bytes one naturally aligned load of
+// the thread's padded slot; beyond, one load per chunk, chunks of SZ
+// elements from element START on.
 template <typename QT, int EPT, int TB, int START = 0, int SZ = 16 / (int)sizeof(QT)>
 __device__ __forceinline__ void tabu_row(const QT *row, uint32_t tid, int32_t (&q)[EPT])
 {
-    if constexpr (SZ >= 1 && START < EPT) {
+    constexpr int BYTES_ALL = EPT * (int)sizeof(QT);
+    if constexpr (START == 0 && BYTES_ALL <= 16 && qb_pow2_at_least(BYTES_ALL) != BYTES_ALL) {
+        constexpr int SLOT = qb_pow2_at_least(BYTES_ALL);     // bytes
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(row) + tid * (uint32_t)SLOT;
+        uint32_t w[4];
+        if constexpr (SLOT == 16) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(p);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else if constexpr (SLOT == 8) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(p);
+            w[0] = v.x; w[1] = v.y; w[2] = 0u; w[3] = 0u;
+        } else {
+            w[0] = *reinterpret_cast<const uint32_t *>(p); w[1] = w[2] = w[3] = 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const uint32_t word = w[(k * (int)sizeof(QT)) / 4];
+            const int sh = ((k * (int)sizeof(QT)) % 4) * 8;
+            q[k] = sizeof(QT) == 1 ? (int32_t)(int8_t)(word >> sh) : (int32_t)(int16_t)(word >> sh);
+        }
+    } else if constexpr (SZ >= 1 && START < EPT) {
         if constexpr (EPT - START >= SZ) {
             constexpr int BYTES = SZ * (int)sizeof(QT);
             const uint8_t *p = reinterpret_cast<const uint8_t *>(row + START * TB) + tid * (uint32_t)BYTES;
@@ -383,7 +407,7 @@ qb_status launch_tabu(qb_problem P, const QT *Qt, int ldp, int z, uint8_t *X, in
                       int tenure, int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
     const int ept = P->tabu_ept, tb = P->tabu_tb;
-    if (ept == 0 || ldp != tb * ept) return QB_E_CAPACITY;
+    if (ept == 0 || ldp != qb_tabu_pitch(tb, ept, (int)sizeof(QT))) return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
 #define QB_T(K, W)                                                                                 \
     if (ept == K && tb == W)                                                                      \

@@ -1,8 +1,9 @@
 """Host-side check of the dense Tabu kernel's copy of Q (qb_tabu_pos in the
 library's internal header, used by the builder kernel on the device): for
-every elements-per-thread count, element size and workgroup size it is a
-permutation of a row, and each thread's elements of a chunk are contiguous
-and naturally aligned for one vector load.  Compiled with hipcc for the
+every elements-per-thread count, element size and workgroup size it places
+each element once within the row pitch, a thread's elements up to 16 bytes
+fill the front of one aligned power-of-two slot, and beyond that each
+chunk is contiguous and naturally aligned for one vector load.  Compiled with hipcc for the
 host only (the header also holds device code); no GPU work."""
 import os
 import subprocess
@@ -22,16 +23,26 @@ int main() {
     for (int tb : {512, 1024})
         for (int esz : {1, 2})
             for (int ept : opts) {
-                std::vector<int> seen(tb * ept, 0);
+                const int pitch = qb_tabu_pitch(tb, ept, esz);
+                const int slot = qb_tabu_slot(ept, esz);
+                if (pitch < tb * ept) ++bad;
+                std::vector<int> seen(pitch, 0);
                 for (int t = 0; t < tb; ++t) {
-                    int prev = -2, run = 0;
+                    int prev = -2;
                     for (int e = 0; e < ept; ++e) {
                         const int pos = qb_tabu_pos(e, t, ept, esz, tb);
-                        if (pos < 0 || pos >= tb * ept) { ++bad; continue; }
+                        if (pos < 0 || pos >= pitch) { ++bad; continue; }
                         ++seen[pos];
+                        if (ept * esz <= 16) {
+                            // one slot per thread: a power of two of at most
+                            // 16 bytes, aligned, holding the elements in order
+                            const int sb = slot * esz;
+                            if (sb > 16 || (sb & (sb - 1)) != 0 || slot < ept) ++bad;
+                            if (pos != t * slot + e) ++bad;
+                            continue;
+                        }
                         // a new chunk starts where the position is not the next element
                         if (pos != prev + 1) {
-                            run = 0;
                             // the chunk's first element is aligned to the chunk size
                             int sz = 1;
                             while (e + sz < ept && qb_tabu_pos(e + sz, t, ept, esz, tb) == pos + sz) ++sz;
@@ -39,10 +50,11 @@ int main() {
                             if (sz * esz > 16 || (sz & (sz - 1)) != 0) ++bad;
                         }
                         prev = pos;
-                        ++run;
                     }
                 }
-                for (int c : seen) bad += c != 1;
+                int used = 0;
+                for (int c : seen) { bad += c > 1; used += c; }
+                bad += used != tb * ept;
             }
     std::printf("%d\n", bad);
     return bad != 0;
