@@ -186,6 +186,13 @@ qb_status qb_batch_get_info(qb_batch b, qb_batch_info *info_h);
  * validated on the host (ascending within a job, in [0,n), disjoint within a
  * solution: QB_E_ARG / QB_E_OVERLAP), then copied to the handle's idx. */
 qb_status qb_batch_set_idx(qb_batch b, const int32_t *idx_h, void *stream);
+/* Synchronises `stream` and returns QB_E_STATE if, since the last
+ * qb_batch_check, qb_writeback met a job with a replica that did not finish
+ * (e = INT64_MIN, see qb_set_anneal_wait_limit); the latch is then cleared.
+ * Such replicas are never chosen: a job none of whose replicas finished is
+ * not written back (qb_writeback), gives no gain (qb_gain_update) and no
+ * positive label (qb_trace). */
+qb_status qb_batch_check(qb_batch b, void *stream);
 /* Copies the handle's index sets (int32 [total]) into idx_d. */
 qb_status qb_batch_copy_idx(qb_batch b, int32_t *idx_d, void *stream);
 
@@ -289,8 +296,10 @@ qb_status qb_threshold_table(int32_t nsw, int32_t B, double tmax, double tmin, i
 
 /* ---------------------------------------------------------------- a6/a7/a8
  * Write-back (the last step of Alg. 3): per job the replica with the lowest e (lowest
- * r on ties) is written into X[sol][S] unconditionally, and dX[sol][S] =
- * Y - y0 (int8 in {-1,0,1}).  flags bit 0 (QB_WB_NOT_WORSE): write a job
+ * r on ties; replicas reporting e = INT64_MIN did not finish and are skipped,
+ * a job with none left is not written back and its ebest_job is INT64_MIN,
+ * and the batch latches QB_E_STATE for qb_batch_check) is written into
+ * X[sol][S] unconditionally, and dX[sol][S] = Y - y0 (int8 in {-1,0,1}).  flags bit 0 (QB_WB_NOT_WORSE): write a job
  * back only if that e <= 0 (the "only if not worse" variant; otherwise X
  * and dX of the job are left untouched).  dX_d (int8 [z][n]) must be all
  * zero on entry outside the jobs' variables.  ebest_job_d (optional, int64

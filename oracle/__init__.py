@@ -50,6 +50,10 @@ def lib():
         L.qbo_flip_delta.argtypes = [i32, P, P, P, i32]
         L.qbo_flip_delta.restype = i32
         L.qbo_eta.argtypes = [i32, P, P]
+        L.qbo_sigma.argtypes = [i32, P]
+        L.qbo_sigma.restype = f64
+        L.qbo_sigma_csr.argtypes = [i32, P, P, P]
+        L.qbo_sigma_csr.restype = f64
         L.qbo_init_x.argtypes = [i32, i32, u64, P]
         L.qbo_tabu.argtypes = [i32, P, P, P, P, i32, i32, i32, P, P]
         L.qbo_keys.argtypes = [i32, i32, P, P, P, i32, i32, i32, P]
@@ -146,6 +150,36 @@ def eta(Q) -> np.ndarray:
     out = np.zeros(Q.shape[0], np.int64)
     lib().qbo_eta(Q.shape[0], _p(Q), _p(out))
     return out
+
+
+def sigma(Q) -> float:
+    """sqrt(sum_{i != j} Q_ij^2 / n), the unit of the annealer's temperature
+    schedule and of the field features."""
+    Q = _c(Q, np.int16)
+    return float(lib().qbo_sigma(Q.shape[0], _p(Q)))
+
+
+def sigma_csr(n, rowptr, col, val) -> float:
+    """sigma of a problem given in compressed sparse rows."""
+    rp, c, v = _c(rowptr, np.int32), _c(col, np.int32), _c(val, np.int16)
+    return float(lib().qbo_sigma_csr(int(n), _p(rp), _p(c), _p(v)))
+
+
+def thresholds(Q, nsw, B=10, tmax_sigma=0.25, tmin_sigma=0.002) -> np.ndarray:
+    """The cosine-schedule acceptance table in units of this problem's sigma
+    (at least 1), as the solver's default schedule uses it."""
+    s = max(sigma(Q), 1.0)
+    return threshold_table(nsw, B, tmax_sigma * s, tmin_sigma * s)
+
+
+def feature_scales(Q, alpha, z) -> np.ndarray:
+    """FP32 scales of the learned selector's features 0..6: 1/sigma for the
+    field, the diagonal and the last gain, 1/alpha for the flip count and the
+    Tabu age, 1/eta_max for eta and 1/z for gamma z."""
+    sg = max(sigma(Q), 1.0)
+    a = max(int(alpha), 1)
+    em = max(int(eta(Q).max()), 1)
+    return np.array([1.0 / sg, 1.0 / sg, 1.0 / a, 1.0 / a, 1.0 / sg, 1.0 / em, 1.0 / z], np.float32)
 
 
 def init_x(n: int, z: int, seed: int) -> np.ndarray:

@@ -114,6 +114,37 @@ void qbo_eta(int n, const int16_t *Q, int64_t *eta)
     }
 }
 
+/* Scale of the annealer's temperature schedule and of the learned
+ * selector's field features (Reading 14: the IM's temperature is stated in
+ * units of the typical local-field size).  sigma = sqrt(S / n) with
+ * S = sum over i != j of Q_ij^2, summed exactly in 64-bit integers: the
+ * root-mean-square, over the variables, of the field's spread. */
+double qbo_sigma(int n, const int16_t *Q)
+{
+    uint64_t acc = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            int64_t v = Q[(int64_t)i * n + j];
+            acc += (uint64_t)(v * v);
+        }
+    return sqrt((double)acc / (double)n);
+}
+
+/* The same sum over the stored entries of compressed sparse rows (row i's
+ * entries col[rowptr[i] .. rowptr[i+1]), values val), skipping the diagonal. */
+double qbo_sigma_csr(int n, const int32_t *rowptr, const int32_t *col, const int16_t *val)
+{
+    uint64_t acc = 0;
+    for (int i = 0; i < n; ++i)
+        for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+            if (col[t] == i) continue;
+            int64_t v = val[t];
+            acc += (uint64_t)(v * v);
+        }
+    return sqrt((double)acc / (double)n);
+}
+
 /* Generate_Initial_Solution_Set (Alg. 2): z uniformly random binary rows.
  * Reading: bit = top bit of a Philox word, counter (j/4, p, 0, 3<<28),
  * word j mod 4, key = 64-bit seed. */

@@ -40,6 +40,10 @@ int32_t qbo_flip_delta(int n, const int16_t *Q, const uint8_t *x, const int32_t 
 /* eta_j = sum_i |Q_ij|  (Weight_Effect_Extraction). */
 void qbo_eta(int n, const int16_t *Q, int64_t *eta);
 
+/* sqrt(sum_{i != j} Q_ij^2 / n): the unit of the annealer's temperatures. */
+double qbo_sigma(int n, const int16_t *Q);
+double qbo_sigma_csr(int n, const int32_t *rowptr, const int32_t *col, const int16_t *val);
+
 /* Initial random solution set (Alg. 2, Generate_Initial_Solution_Set). */
 void qbo_init_x(int n, int z, uint64_t seed, uint8_t *X);
 

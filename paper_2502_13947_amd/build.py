@@ -22,9 +22,7 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    subprocess.check_call([HIPCC, *FLAGS, "-c", src, "-o", obj],
-                          stderr=subprocess.STDOUT if os.environ.get("QB_BUILD_VERBOSE") else subprocess.DEVNULL
-                          if False else None)
+    subprocess.check_call([HIPCC, *FLAGS, "-c", src, "-o", obj])
     return obj
 
 

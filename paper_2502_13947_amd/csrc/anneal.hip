@@ -898,14 +898,15 @@ __global__ void __launch_bounds__(256) k_writeback(int n, int R, const int32_t *
                                                    const uint8_t *__restrict__ Y, const int64_t *__restrict__ e,
                                                    const uint8_t *__restrict__ y0, uint8_t *__restrict__ X,
                                                    int8_t *__restrict__ dX, int64_t *__restrict__ ebest,
-                                                   int not_worse)
+                                                   int not_worse, int32_t *__restrict__ status)
 {
     const int q = blockIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
-    int rb = 0;
-    for (int r = 1; r < R; ++r)
-        if (e[(size_t)q * R + r] < e[(size_t)q * R + rb]) rb = r;
-    if (ebest && threadIdx.x == 0) ebest[q] = e[(size_t)q * R + rb];
+    bool failed;
+    const int rb = qb_best_replica(e + (size_t)q * R, R, &failed);
+    if (failed && threadIdx.x == 0) atomicOr(status, QB_FLAG_STATE);
+    if (ebest && threadIdx.x == 0) ebest[q] = rb < 0 ? INT64_MIN : e[(size_t)q * R + rb];
+    if (rb < 0) return;                                    // no replica finished: x_S and dX stay
     if (not_worse && e[(size_t)q * R + rb] > 0) return;   // x_S and dX stay as they are
     const uint8_t *Yr = Y + (size_t)base * R + (size_t)rb * m;
     for (int a = threadIdx.x; a < m; a += 256) {
@@ -979,7 +980,7 @@ extern "C" qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, con
     if (!b || R < 1 || R > 16 || !Y_d || !e_d || !y0_d || !X_d || !dX_d || (flags & ~1)) return QB_E_ARG;
     if (b->J == 0) return QB_OK;
     k_writeback<<<b->J, 256, 0, qb_stream(stream)>>>(b->n, R, b->sol_d, b->off_d, b->idx_d, Y_d, e_d, y0_d, X_d,
-                                                     dX_d, ebest_job_d, flags & 1);
+                                                     dX_d, ebest_job_d, flags & 1, b->status_d);
     QB_LAUNCH_CHECK();
     return QB_OK;
 }

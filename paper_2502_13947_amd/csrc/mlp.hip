@@ -119,11 +119,11 @@ __global__ void __launch_bounds__(256) k_trace(int n, int R, const int32_t *__re
 {
     const int q = blockIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
-    int rb = 0;
-    for (int r = 1; r < R; ++r)
-        if (e[(size_t)q * R + r] < e[(size_t)q * R + rb]) rb = r;
-    const bool gain = e[(size_t)q * R + rb] < 0;
-    const uint8_t *Yr = Y + (size_t)base * R + (size_t)rb * m;
+    bool failed;
+    const int rb = qb_best_replica(e + (size_t)q * R, R, &failed);
+    // a job without a finished replica gives no gain (and its Y is not read)
+    const bool gain = rb >= 0 && e[(size_t)q * R + rb] < 0;
+    const uint8_t *Yr = Y + (size_t)base * R + (size_t)(rb < 0 ? 0 : rb) * m;
     for (int a = threadIdx.x; a < m; a += 256) {
         const int j = idx[base + a];
         *reinterpret_cast<uint4 *>(outF + (int64_t)(base + a) * 8) =
@@ -141,9 +141,9 @@ __global__ void __launch_bounds__(256) k_gain(int n, int R, const int32_t *__res
 {
     const int q = blockIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
-    int rb = 0;
-    for (int r = 1; r < R; ++r)
-        if (e[(size_t)q * R + r] < e[(size_t)q * R + rb]) rb = r;
+    bool failed;
+    const int rb = qb_best_replica(e + (size_t)q * R, R, &failed);
+    if (rb < 0) return;                       // no finished replica: nothing changed
     const int64_t g = -e[(size_t)q * R + rb];
     const int32_t gs = (int32_t)max(min(g, (int64_t)INT32_MAX), (int64_t)INT32_MIN);
     const uint8_t *Yr = Y + (size_t)base * R + (size_t)rb * m;

@@ -214,6 +214,12 @@ extern "C" qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const i
                 break;
             }
         }
+        // the derived copies are complete before the handle is returned, so
+        // calls on other streams may use them at once
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            fail(QB_E_HIP);
+            break;
+        }
     } while (0);
     if (scan_d) (void)hipFree(scan_d);
     if (rc != QB_OK) {

@@ -58,8 +58,9 @@ static inline __host__ __device__ int qb_tabu_threads(int n)
     return ((n > 2048 && n <= 3072) || (n > 4096 && n <= 5120)) ? 512 : QB_TABU_THREADS;
 }
 
-// Elements per thread of the dense Tabu kernel with tb threads; the padded
-// copies of Q have pitch tb * EPT.  0 if n is too large.
+// Elements per thread of the dense Tabu kernel with tb threads (the padded
+// copies of Q have pitch qb_tabu_pitch(tb, EPT, element size)).  0 if n is
+// too large.
 static inline int qb_tabu_ept(int n, int tb)
 {
     // beyond 16 elements per thread the state no longer fits 128 VGPRs
@@ -141,6 +142,7 @@ struct qb_batch_s {
     int32_t *lpt_d = nullptr;         // [J] jobs by class, then size descending
     int cls_begin[QB_NCLASS] = {0}, cls_end[QB_NCLASS] = {0};
     hipStream_t side[QB_NCLASS] = {nullptr};
+    int32_t *status_d = nullptr;      // device status word (QB_FLAG_STATE: a job had a failed replica)
     hipEvent_t ev_fork = nullptr, ev_join[QB_NCLASS] = {nullptr};
 };
 
@@ -187,6 +189,26 @@ __device__ __forceinline__ uint4 qb_philox(uint4 c, uint32_t k0, uint32_t k1)
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     }
     return c;
+}
+
+// Replica chosen for job q (the write-back step of Alg. 3): the lowest e,
+// the lowest r on ties, over the replicas that finished.  A replica whose
+// bounded wait ran out reports e = INT64_MIN and is never chosen; -1 when
+// no replica of the job finished.  *failed is set when any replica did not.
+__device__ __forceinline__ int qb_best_replica(const int64_t *__restrict__ eq, int R, bool *failed)
+{
+    int rb = -1;
+    bool f = false;
+    for (int r = 0; r < R; ++r) {
+        const int64_t v = eq[r];
+        if (v == INT64_MIN) {
+            f = true;
+            continue;
+        }
+        if (rb < 0 || v < eq[rb]) rb = r;
+    }
+    *failed = f;
+    return rb;
 }
 
 __device__ __forceinline__ uint32_t qb_word(uint4 v, int w)

@@ -407,7 +407,7 @@ extern "C" void qb_batch_destroy(qb_batch b)
 {
     if (!b) return;
     for (void *ptr : {(void *)b->sol_d, (void *)b->off_d, (void *)b->rank0_d, (void *)b->idx_d,
-                      (void *)b->sol_begin_d, (void *)b->tile_off_d, (void *)b->lpt_d})
+                      (void *)b->sol_begin_d, (void *)b->tile_off_d, (void *)b->lpt_d, (void *)b->status_d})
         if (ptr) (void)hipFree(ptr);
     for (int c = 0; c < QB_NCLASS; ++c) {
         if (b->side[c]) (void)hipStreamDestroy(b->side[c]);
@@ -490,6 +490,7 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
         !up((void **)&b->sol_begin_d, sb.data(), sizeof(int32_t) * (z + 1)) ||
         !up((void **)&b->tile_off_d, toff.data(), sizeof(int64_t) * J) ||
         !up((void **)&b->lpt_d, lpt.data(), sizeof(int32_t) * J) ||
+        !up((void **)&b->status_d, nullptr, 0) ||
         hipMalloc((void **)&b->idx_d, sizeof(int32_t) * std::max(b->total, 4)) != hipSuccess ||
         hipMemset(b->idx_d, 0, sizeof(int32_t) * std::max(b->total, 4)) != hipSuccess)
         rc = QB_E_HIP;
@@ -530,6 +531,20 @@ extern "C" qb_status qb_batch_get_info(qb_batch b, qb_batch_info *info)
     info->off_d = b->off_d;
     info->idx_d = b->idx_d;
     return QB_OK;
+}
+
+extern "C" qb_status qb_batch_check(qb_batch b, void *stream)
+{
+    if (!b) return QB_E_ARG;
+    hipStream_t s = qb_stream(stream);
+    int32_t st = 0;
+    QB_TRY_HIP(hipMemcpyAsync(&st, b->status_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QB_TRY_HIP(hipStreamSynchronize(s));
+    if (st == 0) return QB_OK;
+    const int32_t zero = 0;
+    QB_TRY_HIP(hipMemcpyAsync(b->status_d, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    QB_TRY_HIP(hipStreamSynchronize(s));
+    return QB_E_STATE;
 }
 
 extern "C" qb_status qb_batch_set_idx(qb_batch b, const int32_t *idx_h, void *stream)

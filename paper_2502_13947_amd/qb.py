@@ -68,6 +68,7 @@ SIGNATURES = {
     "qb_batch_get_info": (_I32, [_P, ctypes.POINTER(BatchInfo)]),
     "qb_batch_set_idx": (_I32, [_P, _P, _P]),
     "qb_batch_copy_idx": (_I32, [_P, _P, _P]),
+    "qb_batch_check": (_I32, [_P, _P]),
     "qb_select": (_I32, [_P, _P, _P]),
     "qb_extract": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "qb_anneal": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P]),
@@ -213,6 +214,11 @@ class Batch:
         idx_h = np.ascontiguousarray(idx_h, np.int32)
         assert idx_h.shape[0] == self.total
         _chk(lib().qb_batch_set_idx(self.h, idx_h.ctypes.data, _stream(stream)), "qb_batch_set_idx")
+
+    def check(self, stream=None):
+        """Raises QBError (QB_E_STATE) if a write-back since the last check met
+        a replica that did not finish; clears the latch."""
+        _chk(lib().qb_batch_check(self.h, _stream(stream)), "qb_batch_check")
 
     def idx(self, device, stream=None) -> torch.Tensor:
         """Copy of the handle's index sets."""

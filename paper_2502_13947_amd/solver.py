@@ -303,4 +303,13 @@ class Solver:
                     if stall >= patience:
                         break
         self.stream.synchronize()
+        self.check()
         return [int(v.item()) if torch.is_tensor(v) else v for v in trace]
+
+    def check(self):
+        """Raises if a kernel latched an error or a write-back met a replica
+        that did not finish (the result would then differ from the method's)."""
+        self.P.check(stream=self.stream)
+        self.batch.check(stream=self.stream)
+        if self.init_m:
+            self.ib.check(stream=self.stream)

@@ -1,10 +1,15 @@
 """The dense workloads at their full sizes, in the launch configuration the
 benchmark times: n = 5000 at 50 % density (256 solutions, one sub-QUBO of
 512 each, one replica, 1000 sweeps, alpha = 5n) and n = 7000 fully dense
-(256 solutions, four sub-QUBOs of 128-1024 each).  Sampled solutions and
-jobs are checked against the oracle one by one, the rest against properties
-that hold at any size (H = Q x, E = x.h, flip counts sum to alpha, every
-replica's e equals the sub-QUBO energy change of its Y)."""
+(256 solutions, four sub-QUBOs of 128-1024 each); and the learned selector
+on the n = 5000 shape with fixed random BF16 weights.  Every solution's
+Tabu run, every key, every order row and every job's annealing are compared
+with the oracle element by element (independent oracle calls run on a
+thread pool: the C calls release the interpreter lock); the state after the
+write-back and the rank-k update is checked against H = Q x and E = x.h."""
+import concurrent.futures as cf
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +20,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+WORKERS = min(16, os.cpu_count() or 1)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -44,9 +50,70 @@ def subqubo_energy(T, c, y):
     return int(c @ y + y @ T @ y)
 
 
+def pmap(fn, items):
+    with cf.ThreadPoolExecutor(WORKERS) as ex:
+        return list(ex.map(fn, items))
+
+
+def check_tabu_all(Q, S, X0, H0, E0):
+    """Every solution's Tabu run (x_min, h, OV_min, flips, last flips)."""
+    Xt, Ht, Et, Tt, LFt = (t.cpu().numpy() for t in (S.X, S.H, S.E, S.T, S.LF))
+    assert (Tt.sum(1) == S.alpha).all()
+    refs = pmap(lambda p: oracle.tabu(Q, X0[p], H0[p], int(E0[p]), S.alpha, S.tenure, True), range(S.z))
+    for p, (x, h, ov, To, LFo) in enumerate(refs):
+        assert (Xt[p] == x).all() and (Ht[p] == h).all() and Et[p] == ov, p
+        assert (Tt[p] == To).all() and (LFt[p] == LFo).all(), p
+    return Xt, Ht, Et, Tt
+
+
+def check_order_all(K, order):
+    for p in range(K.shape[0]):
+        assert (order[p] == oracle.order(K[p])).all(), p
+
+
+def check_anneal_all(Q, S, Xt, Ht):
+    """Every job's Y and e against the oracle's sweep on the oracle's own
+    extraction of the same index set."""
+    b, R = S.batch, S.R
+    idx = b.idx(DEV).cpu().numpy()
+    Yh, eh = S.Y.cpu().numpy(), S.e.cpu().numpy()
+    thr_h = S.thr.cpu().numpy()
+
+    def one(q):
+        m = int(b.off[q + 1] - b.off[q])
+        Sq = idx[b.off[q]:b.off[q + 1]]
+        p = int(b.sol[q])
+        Tq, cq, F, yy = oracle.extract(Q, Xt[p], Ht[p], Sq)
+        Yo, eo = oracle.anneal(Tq, F, yy, thr_h, R, S.seed, S.inst + q, S.B)
+        got = Yh[b.off[q] * R:(b.off[q] + m) * R].reshape(R, m)
+        ok = (got == Yo).all() and (eh[q * R:(q + 1) * R] == eo).all()
+        ok = ok and all(eo[r] == subqubo_energy(Tq, cq, Yo[r]) - subqubo_energy(Tq, cq, yy) for r in range(R))
+        return ok, m
+
+    res = pmap(one, range(b.J))
+    bad = [(q, m) for q, (ok, m) in enumerate(res) if not ok]
+    assert not bad, bad[:10]
+    return eh
+
+
+def check_apply(S, Qf, R, eh, Et, one_job):
+    qb().zero(S.dX, stream=S.stream)
+    qb().writeback(S.batch, R, S.Y, S.e, S.y0, S.X, S.dX, stream=S.stream)
+    S._apply(stream=S.stream)
+    S.stream.synchronize()
+    X2, H2, E2 = S.X.cpu().numpy(), S.H.cpu().numpy(), S.E.cpu().numpy()
+    assert (H2 == field_of(Qf, X2)).all()
+    assert (E2 == (X2.astype(np.int64) * H2).sum(1)).all()
+    if one_job:
+        # one job per solution: the write-back moved every solution by exactly
+        # its best replica's sub-QUBO energy change
+        eb = eh.reshape(S.batch.J, R).min(1)
+        assert (E2 - Et == eb).all()
+
+
 @pytest.mark.parametrize("name", ["c2_n5000_d50", "c3_n7000_d100"])
-def test_full_size_dense_workload_sampled(name):
-    from paper_2502_13947_amd.solver import Solver, default_thresholds
+def test_full_size_dense_workload(name):
+    from paper_2502_13947_amd.solver import Solver
     w = dict(inputs.WORKLOADS[name])
     n, z, R = w["n"], w["z"], w["R"]
     say("full size", name)
@@ -54,27 +121,22 @@ def test_full_size_dense_workload_sampled(name):
     Qf = Q.astype(np.float64)
     Qd = torch.as_tensor(Q, device=DEV)
     P = qb().Problem(Qd)
-    thr = default_thresholds(P, w["nsw"])
+    assert P.sigma == oracle.sigma(Q)
+    thr = oracle.thresholds(Q, w["nsw"])
     job_m = inputs.job_sizes(z, w["k"], w["sizes"], seed=w["qseed"] + 100)
     S = Solver(Qd, z=z, seed=2025, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=10, R=R, alpha=5 * n,
                tenure=max(1, n // 150))
     S.init()
     S.stream.synchronize()
     X0, H0, E0 = (t.cpu().numpy() for t in (S.X, S.H, S.E))
+    assert (X0 == oracle.init_x(n, z, 2025)).all()
     assert (H0 == field_of(Qf, X0)).all()
     assert (E0 == (X0.astype(np.int64) * H0).sum(1)).all()
 
     say(name, "tabu")
     qb().tabu(S.P, S.X, S.H, S.E, S.alpha, S.tenure, True, S.T, S.LF, stream=S.stream)
     S.stream.synchronize()
-    Xt, Ht, Et, Tt = (t.cpu().numpy() for t in (S.X, S.H, S.E, S.T))
-    assert (Ht == field_of(Qf, Xt)).all()
-    assert (Et == (Xt.astype(np.int64) * Ht).sum(1)).all()
-    assert (Tt.sum(1) == S.alpha).all()
-    for p in (0, z - 1):
-        x, h, ov, To, LFo = oracle.tabu(Q, X0[p], H0[p], int(E0[p]), S.alpha, S.tenure, True)
-        assert (Xt[p] == x).all() and (Ht[p] == h).all() and Et[p] == ov, p
-        assert (Tt[p] == To).all() and (S.LF[p].cpu().numpy() == LFo).all(), p
+    Xt, Ht, Et, Tt = check_tabu_all(Q, S, X0, H0, E0)
 
     say(name, "keys/select/extract/anneal")
     b = S.batch
@@ -86,41 +148,86 @@ def test_full_size_dense_workload_sampled(name):
     S.stream.synchronize()
     Ko = oracle.keys(oracle.eta(Q), Xt, Tt, S.W)
     assert (S.K.cpu().numpy() == Ko).all()
-    assert (S.order[0].cpu().numpy() == oracle.order(Ko[0])).all()
-    idx = b.idx(DEV).cpu().numpy()
-    Yh, eh = S.Y.cpu().numpy(), S.e.cpu().numpy()
-    thr_h = S.thr.cpu().numpy()
-    # one job of every size class present, and the last job
-    sampled, seen = [], set()
-    for q in range(b.J):
-        m = int(b.off[q + 1] - b.off[q])
-        if m not in seen:
-            seen.add(m)
-            sampled.append(q)
-    sampled.append(b.J - 1)
-    for q in sampled:
-        m = int(b.off[q + 1] - b.off[q])
-        Sq = idx[b.off[q]:b.off[q + 1]]
-        p = int(b.sol[q])
-        Tq, cq, F, yy = oracle.extract(Q, Xt[p], Ht[p], Sq)
-        Yo, eo = oracle.anneal(Tq, F, yy, thr_h, R, S.seed, S.inst + q, S.B)
-        got = Yh[b.off[q] * R:(b.off[q] + m) * R].reshape(R, m)
-        say(name, "job", q, "m", m)
-        assert (got == Yo).all(), (q, m)
-        assert (eh[q * R:(q + 1) * R] == eo).all(), (q, m)
-        for r in range(R):
-            assert eo[r] == subqubo_energy(Tq, cq, Yo[r]) - subqubo_energy(Tq, cq, yy), (q, r)
+    check_order_all(Ko, S.order.cpu().numpy())
+    say(name, "all", b.J, "jobs")
+    eh = check_anneal_all(Q, S, Xt, Ht)
 
     say(name, "write-back/rank-k")
-    qb().zero(S.dX, stream=S.stream)
-    qb().writeback(b, R, S.Y, S.e, S.y0, S.X, S.dX, stream=S.stream)
-    S._apply(stream=S.stream)
+    check_apply(S, Qf, R, eh, Et, w["k"] == 1)
+
+
+def test_full_size_learned_selector_workload():
+    """The learned selector at the n = 5000, 50 %-dense shape (256 solutions,
+    one sub-QUBO of 512, 1000 sweeps) with fixed random BF16 weights: every
+    feature row, every MLP key, every order row of the MLP keys and every
+    job's annealing against the oracle."""
+    from paper_2502_13947_amd.solver import Solver
+    w = dict(inputs.WORKLOADS["c2_n5000_d50"])
+    n, z, R = w["n"], w["z"], w["R"]
+    Q = inputs.dense_qubo(n, w["density"], 44)
+    Qf = Q.astype(np.float64)
+    Qd = torch.as_tensor(Q, device=DEV)
+    thr = oracle.thresholds(Q, w["nsw"])
+    rng = np.random.default_rng(45)
+    W = oracle.bf16(rng.normal(0, 0.25, size=oracle.NPARAM).astype(np.float32))
+    alpha = 5 * n
+    job_m = np.full((z, 1), 512, np.int32)
+    S = Solver(Qd, z=z, seed=46, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=10, R=R, alpha=alpha,
+               tenure=max(1, n // 150), mlp_W=W)
+    scales = oracle.feature_scales(Q, alpha, z)
+    assert (S.scales == scales).all()
+    S.init()
     S.stream.synchronize()
-    X2, H2, E2 = S.X.cpu().numpy(), S.H.cpu().numpy(), S.E.cpu().numpy()
-    assert (H2 == field_of(Qf, X2)).all()
-    assert (E2 == (X2.astype(np.int64) * H2).sum(1)).all()
-    if w["k"] == 1:
-        # one job per solution: the write-back moved every solution by exactly
-        # its best replica's sub-QUBO energy change
-        eb = eh.reshape(b.J, R).min(1)
-        assert (E2 - Et == eb).all()
+    X0, H0, E0 = (t.cpu().numpy() for t in (S.X, S.H, S.E))
+
+    say("learned full size: tabu")
+    qb().tabu(S.P, S.X, S.H, S.E, S.alpha, S.tenure, True, S.T, S.LF, stream=S.stream)
+    S.stream.synchronize()
+    Xt, Ht, Et, Tt = check_tabu_all(Q, S, X0, H0, E0)
+    LFt = S.LF.cpu().numpy()
+
+    say("learned full size: features, scores, order")
+    b = S.batch
+    qb().features(S.P, S.X, S.H, S.T, S.LF, S.G, alpha, S.scales, S.F, stream=S.stream)
+    qb().mlp_score(S.F, S.mlp_W, S.KL, stream=S.stream)
+    qb().rank(S.KL, S.orderL, stream=S.stream)
+    qb().select(b, S.orderL, stream=S.stream)
+    S._extract(b, S.tiles, S.F0, S.y0, S.stream)
+    S._anneal(b, S.tiles, S.F0, S.y0, S.thr, S.Y, S.e, S.stream)
+    S.stream.synchronize()
+    G0 = np.zeros((z, n), np.int32)
+    Fo = oracle.features(Q, oracle.eta(Q), Xt, Ht, Tt, LFt, G0, alpha, scales)
+    assert (S.F.cpu().numpy().view(np.uint16) == Fo).all()
+    rows = Fo.reshape(z, n, 8)
+    KLo = np.stack(pmap(lambda p: oracle.mlp_scores(W, rows[p])[1], range(z)))
+    assert (S.KL.cpu().numpy() == KLo).all()
+    check_order_all(KLo, S.orderL.cpu().numpy())
+
+    say("learned full size: all", b.J, "jobs")
+    eh = check_anneal_all(Q, S, Xt, Ht)
+    check_apply(S, Qf, R, eh, Et, True)
+
+
+def test_c1_workload_full_trajectory():
+    """The n = 2500, 10 %-dense workload exactly as specified: 4 solutions,
+    4 sub-QUBOs of 128 per solution, 200 sweeps, the initial pass in blocks
+    of 128, all 10 outer iterations.  Every iteration's E_best and the final
+    X, H, E, x_best and E_best are bit-exact with the oracle's run."""
+    from paper_2502_13947_amd.solver import Solver
+    w = dict(inputs.WORKLOADS["c1_n2500_d10"])
+    n, z, k, R, iters = w["n"], w["z"], w["k"], w["R"], w["iters"]
+    Q = inputs.dense_qubo(n, w["density"], w["qseed"])
+    thr = oracle.thresholds(Q, w["nsw"])
+    job_m = np.full((z, k), 128, np.int32)
+    kw = dict(z=z, seed=2025, job_m=job_m, init_m=w["init_m"], thr_init=thr, thr=thr, B=10, R=R,
+              alpha=5 * n, tenure=max(1, n // 150))
+    say("c1 workload: gpu")
+    S = Solver(torch.as_tensor(Q, device=DEV), **kw)
+    trace = S.run(iters)
+    say("c1 workload: oracle")
+    ref = oracle.run(Q, iters=iters, **kw)
+    assert len(trace) == iters and trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all()
+    assert (S.H.cpu().numpy() == ref["H"]).all()
+    assert (S.E.cpu().numpy() == ref["E"]).all()
+    assert int(S.ebest.item()) == ref["ebest"] and (S.xbest.cpu().numpy() == ref["xbest"]).all()

@@ -80,7 +80,7 @@ def test_ising_form_of_subqubos_follows_the_qubo_annealer():
     F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
     y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
     qb().extract(P, b, dev(X), dev(H), tiles, F0, y0, c=c)
-    thr = oracle.threshold_table(nsw, B, 0.25 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(nsw, B, 0.25 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
     e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
     qb().anneal(b, tiles, F0, y0, dev(thr), R, 3, 40, Y, e, B)

@@ -328,7 +328,7 @@ def test_anneal_bit_exact(n, z, sizes, nsw, R, int8):
     y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
     qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
     B = 10
-    sig = P.sigma
+    sig = oracle.sigma(Q)
     thr = oracle.threshold_table(nsw, B, 0.5 * sig, 0.002 * sig)
     Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
     e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
@@ -365,7 +365,7 @@ def test_anneal_wait_limit_bails_out_cleanly():
     y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
     qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
     B = 10
-    thr = oracle.threshold_table(nsw, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(nsw, B, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     thr_d = torch.as_tensor(thr, device=DEV)
     seed, inst = 0x51, 300
     ref = []
@@ -393,6 +393,27 @@ def test_anneal_wait_limit_bails_out_cleanly():
             else:
                 assert eh[q * R + r] == eo[r] and (got[r] == Yo[r]).all(), (q, r)
     assert gave_up >= 1
+    # the write-back skips the replicas that did not finish: a job without a
+    # finished replica keeps x_S and dX, and the batch latches the failure
+    Xd = torch.as_tensor(X, device=DEV)
+    dX = torch.zeros((z, n), dtype=torch.int8, device=DEV)
+    eb = torch.zeros(b.J, dtype=torch.int64, device=DEV)
+    qb().writeback(b, R, Y, e, y0, Xd, dX, ebest_job=eb)
+    Xo = X.copy()
+    for q in range(b.J):
+        mm = int(b.off[q + 1] - b.off[q])
+        ok = [r for r in range(R) if eh[q * R + r] != np.iinfo(np.int64).min]
+        if not ok:
+            assert int(eb[q].item()) == np.iinfo(np.int64).min
+            continue
+        rb = min(ok, key=lambda r: (eh[q * R + r], r))
+        Xo[sol[q], idx[b.off[q]:b.off[q + 1]]] = Yh[b.off[q] * R + rb * mm:b.off[q] * R + (rb + 1) * mm]
+    assert (Xd.cpu().numpy() == Xo).all()
+    assert (dX.cpu().numpy() == (Xo.astype(np.int16) - X).astype(np.int8)).all()
+    with pytest.raises(qb().QBError) as ei:
+        b.check()
+    assert ei.value.status == -7
+    b.check()                                   # the latch was cleared
     with pytest.raises(qb().QBError):
         qb().set_anneal_wait_limit(-1)
     qb().anneal(b, tiles, F0, y0, thr_d, R, seed, inst, Y, e, B)
@@ -427,7 +448,7 @@ def test_writeback_rankk(variant):
     F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
     y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
     qb().extract(P, b, Xd, Hd, tiles, F0, y0)
-    thr = oracle.threshold_table(8, 10, 0.5 * P.sigma, 0.01 * P.sigma)
+    thr = oracle.threshold_table(8, 10, 0.5 * oracle.sigma(Q), 0.01 * oracle.sigma(Q))
     Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
     e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
     qb().anneal(b, tiles, F0, y0, torch.as_tensor(thr, device=DEV), R, 7, 0, Y, e, 10)
@@ -453,7 +474,7 @@ def test_writeback_rankk(variant):
 @pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("n,z,int8", [(37, 5, True), (1000, 70, True), (1003, 129, True), (5000, 256, True),
                                       (300, 40, False),
-                                      # padded-copy pitch 2560 (eight-wave Tabu sizing)
+                                      # eight-wave Tabu sizing: int8 slots of 8 bytes, padded-copy pitch 4096
                                       (2500, 64, True)])
 def test_rankk_variants(n, z, int8, variant):
     """H(X_old) + Q (X_new - X_old) must equal the field of X_new."""
@@ -522,8 +543,8 @@ def test_full_trajectory_small_config():
     Q = inputs.dense_qubo(n, 0.1, 51)
     job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
     P = qb().Problem(dq(Q))
-    thr = oracle.threshold_table(30, B, 0.5 * P.sigma, 0.002 * P.sigma)
-    thr0 = oracle.threshold_table(20, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(30, B, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
+    thr0 = oracle.threshold_table(20, B, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     S = Solver(dq(Q), z=z, seed=5, job_m=job_m, init_m=128, thr_init=thr0, thr=thr, B=B, R=R,
                alpha=5 * n, tenure=max(1, n // 150))
     trace = S.run(iters)
@@ -545,7 +566,7 @@ def test_graph_replay_matches_eager_and_oracle():
     Q = inputs.dense_qubo(n, 0.2, 61)
     job_m = np.tile([128, 64], (z, 1)).astype(np.int32)
     P = qb().Problem(dq(Q))
-    thr = oracle.threshold_table(25, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(25, B, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     kw = dict(z=z, seed=9, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=B, R=R, alpha=5 * n, tenure=4)
     G = Solver(dq(Q), **kw)
     G.init()
@@ -570,7 +591,7 @@ def test_autotuner_picks_a_variant_and_keeps_parity():
     n, z = 900, 64
     Q = inputs.dense_qubo(n, 0.5, 71)
     P = qb().Problem(dq(Q))
-    thr = oracle.threshold_table(5, 10, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(5, 10, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     S = Solver(dq(Q), z=z, seed=3, job_m=np.full((z, 1), 64, np.int32), init_m=0, thr_init=thr, thr=thr,
                B=10, R=1, alpha=50, tenure=6)
     S.init()
@@ -598,8 +619,8 @@ def test_features_bit_exact(n, z):
     LF = (rng.integers(0, 50, size=(z, n)) * (T > 0)).astype(np.int32)
     G = rng.integers(-5000, 5000, size=(z, n)).astype(np.int32)
     P = qb().Problem(dq(Q))
-    sg = max(P.sigma, 1.0)
-    sc = np.array([1 / sg, 1 / sg, 1 / 50, 1 / 50, 1 / sg, 1 / max(P.eta_max, 1), 1 / z], np.float32)
+    sg = max(oracle.sigma(Q), 1.0)
+    sc = np.array([1 / sg, 1 / sg, 1 / 50, 1 / 50, 1 / sg, 1 / max(int(oracle.eta(Q).max()), 1), 1 / z], np.float32)
     F = torch.zeros((z, n, 8), dtype=torch.int16, device=DEV)
     qb().features(P, *(torch.as_tensor(a, device=DEV) for a in (X, H, T, LF, G)), 50, sc, F)
     Fo = oracle.features(Q, oracle.eta(Q), X, H, T, LF, G, 50, sc)
@@ -668,7 +689,7 @@ def test_trace_and_gain_vs_oracle():
     F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
     y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
     qb().extract(P, b, Xd, Hd, tiles, F0, y0)
-    thr = oracle.threshold_table(6, 10, 0.3 * P.sigma, 0.01 * P.sigma)
+    thr = oracle.threshold_table(6, 10, 0.3 * oracle.sigma(Q), 0.01 * oracle.sigma(Q))
     Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
     e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
     qb().anneal(b, tiles, F0, y0, torch.as_tensor(thr, device=DEV), R, 5, 0, Y, e, 10)
@@ -697,19 +718,19 @@ def test_trace_and_gain_vs_oracle():
 
 def test_learned_selection_full_trajectory_vs_oracle():
     """Alg. 2 with the MLP choosing the IM variables: bit-exact trajectory."""
-    from paper_2502_13947_amd.solver import Solver, feature_scales
+    from paper_2502_13947_amd.solver import Solver
     n, z, iters, B, R = 500, 4, 3, 10, 2
     Q = inputs.dense_qubo(n, 0.15, 101)
     job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
     P = qb().Problem(dq(Q))
-    thr = oracle.threshold_table(20, B, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(20, B, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     W = _rand_params(102, 0.25)
     alpha = 5 * n
     S = Solver(dq(Q), z=z, seed=13, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=B, R=R, alpha=alpha,
                tenure=3, mlp_W=W)
     trace = S.run(iters)
     ref = oracle.run(Q, z=z, seed=13, iters=iters, alpha=alpha, tenure=3, job_m=job_m, init_m=0, thr_init=thr,
-                     thr=thr, B=B, R=R, mlp_W=W, scales=feature_scales(P, alpha, z))
+                     thr=thr, B=B, R=R, mlp_W=W, scales=oracle.feature_scales(Q, alpha, z))
     assert trace == list(ref["trace"])
     assert (S.X.cpu().numpy() == ref["X"]).all()
     assert (S.H.cpu().numpy() == ref["H"]).all()
@@ -721,7 +742,7 @@ def test_traces_and_training_are_deterministic():
     n, z = 600, 8
     Q = inputs.dense_qubo(n, 0.3, 111)
     P = qb().Problem(dq(Q))
-    thr = oracle.threshold_table(30, 10, 0.5 * P.sigma, 0.002 * P.sigma)
+    thr = oracle.threshold_table(30, 10, 0.5 * oracle.sigma(Q), 0.002 * oracle.sigma(Q))
     job_m = np.full((z, 1), 128, np.int32)
     S = Solver(dq(Q), z=z, seed=1, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=10, R=1, alpha=5 * n,
                tenure=4, trace_capacity=z * 128 * 4)

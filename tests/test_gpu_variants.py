@@ -106,8 +106,8 @@ def test_write_back_only_if_not_worse():
     assert (dX.cpu().numpy() == (Xo.astype(np.int16) - X).astype(np.int8)).all()
 
 
-def _kw(n, P, z, job_m, R, nsw=20, init_m=128, B=10):
-    sg = max(P.sigma, 1.0)
+def _kw(n, Q, z, job_m, R, nsw=20, init_m=128, B=10):
+    sg = max(oracle.sigma(Q), 1.0)
     thr = oracle.threshold_table(nsw, B, 0.25 * sg, 0.002 * sg)
     return dict(z=z, seed=5, job_m=job_m, init_m=init_m, thr_init=thr, thr=thr, B=B, R=R,
                 alpha=5 * n, tenure=max(1, n // 150))
@@ -138,7 +138,7 @@ def test_variant_trajectory_vs_oracle(variant, sparse):
         Q = inputs.dense_qubo(n, 0.1, 42)
         P = qb().Problem(dev(Q))
     job_m = np.tile([64, 100], (z, 1)).astype(np.int32)
-    kw = _kw(n, P, z, job_m, R)
+    kw = _kw(n, Q, z, job_m, R)
     if sparse:
         S = Solver(csr=(rp, col, val.astype(np.int16)), device=DEV, **kw, **variant)
     else:
@@ -158,7 +158,7 @@ def test_stall_termination_vs_oracle(patience):
     n, z, R = 400, 3, 1
     Q = inputs.dense_qubo(n, 0.1, 43)
     P = qb().Problem(dev(Q))
-    kw = _kw(n, P, z, np.tile([64], (z, 1)).astype(np.int32), R, init_m=0)
+    kw = _kw(n, Q, z, np.tile([64], (z, 1)).astype(np.int32), R, init_m=0)
     S = Solver(dev(Q), **kw)
     trace = S.run(25, patience=patience)
     ref = oracle.run(Q, iters=25, patience=patience, **kw)

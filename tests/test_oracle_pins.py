@@ -98,6 +98,41 @@ def test_eta_is_column_abs_sum():
     assert (oracle.eta(Q) == np.abs(Q.astype(np.int64)).sum(0)).all()
 
 
+def test_sigma_hand_computed_and_closed_forms():
+    # off-diagonal squares 1, 4, 9 (each twice): 28; the diagonal is excluded
+    Q = np.array([[5, 1, -2], [1, 0, 3], [-2, 3, 7]], np.int16)
+    assert oracle.sigma(Q) == math.sqrt(28 / 3)
+    assert oracle.sigma(np.diag(np.array([3, -9, 4], np.int16))) == 0.0
+    # every off-diagonal entry +-c: sigma = c sqrt(n - 1)
+    n, c = 41, 37
+    rng = np.random.default_rng(5)
+    S = rng.choice([-1, 1], size=(n, n))
+    S = np.triu(S, 1) + np.triu(S, 1).T
+    Qc = (S * c + np.diag(rng.integers(-100, 101, n))).astype(np.int16)
+    assert math.isclose(oracle.sigma(Qc), c * math.sqrt(n - 1), rel_tol=1e-15)
+
+
+def test_sigma_csr_equals_dense_sigma():
+    from paper_2502_13947_amd import inputs
+    rp, col, val = inputs.torus_graph_qubo(12, 15, 4.0, 3)
+    n = 180
+    Q = inputs.csr_to_dense(n, rp, col, val)
+    Q[np.arange(n), np.arange(n)] = 9                 # a stored diagonal is skipped
+    rp2, col2, val2 = inputs.dense_to_csr(Q)
+    assert oracle.sigma_csr(n, rp2, col2, val2) == oracle.sigma(Q) == math.sqrt(np.count_nonzero(
+        Q - np.diag(np.diag(Q))) / n)
+
+
+def test_sigma_of_the_random_instances_matches_their_distribution():
+    # pairs present with probability d, values uniform on [-100, 100]:
+    # E[sigma^2] = d (n - 1) E[v^2] with E[v^2] = 100 * 101 / 3
+    from paper_2502_13947_amd import inputs
+    for n, d, seed in [(2500, 0.1, 1), (1200, 0.5, 2)]:
+        Q = inputs.dense_qubo(n, d, seed)
+        want = math.sqrt(d * (n - 1) * 100 * 101 / 3)
+        assert abs(oracle.sigma(Q) / want - 1) < 0.01, (n, d)
+
+
 # --------------------------------------------------------------------------- Alg. 1 Tabu
 def test_tabu_hand_worked_fixtures():
     fx = json.load(open(os.path.join(GOLDEN, "tabu_fixtures.json")))
@@ -498,6 +533,70 @@ def test_mutation_probability_extremes():
     K2[:300] = 10                                            # top 240 all at K_hi -> P = 2^32-1
     _, flip2, k2 = oracle.mutate(x, K2, inU, t=0, p=0, seed=9)
     assert flip2[:240].sum() == 240 and flip2[240:].sum() == 0
+
+
+def _mutation_quartile_case():
+    """n = 5000: 100 IM variables, half holding the global K_lo = 0 and half
+    K_hi = 1000; 700 candidates each at K = 800, 600, 400, 200 and 2100 at
+    K = 100, interleaved.  At t = 0, k = floor(4900 r_0) = 2940: the four
+    upper groups and the 140 lowest-index candidates of K = 100."""
+    n = 5000
+    K = np.zeros(n, np.int64)
+    inU = np.zeros(n, np.uint8)
+    inU[::50] = 1                                   # 100 variables
+    U = np.flatnonzero(inU)
+    K[U[::2]] = 0
+    K[U[1::2]] = 1000
+    cand = np.flatnonzero(inU == 0)
+    groups = np.full(cand.size, 100, np.int64)
+    groups[:2800] = np.repeat([800, 600, 400, 200], 700)
+    rng = np.random.default_rng(17)
+    K[cand] = groups[rng.permutation(cand.size)]
+    return n, K, inU
+
+
+def test_mutation_flip_frequency_at_intermediate_keys():
+    """Reading 17: P_j = (K_j - K_lo)/(K_hi - K_lo) over all n variables, so
+    each key level flips at K/1000 here.  A min-max over the candidates only
+    (K_lo = 100, K_hi = 800) would give 1, 0.71, 0.43, 0.14 and 0 instead."""
+    n, K, inU = _mutation_quartile_case()
+    x = np.zeros(n, np.uint8)
+    counts = {v: [0, 0] for v in (800, 600, 400, 200, 100)}
+    for seed in range(4):
+        _, flip, k = oracle.mutate(x, K, inU, t=0, p=seed, seed=1000 + seed)
+        assert k == math.floor(4900 * 0.6)
+        cand = np.flatnonzero(inU == 0)
+        top = cand[np.lexsort((cand, -K[cand]))][:k]
+        assert flip[inU == 1].sum() == 0
+        assert set(np.flatnonzero(flip)) <= set(top)
+        for v in counts:
+            sel = top[K[top] == v]
+            counts[v][0] += int(flip[sel].sum())
+            counts[v][1] += sel.size
+    for v, (f, tot) in counts.items():
+        pr = v / 1000
+        assert tot > 0
+        assert abs(f / tot - pr) < 5 * math.sqrt(pr * (1 - pr) / tot), (v, f, tot)
+
+
+def test_mutation_key_minimum_held_by_an_im_variable():
+    """The global K_lo sits on an IM variable: a candidate with K = K_lo + 1
+    still flips only with probability 1/(K_hi - K_lo)."""
+    n = 64
+    x = np.zeros(n, np.uint8)
+    inU = np.zeros(n, np.uint8)
+    inU[0] = 1
+    K = np.full(n, 1, np.int64)
+    K[0] = 0                                        # K_lo, not a candidate
+    K[1] = 2**40                                    # K_hi
+    flips = 0
+    for seed in range(50):
+        _, flip, k = oracle.mutate(x, K, inU, t=0, p=0, seed=seed)
+        assert k == math.floor(63 * 0.6)
+        flips += int(flip[2:].sum())
+        assert flip[1] == 1                         # P = 2^32 - 1 for K_hi
+    # P = floor(2^32 / 2^40) = 0 for every K = 1 candidate
+    assert flips == 0
 
 
 # --------------------------------------------------------------------------- Alg. 2
