@@ -4,9 +4,15 @@
 A step is one outer iteration of Alg. 2 over the whole solution set: Tabu
 search, control-parameter keys, rank and selection, sub-QUBO extraction, the
 batched annealer (the Ising-machine stage), write-back, rank-k field update,
-exact energy, best tracking, mutation and its field update.  The metric is
+exact energy, best tracking, mutation and its field update, all inside the
+library (qb_iterate replays one captured iteration).  The metric is
 spin-flip attempts per second of the whole step (attempts = sum over jobs of
 replicas x sub-QUBO size x sweeps), with every input resident in HBM.
+
+The headline line is the n = 20000 sparse workload (the largest of the
+method's configurations: 2048 replicas of 1024-variable sub-QUBOs per step);
+the n = 7000 and n = 5000 dense workloads ride along under
+``extra_workloads``, each with its own roofline blocks.
 
 Prints one JSON line.  --gpus above 1 is rejected: the benchmark runs on one GPU.
 """
@@ -24,12 +30,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
 # int32 VALU: 256 CUs x 64 lanes x 2.4 GHz, one op per lane per clock
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # ALU work charged per annealer attempt: a quarter of a Philox4x32-10 block
 # (10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) = 80 ops / 4 words) plus the
 # move value, threshold index and compare (3 ops).
 ANNEAL_OPS_PER_ATTEMPT = 80 / 4 + 3
+HEADLINE = "c5_n20000_sparse"
+EXTRAS = ("c3_n7000_d100", "c2_n5000_d50")
 
 
 def parse():
@@ -37,10 +47,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_n5000_d50")
-    ap.add_argument("--cpu-sample", type=int, default=24, help="solutions in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated further workloads measured after the headline ('' = none)")
+    ap.add_argument("--extra-steps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of each oracle timing (single thread, all cores); 0 = skip")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="all-cores leg: worker processes (0 = automatic)")
     ap.add_argument("--no-init-pass", action="store_true")
-    ap.add_argument("--graph", type=int, default=1, help="also time a captured HIP graph of the same steps")
     ap.add_argument("--ttt", action="store_true",
                     help="time-to-target: learned vs plain selection (trains the selector first)")
     ap.add_argument("--ttt-seeds", type=int, default=5)
@@ -59,63 +73,91 @@ def workload(name):
     from paper_2502_13947_amd import inputs
     w = dict(inputs.WORKLOADS[name])
     n = w["n"]
-    w.update(alpha=5 * n, tenure=max(1, n // 150), B=10, seed=2025)
+    w.update(alpha=5 * n, tenure=max(1, n // 150), B=10, seed=2025, name=name)
     w["job_m"] = inputs.job_sizes(w["z"], w["k"], w["sizes"], seed=w["qseed"] + 100)
     return w
 
 
-def cpu_baseline(Q, w, thr, nsol, max_jobs=None):
-    """The oracle, untuned, on a bounded sample: `nsol` solutions through one
-    full outer iteration (Tabu, keys, selection, extraction, annealing,
-    write-back, field, mutation) on one host thread; with `max_jobs`, only
-    that many of each solution's sub-QUBOs are annealed."""
+# --------------------------------------------------------------------------- the oracle on the host
+_CPU = {}
+
+
+def _cpu_unit(args):
+    """One solution of the oracle's outer iteration: Tabu, then `jobs`
+    sub-QUBOs (extraction from the plain keys' order, annealing).  Returns
+    the attempts it annealed."""
     import oracle
+    p, jobs = args
+    Q, w, thr = _CPU["Q"], _CPU["w"], _CPU["thr"]
     n = w["n"]
-    X = oracle.init_x(n, nsol, w["seed"])
-    H = oracle.field(Q, X)
-    E = oracle.energy(X, H)
-    et = oracle.eta(Q)
+    x = oracle.init_x(n, p + 1, w["seed"])[p]
+    h = oracle.field(Q, x[None])[0]
+    ov = int(oracle.energy(x[None], h[None])[0])
+    x, h, ov, T, _ = oracle.tabu(Q, x, h, ov, w["alpha"], w["tenure"], True)
+    K = oracle.keys(_CPU["eta"], x[None], T[None], (2, 2, 1))[0]
+    o = oracle.order(K)
+    off, attempts = 0, 0
+    for m in w["job_m"][p][:jobs]:
+        S = np.sort(o[off:off + m]).astype(np.int32)
+        off += m
+        Tq, c, F0, y0 = oracle.extract(Q, x, h, S)
+        oracle.anneal(Tq, F0, y0, thr, w["R"], w["seed"], p, w["B"])
+        attempts += w["R"] * int(m) * thr.shape[0]
+    return attempts
+
+
+def cpu_baseline(Q, w, thr, seconds, workers):
+    """The oracle, untuned, on a bounded sample of the same workload: whole
+    solutions (Tabu, keys, order, extraction and annealing of their
+    sub-QUBOs), first on one host thread, then on `workers` processes over
+    independent solutions (multiprocessing; the oracle itself is unchanged).
+    The sample grows until it takes about `seconds`."""
+    import multiprocessing as mp
+
+    import oracle
+    _CPU.update(Q=Q, w=w, thr=thr, eta=oracle.eta(Q))
+    n_jobs = len(w["job_m"][0])
+    # one unit first, to size the samples
     t0 = time.perf_counter()
-    T = np.zeros((nsol, n), np.int32)
-    for p in range(nsol):
-        X[p], H[p], ov, T[p], _ = oracle.tabu(Q, X[p], H[p], int(E[p]), w["alpha"], w["tenure"], True)
-        E[p] = ov
-    K = oracle.keys(et, X, T, (2, 2, 1))
-    attempts = 0
-    for p in range(nsol):
-        o = oracle.order(K[p])
-        off = 0
-        inU = np.zeros(n, np.uint8)
-        for m in w["job_m"][p][:max_jobs]:
-            S = np.sort(o[off:off + m]).astype(np.int32)
-            off += m
-            Tq, c, F0, y0 = oracle.extract(Q, X[p], H[p], S)
-            Y, e = oracle.anneal(Tq, F0, y0, thr, w["R"], w["seed"], p, w["B"])
-            X[p, S] = Y[int(np.argmin(e))]
-            inU[S] = 1
-            attempts += w["R"] * m * thr.shape[0]
-        X[p], _, _ = oracle.mutate(X[p], K[p], inU, 0, p, w["seed"])
-    H = oracle.field(Q, X)
-    E = oracle.energy(X, H)
+    a0 = _cpu_unit((0, 1))
+    t_unit = time.perf_counter() - t0
+    jobs = max(1, min(n_jobs, int(seconds / max(t_unit, 1e-3))))
+    t0 = time.perf_counter()
+    a1 = _cpu_unit((0, jobs))
+    dt1 = time.perf_counter() - t0
+    single = dict(value=a1 / dt1, unit="spin-flip attempts/s", cores=1, kind="oracle",
+                  sample=f"1 of {w['z']} solutions: Tabu ({w['alpha']} steps), keys, order, and {jobs} of its "
+                         f"{n_jobs} sub-QUBOs annealed ({a1} attempts, {dt1:.1f} s)")
+    units = [(p % w["z"], jobs) for p in range(workers)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        att = sum(pool.map(_cpu_unit, units))
     dt = time.perf_counter() - t0
-    return dict(value=attempts / dt, unit="spin-flip attempts/s", cores=1, kind="oracle",
-                sample=f"{nsol} of {w['z']} solutions through one outer iteration"
-                       + (f", {max_jobs} of {len(w['job_m'][0])} sub-QUBOs each" if max_jobs else "")
-                       + f" ({attempts} attempts, {dt:.1f} s, single thread)")
+    return dict(value=att / dt, unit="spin-flip attempts/s", cores=workers, kind="oracle",
+                sample=f"{workers} solutions in {workers} worker processes, each as the single-thread sample "
+                       f"({att} attempts, {dt:.1f} s wall)",
+                nproc=os.cpu_count(), single_thread=single)
 
 
 def measured_traffic(workload_name, kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel's source changed since the counters were taken."""
+    or None when a source the kernel is built from changed since the
+    counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_name}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get("kernels", {}).get(kernel)
-    if not rec:
+    if not rec or "sources" not in rec:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        fn = os.path.join(ROOT, src)
+        if not os.path.exists(fn):
+            return None
+        h.update(open(fn, "rb").read())
+    if h.hexdigest() != rec["sources_sha256"]:
         return None
     return rec["bytes_per_launch"]
 
@@ -279,32 +321,29 @@ def ablation_main(a):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
-        sys.exit(2)
-    if a.ttt:
-        return ttt_main(a)
-    if a.ablation:
-        return ablation_main(a)
+
+
+def measure_workload(a, name, steps, warmup, cpu_seconds, headline):
+    """Set-up, `warmup` and `steps` timed outer iterations (one captured
+    iteration replayed), then the same number of eager iterations with the
+    library's stage events and the annealer's accept counters."""
     import torch
 
     from paper_2502_13947_amd import inputs, qb
     from paper_2502_13947_amd.solver import Solver, default_thresholds
 
-    w = workload(a.workload)
+    w = workload(name)
     n, z = w["n"], w["z"]
     dev = torch.device("cuda:0")
     sparse = bool(w.get("sparse"))
     kw = dict(z=z, seed=w["seed"], job_m=w["job_m"], init_m=0 if a.no_init_pass else w["init_m"], B=w["B"],
               R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
+    t_setup = time.perf_counter()
     if sparse:
         rp, col, val = inputs.torus_graph_qubo(w["rows"], w["cols"], w["avg_degree"], w["qseed"])
         csr = (rp, col, val.astype(np.int16))
         thr = default_thresholds(qb.Problem.from_csr(*csr, device=dev), w["nsw"], w["B"])
         S = Solver(csr=csr, device=dev, thr_init=thr, thr=thr, **kw)
-        Q = None
     else:
         Q = inputs.dense_qubo(n, w["density"], w["qseed"])
         Qd = torch.as_tensor(Q, device=dev)
@@ -313,146 +352,194 @@ def main():
     S.init()
     tuned_variant, tuned_ms = S.autotune()
     tuned_rw = S.autotune_anneal() if sparse else None
-    with torch.cuda.stream(S.stream):
-        for _ in range(a.warmup):
-            S.iterate()
-    S.stream.synchronize()
-
     stream = S.stream
-    stage_ev = []
+    S.state.iterate(warmup, graph=True, stream=stream)
+    stream.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] {name}: set-up and {warmup} warm-up steps in {t_setup:.1f} s", file=sys.stderr, flush=True)
 
-    def marks_for(step_events):
-        def mark(name):
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(stream)
-            step_events.append((name, ev))
-        return mark
-
+    # the timed region: `steps` replays of the captured iteration
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    stream.synchronize()
+    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        for _ in range(a.steps):
-            evs = []
-            S.iterate(marks=marks_for(evs))
-            stage_ev.append(evs)
-        end.record(stream)
+    start.record(stream)
+    S.state.iterate(steps, graph=True, stream=stream)
+    end.record(stream)
     stream.synchronize()
+    torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     total_ms = start.elapsed_time(end)
+    S.check()
 
-    # the same number of iterations replayed from one captured HIP graph
-    graph_ms = None
-    if a.graph:
-        g = S.capture(a.steps)
-        g0 = torch.cuda.Event(enable_timing=True)
-        g1 = torch.cuda.Event(enable_timing=True)
-        stream.synchronize()
-        g0.record(stream)
-        g.launch()
-        g1.record(stream)
-        stream.synchronize()
-        graph_ms = g0.elapsed_time(g1) / a.steps
-
-    stages = {}
-    for evs in stage_ev:
-        for (name, e0), (_, e1) in zip(evs, evs[1:]):
-            stages[name] = stages.get(name, 0.0) + e0.elapsed_time(e1)
-    stages = {k: v / a.steps for k, v in stages.items()}
-
+    # stage and kernel attribution: eager iterations with stage events, the
+    # annealer counting its accepted moves
     b = S.batch
-    attempts_per_step = int(w["R"] * w["nsw"] * int(np.sum(w["job_m"])))
-    value = attempts_per_step * a.steps / (total_ms / 1e3)
+    acnt = torch.zeros(b.J * w["R"], dtype=torch.int32, device=dev)
+    b.count_accepts(acnt)
+    S.state.enable_timing(True)
+    stages = np.zeros(6)
+    accepts = 0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        S.state.iterate(1, graph=False, stream=stream)
+        stages += S.state.stage_ms(stream=stream)
+        accepts += int(acnt.sum().item())
+    e1.record(stream)
+    stream.synchronize()
+    eager_ms = e0.elapsed_time(e1) / steps
+    S.state.enable_timing(False)
+    b.count_accepts(None)
+    stages = {k: float(v) / steps for k, v in zip(qb.STAGES, stages)}
+    accepts = accepts / steps
 
-    # roofline of the dominant kernel (Tabu and the annealer are single launches)
-    qbytes = 1 if S.P.int8_ok else 2
-    if sparse:
-        # one ELL row (ell_width 4-byte words) per step, plus the state in and out
-        tabu_bytes = z * w["alpha"] * S.P.ell_width * 4 + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
-        tabu_what = f"{z} solutions x {w['alpha']} steps x one {S.P.ell_width}-word ELL row"
-    else:
-        tabu_bytes = z * w["alpha"] * n * qbytes + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
-        tabu_what = f"{z} solutions x {w['alpha']} steps x one {n}-entry int{8 * qbytes} row of Q"
+    attempts = int(w["R"] * w["nsw"] * int(np.sum(w["job_m"])))
+    value = attempts * steps / (total_ms / 1e3)
     t_tabu, t_ann = stages["tabu"] / 1e3, stages["anneal"] / 1e3
-    # sparse Tabu: the method's step is an argmin over all n move values (one
-    # compare-select each); the row it reads is a few dozen bytes
-    tabu_ops = z * w["alpha"] * n
+
+    # the annealer against its roofline (per launch): row bytes of the
+    # accepted moves (a m b; an ELL row of W words on a sparse problem) and
+    # the VALU work (Philox quarter block + compare per attempt, one add per
+    # row element per accepted move)
+    if sparse:
+        row_bytes = 4 * S.P.ell_width
+        adds = S.P.ell_width
+        placement = "ELL tile in LDS"
+    else:
+        esz = 1 if S.P.int8_ok else 2
+        mavg = float(np.sum(w["job_m"])) / b.J
+        row_bytes = mavg * esz
+        adds = mavg
+        placement = "tiles of m <= 512 in LDS, m = 1024 rows streamed from L2/HBM"
+    lds_bytes = accepts * row_bytes
+    valu_ops = attempts * ANNEAL_OPS_PER_ATTEMPT + accepts * adds
+    t_lds = lds_bytes / (LDS_PEAK_GBS * 1e9)
+    t_valu = valu_ops / (ALU_PEAK_TOPS * 1e12)
+    binds = "lds" if t_lds >= t_valu else "alu"
+    anneal = dict(
+        ms=stages["anneal"], attempts=attempts, attempts_per_s=attempts / t_ann,
+        sweeps_per_s=b.J * w["R"] * w["nsw"] / t_ann, accepts=accepts, acceptance=accepts / attempts,
+        placement=placement,
+        roofline=dict(
+            binds=binds,
+            lds=dict(bytes=lds_bytes, achieved=lds_bytes / t_ann / 1e9, peak=LDS_PEAK_GBS, unit="GB/s",
+                     frac=lds_bytes / t_ann / 1e9 / LDS_PEAK_GBS,
+                     algorithmic=f"{accepts:.0f} accepted moves x {row_bytes:g} bytes of the accepted row"),
+            alu=dict(ops=valu_ops, achieved=valu_ops / t_ann / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s",
+                     frac=valu_ops / t_ann / 1e12 / ALU_PEAK_TOPS,
+                     algorithmic=f"{attempts} attempts x {ANNEAL_OPS_PER_ATTEMPT:g} int ops + "
+                                 f"{accepts:.0f} accepts x {adds:g} adds"),
+            frac=max(t_lds, t_valu) / t_ann))
+
+    # the dominant kernel's roofline
+    qbytes = 1 if S.P.int8_ok else 2
     if t_tabu >= t_ann and sparse:
-        ach = tabu_ops / t_tabu / 1e12
+        # the method's step is an argmin over all n move values (one
+        # compare-select each); the row a step reads is a few dozen bytes
+        ops = z * w["alpha"] * n
+        ach = ops / t_tabu / 1e12
         roof = dict(kernel="k_tabu_sp", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
-                    frac=ach / ALU_PEAK_TOPS, traffic=None,
-                    algorithmic=f"{z} solutions x {w['alpha']} steps x an argmin over {n} move values")
+                    frac=ach / ALU_PEAK_TOPS, traffic=measured_traffic(name, "k_tabu_sp"),
+                    algorithmic=f"{z} solutions x {w['alpha']} steps x an argmin over {n} move values",
+                    ns_per_step=t_tabu * 1e9 / w["alpha"])
     elif t_tabu >= t_ann:
+        tabu_bytes = z * w["alpha"] * n * qbytes + z * n * (1 + 4) + z * n * (1 + 4 + 4 + 4)
         ach = tabu_bytes / t_tabu / 1e9
         roof = dict(kernel="k_tabu", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(a.workload, "k_tabu"),
-                    algorithmic=tabu_what)
+                    frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(name, "k_tabu"),
+                    algorithmic=f"{z} solutions x {w['alpha']} steps x one {n}-entry int{8 * qbytes} row of Q",
+                    ns_per_step=t_tabu * 1e9 / w["alpha"])
     else:
-        ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
-        ach = ops / t_ann / 1e12
-        roof = dict(kernel="k_anneal", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
-                    frac=ach / ALU_PEAK_TOPS, traffic=measured_traffic(a.workload, "k_anneal"),
-                    algorithmic=f"{attempts_per_step} attempts x {ANNEAL_OPS_PER_ATTEMPT} int ops")
-    other = {}
-    ops = attempts_per_step * ANNEAL_OPS_PER_ATTEMPT
-    other["k_anneal"] = dict(ms=stages["anneal"], attempts_per_s=attempts_per_step / t_ann,
-                             alu_frac=ops / t_ann / 1e12 / ALU_PEAK_TOPS)
-    if sparse:
-        other["k_tabu_sp"] = dict(ms=stages["tabu"], ns_per_step=t_tabu * 1e9 / w["alpha"],
-                                  alu_frac=tabu_ops / t_tabu / 1e12 / ALU_PEAK_TOPS)
-    else:
-        other["k_tabu"] = dict(ms=stages["tabu"], GBps=tabu_bytes / t_tabu / 1e9,
-                               hbm_frac=tabu_bytes / t_tabu / 1e9 / HBM_PEAK_GBS,
-                               ns_per_step=t_tabu * 1e9 / w["alpha"])
+        roof = dict(kernel="anneal", bound=binds, achieved=anneal["roofline"][binds]["achieved"],
+                    peak=anneal["roofline"][binds]["peak"], unit=anneal["roofline"][binds]["unit"],
+                    frac=anneal["roofline"][binds]["frac"], traffic=measured_traffic(name, "anneal"),
+                    algorithmic=anneal["roofline"][binds]["algorithmic"])
+
+    cpu = None
+    if cpu_seconds > 0:
+        if sparse:
+            Qh = inputs.csr_to_dense(n, rp, col, val)
+        else:
+            Qh = Q
+        workers = a.cpu_workers or max(1, min(16, len(os.sched_getaffinity(0))))
+        print(f"[bench] {name}: oracle on the host ({workers} workers)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(Qh, w, thr, cpu_seconds, workers)
+
+    cfg = {"workload": name, "n": n,
+           **({"graph": f"{w['rows']}x{w['cols']} torus + random graph of average degree "
+                       f"{w['avg_degree']}, +-1 couplings, CSR", "ell_width": S.P.ell_width}
+              if sparse else {"density": w["density"]}), "z": z,
+           "subqubos_per_step": b.J, "m": sorted(set(int(v) for v in np.ravel(w["job_m"]))),
+           "sweeps": w["nsw"], "replicas": w["R"], "tabu_alpha": w["alpha"], "attempts_per_step": attempts}
+    out = dict(value=value, ms_per_step=total_ms / steps, config=cfg,
+               sweeps_per_s=b.J * w["R"] * w["nsw"] * steps / (total_ms / 1e3),
+               roofline=roof, anneal=anneal, stages_ms=stages, eager_ms_per_step=eager_ms,
+               rankk_variant={"chosen": tuned_variant, "ms": tuned_ms, "by": "autotuner"},
+               wall_s=t_wall, setup_s=t_setup)
+    if tuned_rw:
+        out["anneal_replicas_per_workgroup"] = {"chosen": tuned_rw[0], "ms": tuned_rw[1], "by": "autotuner"}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    del S
+    torch.cuda.synchronize()
+    return out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU (the method's state fits one MI355X); "
+                                   "--gpus must be 1"}))
+        sys.exit(2)
+    if a.ttt:
+        return ttt_main(a)
+    if a.ablation:
+        return ablation_main(a)
+    import torch
+
+    head = measure_workload(a, a.workload, a.steps, a.warmup, a.cpu_seconds, True)
+    extras = {}
+    for name in [x for x in a.extras.split(",") if x and x != a.workload]:
+        r = measure_workload(a, name, a.extra_steps, 2, 0.0, False)
+        extras[name] = {k: r[k] for k in ("value", "ms_per_step", "config", "roofline", "anneal", "stages_ms",
+                                          "eager_ms_per_step", "rankk_variant")}
 
     if a.copy_probe > 0:
         nb = a.copy_probe << 20
-        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
-        with torch.cuda.stream(stream):
-            for _ in range(3):
-                dst.copy_(src)
-        stream.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
         del src, dst
-
-    cpu = None
-    if a.cpu_sample > 0:
-        if sparse:
-            Q = inputs.csr_to_dense(n, rp, col, val)
-        cpu = cpu_baseline(Q, w, thr, 1, max_jobs=2) if sparse else cpu_baseline(Q, w, thr, a.cpu_sample)
 
     out = {
         "metric": "spin-flip attempts/sec",
-        "value": value,
+        "value": head["value"],
         "unit": "spin-flip attempts/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": total_ms / a.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": a.workload, "n": n,
-                   **({"graph": f"{w['rows']}x{w['cols']} torus + random graph of average degree "
-                               f"{w['avg_degree']}, +-1 couplings, CSR", "ell_width": S.P.ell_width}
-                      if sparse else {"density": w["density"]}), "z": z,
-                   "subqubos_per_step": b.J, "m": sorted(set(int(v) for v in np.ravel(w["job_m"]))),
-                   "sweeps": w["nsw"], "replicas": w["R"], "tabu_alpha": w["alpha"],
-                   "attempts_per_step": attempts_per_step},
-        "sweeps_per_s": b.J * w["R"] * w["nsw"] * a.steps / (total_ms / 1e3),
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "stages_ms": stages,
-        "kernels": other,
-        "graph_ms_per_step": graph_ms,
-        "rankk_variant": {"chosen": tuned_variant, "ms": tuned_ms, "by": "autotuner"},
-        **({"anneal_replicas_per_workgroup": {"chosen": tuned_rw[0], "ms": tuned_rw[1], "by": "autotuner"}}
-           if tuned_rw else {}),
-        "wall_s": t_wall,
+        "config": head["config"],
+        "sweeps_per_s": head["sweeps_per_s"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head.get("cpu_baseline"),
+        "anneal": head["anneal"],
+        "stages_ms": head["stages_ms"],
+        "eager_ms_per_step": head["eager_ms_per_step"],
+        "rankk_variant": head["rankk_variant"],
+        **({"anneal_replicas_per_workgroup": head["anneal_replicas_per_workgroup"]}
+           if "anneal_replicas_per_workgroup" in head else {}),
+        "extra_workloads": extras,
+        "wall_s": head["wall_s"],
     }
     print(json.dumps(out), flush=True)
 

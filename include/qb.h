@@ -193,6 +193,12 @@ qb_status qb_batch_set_idx(qb_batch b, const int32_t *idx_h, void *stream);
  * not written back (qb_writeback), gives no gain (qb_gain_update) and no
  * positive label (qb_trace). */
 qb_status qb_batch_check(qb_batch b, void *stream);
+/* Measurement hook: with acnt_d (device int32 [J * R], caller-owned) set,
+ * every later qb_anneal / qb_anneal_ell on the batch also writes the number
+ * of accepted moves of replica r of job q to acnt_d[q * R + r] (the count
+ * that sets the annealer's row traffic); NULL turns it off.  Results are
+ * unchanged. */
+qb_status qb_batch_count_accepts(qb_batch b, int32_t *acnt_d);
 /* Copies the handle's index sets (int32 [total]) into idx_d. */
 qb_status qb_batch_copy_idx(qb_batch b, int32_t *idx_d, void *stream);
 
@@ -412,6 +418,124 @@ qb_status qb_autotune_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, 
                                  const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
                                  uint64_t seed, uint32_t inst_base, int32_t reps, int32_t *rw_out, float *ms_out,
                                  void *stream);
+
+/* ---------------------------------------------------------------- a11 / b: state
+ * The main loop of Alg. 2 inside the library.  A qb_state holds one run of
+ * the method on a problem: the solution set and its fields, energies and
+ * Tabu statistics, the keys and orders of the selection, the sub-QUBO
+ * batch with its tiles and annealer outputs, the best solution, the
+ * per-iteration E_best trace and a device record of the iteration number
+ * and annealer instance, so that one captured outer iteration replays
+ * every later one.  Each buffer of qb_state_buffers given non-NULL at
+ * creation is BORROWED (caller-owned device memory of the stated size,
+ * which must outlive the state); the others are allocated and OWNED by the
+ * state.  Creation and destruction are not hot calls; qb_state_init,
+ * qb_iterate and qb_apply allocate nothing.
+ *
+ * One outer iteration (Alg. 2, in this order on `stream`):
+ *   Tabu (Alg. 1) on every solution, best;
+ *   keys (Alg. 4), rank; selection: the top control-parameter values
+ *     (plain), the top MLP scores of the features (QB_RUN_LEARNED) or random
+ *     keys (QB_RUN_RANDOM_SELECT, the No_SM ablation);
+ *   unless QB_RUN_NO_IM: extraction (eq. 4), the annealer (instance numbers
+ *     continuing from the previous iteration), gains and traces when kept,
+ *     write-back (Alg. 3), rank-k field update, energy, best;
+ *   mutation with r_t of the MRAnnealer, field update, energy, best;
+ *   E_best recorded for the iteration; iteration number advanced. */
+typedef struct qb_state_s *qb_state;
+#define QB_RUN_RANDOM_SELECT 1   /* No_SM ablation: random keys rank the IM variables and mutation candidates */
+#define QB_RUN_NO_IM 2           /* No_IM ablation: no Ising-machine stage */
+#define QB_RUN_INIT_JACOBI 4     /* initial pass: all blocks against one state (else block after block) */
+#define QB_RUN_WB_NOT_WORSE 8    /* write a sub-solution back only if its e <= 0 */
+#define QB_RUN_LEARNED 16        /* the MLP (mlp_W_d) picks the IM variables */
+typedef struct {
+    int32_t z;                  /* solutions, >= 1 */
+    int32_t k;                  /* sub-QUBO jobs per solution, >= 1 */
+    const int32_t *job_m_h;     /* host int32 [z][k] job sizes (1..1024, sum per solution <= n) */
+    uint64_t seed;              /* key of every Philox stream of the run */
+    int32_t init_m;             /* block size of the initial pass (Call_IM_Solution_Set); 0 = none */
+    int32_t nsw_init;           /* sweeps of the initial pass (>= 1 when init_m > 0) */
+    const int32_t *thr_init_h;  /* host int32 [nsw_init][2^B] acceptance table of the initial pass */
+    int32_t nsw;                /* sweeps of the IM stage */
+    const int32_t *thr_h;       /* host int32 [nsw][2^B] acceptance table of the IM stage */
+    int32_t B;                  /* table index bits (1..16) */
+    int32_t R;                  /* replicas per job (1..16) */
+    int32_t alpha, tenure, aspiration;   /* Tabu (qb_tabu) */
+    int32_t W1, W2, W3;         /* Alg. 4 weights as integers (Table 1: 2, 2, 1) */
+    int32_t flags;              /* QB_RUN_* */
+    const uint16_t *mlp_W_d;    /* device BF16 [4801] MLP parameters (QB_RUN_LEARNED; borrowed) */
+    const float *scales_h;      /* host float [7] feature scales (qb_features); needed when learned or tracing */
+    int64_t trace_capacity;     /* rows of the improvement-trace buffers; 0 = no traces */
+    int32_t max_iters;          /* iterations with their own r_t and E_best trace entry (later ones reuse the last r_t) */
+    int32_t rankk_variant;      /* qb_rankk variant (0 = automatic) */
+    int32_t anneal_rw;          /* sparse problems: qb_anneal_ell replicas per workgroup (0 = automatic) */
+} qb_run_cfg;
+typedef struct {
+    uint8_t *X;  int32_t *H;  int64_t *E;          /* [z][n], [z][n], [z] */
+    uint8_t *xbest; int64_t *ebest;                /* [n], [1] */
+    int64_t *ebest_trace;                          /* [max_iters]: E_best after iteration t */
+    int32_t *T, *LF, *G;                           /* [z][n] flips, last flips, last gains */
+    int64_t *K; int32_t *order;                    /* [z][n] keys and their order */
+    int8_t *dX;                                    /* [z][n] */
+    void *tiles;                                   /* qb_batch_info.tile_elems elements (int8 when the
+                                                      problem is int8_ok, else int16), or total * ell_width
+                                                      uint32 words on a sparse problem; 16-byte aligned */
+    int32_t *F0; uint8_t *y0;                      /* [total] */
+    uint8_t *Y; int64_t *e;                        /* [total * R], [J * R] */
+    uint16_t *F;                                   /* [z][n][8] features (learned or tracing), 16-byte aligned */
+    int64_t *KL; int32_t *orderL;                  /* [z][n] MLP keys and their order (learned) */
+    uint16_t *trace_F; uint8_t *trace_L;           /* [trace_capacity][8], [trace_capacity] */
+} qb_state_buffers;
+/* Validates cfg (QB_E_ARG, QB_E_CAPACITY as qb_batch_create, qb_tabu and
+ * qb_anneal state them; QB_E_RANGE when the run's instance numbers could
+ * reach 2^28 within max_iters), builds the sub-QUBO batch and the
+ * initial-pass batch, copies the tables, r_t for t < max_iters and the
+ * scales, and allocates what bufs_h does not give.  Synchronises `stream`. */
+qb_status qb_state_create(qb_state *out, qb_problem P, const qb_run_cfg *cfg, const qb_state_buffers *bufs_h,
+                          void *stream);
+void qb_state_destroy(qb_state S);
+/* The device buffers in use (borrowed or owned) and the sub-QUBO batch. */
+qb_status qb_state_get_buffers(qb_state S, qb_state_buffers *out_h);
+qb_batch qb_state_batch(qb_state S);
+/* Start of Alg. 2: Generate_Initial_Solution_Set (qb_init_solutions),
+ * field, energy, E_best reset and best, then Call_IM_Solution_Set in
+ * contiguous blocks of init_m (one after another, each seeing the previous
+ * blocks' results, or all at once with QB_RUN_INIT_JACOBI); the iteration
+ * record is set to t = 0 and the instance number that follows the pass. */
+qb_status qb_state_init(qb_state S, void *stream);
+/* `iters` outer iterations.  graph != 0: the first call captures one
+ * iteration into a HIP graph (on a stream of the state's own) and every
+ * iteration replays it on `stream`; graph == 0: the launches are enqueued
+ * directly (such a call may itself be captured).  patience > 0 stops after
+ * `patience` consecutive iterations without a lower E_best (the stall
+ * criterion of the termination remark; E_best is then read after every
+ * iteration, which synchronises `stream`).  *ran_h (optional) receives the
+ * number of iterations run. */
+qb_status qb_iterate(qb_state S, int32_t iters, int32_t graph, int32_t patience, int32_t *ran_h, void *stream);
+/* The state's iteration number t and annealer instance base (synchronises
+ * `stream`), and a rewind to iteration t (instance base as a run that went
+ * straight from qb_state_init to t; trace rows kept) -- a kernel, so it may
+ * be captured. */
+qb_status qb_state_get_iteration(qb_state S, int32_t *t_h, uint32_t *inst_h, int64_t *trace_rows_h, void *stream);
+qb_status qb_state_set_iteration(qb_state S, int32_t t, void *stream);
+/* Write-back of the state's last annealing (Alg. 3: the best finished
+ * replica of every job into X, the changes into dX), then the rank-k field
+ * update, energy and best: the apply step of one iteration, for callers
+ * that run the stages themselves. */
+qb_status qb_apply(qb_state S, void *stream);
+/* Kernel variants of later iterations (result-invariant: qb_rankk's variant,
+ * qb_anneal_ell's replicas per workgroup, 0 = automatic); a captured
+ * iteration is captured again. */
+qb_status qb_state_set_variants(qb_state S, int32_t rankk_variant, int32_t anneal_rw);
+/* Stage timing of iterations run with graph == 0: with timing on, each such
+ * iteration records events at its stage boundaries, and qb_state_stage_ms
+ * (synchronises `stream`) returns the last one's milliseconds for Tabu and
+ * best, keys and selection, extraction, annealing, write-back with its
+ * field update, and mutation with its field update (ms_h: float [6]). */
+qb_status qb_state_enable_timing(qb_state S, int32_t on);
+qb_status qb_state_stage_ms(qb_state S, float *ms_h, void *stream);
+/* qb_check of the problem and qb_batch_check of the state's batches. */
+qb_status qb_state_check(qb_state S, void *stream);
 
 #ifdef __cplusplus
 }

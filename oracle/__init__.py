@@ -67,6 +67,7 @@ def lib():
         L.qbo_mutation_rate.argtypes = [i32]
         L.qbo_mutation_rate.restype = f64
         L.qbo_anneal.argtypes = [i32, P, P, P, i32, i32, P, i32, u64, u32, P, P]
+        L.qbo_anneal_count.argtypes = [i32, P, P, P, i32, i32, P, i32, u64, u32, P, P, P]
         L.qbo_mutate.argtypes = [i32, P, P, P, i32, i32, u64, P]
         L.qbo_mutate.restype = i32
         L.qbo_mutate2.argtypes = [i32, P, P, P, P, i32, i32, u64, P]
@@ -255,8 +256,9 @@ def mutation_rate(t) -> float:
     return float(lib().qbo_mutation_rate(int(t)))
 
 
-def anneal(Tq, F0, y0, thr, R, seed, inst, B):
-    """Returns (Y [R,m] uint8, e [R] int64)."""
+def anneal(Tq, F0, y0, thr, R, seed, inst, B, count=False):
+    """Returns (Y [R,m] uint8, e [R] int64), and with ``count`` the
+    accepted moves per replica (int32 [R]) as a third element."""
     Tq = _c(Tq, np.int32)
     F0 = _c(F0, np.int32)
     y0 = _c(y0, np.uint8)
@@ -266,9 +268,10 @@ def anneal(Tq, F0, y0, thr, R, seed, inst, B):
     assert thr.shape[1] == (1 << B)
     Y = np.zeros((R, m), np.uint8)
     e = np.zeros(R, np.int64)
-    lib().qbo_anneal(m, _p(Tq), _p(F0), _p(y0), nsw, int(B), _p(thr), int(R), int(seed), int(inst),
-                     _p(Y), _p(e))
-    return Y, e
+    na = np.zeros(R, np.int32)
+    lib().qbo_anneal_count(m, _p(Tq), _p(F0), _p(y0), nsw, int(B), _p(thr), int(R), int(seed), int(inst),
+                           _p(Y), _p(e), _p(na))
+    return (Y, e, na) if count else (Y, e)
 
 
 def mutate(x, K, inU, t, p, seed):

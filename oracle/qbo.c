@@ -374,12 +374,22 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
                 int nsw, int B, const int32_t *thr, int R, uint64_t seed, uint32_t inst,
                 uint8_t *Y, int64_t *e)
 {
+    qbo_anneal_count(m, Tq, F0, y0, nsw, B, thr, R, seed, inst, Y, e, NULL);
+}
+
+/* The same sweep; nacc[r] (optional) receives the number of accepted moves
+ * of replica r. */
+void qbo_anneal_count(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
+                      int nsw, int B, const int32_t *thr, int R, uint64_t seed, uint32_t inst,
+                      uint8_t *Y, int64_t *e, int32_t *nacc)
+{
     int32_t *F = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
     for (int r = 0; r < R; ++r) {
         uint8_t *y = Y + (int64_t)r * m;
         memcpy(y, y0, (size_t)m);
         memcpy(F, F0, sizeof(int32_t) * (size_t)m);
         int64_t acc = 0;
+        int32_t na = 0;
         for (int s = 0; s < nsw; ++s) {
             for (int k = 0; k < m; ++k) {
                 int32_t dE = y[k] ? -F[k] : F[k];
@@ -391,11 +401,13 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
                     int32_t d = y[k] ? -1 : 1;
                     y[k] ^= 1;
                     acc += dE;
+                    ++na;
                     for (int i = 0; i < m; ++i) F[i] += 2 * d * Tq[(int64_t)i * m + k];
                 }
             }
         }
         e[r] = acc;
+        if (nacc) nacc[r] = na;
     }
     free(F);
 }

@@ -81,6 +81,10 @@ void qbo_anneal(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
                 int nsw, int B, const int32_t *thr, int R, uint64_t seed, uint32_t inst,
                 uint8_t *Y, int64_t *e);
 
+void qbo_anneal_count(int m, const int32_t *Tq, const int32_t *F0, const uint8_t *y0,
+                      int nsw, int B, const int32_t *thr, int R, uint64_t seed, uint32_t inst,
+                      uint8_t *Y, int64_t *e, int32_t *nacc);
+
 /* Ising form (eq. 2, eq. 3) in quarter units: 4 f(x) = E'(2x - 1) + const4
  * with J = -Q off the diagonal (J[n][n], zero diagonal) and h[n]; returns
  * const4.  qbo_ising_energy: E'(s).  qbo_anneal_ising: the spin-form

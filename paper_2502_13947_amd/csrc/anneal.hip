@@ -191,8 +191,8 @@ __global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ job
                                                  const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
                                                  const uint8_t *__restrict__ y0, int nsw, int B,
                                                  const int32_t *__restrict__ thr, int R, uint32_t k0,
-                                                 uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
-                                                 int64_t *__restrict__ eout)
+                                                 uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                 int64_t *__restrict__ eout, int32_t *__restrict__ acnt)
 {
     constexpr int MP = 64 * MS;
     __shared__ __align__(16) uint8_t lds[AnnealLds<MS, TT, MODE>::bytes];
@@ -233,7 +233,8 @@ __global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ job
         active[s] = na == 64 ? ~0ull : ((1ull << na) - 1ull);
     }
     int64_t e = 0;
-    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    int32_t nacc = 0;
+    const uint32_t tag = (1u << 28) | (inst_base + (it ? it->inst : 0u) + (uint32_t)q);
     constexpr int G = (MS + 3) / 4;
     const int sh = 32 - B;
 
@@ -263,6 +264,7 @@ __global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ job
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
                 const int32_t ykb = __builtin_amdgcn_readlane((int32_t)yb, k);
                 e += dEk;
+                ++nacc;
                 const int32_t d2 = ykb ? -2 : 2;
                 if (lane == k) ybits ^= 1u << s;
                 int32_t rv[MS];
@@ -281,16 +283,17 @@ __global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ job
         if (pos < m) Yr[pos] = (uint8_t)((ybits >> s) & 1u);
     }
     if (lane == 0) eout[(size_t)q * R + r] = e;
+    if (acnt && lane == 0) acnt[(size_t)q * R + r] = nacc;
 }
 
 template <int MS, typename TT, int MODE>
 void launch_anneal(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
                    const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
-                   uint32_t inst_base, uint8_t *Y, int64_t *e)
+                   uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
     k_anneal<MS, TT, MODE><<<nblocks, 64 * R, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0,
                                                       nsw, B, thr, R, (uint32_t)seed, (uint32_t)(seed >> 32),
-                                                      inst_base, Y, e);
+                                                      inst_base, it, Y, e, b->acnt_d);
 }
 
 // ------------------------------------------------------------ anneal, waves
@@ -379,8 +382,9 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
                                                     const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
                                                     const uint8_t *__restrict__ y0, int nsw, int B,
                                                     const int32_t *__restrict__ thr, int R, uint32_t k0,
-                                                    uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
-                                                    int64_t *__restrict__ eout, int wait_limit)
+                                                    uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                    int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
+                                                    int wait_limit)
 {
     using C = AnnealMw<MS, TT, MODE>;
     constexpr int NW = C::NW, NB = C::NB, DW = C::DW, MP = 64 * MS;
@@ -388,6 +392,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
     __shared__ __align__(16) uint8_t lds[C::tile];
     __shared__ uint32_t lists[C::RMAX][MS][MW_SLOTS];
     __shared__ int64_t esum[16];
+    __shared__ int32_t asum[16];
     __shared__ int32_t bad[C::RMAX];
     const int q = jobs[blockIdx.x];
     const int base = off[q], m = off[q + 1] - base;
@@ -439,7 +444,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
             dcol[j][i] = wv;
         }
     }
-    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    const uint32_t tag = (1u << 28) | (inst_base + (it ? it->inst : 0u) + (uint32_t)q);
     const int sh = 32 - B;
     // thresholds of one sweep for the own blocks: they lie in one Philox
     // group (s0 >> 2), the uniform of block s being word s & 3
@@ -457,6 +462,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
     int32_t tvn[NB];
     thresholds(0, tvn);
     int64_t e = 0;
+    int32_t nacc = 0;
     int Gc = 0;                // next list this wave has to apply
     bool ok = true;
 
@@ -550,6 +556,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
             M[j] = ((ym >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gt | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             e += ej;
+            nacc += c;
         }
         Gc = G0 + NB;
         if (sw + 1 < nsw) thresholds(sw + 1, tvn);
@@ -557,6 +564,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
 
     if (!ok && lane == 0) __hip_atomic_store(&bad[r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (lane == 0) esum[wg] = e;
+    if (lane == 0) asum[wg] = nacc;
     uint8_t *Yr = Y + (size_t)base * R + (size_t)r * m;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -566,15 +574,20 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
     __syncthreads();
     if (w == 0 && lane == 0) {
         int64_t t = 0;
-        for (int v = 0; v < NW; ++v) t += esum[r * NW + v];
+        int32_t na = 0;
+        for (int v = 0; v < NW; ++v) {
+            t += esum[r * NW + v];
+            na += asum[r * NW + v];
+        }
         eout[(size_t)q * R + r] = bad[r] ? INT64_MIN : t;
+        if (acnt) acnt[(size_t)q * R + r] = na;
     }
 }
 
 template <int MS, typename TT, int MODE>
 bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
                       const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
-                      uint32_t inst_base, uint8_t *Y, int64_t *e)
+                      uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
     using C = AnnealMw<MS, TT, MODE>;
     // replicas per workgroup, and list tags G + 1 < 2^24 that cannot wrap
@@ -583,11 +596,11 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
     if (lim == MW_WAIT_DEFAULT)
         k_anneal_mw<MS, TT, MODE, false><<<nblocks, 64 * C::NW * R, 0, s>>>(
             jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
-            (uint32_t)(seed >> 32), inst_base, Y, e, lim);
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim);
     else
         k_anneal_mw<MS, TT, MODE, true><<<nblocks, 64 * C::NW * R, 0, s>>>(
             jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
-            (uint32_t)(seed >> 32), inst_base, Y, e, lim);
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim);
     return true;
 }
 
@@ -627,8 +640,9 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                                                      const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
                                                      const uint8_t *__restrict__ y0, int nsw, int B,
                                                      const int32_t *__restrict__ thr, int R, uint32_t k0,
-                                                     uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
-                                                     int64_t *__restrict__ eout, int wait_limit)
+                                                     uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                     int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
+                                                     int wait_limit)
 {
     using C = AnnealMwG<MS, TT>;
     constexpr int NW = C::NW, NB = C::NB, DW = C::DW, PER = C::PER, P = C::P, SLOTS = C::SLOTS;
@@ -638,6 +652,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
     __shared__ __align__(16) uint8_t own[NW][C::NOFF > 0 ? C::NOFF : 1][C::OBLK];
     __shared__ uint32_t lists[MS][SLOTS];
     __shared__ int64_t esum[NW];
+    __shared__ int32_t asum[NW];
     __shared__ int32_t bad;
     const int q = jobs[blockIdx.x];
     const int base = off[q], m = off[q + 1] - base;
@@ -693,7 +708,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
         const int na = min(max(m - 64 * (s0 + j), 0), 64);
         active[j] = na == 64 ? ~0ull : ((1ull << na) - 1ull);
     }
-    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    const uint32_t tag = (1u << 28) | (inst_base + (it ? it->inst : 0u) + (uint32_t)q);
     const int sh = 32 - B;
     auto thresholds = [&](int sw, int32_t (&tv)[NB]) {
         const uint4 o = qb_philox(make_uint4(((uint32_t)(s0 >> 2) << 6) | (uint32_t)lane, (uint32_t)sw, (uint32_t)r, tag),
@@ -708,6 +723,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
     int32_t tvn[NB];
     thresholds(0, tvn);
     int64_t e = 0;
+    int32_t nacc = 0;
     int Gc = 0;
     bool ok = true;
 
@@ -811,6 +827,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
             M[j] = ((ym >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gtag | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             e += ej;
+            nacc += c;
         }
         Gc = G0 + NB;
         if (sw + 1 < nsw) thresholds(sw + 1, tvn);
@@ -818,6 +835,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
 
     if (!ok && lane == 0) __hip_atomic_store(&bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (lane == 0) esum[w] = e;
+    if (lane == 0) asum[w] = nacc;
     uint8_t *Yr = Y + (size_t)base * R;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -827,15 +845,20 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
     __syncthreads();
     if (tid == 0) {
         int64_t t = 0;
-        for (int v = 0; v < NW; ++v) t += esum[v];
+        int32_t na = 0;
+        for (int v = 0; v < NW; ++v) {
+            t += esum[v];
+            na += asum[v];
+        }
         eout[(size_t)q * R] = bad ? INT64_MIN : t;
+        if (acnt) acnt[(size_t)q * R] = na;
     }
 }
 
 template <int MS, typename TT>
 bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
                         const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
-                        uint32_t inst_base, uint8_t *Y, int64_t *e)
+                        uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
     if (R != 1 || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
     const int32_t lim = g_wait_limit.load(std::memory_order_relaxed);
@@ -843,19 +866,21 @@ bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, 
     if (lim == MW_WAIT_DEFAULT)
         k_anneal_mw_g<MS, TT, false><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
                                                             y0, nsw, B, thr, R, (uint32_t)seed,
-                                                            (uint32_t)(seed >> 32), inst_base, Y, e, lim);
+                                                            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d,
+                                                            lim);
     else
         k_anneal_mw_g<MS, TT, true><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
                                                            y0, nsw, B, thr, R, (uint32_t)seed,
-                                                           (uint32_t)(seed >> 32), inst_base, Y, e, lim);
+                                                           (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d,
+                                                           lim);
     return true;
 }
 
 bool dispatch_anneal(int cls, bool int8_tile, int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b,
                      const void *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr,
-                     uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
+                     uint64_t seed, uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
-#define QB_ARGS nblocks, R, s, jobs, b, tiles, F0, y0, nsw, B, thr, seed, inst_base, Y, e
+#define QB_ARGS nblocks, R, s, jobs, b, tiles, F0, y0, nsw, B, thr, seed, inst_base, it, Y, e
     // the multi-wave kernel where its replicas fit one workgroup
     if (int8_tile) {
         switch (cls) {
@@ -938,9 +963,9 @@ extern "C" qb_status qb_extract(qb_problem P, qb_batch b, const uint8_t *X_d, co
     return QB_OK;
 }
 
-extern "C" qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
-                              const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
-                              uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream)
+qb_status qb_anneal_x(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d, const uint8_t *y0_d,
+                      int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R, uint64_t seed, uint32_t inst_base,
+                      const qb_iter *it, uint8_t *Y_d, int64_t *e_d, void *stream)
 {
     if (!b || !tile_d || !F0_d || !y0_d || !thr_d || !Y_d || !e_d) return QB_E_ARG;
     if (nsw < 1 || B < 1 || B > 16 || R < 1 || R > 16) return QB_E_ARG;
@@ -961,7 +986,7 @@ extern "C" qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile
             QB_TRY_HIP(hipStreamWaitEvent(ls, b->ev_fork, 0));
         }
         if (!dispatch_anneal(c, int8_tile != 0, nblk, R, ls, b->lpt_d + b->cls_begin[c], b, tile_d, F0_d, y0_d,
-                             nsw, B, thr_d, seed, inst_base, Y_d, e_d))
+                             nsw, B, thr_d, seed, inst_base, it, Y_d, e_d))
             return QB_E_UNSUPPORTED;
         QB_LAUNCH_CHECK();
         if (!first) {
@@ -971,6 +996,13 @@ extern "C" qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile
         first = false;
     }
     return QB_OK;
+}
+
+extern "C" qb_status qb_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
+                              const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                              uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d, void *stream)
+{
+    return qb_anneal_x(b, tile_d, int8_tile, F0_d, y0_d, nsw, B, thr_d, R, seed, inst_base, nullptr, Y_d, e_d, stream);
 }
 
 extern "C" qb_status qb_writeback(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d,

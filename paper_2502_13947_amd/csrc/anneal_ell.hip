@@ -93,8 +93,8 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
                                                      const int32_t *__restrict__ F0,
                                                      const uint8_t *__restrict__ y0, int nsw, int B,
                                                      const int32_t *__restrict__ thr, int R, int rw, uint32_t k0,
-                                                     uint32_t k1, uint32_t inst_base, uint8_t *__restrict__ Y,
-                                                     int64_t *__restrict__ eout)
+                                                     uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                     int64_t *__restrict__ eout, int32_t *__restrict__ acnt)
 {
     constexpr int MP = 64 * MS;
     extern __shared__ __align__(16) uint32_t dl[];
@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
         active[s] = na == 64 ? ~0ull : ((1ull << na) - 1ull);
     }
     int64_t e = 0;
-    const uint32_t tag = (1u << 28) | (inst_base + (uint32_t)q);
+    int32_t nacc = 0;
+    const uint32_t tag = (1u << 28) | (inst_base + (it ? it->inst : 0u) + (uint32_t)q);
     constexpr int G = (MS + 3) / 4;
     const int sh = 32 - B;
 
@@ -169,6 +170,7 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
                 const int32_t ykb = __builtin_amdgcn_readlane((int32_t)yb, k);
                 e += dEk;
+                ++nacc;
                 const int32_t d2 = ykb ? -2 : 2;
                 if (lane == k) ybits ^= 1u << s;
                 const uint32_t *row = tl + (size_t)(64 * s + k) * W;
@@ -201,6 +203,7 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
         if (pos < m) Yr[pos] = (uint8_t)((ybits >> s) & 1u);
     }
     if (lane == 0) eout[(size_t)q * R + r] = e;
+    if (acnt && lane == 0) acnt[(size_t)q * R + r] = nacc;
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -210,7 +213,7 @@ inline size_t ell_lds_bytes(int ms, int W, int rw) { return sizeof(uint32_t) * (
 template <int MS>
 qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *jobs, qb_batch b, int W,
                      const uint32_t *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr,
-                     uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
+                     uint64_t seed, uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
     const size_t lds = ell_lds_bytes(MS, W, rw);
     // set on every launch (no cached flag shared between devices or threads)
@@ -218,17 +221,17 @@ qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *job
                                    (int)LDS_MAX));
     const int rgroups = (R + rw - 1) / rw;
     k_anneal_ell<MS><<<njobs * rgroups, 64 * rw, lds, s>>>(jobs, rgroups, b->off_d, W, tiles, F0, y0, nsw, B, thr, R,
-                                                           rw, (uint32_t)seed, (uint32_t)(seed >> 32), inst_base, Y,
-                                                           e);
+                                                           rw, (uint32_t)seed, (uint32_t)(seed >> 32), inst_base, it,
+                                                           Y, e, b->acnt_d);
     QB_LAUNCH_CHECK();
     return QB_OK;
 }
 
 qb_status dispatch_ell(int cls, int njobs, int rw, int R, hipStream_t s, const int32_t *jobs, qb_batch b, int W,
                        const uint32_t *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B,
-                       const int32_t *thr, uint64_t seed, uint32_t inst_base, uint8_t *Y, int64_t *e)
+                       const int32_t *thr, uint64_t seed, uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
-#define QB_ARGS njobs, rw, R, s, jobs, b, W, tiles, F0, y0, nsw, B, thr, seed, inst_base, Y, e
+#define QB_ARGS njobs, rw, R, s, jobs, b, W, tiles, F0, y0, nsw, B, thr, seed, inst_base, it, Y, e
     switch (cls) {
     case 0: return launch_ell<16>(QB_ARGS);
     case 1: return launch_ell<8>(QB_ARGS);
@@ -256,10 +259,9 @@ extern "C" qb_status qb_extract_ell(qb_problem P, qb_batch b, const uint8_t *X_d
     return QB_OK;
 }
 
-extern "C" qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d,
-                                  const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
-                                  int32_t rw, uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d,
-                                  void *stream)
+qb_status qb_anneal_ell_x(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d, const uint8_t *y0_d,
+                          int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R, int32_t rw, uint64_t seed,
+                          uint32_t inst_base, const qb_iter *it, uint8_t *Y_d, int64_t *e_d, void *stream)
 {
     if (!b || !tile_d || !F0_d || !y0_d || !thr_d || !Y_d || !e_d) return QB_E_ARG;
     if (nsw < 1 || B < 1 || B > 16 || R < 1 || R > 16 || rw < 0 || rw > 16) return QB_E_ARG;
@@ -289,7 +291,7 @@ extern "C" qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d
             QB_TRY_HIP(hipStreamWaitEvent(ls, b->ev_fork, 0));
         }
         const qb_status rc = dispatch_ell(c, nj, r2, R, ls, b->lpt_d + b->cls_begin[c], b, W, tile_d, F0_d, y0_d, nsw,
-                                          B, thr_d, seed, inst_base, Y_d, e_d);
+                                          B, thr_d, seed, inst_base, it, Y_d, e_d);
         if (rc != QB_OK) return rc;
         if (!first) {
             QB_TRY_HIP(hipEventRecord(b->ev_join[c], ls));
@@ -298,4 +300,12 @@ extern "C" qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d
         first = false;
     }
     return QB_OK;
+}
+
+extern "C" qb_status qb_anneal_ell(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d,
+                                  const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                                  int32_t rw, uint64_t seed, uint32_t inst_base, uint8_t *Y_d, int64_t *e_d,
+                                  void *stream)
+{
+    return qb_anneal_ell_x(b, W, tile_d, F0_d, y0_d, nsw, B, thr_d, R, rw, seed, inst_base, nullptr, Y_d, e_d, stream);
 }

@@ -115,10 +115,18 @@ __global__ void __launch_bounds__(256) k_trace(int n, int R, const int32_t *__re
                                                const int32_t *__restrict__ off, const int32_t *__restrict__ idx,
                                                const uint16_t *__restrict__ F, const uint8_t *__restrict__ Y,
                                                const int64_t *__restrict__ e, const uint8_t *__restrict__ y0,
-                                               uint16_t *__restrict__ outF, uint8_t *__restrict__ outL)
+                                               uint16_t *__restrict__ outF, uint8_t *__restrict__ outL,
+                                               const qb_iter *__restrict__ it, int64_t cap, int total)
 {
     const int q = blockIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
+    if (it) {
+        // appended after the rows already written, only while the ring has room
+        const int64_t at = it->trn;
+        if (at + total > cap) return;
+        outF += at * 8;
+        outL += at;
+    }
     bool failed;
     const int rb = qb_best_replica(e + (size_t)q * R, R, &failed);
     // a job without a finished replica gives no gain (and its Y is not read)
@@ -311,16 +319,23 @@ extern "C" qb_status qb_mlp_score(int64_t count, const uint16_t *F_d, const uint
     return QB_OK;
 }
 
-extern "C" qb_status qb_trace(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_d, const int64_t *e_d,
-                             const uint8_t *y0_d, uint16_t *outF_d, uint8_t *outL_d, void *stream)
+qb_status qb_trace_x(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_d, const int64_t *e_d,
+                     const uint8_t *y0_d, uint16_t *outF_d, uint8_t *outL_d, const qb_iter *it, int64_t cap,
+                     void *stream)
 {
     if (!b || R < 1 || R > 16 || !F_d || !Y_d || !e_d || !y0_d || !outF_d || !outL_d) return QB_E_ARG;
     if (((uintptr_t)F_d & 15) || ((uintptr_t)outF_d & 15)) return QB_E_ARG;
     if (b->J == 0) return QB_OK;
     k_trace<<<b->J, 256, 0, qb_stream(stream)>>>(b->n, R, b->sol_d, b->off_d, b->idx_d, F_d, Y_d, e_d, y0_d, outF_d,
-                                                 outL_d);
+                                                 outL_d, it, cap, b->total);
     QB_LAUNCH_CHECK();
     return QB_OK;
+}
+
+extern "C" qb_status qb_trace(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_d, const int64_t *e_d,
+                             const uint8_t *y0_d, uint16_t *outF_d, uint8_t *outL_d, void *stream)
+{
+    return qb_trace_x(b, R, F_d, Y_d, e_d, y0_d, outF_d, outL_d, nullptr, 0, stream);
 }
 
 extern "C" qb_status qb_gain_update(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d,

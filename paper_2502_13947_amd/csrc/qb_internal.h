@@ -143,8 +143,43 @@ struct qb_batch_s {
     int cls_begin[QB_NCLASS] = {0}, cls_end[QB_NCLASS] = {0};
     hipStream_t side[QB_NCLASS] = {nullptr};
     int32_t *status_d = nullptr;      // device status word (QB_FLAG_STATE: a job had a failed replica)
+    int32_t *acnt_d = nullptr;        // optional, caller's: accepted moves per replica of the last annealing
     hipEvent_t ev_fork = nullptr, ev_join[QB_NCLASS] = {nullptr};
 };
+
+// Per-iteration scalars of a captured outer iteration (Alg. 2), held in
+// device memory so that one graph replays every iteration: kernels given a
+// non-null record read t (mutation, random keys), add inst to the
+// annealer's instance numbers and append traces at trn; the state's
+// advance kernel moves it to the next iteration.
+// Stages of one outer iteration timed by qb_state_stage_ms.
+#define QB_NSTAGE 6
+
+struct qb_iter {
+    int32_t t;          // outer iteration, from 0
+    uint32_t inst;      // instance number of the batch's first job
+    int32_t trn;        // trace rows written
+    int32_t pad;
+};
+
+// Entry points with the iteration record (nullptr: the scalars given).
+qb_status qb_anneal_x(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d, const uint8_t *y0_d,
+                      int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R, uint64_t seed, uint32_t inst_base,
+                      const qb_iter *it, uint8_t *Y_d, int64_t *e_d, void *stream);
+qb_status qb_anneal_ell_x(qb_batch b, int32_t W, const uint32_t *tile_d, const int32_t *F0_d, const uint8_t *y0_d,
+                          int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R, int32_t rw, uint64_t seed,
+                          uint32_t inst_base, const qb_iter *it, uint8_t *Y_d, int64_t *e_d, void *stream);
+// rate_tab (device, ntab entries) gives r_t for the record's t (the last
+// entry beyond the table)
+qb_status qb_mutate_x(qb_batch b, const int64_t *K_d, const int32_t *order_d, double rate, int32_t t,
+                      const qb_iter *it, const double *rate_tab, int32_t ntab, uint64_t seed, uint8_t *X_d,
+                      int8_t *dX_d, int32_t *kcount_d, void *stream);
+qb_status qb_random_keys_x(int32_t n, int32_t z, int32_t t, const qb_iter *it, uint64_t seed, int64_t *K_d,
+                           void *stream);
+// traces appended at the record's trn when cap rows leave room (else none)
+qb_status qb_trace_x(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_d, const int64_t *e_d,
+                     const uint8_t *y0_d, uint16_t *outF_d, uint8_t *outL_d, const qb_iter *it, int64_t cap,
+                     void *stream);
 
 // Column counts c_j = sum_p X[p][j] into P->colcnt (enqueued on stream).
 qb_status qb_column_counts(qb_problem P, int z, const uint8_t *X, void *stream);

@@ -56,8 +56,10 @@ __global__ void __launch_bounds__(256) k_keys(int n, int z, const int64_t *__res
 
 // Random keys of the ablation without control parameters: one Philox word
 // per (solution, variable), stream tag 4 in counter word 3.
-__global__ void k_random_keys(int n, int t, uint32_t k0, uint32_t k1, int64_t *__restrict__ K)
+__global__ void k_random_keys(int n, int t, const qb_iter *__restrict__ it, uint32_t k0, uint32_t k1,
+                              int64_t *__restrict__ K)
 {
+    if (it) t = it->t;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;   // group of 4 variables
     const int p = blockIdx.y;
     if (4 * g >= n) return;
@@ -271,9 +273,15 @@ __global__ void __launch_bounds__(1024) k_mutate(int n, const int32_t *__restric
                                                  const int32_t *__restrict__ idx,
                                                  const int64_t *__restrict__ K,
                                                  const int32_t *__restrict__ order, double rate, int t,
+                                                 const qb_iter *__restrict__ it,
+                                                 const double *__restrict__ rate_tab, int ntab,
                                                  uint32_t k0, uint32_t k1, uint8_t *__restrict__ X,
                                                  int8_t *__restrict__ dX, int32_t *__restrict__ kcount)
 {
+    if (it) {
+        t = it->t;
+        rate = rate_tab[t < ntab ? t : ntab - 1];
+    }
     __shared__ uint32_t inU[2048];
     __shared__ int wsum[16];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -364,13 +372,19 @@ extern "C" qb_status qb_keys(qb_problem P, int32_t z, const uint8_t *X_d, const 
     return QB_OK;
 }
 
-extern "C" qb_status qb_random_keys(int32_t n, int32_t z, int32_t t, uint64_t seed, int64_t *K_d, void *stream)
+qb_status qb_random_keys_x(int32_t n, int32_t z, int32_t t, const qb_iter *it, uint64_t seed, int64_t *K_d,
+                           void *stream)
 {
     if (n < 1 || z < 1 || z > 65535 || t < 0 || !K_d) return QB_E_ARG;
     dim3 grid(((n + 3) / 4 + 255) / 256, z);
-    k_random_keys<<<grid, 256, 0, qb_stream(stream)>>>(n, t, (uint32_t)seed, (uint32_t)(seed >> 32), K_d);
+    k_random_keys<<<grid, 256, 0, qb_stream(stream)>>>(n, t, it, (uint32_t)seed, (uint32_t)(seed >> 32), K_d);
     QB_LAUNCH_CHECK();
     return QB_OK;
+}
+
+extern "C" qb_status qb_random_keys(int32_t n, int32_t z, int32_t t, uint64_t seed, int64_t *K_d, void *stream)
+{
+    return qb_random_keys_x(n, z, t, nullptr, seed, K_d, stream);
 }
 
 extern "C" qb_status qb_rank(int32_t n, int32_t z, const int64_t *K_d, int32_t *order_d, void *stream)
@@ -533,6 +547,13 @@ extern "C" qb_status qb_batch_get_info(qb_batch b, qb_batch_info *info)
     return QB_OK;
 }
 
+extern "C" qb_status qb_batch_count_accepts(qb_batch b, int32_t *acnt_d)
+{
+    if (!b) return QB_E_ARG;
+    b->acnt_d = acnt_d;
+    return QB_OK;
+}
+
 extern "C" qb_status qb_batch_check(qb_batch b, void *stream)
 {
     if (!b) return QB_E_ARG;
@@ -589,14 +610,22 @@ extern "C" qb_status qb_select(qb_batch b, const int32_t *order_d, void *stream)
     return QB_OK;
 }
 
+qb_status qb_mutate_x(qb_batch b, const int64_t *K_d, const int32_t *order_d, double rate, int32_t t,
+                      const qb_iter *it, const double *rate_tab, int32_t ntab, uint64_t seed, uint8_t *X_d,
+                      int8_t *dX_d, int32_t *kcount_d, void *stream)
+{
+    if (!b || !K_d || !order_d || !X_d || !dX_d || !(rate >= 0.0) || t < 0) return QB_E_ARG;
+    if (it && (!rate_tab || ntab < 1)) return QB_E_ARG;
+    k_mutate<<<b->z, 1024, 0, qb_stream(stream)>>>(b->n, b->sol_begin_d, b->off_d, b->idx_d, K_d,
+                                                  order_d, rate, t, it, rate_tab, ntab, (uint32_t)seed,
+                                                  (uint32_t)(seed >> 32), X_d, dX_d, kcount_d);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
 extern "C" qb_status qb_mutate(qb_batch b, const int64_t *K_d, const int32_t *order_d, double rate,
                               int32_t t, uint64_t seed, uint8_t *X_d, int8_t *dX_d, int32_t *kcount_d,
                               void *stream)
 {
-    if (!b || !K_d || !order_d || !X_d || !dX_d || !(rate >= 0.0) || t < 0) return QB_E_ARG;
-    k_mutate<<<b->z, 1024, 0, qb_stream(stream)>>>(b->n, b->sol_begin_d, b->off_d, b->idx_d, K_d,
-                                                  order_d, rate, t, (uint32_t)seed,
-                                                  (uint32_t)(seed >> 32), X_d, dX_d, kcount_d);
-    QB_LAUNCH_CHECK();
-    return QB_OK;
+    return qb_mutate_x(b, K_d, order_d, rate, t, nullptr, nullptr, 0, seed, X_d, dX_d, kcount_d, stream);
 }

@@ -42,6 +42,29 @@ class BatchInfo(ctypes.Structure):
                 ("off_d", ctypes.c_void_p), ("idx_d", ctypes.c_void_p)]
 
 
+class RunCfg(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_int32), ("k", ctypes.c_int32), ("job_m_h", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("init_m", ctypes.c_int32), ("nsw_init", ctypes.c_int32),
+                ("thr_init_h", ctypes.c_void_p), ("nsw", ctypes.c_int32), ("thr_h", ctypes.c_void_p),
+                ("B", ctypes.c_int32), ("R", ctypes.c_int32), ("alpha", ctypes.c_int32),
+                ("tenure", ctypes.c_int32), ("aspiration", ctypes.c_int32), ("W1", ctypes.c_int32),
+                ("W2", ctypes.c_int32), ("W3", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("mlp_W_d", ctypes.c_void_p), ("scales_h", ctypes.c_void_p),
+                ("trace_capacity", ctypes.c_int64), ("max_iters", ctypes.c_int32),
+                ("rankk_variant", ctypes.c_int32), ("anneal_rw", ctypes.c_int32)]
+
+
+STATE_BUFFERS = ["X", "H", "E", "xbest", "ebest", "ebest_trace", "T", "LF", "G", "K", "order", "dX", "tiles",
+                 "F0", "y0", "Y", "e", "F", "KL", "orderL", "trace_F", "trace_L"]
+
+
+class StateBuffers(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in STATE_BUFFERS]
+
+
+RUN_RANDOM_SELECT, RUN_NO_IM, RUN_INIT_JACOBI, RUN_WB_NOT_WORSE, RUN_LEARNED = 1, 2, 4, 8, 16
+
+
 # name -> (restype, argtypes)
 _P, _I32, _I64, _U32, _U64, _F64, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                           ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
@@ -68,7 +91,6 @@ SIGNATURES = {
     "qb_batch_get_info": (_I32, [_P, ctypes.POINTER(BatchInfo)]),
     "qb_batch_set_idx": (_I32, [_P, _P, _P]),
     "qb_batch_copy_idx": (_I32, [_P, _P, _P]),
-    "qb_batch_check": (_I32, [_P, _P]),
     "qb_select": (_I32, [_P, _P, _P]),
     "qb_extract": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "qb_anneal": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _P, _P, _P]),
@@ -97,6 +119,21 @@ SIGNATURES = {
     "qb_graph_launch": (_I32, [_P, _P]),
     "qb_graph_destroy": (None, [_P]),
     "qb_autotune_rankk": (_I32, [_P, _I32, _P, _P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
+    "qb_batch_check": (_I32, [_P, _P]),
+    "qb_batch_count_accepts": (_I32, [_P, _P]),
+    "qb_state_create": (_I32, [ctypes.POINTER(_P), _P, ctypes.POINTER(RunCfg), ctypes.POINTER(StateBuffers), _P]),
+    "qb_state_destroy": (None, [_P]),
+    "qb_state_get_buffers": (_I32, [_P, ctypes.POINTER(StateBuffers)]),
+    "qb_state_batch": (_P, [_P]),
+    "qb_state_init": (_I32, [_P, _P]),
+    "qb_iterate": (_I32, [_P, _I32, _I32, _I32, ctypes.POINTER(_I32), _P]),
+    "qb_state_get_iteration": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_U32), ctypes.POINTER(_I64), _P]),
+    "qb_state_set_iteration": (_I32, [_P, _I32, _P]),
+    "qb_apply": (_I32, [_P, _P]),
+    "qb_state_set_variants": (_I32, [_P, _I32, _I32]),
+    "qb_state_enable_timing": (_I32, [_P, _I32]),
+    "qb_state_stage_ms": (_I32, [_P, _P, _P]),
+    "qb_state_check": (_I32, [_P, _P]),
     "qb_autotune_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _I32,
                                       ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
 }
@@ -192,17 +229,19 @@ class Problem:
 class Batch:
     """A batch of sub-QUBO jobs (sol non-decreasing; sizes 1..1024)."""
 
-    def __init__(self, n: int, z: int, sol, sizes, rank0=None):
+    def __init__(self, n: int, z: int, sol, sizes, rank0=None, handle=None):
         self.n, self.z = n, z
         self.sol = np.ascontiguousarray(sol, np.int32)
         self.sizes = np.ascontiguousarray(sizes, np.int32)
         self.rank0 = None if rank0 is None else np.ascontiguousarray(rank0, np.int32)
-        h = ctypes.c_void_p()
-        _chk(lib().qb_batch_create(ctypes.byref(h), n, z, len(self.sol),
-                                   self.sol.ctypes.data if len(self.sol) else None,
-                                   self.sizes.ctypes.data if len(self.sizes) else None,
-                                   None if self.rank0 is None else self.rank0.ctypes.data),
-             "qb_batch_create")
+        self.owned = handle is None
+        h = ctypes.c_void_p(handle) if handle is not None else ctypes.c_void_p()
+        if self.owned:
+            _chk(lib().qb_batch_create(ctypes.byref(h), n, z, len(self.sol),
+                                       self.sol.ctypes.data if len(self.sol) else None,
+                                       self.sizes.ctypes.data if len(self.sizes) else None,
+                                       None if self.rank0 is None else self.rank0.ctypes.data),
+                 "qb_batch_create")
         self.h = h
         info = BatchInfo()
         _chk(lib().qb_batch_get_info(self.h, ctypes.byref(info)), "qb_batch_get_info")
@@ -214,6 +253,12 @@ class Batch:
         idx_h = np.ascontiguousarray(idx_h, np.int32)
         assert idx_h.shape[0] == self.total
         _chk(lib().qb_batch_set_idx(self.h, idx_h.ctypes.data, _stream(stream)), "qb_batch_set_idx")
+
+    def count_accepts(self, acnt=None):
+        """Accepted moves per replica of later annealings into ``acnt``
+        (int32 [J * R] device tensor); None turns it off."""
+        self._acnt = acnt
+        _chk(lib().qb_batch_count_accepts(self.h, _ptr(acnt)), "qb_batch_count_accepts")
 
     def check(self, stream=None):
         """Raises QBError (QB_E_STATE) if a write-back since the last check met
@@ -227,9 +272,96 @@ class Batch:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib is not None:
+        if getattr(self, "h", None) and _lib is not None and self.owned:
             _lib.qb_batch_destroy(self.h)
+        self.h = None
+
+
+class State:
+    """One run of Alg. 2 inside the library (qb_state): the solution set,
+    its fields, energies and Tabu statistics, the selection, the sub-QUBO
+    batch with its annealer buffers and the best solution.  ``buffers`` maps
+    names of STATE_BUFFERS to device tensors the state borrows (kept alive
+    here); the others are the library's own."""
+
+    def __init__(self, P: Problem, *, z, job_m, seed, init_m, thr_init, thr, B, R, alpha, tenure,
+                 aspiration=True, W=(2, 2, 1), flags=0, mlp_W=None, scales=None, trace_capacity=0,
+                 max_iters=4096, rankk_variant=0, anneal_rw=0, buffers=None, stream=None):
+        job_m = np.ascontiguousarray(np.atleast_2d(job_m), np.int32)
+        assert job_m.shape[0] == z
+        thr = np.ascontiguousarray(thr, np.int32)
+        thr_init = np.ascontiguousarray(thr_init if thr_init is not None else thr, np.int32)
+        sc = np.ascontiguousarray(scales if scales is not None else np.zeros(7), np.float32)
+        cfg = RunCfg(z=z, k=job_m.shape[1], job_m_h=job_m.ctypes.data, seed=int(seed), init_m=int(init_m),
+                     nsw_init=thr_init.shape[0], thr_init_h=thr_init.ctypes.data, nsw=thr.shape[0],
+                     thr_h=thr.ctypes.data, B=B, R=R, alpha=int(alpha), tenure=int(tenure),
+                     aspiration=int(bool(aspiration)), W1=W[0], W2=W[1], W3=W[2], flags=int(flags),
+                     mlp_W_d=_ptr(mlp_W), scales_h=sc.ctypes.data if scales is not None else None,
+                     trace_capacity=int(trace_capacity), max_iters=int(max_iters),
+                     rankk_variant=int(rankk_variant), anneal_rw=int(anneal_rw))
+        self.buffers = dict(buffers or {})
+        bufs = StateBuffers()
+        for name, t in self.buffers.items():
+            setattr(bufs, name, _ptr(t))
+        self.P, self.mlp_W = P, mlp_W
+        self.n, self.z, self.R = P.n, z, R
+        h = ctypes.c_void_p()
+        _chk(lib().qb_state_create(ctypes.byref(h), P.h, ctypes.byref(cfg), ctypes.byref(bufs), _stream(stream)),
+             "qb_state_create")
+        self.h = h
+        k = job_m.shape[1]
+        self.batch = Batch(P.n, z, np.repeat(np.arange(z, dtype=np.int32), k), job_m.reshape(-1),
+                           handle=lib().qb_state_batch(self.h))
+
+    def pointers(self) -> dict:
+        out = StateBuffers()
+        _chk(lib().qb_state_get_buffers(self.h, ctypes.byref(out)), "qb_state_get_buffers")
+        return {name: getattr(out, name) for name in STATE_BUFFERS}
+
+    def init(self, stream=None):
+        _chk(lib().qb_state_init(self.h, _stream(stream)), "qb_state_init")
+
+    def iterate(self, iters=1, graph=True, patience=0, stream=None) -> int:
+        ran = ctypes.c_int32(0)
+        _chk(lib().qb_iterate(self.h, int(iters), int(bool(graph)), int(patience), ctypes.byref(ran),
+                              _stream(stream)), "qb_iterate")
+        return int(ran.value)
+
+    def iteration(self, stream=None):
+        """(t, instance base, trace rows) from the device record (synchronises)."""
+        t, inst, trn = ctypes.c_int32(), ctypes.c_uint32(), ctypes.c_int64()
+        _chk(lib().qb_state_get_iteration(self.h, ctypes.byref(t), ctypes.byref(inst), ctypes.byref(trn),
+                                          _stream(stream)), "qb_state_get_iteration")
+        return int(t.value), int(inst.value), int(trn.value)
+
+    def set_iteration(self, t, stream=None):
+        _chk(lib().qb_state_set_iteration(self.h, int(t), _stream(stream)), "qb_state_set_iteration")
+
+    def apply(self, stream=None):
+        _chk(lib().qb_apply(self.h, _stream(stream)), "qb_apply")
+
+    def set_variants(self, rankk_variant=0, anneal_rw=0):
+        _chk(lib().qb_state_set_variants(self.h, int(rankk_variant), int(anneal_rw)), "qb_state_set_variants")
+
+    def enable_timing(self, on=True):
+        _chk(lib().qb_state_enable_timing(self.h, int(bool(on))), "qb_state_enable_timing")
+
+    def stage_ms(self, stream=None) -> np.ndarray:
+        ms = np.zeros(6, np.float32)
+        _chk(lib().qb_state_stage_ms(self.h, ms.ctypes.data, _stream(stream)), "qb_state_stage_ms")
+        return ms
+
+    def check(self, stream=None):
+        _chk(lib().qb_state_check(self.h, _stream(stream)), "qb_state_check")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            self.batch = None
+            _lib.qb_state_destroy(self.h)
             self.h = None
+
+
+STAGES = ("tabu", "select", "extract", "anneal", "apply", "mutate")
 
 
 # --------------------------------------------------------------------------- calls

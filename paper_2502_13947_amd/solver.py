@@ -1,10 +1,9 @@
 """IC-D^2S outer loop (Alg. 2) driven through the C ABI.
 
-Host-side sequencing only: every step is a kernel of libqb.so.  The state
-(X, H, E, T, LF, K, order, dX, tiles, ...) lives in HBM for the whole run;
-one outer iteration is a fixed sequence of launches on the solver's own
-stream, so any number of iterations can be captured into one HIP graph
-(``capture``) and replayed without host involvement.
+Marshalling only: the library's qb_state runs the sequence of Alg. 2 (every
+step a kernel of libqb.so) and replays one captured outer iteration per
+iteration; the per-iteration scalars live in device memory.  The state's
+main buffers are torch tensors allocated here, so tests can inspect them.
 """
 from __future__ import annotations
 
@@ -12,6 +11,12 @@ import numpy as np
 import torch
 
 from . import qb
+
+
+def qb_tile_ms(m: int) -> int:
+    """Padded tile width / 64 of a job of m variables (power of two >= m/64)."""
+    ms = (m + 63) // 64
+    return 16 if ms > 8 else 8 if ms > 4 else 4 if ms > 2 else 2 if ms > 1 else 1
 
 
 # Cosine temperature schedule of the IM stage, in units of the typical local
@@ -41,6 +46,10 @@ class Solver:
     """The outer loop on one problem: dense (``Q``, int16 [n, n] on the
     device) or sparse (``csr`` = (rowptr, col, val) with ``device``).
 
+    The sequence of Alg. 2 runs inside the library (``qb.State``: qb_state_*,
+    qb_iterate); this class allocates the state's main buffers as torch
+    tensors (so that they can be inspected) and marshals the calls.
+
     Variants of the method (all off by default, i.e. the paper's method):
     ``random_select`` and ``no_im`` are the two ablations of the Discussion
     section (sub-QUBO variables and mutation candidates ranked by random keys,
@@ -55,7 +64,7 @@ class Solver:
                  B: int, R: int, alpha: int, tenure: int, aspiration: bool = True, W=(2, 2, 1),
                  rankk_variant: int = 0, mlp_W=None, trace_capacity: int = 0, csr=None, device=None,
                  anneal_rw: int = 0, random_select: bool = False, no_im: bool = False,
-                 init_jacobi: bool = False, wb_not_worse: bool = False):
+                 init_jacobi: bool = False, wb_not_worse: bool = False, max_iters: int = 4096):
         if mlp_W is not None and (random_select or no_im or wb_not_worse):
             raise ValueError("the learned selector runs with the plain method only")
         dev = Q.device if csr is None else torch.device(device)
@@ -78,69 +87,70 @@ class Solver:
         assert job_m.shape[0] == z
         self.job_m = job_m
         k = job_m.shape[1]
-        self.batch = qb.Batch(n, z, np.repeat(np.arange(z, dtype=np.int32), k), job_m.reshape(-1))
-        b = self.batch
+        total = int(job_m.sum())
+        J = z * k
         # dense tiles (int8/int16) or ELL tiles (uint32 words held as int32)
         self.tile_dtype = torch.int32 if self.sparse else qb.tile_dtype(self.P)
-        tile_len = (lambda bb: bb.total * self.P.ell_width) if self.sparse else (lambda bb: bb.tile_elems)
-        self.X = torch.zeros((z, n), dtype=torch.uint8, device=dev)
-        self.H = torch.zeros((z, n), dtype=torch.int32, device=dev)
-        self.E = torch.zeros(z, dtype=torch.int64, device=dev)
-        self.T = torch.zeros((z, n), dtype=torch.int32, device=dev)
-        self.LF = torch.zeros((z, n), dtype=torch.int32, device=dev)
-        self.K = torch.zeros((z, n), dtype=torch.int64, device=dev)
-        self.order = torch.zeros((z, n), dtype=torch.int32, device=dev)
-        self.dX = torch.zeros((z, n), dtype=torch.int8, device=dev)
-        self.xbest = torch.zeros(n, dtype=torch.uint8, device=dev)
+        if self.sparse:
+            tile_len = total * self.P.ell_width
+        else:
+            ms = [qb_tile_ms(int(m)) for m in job_m.reshape(-1)]
+            tile_len = sum((64 * v) ** 2 for v in ms)
+        zeros = lambda shape, dt: torch.zeros(shape, dtype=dt, device=dev)
+        self.X = zeros((z, n), torch.uint8)
+        self.H = zeros((z, n), torch.int32)
+        self.E = zeros(z, torch.int64)
+        self.T = zeros((z, n), torch.int32)
+        self.LF = zeros((z, n), torch.int32)
+        self.K = zeros((z, n), torch.int64)
+        self.order = zeros((z, n), torch.int32)
+        self.dX = zeros((z, n), torch.int8)
+        self.xbest = zeros(n, torch.uint8)
         self.ebest = torch.full((1,), 2**63 - 1, dtype=torch.int64, device=dev)
-        self.kcount = torch.zeros(z, dtype=torch.int32, device=dev)
-        self.tiles = torch.zeros(max(tile_len(b), 16), dtype=self.tile_dtype, device=dev)
-        self.F0 = torch.zeros(b.total, dtype=torch.int32, device=dev)
-        self.y0 = torch.zeros(b.total, dtype=torch.uint8, device=dev)
-        self.Y = torch.zeros(b.total * R, dtype=torch.uint8, device=dev)
-        self.e = torch.zeros(b.J * R, dtype=torch.int64, device=dev)
+        self.ebest_trace = zeros(max_iters, torch.int64)
+        self.tiles = zeros(max(tile_len, 16), self.tile_dtype)
+        self.F0 = zeros(total, torch.int32)
+        self.y0 = zeros(total, torch.uint8)
+        self.Y = zeros(total * R, torch.uint8)
+        self.e = zeros(J * R, torch.int64)
         self.thr = torch.as_tensor(np.ascontiguousarray(thr, np.int32), device=dev)
         self.init_m = init_m
-        if self.random_select:
-            self.KR = torch.zeros((z, n), dtype=torch.int64, device=dev)
-            self.orderR = torch.zeros((z, n), dtype=torch.int32, device=dev)
-            self.K0 = torch.zeros((z, n), dtype=torch.int64, device=dev)   # equal keys: P = 1/2
-        if self.no_im:
-            self.empty = qb.Batch(n, z, np.zeros(0, np.int32), np.zeros(0, np.int32))
-        if init_m:
-            self.thr_init = torch.as_tensor(np.ascontiguousarray(thr_init, np.int32), device=dev)
-            L0 = n // init_m
-            if self.init_jacobi:
-                # every block of every solution in one batch, jobs solution-major
-                self.ib = qb.Batch(n, z, np.repeat(np.arange(z, dtype=np.int32), L0),
-                                   np.full(z * L0, init_m, np.int32))
-            else:
-                self.ib = qb.Batch(n, z, np.arange(z, dtype=np.int32), np.full(z, init_m, np.int32))
-            ib = self.ib
-            self.itiles = torch.zeros(max(tile_len(ib), 16), dtype=self.tile_dtype, device=dev)
-            self.iF0 = torch.zeros(ib.total, dtype=torch.int32, device=dev)
-            self.iy0 = torch.zeros(ib.total, dtype=torch.uint8, device=dev)
-            self.iY = torch.zeros(ib.total * R, dtype=torch.uint8, device=dev)
-            self.ie = torch.zeros(ib.J * R, dtype=torch.int64, device=dev)
-        # learned selection and traces (features of the Tabu state)
-        self.G = torch.zeros((z, n), dtype=torch.int32, device=dev)
+        self.L0 = n // init_m if init_m else 0
+        self.G = zeros((z, n), torch.int32)
         self.scales = feature_scales(self.P, alpha, z)
         self.learned = mlp_W is not None
         self.tracing = trace_capacity > 0
+        bufs = dict(X=self.X, H=self.H, E=self.E, xbest=self.xbest, ebest=self.ebest, ebest_trace=self.ebest_trace,
+                    T=self.T, LF=self.LF, G=self.G, K=self.K, order=self.order, dX=self.dX, tiles=self.tiles,
+                    F0=self.F0, y0=self.y0, Y=self.Y, e=self.e)
         if self.learned or self.tracing:
-            self.F = torch.zeros((z, n, 8), dtype=torch.int16, device=dev)
+            self.F = zeros((z, n, 8), torch.int16)
+            bufs["F"] = self.F
         if self.learned:
             self.mlp_W = torch.as_tensor(np.ascontiguousarray(mlp_W, np.uint16).view(np.int16), device=dev)
-            self.KL = torch.zeros((z, n), dtype=torch.int64, device=dev)
-            self.orderL = torch.zeros((z, n), dtype=torch.int32, device=dev)
+            self.KL = zeros((z, n), torch.int64)
+            self.orderL = zeros((z, n), torch.int32)
+            bufs.update(KL=self.KL, orderL=self.orderL)
         if self.tracing:
-            self.trF = torch.zeros((trace_capacity, 8), dtype=torch.int16, device=dev)
-            self.trL = torch.zeros(trace_capacity, dtype=torch.uint8, device=dev)
-            self.trN = 0
+            self.trF = zeros((trace_capacity, 8), torch.int16)
+            self.trL = zeros(trace_capacity, torch.uint8)
+            bufs.update(trace_F=self.trF, trace_L=self.trL)
+        flags = ((qb.RUN_RANDOM_SELECT if self.random_select else 0) | (qb.RUN_NO_IM if self.no_im else 0) |
+                 (qb.RUN_INIT_JACOBI if self.init_jacobi else 0) | (qb.RUN_WB_NOT_WORSE if wb_not_worse else 0) |
+                 (qb.RUN_LEARNED if self.learned else 0))
+        self.state = qb.State(self.P, z=z, job_m=job_m, seed=self.seed, init_m=init_m, thr_init=thr_init, thr=thr,
+                              B=B, R=R, alpha=alpha, tenure=tenure, aspiration=aspiration, W=W, flags=flags,
+                              mlp_W=self.mlp_W if self.learned else None,
+                              scales=self.scales if (self.learned or self.tracing) else None,
+                              trace_capacity=trace_capacity, max_iters=max_iters, rankk_variant=rankk_variant,
+                              anneal_rw=anneal_rw, buffers=bufs, stream=self.stream)
+        self.batch = self.state.batch
+        assert self.batch.tile_elems <= self.tiles.numel() or self.sparse
+        # host mirrors of the device iteration record
         self.inst = 0
         self.t = 0
 
-    # ------------------------------------------------------------------ stages
+    # ------------------------------------------------------------------ stages (tests and autotuning)
     def _extract(self, b, tiles, F0, y0, stream):
         if self.sparse:
             qb.extract_ell(self.P, b, self.X, self.H, tiles, F0, y0, stream=stream)
@@ -159,37 +169,46 @@ class Solver:
         qb.energy(self.X, self.H, self.E, stream=stream)
         qb.best(self.X, self.E, self.ebest, self.xbest, stream=stream)
 
+    # ------------------------------------------------------------------ the method
     def init(self):
-        """Start of Alg. 2: random set, field, energy, then the initial pass."""
-        n, z, s = self.n, self.z, self.stream
-        qb.init_solutions(n, z, self.seed, self.X, stream=s)
-        qb.field(self.P, self.X, self.H, stream=s)
-        qb.energy(self.X, self.H, self.E, stream=s)
-        with torch.cuda.stream(s):
-            self.ebest.fill_(2**63 - 1)
-        qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
-        if self.init_m and self.init_jacobi:
-            m0 = self.init_m
-            L0 = n // m0
-            self.ib.set_idx(np.tile(np.arange(L0 * m0, dtype=np.int32), z), stream=s)
-            self._extract(self.ib, self.itiles, self.iF0, self.iy0, s)
-            self._anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.iY, self.ie, s)
-            self.inst += z * L0
-            qb.zero(self.dX, stream=s)
-            qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, flags=self.wb_flags,
-                         stream=s)
-            self._apply(stream=s)
-        elif self.init_m:
-            m0 = self.init_m
-            for l in range(n // m0):
-                self.ib.set_idx(np.tile(np.arange(l * m0, (l + 1) * m0, dtype=np.int32), z), stream=s)
-                self._extract(self.ib, self.itiles, self.iF0, self.iy0, s)
-                self._anneal(self.ib, self.itiles, self.iF0, self.iy0, self.thr_init, self.iY, self.ie, s)
-                self.inst += z
-                qb.zero(self.dX, stream=s)
-                qb.writeback(self.ib, self.R, self.iY, self.ie, self.iy0, self.X, self.dX, flags=self.wb_flags,
-                             stream=s)
-                self._apply(stream=s)
+        """Start of Alg. 2: random set, field, energy, then the initial pass
+        (qb_state_init)."""
+        self.state.init(stream=self.stream)
+        self.inst = self.z * self.L0
+        self.t = 0
+
+    def _advance(self, iters):
+        self.t += iters
+        if not self.no_im:
+            self.inst += iters * self.batch.J
+
+    def iterate(self, stream=None):
+        """One outer iteration of the main loop of Alg. 2, its launches
+        enqueued directly (qb_iterate without a graph)."""
+        s = stream if stream is not None else self.stream
+        self.state.iterate(1, graph=False, stream=s)
+        self._advance(1)
+
+    def capture(self, iters: int) -> "qb.Graph":
+        """One HIP graph holding the next `iters` outer iterations (each reads
+        its iteration number from the state's device record, so a replay
+        continues where the previous one ended; set_iteration rewinds)."""
+        g = qb.Graph(self.stream)
+        with torch.cuda.stream(self.stream), g:
+            self.state.iterate(iters, graph=False, stream=self.stream)
+        self._advance(iters)
+        return g
+
+    def set_iteration(self, t: int):
+        """Rewind the device record to iteration t (as after init + t iterations)."""
+        self.state.set_iteration(t, stream=self.stream)
+        self.t = t
+        self.inst = self.z * self.L0 + (0 if self.no_im else t * self.batch.J)
+
+    @property
+    def trN(self) -> int:
+        """Trace rows written so far (reads the device record)."""
+        return self.state.iteration(stream=self.stream)[2]
 
     def autotune(self, reps=3, density=0.3, seed=0):
         """Pick the fastest rank-k variant for this problem and solution count
@@ -199,6 +218,7 @@ class Solver:
         dX = torch.as_tensor(d.astype(np.int8), device=self.dev)
         self.stream.synchronize()
         self.rankk_variant, ms = qb.autotune_rankk(self.P, dX, self.H, reps=reps, stream=self.stream)
+        self.state.set_variants(self.rankk_variant, self.anneal_rw)
         return self.rankk_variant, ms
 
     def autotune_anneal(self, reps=2):
@@ -215,101 +235,22 @@ class Solver:
         self._extract(b, self.tiles, self.F0, self.y0, s)
         self.anneal_rw, ms = qb.autotune_anneal_ell(b, self.P.ell_width, self.tiles, self.F0, self.y0, self.thr,
                                                     self.R, self.seed ^ 0x5A5A, 0, self.B, reps=reps, stream=s)
+        self.state.set_variants(self.rankk_variant, self.anneal_rw)
         return self.anneal_rw, ms
 
-    def capture(self, iters: int) -> "qb.Graph":
-        """One HIP graph holding the next `iters` outer iterations."""
-        g = qb.Graph(self.stream)
-        with torch.cuda.stream(self.stream), g:
-            for _ in range(iters):
-                self.iterate()
-        return g
-
-    def iterate(self, stream=None, marks=None):
-        """One outer iteration of the main loop of Alg. 2.  ``marks`` (optional) is
-        a callable invoked with a stage name between launches, e.g. to record
-        timing events on the stream."""
-        s = stream if stream is not None else self.stream
-        b = self.batch
-        mark = marks or (lambda name: None)
-        mark("tabu")
-        qb.tabu(self.P, self.X, self.H, self.E, self.alpha, self.tenure, self.aspiration, self.T, self.LF,
-                stream=s)
-        mark("select")
-        qb.best(self.X, self.E, self.ebest, self.xbest, stream=s)
-        qb.keys(self.P, self.X, self.T, self.K, self.W, t_bound=max(self.alpha, 1), stream=s)
-        qb.rank(self.K, self.order, stream=s)
-        if self.learned or self.tracing:
-            qb.features(self.P, self.X, self.H, self.T, self.LF, self.G, self.alpha, self.scales, self.F,
-                        stream=s)
-        if self.learned:
-            qb.mlp_score(self.F, self.mlp_W, self.KL, stream=s)
-            qb.rank(self.KL, self.orderL, stream=s)
-            qb.select(b, self.orderL, stream=s)
-        elif self.random_select:
-            qb.random_keys(self.t, self.seed, self.KR, stream=s)
-            qb.rank(self.KR, self.orderR, stream=s)
-            qb.select(b, self.orderR, stream=s)
-        else:
-            qb.select(b, self.order, stream=s)
-        if not self.no_im:
-            mark("extract")
-            self._extract(b, self.tiles, self.F0, self.y0, s)
-            mark("anneal")
-            self._anneal(b, self.tiles, self.F0, self.y0, self.thr, self.Y, self.e, s)
-            mark("apply")
-            self.inst += b.J
-            if self.learned or self.tracing:
-                qb.gain_update(b, self.R, self.Y, self.e, self.y0, self.G, stream=s)
-            if self.tracing and self.trN + b.total <= self.trF.shape[0]:
-                qb.trace(b, self.R, self.F, self.Y, self.e, self.y0, self.trF[self.trN:], self.trL[self.trN:],
-                         stream=s)
-                self.trN += b.total
-            qb.zero(self.dX, stream=s)
-            qb.writeback(b, self.R, self.Y, self.e, self.y0, self.X, self.dX, flags=self.wb_flags, stream=s)
-            self._apply(stream=s)
-        mark("mutate")
-        qb.zero(self.dX, stream=s)
-        mb = self.empty if self.no_im else b
-        if self.random_select:
-            qb.mutate(mb, self.K0, self.orderR, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
-                      self.kcount, stream=s)
-        else:
-            qb.mutate(mb, self.K, self.order, qb.mutation_rate(self.t), self.t, self.seed, self.X, self.dX,
-                      self.kcount, stream=s)
-        self._apply(stream=s)
-        mark("end")
-        self.t += 1
-
-    def run(self, iters: int, patience: int = 0):
-        """init() and up to ``iters`` outer iterations; E_best after each.
-        With ``patience`` > 0 the loop stops once E_best has not improved for
-        that many consecutive iterations (read back after every iteration)."""
+    def run(self, iters: int, patience: int = 0, graph: bool = True):
+        """init() and up to ``iters`` outer iterations (qb_iterate, by default
+        replaying one captured iteration); E_best after each.  With
+        ``patience`` > 0 the loop stops once E_best has not improved for that
+        many consecutive iterations."""
         self.init()
-        trace = []
-        with torch.cuda.stream(self.stream):
-            if patience <= 0:
-                for _ in range(iters):
-                    self.iterate()
-                    trace.append(self.ebest.clone())
-            else:
-                best, stall = int(self.ebest.item()), 0
-                for _ in range(iters):
-                    self.iterate()
-                    eb = int(self.ebest.item())
-                    trace.append(eb)
-                    stall = 0 if eb < best else stall + 1
-                    best = eb   # E_best never increases
-                    if stall >= patience:
-                        break
+        ran = self.state.iterate(iters, graph=graph, patience=patience, stream=self.stream)
         self.stream.synchronize()
         self.check()
-        return [int(v.item()) if torch.is_tensor(v) else v for v in trace]
+        self._advance(ran)
+        return [int(v) for v in self.ebest_trace[:ran].cpu().numpy()]
 
     def check(self):
         """Raises if a kernel latched an error or a write-back met a replica
         that did not finish (the result would then differ from the method's)."""
-        self.P.check(stream=self.stream)
-        self.batch.check(stream=self.stream)
-        if self.init_m:
-            self.ib.check(stream=self.stream)
+        self.state.check(stream=self.stream)

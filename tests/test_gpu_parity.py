@@ -425,6 +425,42 @@ def test_anneal_wait_limit_bails_out_cleanly():
         assert (eh[q * R:(q + 1) * R] == eo).all(), q
 
 
+@pytest.mark.parametrize("R", [1, 5])
+def test_anneal_accept_counts_match_oracle(R):
+    """qb_batch_count_accepts: every kernel class (multi-wave kernels at
+    R = 1, the one-wave kernel at R = 5) reports the oracle's number of
+    accepted moves per replica, and Y and e are unchanged by counting."""
+    n, z, sizes, nsw = 3000, 2, [1024, 512, 256, 100, 40], 7
+    say("accept counts", R)
+    Q = inputs.dense_qubo(n, 0.5, 151)
+    X = inputs.random_solutions(z, n, 152)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, sizes, 153)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    tiles = torch.zeros(b.tile_elems, dtype=qb().tile_dtype(P), device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
+    thr = oracle.thresholds(Q, nsw)
+    thr_d = torch.as_tensor(thr, device=DEV)
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    acnt = torch.full((b.J * R,), -1, dtype=torch.int32, device=DEV)
+    b.count_accepts(acnt)
+    qb().anneal(b, tiles, F0, y0, thr_d, R, 77, 9, Y, e, 10)
+    b.count_accepts(None)
+    Yh, eh, ah = Y.cpu().numpy(), e.cpu().numpy(), acnt.cpu().numpy()
+    for q in range(b.J):
+        mm = int(b.off[q + 1] - b.off[q])
+        Tq, c, F, yy = oracle.extract(Q, X[sol[q]], H[sol[q]], idx[b.off[q]:b.off[q + 1]])
+        Yo, eo, no = oracle.anneal(Tq, F, yy, thr, R, 77, 9 + q, 10, count=True)
+        assert (Yh[b.off[q] * R:(b.off[q] + mm) * R].reshape(R, mm) == Yo).all(), q
+        assert (eh[q * R:(q + 1) * R] == eo).all(), q
+        assert (ah[q * R:(q + 1) * R] == no).all(), (q, mm, ah[q * R:(q + 1) * R], no)
+
+
 def test_threshold_table_matches_oracle():
     for nsw, B, tmax, tmin in [(1, 10, 100.0, 1.0), (200, 10, 2047.3, 8.2), (37, 4, 5.0, 0.0),
                                (3, 16, 1e9, 1e8)]:
@@ -578,12 +614,75 @@ def test_graph_replay_matches_eager_and_oracle():
         with torch.cuda.stream(G.stream):
             for t, s0 in zip((G.X, G.H, G.E, G.ebest, G.xbest), snap):
                 t.copy_(s0)
+        G.set_iteration(0)
         G.stream.synchronize()
         graph.launch()
         G.stream.synchronize()
         assert (G.X.cpu().numpy() == ref["X"]).all(), rep
         assert (G.H.cpu().numpy() == ref["H"]).all(), rep
         assert int(G.ebest.item()) == ref["ebest"], rep
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_state_iterate_matches_oracle_and_advances_its_record(graph):
+    """qb_state_init + qb_iterate (eager launches, or one captured iteration
+    replayed): the E_best trace and the final state are the oracle's, and
+    the device record holds t = iters and the instance base after them."""
+    from paper_2502_13947_amd.solver import Solver
+    n, z, iters, B, R = 640, 3, 5, 10, 2
+    Q = inputs.dense_qubo(n, 0.15, 131)
+    thr = oracle.thresholds(Q, 24, B)
+    job_m = np.tile([100, 64], (z, 1)).astype(np.int32)
+    kw = dict(z=z, seed=17, job_m=job_m, init_m=128, thr_init=thr, thr=thr, B=B, R=R, alpha=5 * n,
+              tenure=max(1, n // 150))
+    S = Solver(dq(Q), **kw)
+    trace = S.run(iters, graph=graph)
+    ref = oracle.run(Q, iters=iters, **kw)
+    assert trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all() and (S.H.cpu().numpy() == ref["H"]).all()
+    assert (S.E.cpu().numpy() == ref["E"]).all() and int(S.ebest.item()) == ref["ebest"]
+    t, inst, _ = S.state.iteration()
+    assert t == iters and inst == z * (n // 128) + iters * z * 2 == S.inst
+    # rewind and replay the last two iterations from a saved state
+    S.set_iteration(iters - 2)
+    assert S.state.iteration()[:2] == (iters - 2, z * (n // 128) + (iters - 2) * z * 2)
+
+
+def test_apply_after_stage_calls_matches_the_oracle():
+    """The stages of one iteration called one by one on the state's buffers,
+    then qb_apply (write-back of the best finished replica, rank-k update,
+    energy, best)."""
+    from paper_2502_13947_amd.solver import Solver
+    n, z, B, R = 500, 4, 10, 3
+    Q = inputs.dense_qubo(n, 0.2, 141)
+    thr = oracle.thresholds(Q, 12, B)
+    job_m = np.tile([64, 128], (z, 1)).astype(np.int32)
+    S = Solver(dq(Q), z=z, seed=23, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=B, R=R, alpha=0, tenure=1)
+    S.init()
+    s = S.stream
+    qb().keys(S.P, S.X, S.T, S.K, S.W, t_bound=1, stream=s)
+    qb().rank(S.K, S.order, stream=s)
+    qb().select(S.batch, S.order, stream=s)
+    S._extract(S.batch, S.tiles, S.F0, S.y0, s)
+    S._anneal(S.batch, S.tiles, S.F0, S.y0, S.thr, S.Y, S.e, s)
+    s.synchronize()
+    X0, H0 = S.X.cpu().numpy(), S.H.cpu().numpy()
+    idx = S.batch.idx(DEV).cpu().numpy()
+    S.state.apply(stream=s)
+    s.synchronize()
+    Xo = X0.copy()
+    b = S.batch
+    for q in range(b.J):
+        p = int(b.sol[q])
+        Sq = idx[b.off[q]:b.off[q + 1]]
+        Tq, c, F, yy = oracle.extract(Q, X0[p], H0[p], Sq)
+        Yo, eo = oracle.anneal(Tq, F, yy, thr, R, S.seed, q, B)
+        Xo[p, Sq] = Yo[int(np.argmin(eo))]
+    Ho = oracle.field(Q, Xo)
+    Eo = oracle.energy(Xo, Ho)
+    assert (S.X.cpu().numpy() == Xo).all() and (S.H.cpu().numpy() == Ho).all()
+    assert (S.E.cpu().numpy() == Eo).all()
+    assert int(S.ebest.item()) == min(int(Eo.min()), int(oracle.energy(X0, H0).min()))
 
 
 def test_autotuner_picks_a_variant_and_keeps_parity():

@@ -306,6 +306,27 @@ def test_anneal_ell_bit_exact(case, z, sizes, nsw, R, rw):
         assert (eh[q * R:(q + 1) * R] == eo).all(), (q, mm)
 
 
+def test_anneal_ell_accept_counts_match_oracle():
+    n, csr, Q = torus(40, 50, 161)
+    z, sizes, nsw, R = 2, [1024, 300, 65], 6, 4
+    P = csr_problem(csr)
+    X = inputs.random_solutions(z, n, 162)
+    H = field_csr(csr, X)
+    b, sol, idx, tiles, c, F0, y0 = _extract_ell(P, n, z, sizes, X, H, 163)
+    thr = oracle.thresholds(Q, nsw)
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    acnt = torch.full((b.J * R,), -1, dtype=torch.int32, device=DEV)
+    b.count_accepts(acnt)
+    qb().anneal_ell(b, P.ell_width, tiles, F0, y0, dev(thr), R, 5, 0, Y, e, 10, rw=2)
+    b.count_accepts(None)
+    ah = acnt.cpu().numpy()
+    for q in range(b.J):
+        Tq, _, F, yy = oracle.extract(Q, X[sol[q]], H[sol[q]], idx[b.off[q]:b.off[q + 1]])
+        _, _, no = oracle.anneal(Tq, F, yy, thr, R, 5, q, 10, count=True)
+        assert (ah[q * R:(q + 1) * R] == no).all(), q
+
+
 def test_anneal_ell_equals_dense_annealer():
     """The same jobs annealed from the dense tiles of the dense form give the
     same states and energies."""
@@ -395,6 +416,7 @@ def test_sparse_autotune_and_graph_replay():
         with torch.cuda.stream(G.stream):
             for t, s0 in zip((G.X, G.H, G.E, G.ebest, G.xbest), snap):
                 t.copy_(s0)
+        G.set_iteration(0)
         G.stream.synchronize()
         graph.launch()
         G.stream.synchronize()

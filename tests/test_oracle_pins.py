@@ -411,6 +411,32 @@ def test_anneal_all_accept_table_flips_every_variable_each_sweep():
             assert e[r] == oracle.sub_energy(Tq, c, expect) - oracle.sub_energy(Tq, c, y0)
 
 
+def test_anneal_accept_counts_closed_forms():
+    # all-accept table: every position accepted every sweep; none-accept: 0;
+    # otherwise the count equals the number of positions whose spin changed
+    # between consecutive sweeps' states -- checked through the parity of
+    # the flips: each accepted move flips one spin, so the count has the
+    # parity of the Hamming distance between start and end
+    rng = np.random.default_rng(3)
+    m, nsw, B, R = 37, 9, 6, 3
+    A = rng.integers(-40, 41, size=(m, m))
+    Tq = np.triu(A, 1) + np.triu(A, 1).T
+    y0 = rng.integers(0, 2, m).astype(np.uint8)
+    F0 = (rng.integers(-50, 51, m) + 2 * Tq @ y0).astype(np.int32)
+    big = np.full((nsw, 1 << B), 2**31 - 1, np.int32)
+    _, _, na = oracle.anneal(Tq, F0, y0, big, R, 1, 2, B, count=True)
+    assert (na == m * nsw).all()
+    low = np.full((nsw, 1 << B), -2**31, np.int32)
+    _, _, na = oracle.anneal(Tq, F0, y0, low, R, 1, 2, B, count=True)
+    assert (na == 0).all()
+    thr = oracle.threshold_table(nsw, B, 60.0, 1.0)
+    Y, e, na = oracle.anneal(Tq, F0, y0, thr, R, 1, 2, B, count=True)
+    Y2, e2 = oracle.anneal(Tq, F0, y0, thr, R, 1, 2, B)
+    assert (Y == Y2).all() and (e == e2).all()
+    for r in range(R):
+        assert na[r] % 2 == int((Y[r] != y0).sum()) % 2 and 0 < na[r] < m * nsw
+
+
 def test_anneal_none_accept_table_keeps_the_start():
     Tq, c, F0, y0 = _job(seed=1)
     thr = np.full((3, 16), -(2**31), np.int32)
