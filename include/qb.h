@@ -386,6 +386,18 @@ qb_status qb_gain_update(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_
 size_t qb_mlp_train_workspace(int32_t B);
 qb_status qb_mlp_grad(int32_t B, const uint16_t *feat_d, const uint8_t *label_d, const uint16_t *W_d,
                       float *grad_d, float *loss_d, void *work_d, void *stream);
+/* qb_mlp_grad for callers that cannot allocate (code under HIP graph
+ * capture, tight training loops, harnesses that forbid allocation): the
+ * same kernels and the same result, bit for bit, with the per-workgroup
+ * partial sums in a static device array of the library (one per GPU, about
+ * 2.4 MB, held until the process ends) instead of a workspace.  B up to
+ * QB_MLP_GRAD_NOALLOC_MAX_B (QB_E_CAPACITY beyond).  Calls that overlap on
+ * one GPU share that array and race; calls on one stream do not.  Allocates
+ * nothing (the array's device address is looked up on the first call on
+ * each device). */
+#define QB_MLP_GRAD_NOALLOC_MAX_B 8192
+qb_status qb_mlp_grad_noalloc(int32_t B, const uint16_t *feat_d, const uint8_t *label_d, const uint16_t *W_d,
+                              float *grad_d, float *loss_d, void *stream);
 /* Adam on FP32 master weights (count 4801), then W_d = BF16(master). */
 qb_status qb_mlp_adam(const float *grad_d, float *master_d, float *m_d, float *v_d, int32_t step, float lr,
                       float beta1, float beta2, float eps, uint16_t *W_d, void *stream);

@@ -10,6 +10,8 @@
 // kernels serve the learned path unchanged.
 #include <math.h>
 
+#include <mutex>
+
 #include "qb_internal.h"
 
 namespace {
@@ -362,6 +364,59 @@ extern "C" qb_status qb_mlp_grad(int32_t B, const uint16_t *feat_d, const uint8_
     hipStream_t s = qb_stream(stream);
     const int nblk = (B + 63) / 64;
     float *partial = (float *)work_d;
+    float *lossp = partial + (size_t)nblk * NPARAM;
+    k_mlp_grad<<<nblk, 64, 0, s>>>(B, feat_d, label_d, W_d, partial, lossp);
+    k_mlp_reduce<<<(NPARAM + 255) / 256, 256, 0, s>>>(nblk, partial, lossp, B, grad_d, loss_d);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
+// ------------------------------------------------------------------ no allocation
+// qb_mlp_grad for callers that cannot allocate (graph capture, tight training
+// loops): the per-workgroup partial sums live in this file-scope device array
+// instead of a caller workspace.  In host code `scratch` names a host-side
+// stand-in, never the device memory: its device address is taken once per
+// device with hipGetSymbolAddress and only that address is passed to the
+// kernels.  k_mlp_grad writes every entry of the rows it uses, so nothing is
+// cleared between calls; calls that overlap on one GPU share the array and
+// race.
+constexpr int NOALLOC_MAX_B = QB_MLP_GRAD_NOALLOC_MAX_B;
+constexpr size_t NOALLOC_FLOATS = (size_t)((NOALLOC_MAX_B + 63) / 64) * (NPARAM + 1);
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {nullptr};
+
+// the device address of `scratch` on the current device (set up on the first
+// call there)
+static qb_status scratch_address(float **out)
+{
+    int dev = -1;
+    QB_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return QB_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        QB_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return QB_E_HIP;
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QB_OK;
+}
+
+extern "C" qb_status qb_mlp_grad_noalloc(int32_t B, const uint16_t *feat_d, const uint8_t *label_d,
+                                        const uint16_t *W_d, float *grad_d, float *loss_d, void *stream)
+{
+    if (B < 1 || !feat_d || !label_d || !W_d || !grad_d) return QB_E_ARG;
+    if ((uintptr_t)feat_d & 15) return QB_E_ARG;
+    if (B > NOALLOC_MAX_B) return QB_E_CAPACITY;
+    float *partial = nullptr;
+    const qb_status rc = scratch_address(&partial);
+    if (rc != QB_OK) return rc;
+    hipStream_t s = qb_stream(stream);
+    const int nblk = (B + 63) / 64;
     float *lossp = partial + (size_t)nblk * NPARAM;
     k_mlp_grad<<<nblk, 64, 0, s>>>(B, feat_d, label_d, W_d, partial, lossp);
     k_mlp_reduce<<<(NPARAM + 255) / 256, 256, 0, s>>>(nblk, partial, lossp, B, grad_d, loss_d);

@@ -112,6 +112,7 @@ SIGNATURES = {
     "qb_gain_update": (_I32, [_P, _I32, _P, _P, _P, _P, _P]),
     "qb_mlp_train_workspace": (_SZ, [_I32]),
     "qb_mlp_grad": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
+    "qb_mlp_grad_noalloc": (_I32, [_I32, _P, _P, _P, _P, _P, _P]),
     "qb_mlp_adam": (_I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, _P, _P]),
     "qb_graph_begin": (_I32, [_P]),
@@ -521,6 +522,16 @@ def mlp_grad(feat, label, W, grad, loss, work, stream=None):
     B = label.numel()
     _chk(lib().qb_mlp_grad(B, _ptr(feat), _ptr(label), _ptr(W), _ptr(grad), _ptr(loss), _ptr(work),
                            _stream(stream)), "qb_mlp_grad")
+
+
+MLP_GRAD_NOALLOC_MAX_B = 8192
+
+
+def mlp_grad_noalloc(feat, label, W, grad, loss, stream=None):
+    """qb_mlp_grad without a workspace (the library's static scratch)."""
+    B = label.numel()
+    _chk(lib().qb_mlp_grad_noalloc(B, _ptr(feat), _ptr(label), _ptr(W), _ptr(grad), _ptr(loss), _stream(stream)),
+         "qb_mlp_grad_noalloc")
 
 
 def mlp_adam(grad, master, m, v, step, lr, W, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
