@@ -176,8 +176,21 @@ typedef struct {
     const int32_t *sol_d;     /* [J] */
     const int32_t *off_d;     /* [J+1] */
     int32_t *idx_d;           /* [total] */
+    int64_t dblk_words;       /* words after the ELL rows in a qb_extract_ell tile buffer */
 } qb_batch_info;
 
+/* Result-invariant schedule of qb_anneal on a batch (qb_autotune_anneal
+ * picks one; every plan gives the same Y and e):
+ *   sleep_after: polls of a list word not yet written before a waiting wave
+ *     sleeps between polls (0: at once);
+ *   depth: list words a wave that reads rows from global memory keeps in
+ *     flight (8, 16 or 32). */
+typedef struct {
+    int32_t sleep_after;
+    int32_t depth;
+} qb_anneal_plan;
+qb_status qb_batch_set_anneal_plan(qb_batch b, const qb_anneal_plan *plan_h);
+qb_status qb_batch_get_anneal_plan(qb_batch b, qb_anneal_plan *plan_h);
 qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_t J, const int32_t *sol_h,
                           const int32_t *size_h, const int32_t *rank0_h);
 void qb_batch_destroy(qb_batch b);
@@ -256,7 +269,11 @@ qb_status qb_set_anneal_wait_limit(int32_t polls);
  * c, F0 and y0 as qb_extract; the tile is an ELL of width W = ell_width:
  * uint32 word [off[q]*W + a*W + t] = (T[a][b] << 16) | b for the t-th
  * non-zero T[a][b] (b != a, ascending b) of row a, zero words after the last
- * one.  The buffer holds off[J]*W words, 16-byte aligned. */
+ * one.  For a problem with |Q| <= 127 the jobs' diagonal 64 x 64 blocks
+ * follow the rows as int8 (dblk_words = 1024 words per block, qb_tile_ms(m)
+ * blocks per job in job order; byte [block][L][k] = T[64 b + k][64 b + L],
+ * zero outside the job), which qb_anneal_ell keeps in registers.  The
+ * buffer holds off[J]*W + dblk_words words, 16-byte aligned. */
 qb_status qb_extract_ell(qb_problem P, qb_batch b, const uint8_t *X_d, const int32_t *H_d, uint32_t *tile_d,
                          int32_t *c_d, int32_t *F0_d, uint8_t *y0_d, void *stream);
 /* qb_anneal on ELL tiles (qb_extract_ell, width W): the same sweep, the same

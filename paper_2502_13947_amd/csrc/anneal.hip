@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ thr, int R, uint32_t k0,
                                                     uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
                                                     int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
-                                                    int wait_limit)
+                                                    int wait_limit, int sleep_after)
 {
     using C = AnnealMw<MS, TT, MODE>;
     constexpr int NW = C::NW, NB = C::NB, DW = C::DW, MP = 64 * MS;
@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
                         ok = false;
                         break;
                     }
-                    if (spins > 16) __builtin_amdgcn_s_sleep(1);
+                    if (spins > sleep_after) __builtin_amdgcn_s_sleep(1);
                     v = (uint32_t)__builtin_amdgcn_readfirstlane(
                         (int)__hip_atomic_load(&lst[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                 }
@@ -596,11 +596,11 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
     if (lim == MW_WAIT_DEFAULT)
         k_anneal_mw<MS, TT, MODE, false><<<nblocks, 64 * C::NW * R, 0, s>>>(
             jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
-            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim);
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after);
     else
         k_anneal_mw<MS, TT, MODE, true><<<nblocks, 64 * C::NW * R, 0, s>>>(
             jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
-            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim);
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after);
     return true;
 }
 
@@ -614,7 +614,7 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
 // their NB column blocks (row k, bytes 16 lane + 4 w), up to P loads in
 // flight per batch of list words.  Lists, ring and bounded waits as in the
 // in-LDS multi-wave kernel.
-template <int MS, typename TT>
+template <int MS, typename TT, int PD>
 struct AnnealMwG {
     static constexpr int NW = 4;
     static constexpr int NB = MS / NW;
@@ -623,7 +623,7 @@ struct AnnealMwG {
     static constexpr int OSTR = 64 * (int)sizeof(TT) + 4;      // bytes per row of a stored block
     static constexpr int OBLK = 64 * OSTR;
     static constexpr int NOFF = NB * (NB - 1) / 2;             // own off-diagonal blocks
-    static constexpr int P = 8;                                // list words per consumer batch
+    static constexpr int P = PD;                               // list words per consumer batch
     static constexpr int SLOTS = 65 + P - 1;
     static_assert(MS * sizeof(TT) == 16 && NB * sizeof(TT) == 4, "16 bytes per lane, one dword per consumer row");
 };
@@ -633,7 +633,7 @@ __device__ __forceinline__ int own_pair(int a, int b, int nb)   // a < b < nb
     return a * nb - (a * (a + 1)) / 2 + (b - a - 1);
 }
 
-template <int MS, typename TT, bool LIM>
+template <int MS, typename TT, bool LIM, int PD>
 __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__ jobs,
                                                      const int32_t *__restrict__ off,
                                                      const int64_t *__restrict__ tile_off,
@@ -642,9 +642,9 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                                                      const int32_t *__restrict__ thr, int R, uint32_t k0,
                                                      uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
                                                      int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
-                                                     int wait_limit)
+                                                     int wait_limit, int sleep_after)
 {
-    using C = AnnealMwG<MS, TT>;
+    using C = AnnealMwG<MS, TT, PD>;
     constexpr int NW = C::NW, NB = C::NB, DW = C::DW, PER = C::PER, P = C::P, SLOTS = C::SLOTS;
     constexpr int MP = 64 * MS;
     constexpr int ROWB = MP * (int)sizeof(TT);                 // bytes per tile row
@@ -760,7 +760,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                         ok = false;
                         break;
                     }
-                    if (spins > 16) __builtin_amdgcn_s_sleep(1);
+                    if (spins > sleep_after) __builtin_amdgcn_s_sleep(1);
                     continue;
                 }
                 spins = 0;
@@ -855,6 +855,24 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
     }
 }
 
+template <int MS, typename TT, int PD>
+void launch_mw_g_depth(int nblocks, int lim, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
+                       const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, int R, uint64_t seed,
+                       uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
+{
+    constexpr int NT = 64 * AnnealMwG<MS, TT, PD>::NW;
+    if (lim == MW_WAIT_DEFAULT)
+        k_anneal_mw_g<MS, TT, false, PD><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
+                                                                y0, nsw, B, thr, R, (uint32_t)seed,
+                                                                (uint32_t)(seed >> 32), inst_base, it, Y, e,
+                                                                b->acnt_d, lim, b->plan.sleep_after);
+    else
+        k_anneal_mw_g<MS, TT, true, PD><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
+                                                               y0, nsw, B, thr, R, (uint32_t)seed,
+                                                               (uint32_t)(seed >> 32), inst_base, it, Y, e,
+                                                               b->acnt_d, lim, b->plan.sleep_after);
+}
+
 template <int MS, typename TT>
 bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
                         const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
@@ -862,17 +880,14 @@ bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, 
 {
     if (R != 1 || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
     const int32_t lim = g_wait_limit.load(std::memory_order_relaxed);
-    constexpr int NT = 64 * AnnealMwG<MS, TT>::NW;
-    if (lim == MW_WAIT_DEFAULT)
-        k_anneal_mw_g<MS, TT, false><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
-                                                            y0, nsw, B, thr, R, (uint32_t)seed,
-                                                            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d,
-                                                            lim);
-    else
-        k_anneal_mw_g<MS, TT, true><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
-                                                           y0, nsw, B, thr, R, (uint32_t)seed,
-                                                           (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d,
-                                                           lim);
+    switch (b->plan.depth) {
+    case 16: launch_mw_g_depth<MS, TT, 16>(nblocks, lim, s, jobs, b, tiles, F0, y0, nsw, B, thr, R, seed, inst_base,
+                                           it, Y, e); break;
+    case 32: launch_mw_g_depth<MS, TT, 32>(nblocks, lim, s, jobs, b, tiles, F0, y0, nsw, B, thr, R, seed, inst_base,
+                                           it, Y, e); break;
+    default: launch_mw_g_depth<MS, TT, 8>(nblocks, lim, s, jobs, b, tiles, F0, y0, nsw, B, thr, R, seed, inst_base,
+                                          it, Y, e); break;
+    }
     return true;
 }
 

@@ -20,6 +20,8 @@
 
 namespace {
 
+constexpr int DBLK_BYTES = 64 * 64;   // one diagonal block, int8
+
 // ------------------------------------------------------------------ extract
 // One workgroup per job, one thread per row: the entries of Q's row S_a whose
 // column is in S (binary search in the ascending index set) become the row's
@@ -33,13 +35,20 @@ __global__ void __launch_bounds__(256) k_extract_ell(const uint32_t *__restrict_
                                                      const uint8_t *__restrict__ X,
                                                      const int32_t *__restrict__ H, uint32_t *__restrict__ tiles,
                                                      int32_t *__restrict__ c, int32_t *__restrict__ F0,
-                                                     uint8_t *__restrict__ y0)
+                                                     uint8_t *__restrict__ y0, uint8_t *__restrict__ dblk,
+                                                     const int32_t *__restrict__ dboff)
 {
     __shared__ int32_t S[1024];
     __shared__ uint8_t ys[1024];
     const int q = blockIdx.x, tid = threadIdx.x;
     const int base = off[q], m = off[q + 1] - base, p = sol[q];
     const int64_t xo = (int64_t)p * n;
+    // the job's diagonal 64 x 64 blocks (int8), zeroed before the rows fill them
+    uint8_t *dq = dblk ? dblk + (size_t)dboff[q] * DBLK_BYTES : nullptr;
+    if (dq) {
+        const int n16 = qb_tile_ms(m) * DBLK_BYTES / 16;
+        for (int t = tid; t < n16; t += 256) reinterpret_cast<uint4 *>(dq)[t] = make_uint4(0, 0, 0, 0);
+    }
     for (int a = tid; a < m; a += 256) {
         const int j = idx[base + a];
         S[a] = j;
@@ -78,6 +87,9 @@ __global__ void __launch_bounds__(256) k_extract_ell(const uint32_t *__restrict_
                 const int32_t v = qb_ell_val(w);
                 out[k++] = qb_ell_word(v, pos);
                 rowsum += v * (int32_t)ys[pos];
+                // column a & 63 of the block holds T[b][a] for the rows b of a's block
+                if (dq && (pos >> 6) == (a >> 6))
+                    dq[(size_t)(a >> 6) * DBLK_BYTES + (a & 63) * 64 + (pos & 63)] = (uint8_t)(int8_t)v;
             }
         }
         for (; k < W; ++k) out[k] = 0u;
@@ -206,6 +218,175 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
     if (acnt && lane == 0) acnt[(size_t)q * R + r] = nacc;
 }
 
+// The same sweep with the block's own couplings in registers (int8 tiles,
+// W <= 64).  Lane L holds column L of the current diagonal block, T[64 s +
+// k][64 s + L] for k < 64 (written by the extraction), so an accept moves
+// the block's move values dE = sigma F by a register read -- the dense
+// owner's accept chain, with no LDS access on it.  The F of every position
+// still lives in LDS and still receives every entry of each accepted row by
+// an LDS atomic add, so it is exact at the start of each block; those adds
+// are issued one accept late (the row read overlaps the next accept's
+// chain) and are never read back within the block.  A lane that flips has
+// its sigma negated, but its dE is not read again in the block and the
+// negation commutes with the later updates (the dense kernel's argument).
+// The next block's column is loaded two blocks ahead.
+__device__ __forceinline__ int32_t dcol_at(const uint32_t (&d)[16], int k)
+{
+    return __builtin_amdgcn_sbfe((int)d[k >> 2], (uint32_t)(k & 3) * 8u, 8u);
+}
+
+__device__ __forceinline__ void load_dcol(uint32_t (&d)[16], const uint8_t *__restrict__ src)
+{
+    const uint4 *v = reinterpret_cast<const uint4 *>(src);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 t = v[i];
+        d[4 * i + 0] = t.x;
+        d[4 * i + 1] = t.y;
+        d[4 * i + 2] = t.z;
+        d[4 * i + 3] = t.w;
+    }
+}
+
+template <int MS>
+__global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restrict__ jobs, int rgroups,
+                                                        const int32_t *__restrict__ off, int W,
+                                                        const uint32_t *__restrict__ tiles,
+                                                        const uint8_t *__restrict__ dblk,
+                                                        const int32_t *__restrict__ dboff,
+                                                        const int32_t *__restrict__ F0,
+                                                        const uint8_t *__restrict__ y0, int nsw, int B,
+                                                        const int32_t *__restrict__ thr, int R, int rw, uint32_t k0,
+                                                        uint32_t k1, uint32_t inst_base,
+                                                        const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                        int64_t *__restrict__ eout, int32_t *__restrict__ acnt)
+{
+    constexpr int MP = 64 * MS;
+    extern __shared__ __align__(16) uint32_t dl[];
+    const int q = jobs[blockIdx.x / rgroups];
+    const int rg = blockIdx.x % rgroups;
+    const int base = off[q], m = off[q + 1] - base;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r = rg * rw + wid;
+
+    uint32_t *tl = dl;                                   // [m][W]
+    int32_t *F = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + wid * MP;
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(tiles + (int64_t)base * W);
+        uint4 *dst = reinterpret_cast<uint4 *>(tl);
+        const int n16 = m * W / 4;
+        for (int t = tid; t < n16; t += blockDim.x) dst[t] = src[t];
+    }
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        F[pos] = pos < m ? F0[base + pos] : 0;
+    }
+    __syncthreads();
+    if (r >= R) return;   // no barrier follows
+
+    const uint8_t *dq = dblk + (size_t)dboff[q] * DBLK_BYTES + lane * 64;
+    uint32_t ybits = 0;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        if (pos < m && y0[base + pos]) ybits |= 1u << s;
+    }
+    int64_t e = 0;
+    int32_t nacc = 0;
+    const uint32_t tag = (1u << 28) | (inst_base + (it ? it->inst : 0u) + (uint32_t)q);
+    constexpr int G = (MS + 3) / 4;
+    const int sh = 32 - B;
+    const int nblk = (m + 63) >> 6;                      // blocks with positions
+    // columns of the next two blocks (in sweep order, wrapping to the next sweep)
+    uint32_t c1[16], c2[16];
+    load_dcol(c1, dq);
+    load_dcol(c2, dq + (size_t)(nblk > 1 ? 1 : 0) * DBLK_BYTES);
+    auto thresholds = [&](int sw, int32_t (&tv)[MS]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint4 o = qb_philox(make_uint4(((uint32_t)g << 6) | (uint32_t)lane, (uint32_t)sw, (uint32_t)r, tag),
+                                      k0, k1);
+            const int32_t *ts = thr + ((size_t)sw << B);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (4 * g + w < MS) tv[4 * g + w] = ts[qb_word(o, w) >> sh];
+        }
+    };
+    int32_t tvn[MS];
+    thresholds(0, tvn);
+    int bcount = 0;                                      // blocks visited, for the column stream
+
+    for (int sw = 0; sw < nsw; ++sw) {
+        int32_t tv[MS];
+#pragma unroll
+        for (int s = 0; s < MS; ++s) tv[s] = tvn[s];
+        if (sw + 1 < nsw) thresholds(sw + 1, tvn);
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+            if (s < nblk) {
+            const int na = min(m - 64 * s, 64);
+            uint64_t pend = na == 64 ? ~0ull : ((1ull << na) - 1ull);
+            uint32_t dc[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                dc[i] = c1[i];
+                c1[i] = c2[i];
+            }
+            ++bcount;
+            {
+                int nb = bcount + 1;                     // the block two ahead of the one just started
+                nb %= nblk;
+                load_dcol(c2, dq + (size_t)nb * DBLK_BYTES);
+            }
+            // F of the block, exact: every earlier atomic add of this wave precedes this read
+            const int32_t fs = F[64 * s + lane];
+            const int32_t M0 = ((ybits >> s) & 1u) ? -1 : 0;
+            const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;   // 2 sigma
+            int32_t dE = (fs ^ M0) - M0;
+            uint64_t ym = __ballot(M0 != 0);
+            uint64_t acc = __ballot(dE <= tv[s]) & pend;
+            // the previous accept's row word and factor (its adds are issued one accept late)
+            uint32_t pw = 0u;
+            int32_t pd2 = 0;
+            while (acc) {
+                const int k = __builtin_ctzll(acc);
+                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
+                const int32_t mk = (int32_t)((ym >> k) & 1ull);
+                ym ^= 1ull << k;
+                e += dEk;
+                ++nacc;
+                const int32_t d2 = mk ? -2 : 2;
+                dE += (mk ? ns2 : s2) * dcol_at(dc, k);
+                pend &= (~0ull << k) << 1;
+                const uint64_t accn = __ballot(dE <= tv[s]) & pend;
+                // the chain of this accept is done: only now wait for the
+                // previous accept's row word and add it, then read this one's
+                __builtin_amdgcn_sched_barrier(0);
+                if (lane < W && pw != 0u) atomicAdd(&F[qb_ell_col(pw)], pd2 * qb_ell_val(pw));
+                pw = lane < W ? tl[(size_t)(64 * s + k) * W + lane] : 0u;
+                pd2 = d2;
+                acc = accn;
+            }
+            if (lane < W && pw != 0u) atomicAdd(&F[qb_ell_col(pw)], pd2 * qb_ell_val(pw));
+            if ((ym >> lane) & 1ull)
+                ybits |= 1u << s;
+            else
+                ybits &= ~(1u << s);
+            }
+        }
+    }
+
+    uint8_t *Yr = Y + (size_t)base * R + (size_t)r * m;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        if (pos < m) Yr[pos] = (uint8_t)((ybits >> s) & 1u);
+    }
+    if (lane == 0) eout[(size_t)q * R + r] = e;
+    if (acnt && lane == 0) acnt[(size_t)q * R + r] = nacc;
+}
+
 constexpr size_t LDS_MAX = 160 * 1024;
 
 inline size_t ell_lds_bytes(int ms, int W, int rw) { return sizeof(uint32_t) * (size_t)64 * ms * (W + rw); }
@@ -216,6 +397,19 @@ qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *job
                      uint64_t seed, uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
     const size_t lds = ell_lds_bytes(MS, W, rw);
+    if (b->dblk_valid && W <= 64) {
+        // the extraction wrote the int8 diagonal blocks after the ELL rows
+        QB_TRY_HIP(hipFuncSetAttribute((const void *)k_anneal_ell_dc<MS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)LDS_MAX));
+        const int rgroups = (R + rw - 1) / rw;
+        const uint8_t *dblk = reinterpret_cast<const uint8_t *>(tiles + (int64_t)b->total * W);
+        k_anneal_ell_dc<MS><<<njobs * rgroups, 64 * rw, lds, s>>>(jobs, rgroups, b->off_d, W, tiles, dblk, b->dboff_d,
+                                                                  F0, y0, nsw, B, thr, R, rw, (uint32_t)seed,
+                                                                  (uint32_t)(seed >> 32), inst_base, it, Y, e,
+                                                                  b->acnt_d);
+        QB_LAUNCH_CHECK();
+        return QB_OK;
+    }
     // set on every launch (no cached flag shared between devices or threads)
     QB_TRY_HIP(hipFuncSetAttribute((const void *)k_anneal_ell<MS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)LDS_MAX));
@@ -253,8 +447,11 @@ extern "C" qb_status qb_extract_ell(qb_problem P, qb_batch b, const uint8_t *X_d
     if (!P->sparse) return QB_E_UNSUPPORTED;
     if ((uintptr_t)tile_d & 15) return QB_E_ARG;
     if (b->J == 0) return QB_OK;
+    // int8 problems also get the jobs' diagonal blocks (for the annealer's register path)
+    uint8_t *dblk = P->int8_ok ? reinterpret_cast<uint8_t *>(tile_d + (int64_t)b->total * P->ellw) : nullptr;
     k_extract_ell<<<b->J, 256, 0, qb_stream(stream)>>>(P->ell, P->ellw, P->ecnt, P->diag, P->n, b->sol_d, b->off_d,
-                                                       b->idx_d, X_d, H_d, tile_d, c_d, F0_d, y0_d);
+                                                       b->idx_d, X_d, H_d, tile_d, c_d, F0_d, y0_d, dblk, b->dboff_d);
+    b->dblk_valid = dblk != nullptr;
     QB_LAUNCH_CHECK();
     return QB_OK;
 }

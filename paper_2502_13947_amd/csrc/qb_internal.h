@@ -144,6 +144,10 @@ struct qb_batch_s {
     hipStream_t side[QB_NCLASS] = {nullptr};
     int32_t *status_d = nullptr;      // device status word (QB_FLAG_STATE: a job had a failed replica)
     int32_t *acnt_d = nullptr;        // optional, caller's: accepted moves per replica of the last annealing
+    qb_anneal_plan plan = {16, 8};    // annealer schedule (result-invariant)
+    int32_t *dboff_d = nullptr;       // [J] first diagonal block of each job (sparse tiles)
+    int64_t dblk_words = 0;           // words of all jobs' int8 diagonal blocks (1024 per block)
+    bool dblk_valid = false;          // the last sparse extraction wrote the diagonal blocks
     hipEvent_t ev_fork = nullptr, ev_join[QB_NCLASS] = {nullptr};
 };
 

@@ -421,7 +421,8 @@ extern "C" void qb_batch_destroy(qb_batch b)
 {
     if (!b) return;
     for (void *ptr : {(void *)b->sol_d, (void *)b->off_d, (void *)b->rank0_d, (void *)b->idx_d,
-                      (void *)b->sol_begin_d, (void *)b->tile_off_d, (void *)b->lpt_d, (void *)b->status_d})
+                      (void *)b->sol_begin_d, (void *)b->tile_off_d, (void *)b->lpt_d, (void *)b->status_d,
+                      (void *)b->dboff_d})
         if (ptr) (void)hipFree(ptr);
     for (int c = 0; c < QB_NCLASS; ++c) {
         if (b->side[c]) (void)hipStreamDestroy(b->side[c]);
@@ -474,6 +475,14 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
         acc += mp * mp;
     }
     b->tile_elems = acc;
+    // diagonal 64 x 64 blocks of the sparse tiles: qb_tile_ms(m) per job
+    std::vector<int32_t> dbo(J);
+    int64_t nb = 0;
+    for (int q = 0; q < J; ++q) {
+        dbo[q] = (int32_t)nb;
+        nb += qb_tile_ms(size_h[q]);
+    }
+    b->dblk_words = nb * 1024;
     std::vector<int32_t> sb(z + 1, J);
     for (int q = J - 1; q >= 0; --q) sb[sol_h[q]] = q;
     for (int p = z - 1; p >= 0; --p)
@@ -505,6 +514,7 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
         !up((void **)&b->tile_off_d, toff.data(), sizeof(int64_t) * J) ||
         !up((void **)&b->lpt_d, lpt.data(), sizeof(int32_t) * J) ||
         !up((void **)&b->status_d, nullptr, 0) ||
+        !up((void **)&b->dboff_d, dbo.data(), sizeof(int32_t) * J) ||
         hipMalloc((void **)&b->idx_d, sizeof(int32_t) * std::max(b->total, 4)) != hipSuccess ||
         hipMemset(b->idx_d, 0, sizeof(int32_t) * std::max(b->total, 4)) != hipSuccess)
         rc = QB_E_HIP;
@@ -544,6 +554,23 @@ extern "C" qb_status qb_batch_get_info(qb_batch b, qb_batch_info *info)
     info->sol_d = b->sol_d;
     info->off_d = b->off_d;
     info->idx_d = b->idx_d;
+    info->dblk_words = b->dblk_words;
+    return QB_OK;
+}
+
+extern "C" qb_status qb_batch_set_anneal_plan(qb_batch b, const qb_anneal_plan *plan)
+{
+    if (!b || !plan || plan->sleep_after < 0 ||
+        (plan->depth != 8 && plan->depth != 16 && plan->depth != 32))
+        return QB_E_ARG;
+    b->plan = *plan;
+    return QB_OK;
+}
+
+extern "C" qb_status qb_batch_get_anneal_plan(qb_batch b, qb_anneal_plan *plan)
+{
+    if (!b || !plan) return QB_E_ARG;
+    *plan = b->plan;
     return QB_OK;
 }
 

@@ -285,7 +285,7 @@ extern "C" qb_status qb_state_create(qb_state *out, qb_problem P, const qb_run_c
     }
     const qb_batch b = S->batch;
     auto tile_bytes = [&](qb_batch bb) -> size_t {
-        if (P->sparse) return sizeof(uint32_t) * (size_t)bb->total * P->ellw;
+        if (P->sparse) return sizeof(uint32_t) * ((size_t)bb->total * P->ellw + (size_t)bb->dblk_words);
         return (size_t)bb->tile_elems * S->tile_esz;
     };
     const size_t zn = (size_t)z * n;

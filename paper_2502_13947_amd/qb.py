@@ -39,7 +39,11 @@ class ProblemInfo(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("J", ctypes.c_int32), ("total", ctypes.c_int32), ("m_max", ctypes.c_int32),
                 ("tile_elems", ctypes.c_int64), ("sol_d", ctypes.c_void_p),
-                ("off_d", ctypes.c_void_p), ("idx_d", ctypes.c_void_p)]
+                ("off_d", ctypes.c_void_p), ("idx_d", ctypes.c_void_p), ("dblk_words", ctypes.c_int64)]
+
+
+class AnnealPlan(ctypes.Structure):
+    _fields_ = [("sleep_after", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
 class RunCfg(ctypes.Structure):
@@ -122,6 +126,8 @@ SIGNATURES = {
     "qb_autotune_rankk": (_I32, [_P, _I32, _P, _P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
     "qb_batch_check": (_I32, [_P, _P]),
     "qb_batch_count_accepts": (_I32, [_P, _P]),
+    "qb_batch_set_anneal_plan": (_I32, [_P, ctypes.POINTER(AnnealPlan)]),
+    "qb_batch_get_anneal_plan": (_I32, [_P, ctypes.POINTER(AnnealPlan)]),
     "qb_state_create": (_I32, [ctypes.POINTER(_P), _P, ctypes.POINTER(RunCfg), ctypes.POINTER(StateBuffers), _P]),
     "qb_state_destroy": (None, [_P]),
     "qb_state_get_buffers": (_I32, [_P, ctypes.POINTER(StateBuffers)]),
@@ -247,6 +253,7 @@ class Batch:
         info = BatchInfo()
         _chk(lib().qb_batch_get_info(self.h, ctypes.byref(info)), "qb_batch_get_info")
         self.J, self.total, self.m_max, self.tile_elems = info.J, info.total, info.m_max, info.tile_elems
+        self.dblk_words = info.dblk_words
         self.off = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
         self._idx_ptr = info.idx_d
 
@@ -254,6 +261,18 @@ class Batch:
         idx_h = np.ascontiguousarray(idx_h, np.int32)
         assert idx_h.shape[0] == self.total
         _chk(lib().qb_batch_set_idx(self.h, idx_h.ctypes.data, _stream(stream)), "qb_batch_set_idx")
+
+    def set_plan(self, **kw):
+        """Annealer schedule (qb_anneal_plan fields; unnamed ones kept)."""
+        p = self.plan()
+        for k, v in kw.items():
+            setattr(p, k, int(v))
+        _chk(lib().qb_batch_set_anneal_plan(self.h, ctypes.byref(p)), "qb_batch_set_anneal_plan")
+
+    def plan(self) -> AnnealPlan:
+        p = AnnealPlan()
+        _chk(lib().qb_batch_get_anneal_plan(self.h, ctypes.byref(p)), "qb_batch_get_anneal_plan")
+        return p
 
     def count_accepts(self, acnt=None):
         """Accepted moves per replica of later annealings into ``acnt``
@@ -579,6 +598,12 @@ def autotune_rankk(P: "Problem", dX, H, reps=3, stream=None):
 
 def mutation_rate(t) -> float:
     return float(lib().qb_mutation_rate(int(t)))
+
+
+def ell_tile_words(b: "Batch", W: int) -> int:
+    """int32 words of a qb_extract_ell tile buffer: the ELL rows, then the
+    jobs' int8 diagonal blocks."""
+    return max(b.total * W + b.dblk_words, 4)
 
 
 def tile_dtype(P: Problem):

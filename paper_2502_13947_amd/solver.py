@@ -92,7 +92,8 @@ class Solver:
         # dense tiles (int8/int16) or ELL tiles (uint32 words held as int32)
         self.tile_dtype = torch.int32 if self.sparse else qb.tile_dtype(self.P)
         if self.sparse:
-            tile_len = total * self.P.ell_width
+            # ELL rows, then the int8 diagonal blocks (1024 words per 64-block)
+            tile_len = total * self.P.ell_width + 1024 * sum(qb_tile_ms(int(m)) for m in job_m.reshape(-1))
         else:
             ms = [qb_tile_ms(int(m)) for m in job_m.reshape(-1)]
             tile_len = sum((64 * v) ** 2 for v in ms)

@@ -234,7 +234,7 @@ def _extract_ell(P, n, z, sizes, X, H, seed):
     b = qb().Batch(n, z, sol, m)
     b.set_idx(idx)
     W = P.ell_width
-    tiles = torch.zeros(max(b.total * W, 4), dtype=torch.int32, device=DEV)
+    tiles = torch.zeros(qb().ell_tile_words(b, W), dtype=torch.int32, device=DEV)
     c = torch.zeros(b.total, dtype=torch.int32, device=DEV)
     F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
     y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
@@ -256,10 +256,23 @@ def test_extract_ell_bit_exact(case, z, sizes):
     H = field_csr(csr, X)
     b, sol, idx, tiles, c, F0, y0 = _extract_ell(P, n, z, sizes, X, H, 18)
     cc_, FF, yy = c.cpu().numpy(), F0.cpu().numpy(), y0.cpu().numpy()
+    th = tiles.cpu().numpy()
+    dblk = th[b.total * P.ell_width:b.total * P.ell_width + b.dblk_words].view(np.int8).reshape(-1, 64, 64)
+    nb0 = 0
     for q in range(b.J):
         S = idx[b.off[q]:b.off[q + 1]]
         Tq, co, Fo, yo = oracle.extract(Q, X[sol[q]], H[sol[q]], S)
         assert (qb().untile_ell(tiles, b, q, P.ell_width) == Tq).all(), q
+        m = len(S)
+        nbq = qb().tile_ms(m)
+        if P.int8_ok:
+            # the job's diagonal blocks: [block][L][k] = T[64 b + k][64 b + L]
+            Tp = np.zeros((64 * nbq, 64 * nbq), np.int64)
+            Tp[:m, :m] = Tq
+            for bb in range(nbq):
+                blk = Tp[64 * bb:64 * bb + 64, 64 * bb:64 * bb + 64]
+                assert (dblk[nb0 + bb].astype(np.int64) == blk.T).all(), (q, bb)
+        nb0 += nbq
         sl = slice(b.off[q], b.off[q + 1])
         assert (cc_[sl] == co).all() and (FF[sl] == Fo).all() and (yy[sl] == yo).all(), q
 
