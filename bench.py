@@ -351,7 +351,7 @@ def measure_workload(a, name, steps, warmup, cpu_seconds, headline):
         S = Solver(Qd, thr_init=thr, thr=thr, **kw)
     S.init()
     tuned_variant, tuned_ms = S.autotune()
-    tuned_rw = S.autotune_anneal() if sparse else None
+    tuned_plan = S.autotune_anneal()
     stream = S.stream
     S.state.iterate(warmup, graph=True, stream=stream)
     stream.synchronize()
@@ -478,8 +478,10 @@ def measure_workload(a, name, steps, warmup, cpu_seconds, headline):
                roofline=roof, anneal=anneal, stages_ms=stages, eager_ms_per_step=eager_ms,
                rankk_variant={"chosen": tuned_variant, "ms": tuned_ms, "by": "autotuner"},
                wall_s=t_wall, setup_s=t_setup)
-    if tuned_rw:
-        out["anneal_replicas_per_workgroup"] = {"chosen": tuned_rw[0], "ms": tuned_rw[1], "by": "autotuner"}
+    if sparse:
+        out["anneal_replicas_per_workgroup"] = {"chosen": tuned_plan[0], "ms": tuned_plan[1], "by": "autotuner"}
+    else:
+        out["anneal_plan"] = {"chosen": tuned_plan[0], "ms": tuned_plan[1], "by": "autotuner"}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     del S
@@ -504,7 +506,7 @@ def main():
     for name in [x for x in a.extras.split(",") if x and x != a.workload]:
         r = measure_workload(a, name, a.extra_steps, 2, 0.0, False)
         extras[name] = {k: r[k] for k in ("value", "ms_per_step", "config", "roofline", "anneal", "stages_ms",
-                                          "eager_ms_per_step", "rankk_variant")}
+                                          "eager_ms_per_step", "rankk_variant", "anneal_plan") if k in r}
 
     if a.copy_probe > 0:
         nb = a.copy_probe << 20
@@ -538,6 +540,7 @@ def main():
         "rankk_variant": head["rankk_variant"],
         **({"anneal_replicas_per_workgroup": head["anneal_replicas_per_workgroup"]}
            if "anneal_replicas_per_workgroup" in head else {}),
+        **({"anneal_plan": head["anneal_plan"]} if "anneal_plan" in head else {}),
         "extra_workloads": extras,
         "wall_s": head["wall_s"],
     }

@@ -20,8 +20,9 @@
  *    documented range) are latched in the problem's device status word and
  *    returned by qb_check.  No C++ exception crosses this boundary.
  *  - No call allocates device memory except the handle constructors
- *    qb_problem_create_dense, qb_problem_create_csr and qb_batch_create, and
- *    the setup-time autotuners qb_autotune_rankk and qb_autotune_anneal_ell.
+ *    qb_problem_create_dense, qb_problem_create_csr, qb_batch_create and
+ *    qb_state_create, and the setup-time autotuners qb_autotune_rankk,
+ *    qb_autotune_anneal and qb_autotune_anneal_ell.
  *  - Layouts (row-major): Q int16 [n][n] symmetric; X uint8 [z][n] (0/1);
  *    H int32 [z][n] with H[p][i] = sum_j Q[i][j] X[p][j]; E int64 [z].
  *  - Results depend only on inputs, seeds and instance numbers: never on
@@ -184,10 +185,36 @@ typedef struct {
  *   sleep_after: polls of a list word not yet written before a waiting wave
  *     sleeps between polls (0: at once);
  *   depth: list words a wave that reads rows from global memory keeps in
- *     flight (8, 16 or 32). */
+ *     flight (8, 16 or 32);
+ *   kernel[c]: the kernel of size class c (c = 0..4 for padded widths
+ *     mp = 1024, 512, 256, 128, 64): QB_ANNEAL_AUTO (a replica spread over
+ *     up to four waves where its replicas fit one workgroup, else one wave
+ *     per replica), QB_ANNEAL_MULTI_WAVE, QB_ANNEAL_ONE_WAVE, or
+ *     QB_ANNEAL_ONE_WAVE_REG (one wave per replica holding the current
+ *     diagonal block's couplings in registers; tiles in LDS only: int8
+ *     mp <= 512, int16 mp <= 128), or QB_ANNEAL_MULTI_WAVE_GLOBAL (a
+ *     replica over up to four waves reading the tile rows from global memory,
+ *     a few KB of LDS, so that several jobs share a compute unit; R = 1); a
+ *     kernel that cannot run the class falls back to the automatic choice;
+ *   persistent: 1 = each class runs as a persistent grid of
+ *     wgs_per_cu workgroups per compute unit (at most one per job) that pull
+ *     the class's jobs from an atomic queue; 0 = one workgroup per job;
+ *   lpt: the queue (and dispatch) order within a class: 1 = largest job
+ *     first (longest processing time), 0 = job index order.
+ * Size classes run concurrently (their own streams, joined back into the
+ * caller's). */
+#define QB_ANNEAL_AUTO 0
+#define QB_ANNEAL_MULTI_WAVE 1
+#define QB_ANNEAL_ONE_WAVE 2
+#define QB_ANNEAL_ONE_WAVE_REG 3
+#define QB_ANNEAL_MULTI_WAVE_GLOBAL 4
 typedef struct {
     int32_t sleep_after;
     int32_t depth;
+    int32_t kernel[5];
+    int32_t persistent;
+    int32_t wgs_per_cu;
+    int32_t lpt;
 } qb_anneal_plan;
 qb_status qb_batch_set_anneal_plan(qb_batch b, const qb_anneal_plan *plan_h);
 qb_status qb_batch_get_anneal_plan(qb_batch b, qb_anneal_plan *plan_h);
@@ -438,6 +465,20 @@ void qb_graph_destroy(void *graph_exec);
  * allocates scratch and synchronises `stream`. */
 qb_status qb_autotune_rankk(qb_problem P, int32_t z, const int8_t *dX_d, const int32_t *H_d, int32_t reps,
                             int32_t *variant_out, float *ms_out, void *stream);
+/* Plan autotuner of qb_anneal (the batching schedule): coordinate descent
+ * over qb_anneal_plan on the given jobs -- the kernel of each size class
+ * present (largest first), the persistent job queue with its grid
+ * (workgroups per compute unit) and its order (longest job first or job
+ * order), and the consumers' loads in flight -- timing `reps` launches of
+ * each candidate after a warm-up launch.  Every candidate must give the same
+ * Y and e as the batch's plan on entry (else QB_E_STATE).  The fastest plan
+ * is left set on the batch and returned in *plan_out (its mean time in
+ * *ms_out; both optional).  Not a hot call: it allocates scratch and
+ * synchronises `stream`. */
+qb_status qb_autotune_anneal(qb_batch b, const void *tile_d, int32_t int8_tile, const int32_t *F0_d,
+                             const uint8_t *y0_d, int32_t nsw, int32_t B, const int32_t *thr_d, int32_t R,
+                             uint64_t seed, uint32_t inst_base, int32_t reps, qb_anneal_plan *plan_out, float *ms_out,
+                             void *stream);
 /* Autotuner for qb_anneal_ell's replicas per workgroup: times rw in
  * {1, 2, 4, 8, 16} (those <= R that fit LDS) `reps` times each on the given
  * jobs, checks that every rw gives the same Y and e (else QB_E_STATE), and

@@ -186,7 +186,7 @@ struct AnnealLds {
 };
 
 template <int MS, typename TT, int MODE>
-__global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+__device__ __forceinline__ void anneal_job(int slot, const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
                                                  const int64_t *__restrict__ tile_off,
                                                  const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
                                                  const uint8_t *__restrict__ y0, int nsw, int B,
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ job
 {
     constexpr int MP = 64 * MS;
     __shared__ __align__(16) uint8_t lds[AnnealLds<MS, TT, MODE>::bytes];
-    const int q = jobs[blockIdx.x];
+    const int q = jobs[slot];
     const int base = off[q], m = off[q + 1] - base;
     const TT *gtile = tiles + tile_off[q];
     const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6;
@@ -285,15 +285,35 @@ __global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ job
     if (lane == 0) eout[(size_t)q * R + r] = e;
     if (acnt && lane == 0) acnt[(size_t)q * R + r] = nacc;
 }
+template <int MS, typename TT, int MODE>
+__global__ void __launch_bounds__(1024) k_anneal(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+                                                 const int64_t *__restrict__ tile_off,
+                                                 const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                 const uint8_t *__restrict__ y0, int nsw, int B,
+                                                 const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                 uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                 int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
+        int *__restrict__ queue, int njobs)
+{
+    __shared__ int slot_s;
+    for (int pass = 0;; ++pass) {
+        const int slot = qb_next_slot(queue, njobs, pass, &slot_s);
+        if (slot < 0) break;
+        anneal_job<MS, TT, MODE>(slot, jobs, off, tile_off, tiles, F0, y0, nsw, B, thr, R, k0, k1, inst_base, it, Y, eout, acnt);
+        __syncthreads();   // the next job reuses the workgroup's LDS
+    }
+}
+
 
 template <int MS, typename TT, int MODE>
 void launch_anneal(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
                    const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
                    uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
-    k_anneal<MS, TT, MODE><<<nblocks, 64 * R, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0,
-                                                      nsw, B, thr, R, (uint32_t)seed, (uint32_t)(seed >> 32),
-                                                      inst_base, it, Y, e, b->acnt_d);
+    k_anneal<MS, TT, MODE><<<qb_grid(b, nblocks), 64 * R, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles,
+                                                                   F0, y0, nsw, B, thr, R, (uint32_t)seed,
+                                                                   (uint32_t)(seed >> 32), inst_base, it, Y, e,
+                                                                   b->acnt_d, b->lq, nblocks);
 }
 
 // ------------------------------------------------------------ anneal, waves
@@ -377,7 +397,7 @@ __device__ __forceinline__ int32_t diag_at(const uint32_t (&d)[DW], int k)
 }
 
 template <int MS, typename TT, int MODE, bool LIM>
-__global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+__device__ __forceinline__ void anneal_mw_job(int slot, const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
                                                     const int64_t *__restrict__ tile_off,
                                                     const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
                                                     const uint8_t *__restrict__ y0, int nsw, int B,
@@ -394,7 +414,7 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
     __shared__ int64_t esum[16];
     __shared__ int32_t asum[16];
     __shared__ int32_t bad[C::RMAX];
-    const int q = jobs[blockIdx.x];
+    const int q = jobs[slot];
     const int base = off[q], m = off[q + 1] - base;
     const TT *gtile = tiles + tile_off[q];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -583,6 +603,26 @@ __global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ 
         if (acnt) acnt[(size_t)q * R + r] = na;
     }
 }
+template <int MS, typename TT, int MODE, bool LIM>
+__global__ void __launch_bounds__(1024) k_anneal_mw(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+                                                    const int64_t *__restrict__ tile_off,
+                                                    const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                    const uint8_t *__restrict__ y0, int nsw, int B,
+                                                    const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                    uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                    int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
+                                                    int wait_limit, int sleep_after,
+        int *__restrict__ queue, int njobs)
+{
+    __shared__ int slot_s;
+    for (int pass = 0;; ++pass) {
+        const int slot = qb_next_slot(queue, njobs, pass, &slot_s);
+        if (slot < 0) break;
+        anneal_mw_job<MS, TT, MODE, LIM>(slot, jobs, off, tile_off, tiles, F0, y0, nsw, B, thr, R, k0, k1, inst_base, it, Y, eout, acnt, wait_limit, sleep_after);
+        __syncthreads();   // the next job reuses the workgroup's LDS
+    }
+}
+
 
 template <int MS, typename TT, int MODE>
 bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
@@ -594,13 +634,13 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
     if (R > C::RMAX || (int64_t)nsw * MS + 1 >= (int64_t(1) << 24)) return false;
     const int32_t lim = g_wait_limit.load(std::memory_order_relaxed);
     if (lim == MW_WAIT_DEFAULT)
-        k_anneal_mw<MS, TT, MODE, false><<<nblocks, 64 * C::NW * R, 0, s>>>(
+        k_anneal_mw<MS, TT, MODE, false><<<qb_grid(b, nblocks), 64 * C::NW * R, 0, s>>>(
             jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
-            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after);
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after, b->lq, nblocks);
     else
-        k_anneal_mw<MS, TT, MODE, true><<<nblocks, 64 * C::NW * R, 0, s>>>(
+        k_anneal_mw<MS, TT, MODE, true><<<qb_grid(b, nblocks), 64 * C::NW * R, 0, s>>>(
             jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
-            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after);
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after, b->lq, nblocks);
     return true;
 }
 
@@ -616,7 +656,7 @@ bool launch_anneal_mw(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb
 // in-LDS multi-wave kernel.
 template <int MS, typename TT, int PD>
 struct AnnealMwG {
-    static constexpr int NW = 4;
+    static constexpr int NW = MS < 4 ? MS : 4;
     static constexpr int NB = MS / NW;
     static constexpr int DW = 64 * (int)sizeof(TT) / 4;
     static constexpr int PER = 4 / (int)sizeof(TT);
@@ -625,8 +665,18 @@ struct AnnealMwG {
     static constexpr int NOFF = NB * (NB - 1) / 2;             // own off-diagonal blocks
     static constexpr int P = PD;                               // list words per consumer batch
     static constexpr int SLOTS = 65 + P - 1;
-    static_assert(MS * sizeof(TT) == 16 && NB * sizeof(TT) == 4, "16 bytes per lane, one dword per consumer row");
+    static constexpr int LB = NB * (int)sizeof(TT);            // bytes of a row a consumer reads
+    static_assert(LB == 1 || LB == 2 || LB == 4, "one load of 1, 2 or 4 bytes per consumer row");
 };
+
+// one consumer load of LB bytes, zero-extended
+template <int LB>
+__device__ __forceinline__ uint32_t load_lb(const uint8_t *p)
+{
+    if constexpr (LB == 4) return *reinterpret_cast<const uint32_t *>(p);
+    else if constexpr (LB == 2) return *reinterpret_cast<const uint16_t *>(p);
+    else return *p;
+}
 
 __device__ __forceinline__ int own_pair(int a, int b, int nb)   // a < b < nb
 {
@@ -634,7 +684,7 @@ __device__ __forceinline__ int own_pair(int a, int b, int nb)   // a < b < nb
 }
 
 template <int MS, typename TT, bool LIM, int PD>
-__global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__ jobs,
+__device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restrict__ jobs,
                                                      const int32_t *__restrict__ off,
                                                      const int64_t *__restrict__ tile_off,
                                                      const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
@@ -649,12 +699,12 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
     constexpr int MP = 64 * MS;
     constexpr int ROWB = MP * (int)sizeof(TT);                 // bytes per tile row
     constexpr int EB = 8 * (int)sizeof(TT);                    // bits per element
-    __shared__ __align__(16) uint8_t own[NW][C::NOFF > 0 ? C::NOFF : 1][C::OBLK];
+    __shared__ __align__(16) uint8_t own[NW][C::NOFF > 0 ? C::NOFF : 1][C::NOFF > 0 ? C::OBLK : 16];
     __shared__ uint32_t lists[MS][SLOTS];
     __shared__ int64_t esum[NW];
     __shared__ int32_t asum[NW];
     __shared__ int32_t bad;
-    const int q = jobs[blockIdx.x];
+    const int q = jobs[slot];
     const int base = off[q], m = off[q + 1] - base;
     const uint8_t *gt8 = reinterpret_cast<const uint8_t *>(tiles + tile_off[q]);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -664,7 +714,8 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
     uint8_t *ow = &own[w][0][0];
 
     // this wave's columns of row x: dword 16 lane + 4 w of the row
-    const uint8_t *colp = gt8 + 16 * lane + 4 * w;
+    constexpr int LB = C::LB;
+    const uint8_t *colp = gt8 + MS * (int)sizeof(TT) * lane + LB * w;
     auto elem_of = [&](uint32_t x, int t) -> int32_t {
         return sizeof(TT) == 1 ? (int32_t)(int8_t)(x >> (8 * t)) : (int32_t)(int16_t)(x >> (16 * t));
     };
@@ -683,7 +734,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
                 const int rr = i * PER + p;
-                const uint32_t x = *reinterpret_cast<const uint32_t *>(colp + (size_t)(64 * (s0 + a) + rr) * ROWB);
+                const uint32_t x = load_lb<LB>(colp + (size_t)(64 * (s0 + a) + rr) * ROWB);
                 wv |= ((uint32_t)elem_of(x, a) & (0xFFFFFFFFu >> (32 - EB))) << (p * EB);
 #pragma unroll
                 for (int t = a + 1; t < NB; ++t) {
@@ -767,7 +818,7 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
                 uint32_t x[P];
 #pragma unroll
                 for (int i = 0; i < P; ++i)
-                    if (i < n) x[i] = *reinterpret_cast<const uint32_t *>(rowp + (size_t)((vv[i] >> 1) & 63u) * ROWB);
+                    if (i < n) x[i] = load_lb<LB>(rowp + (size_t)((vv[i] >> 1) & 63u) * ROWB);
 #pragma unroll
                 for (int i = 0; i < P; ++i) {
                     if (i < n) {
@@ -854,6 +905,27 @@ __global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__
         if (acnt) acnt[(size_t)q * R] = na;
     }
 }
+template <int MS, typename TT, bool LIM, int PD>
+__global__ void __launch_bounds__(256) k_anneal_mw_g(const int32_t *__restrict__ jobs,
+                                                     const int32_t *__restrict__ off,
+                                                     const int64_t *__restrict__ tile_off,
+                                                     const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                     const uint8_t *__restrict__ y0, int nsw, int B,
+                                                     const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                     uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it, uint8_t *__restrict__ Y,
+                                                     int64_t *__restrict__ eout, int32_t *__restrict__ acnt,
+                                                     int wait_limit, int sleep_after,
+        int *__restrict__ queue, int njobs)
+{
+    __shared__ int slot_s;
+    for (int pass = 0;; ++pass) {
+        const int slot = qb_next_slot(queue, njobs, pass, &slot_s);
+        if (slot < 0) break;
+        anneal_mw_g_job<MS, TT, LIM, PD>(slot, jobs, off, tile_off, tiles, F0, y0, nsw, B, thr, R, k0, k1, inst_base, it, Y, eout, acnt, wait_limit, sleep_after);
+        __syncthreads();   // the next job reuses the workgroup's LDS
+    }
+}
+
 
 template <int MS, typename TT, int PD>
 void launch_mw_g_depth(int nblocks, int lim, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
@@ -862,15 +934,13 @@ void launch_mw_g_depth(int nblocks, int lim, hipStream_t s, const int32_t *jobs,
 {
     constexpr int NT = 64 * AnnealMwG<MS, TT, PD>::NW;
     if (lim == MW_WAIT_DEFAULT)
-        k_anneal_mw_g<MS, TT, false, PD><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
-                                                                y0, nsw, B, thr, R, (uint32_t)seed,
-                                                                (uint32_t)(seed >> 32), inst_base, it, Y, e,
-                                                                b->acnt_d, lim, b->plan.sleep_after);
+        k_anneal_mw_g<MS, TT, false, PD><<<qb_grid(b, nblocks), NT, 0, s>>>(
+            jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after, b->lq, nblocks);
     else
-        k_anneal_mw_g<MS, TT, true, PD><<<nblocks, NT, 0, s>>>(jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0,
-                                                               y0, nsw, B, thr, R, (uint32_t)seed,
-                                                               (uint32_t)(seed >> 32), inst_base, it, Y, e,
-                                                               b->acnt_d, lim, b->plan.sleep_after);
+        k_anneal_mw_g<MS, TT, true, PD><<<qb_grid(b, nblocks), NT, 0, s>>>(
+            jobs, b->off_d, b->tile_off_d, (const TT *)tiles, F0, y0, nsw, B, thr, R, (uint32_t)seed,
+            (uint32_t)(seed >> 32), inst_base, it, Y, e, b->acnt_d, lim, b->plan.sleep_after, b->lq, nblocks);
 }
 
 template <int MS, typename TT>
@@ -891,20 +961,262 @@ bool launch_anneal_mw_g(int nblocks, int R, hipStream_t s, const int32_t *jobs, 
     return true;
 }
 
+// ------------------------------------------------- anneal, one wave, couplings in registers
+// One replica per wave again (the R replicas of a job share a workgroup and
+// its tile in LDS), with the multi-wave owner's accept chain: lane L holds
+// column L of the current diagonal 64 x 64 block, T[64 s + k][64 s + L] for
+// k < 64, in VGPRs, and the block's move values dE = sigma F are updated
+// from there, so no memory access is on the chain.  The accepted row's
+// elements in the other blocks (one LDS read of the lane's slice) are added
+// to their F one accept late, after the next accept's chain, and the last
+// one at the end of the block.  No wave waits on another: a sweep has no
+// hand-off between waves.  By symmetry column L of a diagonal block is its
+// row L; with the symmetric-block placement (mp = 512, int8) that row is
+// read straight from the stored diagonal block, otherwise (whole tile in
+// LDS) the kernel first copies the diagonal blocks as [block][L][k] rows.
+template <int MS, typename TT, int MODE>
+struct AnnealDc {
+    static constexpr int MP = 64 * MS;
+    static constexpr size_t tile = MODE == 0 ? (size_t)MP * MP * sizeof(TT) : SYM_BYTES;
+    static constexpr size_t dcol = MODE == 0 ? (size_t)MS * 64 * 64 * sizeof(TT) : 0;
+    static constexpr int DW = 64 * (int)sizeof(TT) / 4;
+    static constexpr bool fits = tile + dcol + 256 <= (size_t)MW_LDS_LIMIT;
+};
+
+template <int MS, typename TT, int MODE>
+__device__ __forceinline__ void anneal_dc_job(int slot, const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+                                                    const int64_t *__restrict__ tile_off,
+                                                    const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                    const uint8_t *__restrict__ y0, int nsw, int B,
+                                                    const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                    uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it,
+                                                    uint8_t *__restrict__ Y, int64_t *__restrict__ eout,
+                                                    int32_t *__restrict__ acnt)
+{
+    using C = AnnealDc<MS, TT, MODE>;
+    constexpr int MP = C::MP, DW = C::DW;
+    static_assert(C::fits, "tile and columns must fit LDS");
+    __shared__ __align__(16) uint8_t lds[C::tile + (C::dcol ? C::dcol : 16)];
+    const int q = jobs[slot];
+    const int base = off[q], m = off[q + 1] - base;
+    const TT *gtile = tiles + tile_off[q];
+    const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6;
+
+    if constexpr (MODE == 0) {
+        constexpr int n16 = (int)(C::tile / 16);
+        const uint4 *src = reinterpret_cast<const uint4 *>(gtile);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds);
+        for (int t = tid; t < n16; t += blockDim.x) dst[t] = src[t];
+        // diagonal blocks as rows: [b][L][k] = T[64 b + L][64 b + k]
+        TT *dc = reinterpret_cast<TT *>(lds + C::tile);
+        for (int t = tid; t < MS * 4096; t += blockDim.x) {
+            const int bk = t >> 12, L = (t >> 6) & 63, k = t & 63;
+            dc[t] = gtile[(size_t)(64 * bk + L) * MP + k * MS + bk];
+        }
+        __syncthreads();
+    } else {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(gtile);
+        for (int t = tid; t < MP * 64; t += blockDim.x) {
+            const int x = t >> 6, cc = t & 63;
+            const uint64_t w = src[t];
+            const int a = x >> 6, rr = x & 63;
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (b >= a) lds[sym_block_index(a, b) * SYM_BLOCK + rr * SYM_STRIDE + cc] = (uint8_t)(w >> (8 * b));
+        }
+        __syncthreads();
+    }
+    if (r >= R) return;   // no barrier follows
+
+    int32_t F[MS];
+    uint32_t ybits = 0;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        F[s] = pos < m ? F0[base + pos] : 0;
+        if (pos < m && y0[base + pos]) ybits |= 1u << s;
+    }
+    // row L of diagonal block s (its column L by symmetry)
+    auto column = [&](int s, uint32_t (&d)[DW]) {
+        const uint32_t *src;
+        if constexpr (MODE == 0)
+            src = reinterpret_cast<const uint32_t *>(lds + C::tile + ((size_t)s * 64 + lane) * 64 * sizeof(TT));
+        else
+            src = reinterpret_cast<const uint32_t *>(lds + sym_block_index(s, s) * SYM_BLOCK + lane * SYM_STRIDE);
+#pragma unroll
+        for (int i = 0; i < DW; ++i) d[i] = src[i];
+    };
+    int64_t e = 0;
+    int32_t nacc = 0;
+    const uint32_t tag = (1u << 28) | (inst_base + (it ? it->inst : 0u) + (uint32_t)q);
+    constexpr int G = (MS + 3) / 4;
+    const int sh = 32 - B;
+    auto thresholds = [&](int sw, int32_t (&tv)[MS]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint4 o = qb_philox(make_uint4(((uint32_t)g << 6) | (uint32_t)lane, (uint32_t)sw, (uint32_t)r, tag),
+                                      k0, k1);
+            const int32_t *ts = thr + ((size_t)sw << B);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (4 * g + w < MS) tv[4 * g + w] = ts[qb_word(o, w) >> sh];
+        }
+    };
+    int32_t tvn[MS];
+    thresholds(0, tvn);
+
+    for (int sw = 0; sw < nsw; ++sw) {
+        int32_t tv[MS];
+#pragma unroll
+        for (int s = 0; s < MS; ++s) tv[s] = tvn[s];
+        if (sw + 1 < nsw) thresholds(sw + 1, tvn);
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+            const int na = min(max(m - 64 * s, 0), 64);
+            if (na == 0) continue;
+            uint64_t pend = na == 64 ? ~0ull : ((1ull << na) - 1ull);
+            uint32_t dcl[DW];
+            column(s, dcl);
+            const int32_t M0 = ((ybits >> s) & 1u) ? -1 : 0;
+            const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;   // 2 sigma
+            int32_t dE = (F[s] ^ M0) - M0;
+            uint64_t ym = __ballot(M0 != 0);
+            uint64_t acc = __ballot(dE <= tv[s]) & pend;
+            int32_t pr[MS];
+            int32_t pd2 = 0;                             // 0: nothing pending
+            while (acc) {
+                const int k = __builtin_ctzll(acc);
+                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
+                const int32_t mk = (int32_t)((ym >> k) & 1ull);
+                ym ^= 1ull << k;
+                e += dEk;
+                ++nacc;
+                const int32_t d2 = mk ? -2 : 2;
+                dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcl, k);
+                pend &= (~0ull << k) << 1;
+                const uint64_t accn = __ballot(dE <= tv[s]) & pend;
+                // the chain is done: add the previous accepted row to the
+                // other blocks, then read this one
+                __builtin_amdgcn_sched_barrier(0);
+                if (pd2) {
+#pragma unroll
+                    for (int s3 = 0; s3 < MS; ++s3)
+                        if (s3 != s) F[s3] += pd2 * pr[s3];
+                }
+                fetch_row<MS, TT, MODE>(lds, gtile, 64 * s + k, lane, pr);
+                pd2 = d2;
+                acc = accn;
+            }
+            if (pd2) {
+#pragma unroll
+                for (int s3 = 0; s3 < MS; ++s3)
+                    if (s3 != s) F[s3] += pd2 * pr[s3];
+            }
+            F[s] = (dE ^ M0) - M0;
+            if ((ym >> lane) & 1ull)
+                ybits |= 1u << s;
+            else
+                ybits &= ~(1u << s);
+        }
+    }
+
+    uint8_t *Yr = Y + (size_t)base * R + (size_t)r * m;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int pos = 64 * s + lane;
+        if (pos < m) Yr[pos] = (uint8_t)((ybits >> s) & 1u);
+    }
+    if (lane == 0) eout[(size_t)q * R + r] = e;
+    if (acnt && lane == 0) acnt[(size_t)q * R + r] = nacc;
+}
+template <int MS, typename TT, int MODE>
+__global__ void __launch_bounds__(1024) k_anneal_dc(const int32_t *__restrict__ jobs, const int32_t *__restrict__ off,
+                                                    const int64_t *__restrict__ tile_off,
+                                                    const TT *__restrict__ tiles, const int32_t *__restrict__ F0,
+                                                    const uint8_t *__restrict__ y0, int nsw, int B,
+                                                    const int32_t *__restrict__ thr, int R, uint32_t k0,
+                                                    uint32_t k1, uint32_t inst_base, const qb_iter *__restrict__ it,
+                                                    uint8_t *__restrict__ Y, int64_t *__restrict__ eout,
+                                                    int32_t *__restrict__ acnt,
+        int *__restrict__ queue, int njobs)
+{
+    __shared__ int slot_s;
+    for (int pass = 0;; ++pass) {
+        const int slot = qb_next_slot(queue, njobs, pass, &slot_s);
+        if (slot < 0) break;
+        anneal_dc_job<MS, TT, MODE>(slot, jobs, off, tile_off, tiles, F0, y0, nsw, B, thr, R, k0, k1, inst_base, it, Y, eout, acnt);
+        __syncthreads();   // the next job reuses the workgroup's LDS
+    }
+}
+
+
+template <int MS, typename TT, int MODE>
+bool launch_anneal_dc(int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b, const void *tiles,
+                      const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr, uint64_t seed,
+                      uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
+{
+    if constexpr (!AnnealDc<MS, TT, MODE>::fits) {
+        return false;
+    } else {
+        k_anneal_dc<MS, TT, MODE><<<qb_grid(b, nblocks), 64 * R, 0, s>>>(jobs, b->off_d, b->tile_off_d,
+                                                                          (const TT *)tiles, F0, y0, nsw, B, thr, R,
+                                                                          (uint32_t)seed, (uint32_t)(seed >> 32),
+                                                                          inst_base, it, Y, e, b->acnt_d, b->lq,
+                                                                          nblocks);
+        return true;
+    }
+}
+
+__global__ void k_reset_queues(int *__restrict__ q, int n)
+{
+    if ((int)threadIdx.x < n) q[threadIdx.x] = 0;
+}
+
 bool dispatch_anneal(int cls, bool int8_tile, int nblocks, int R, hipStream_t s, const int32_t *jobs, qb_batch b,
                      const void *tiles, const int32_t *F0, const uint8_t *y0, int nsw, int B, const int32_t *thr,
                      uint64_t seed, uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
 #define QB_ARGS nblocks, R, s, jobs, b, tiles, F0, y0, nsw, B, thr, seed, inst_base, it, Y, e
+    // the multi-wave kernel with rows in global memory, where the plan asks for it
+    if (b->plan.kernel[cls] == QB_ANNEAL_MULTI_WAVE_GLOBAL) {
+        if (int8_tile) {
+            switch (cls) {
+            case 1: if (launch_anneal_mw_g<8, int8_t>(QB_ARGS)) return true; break;
+            case 2: if (launch_anneal_mw_g<4, int8_t>(QB_ARGS)) return true; break;
+            case 3: if (launch_anneal_mw_g<2, int8_t>(QB_ARGS)) return true; break;
+            }
+        } else {
+            switch (cls) {
+            case 2: if (launch_anneal_mw_g<4, int16_t>(QB_ARGS)) return true; break;
+            case 3: if (launch_anneal_mw_g<2, int16_t>(QB_ARGS)) return true; break;
+            }
+        }
+    }
+    // the one-wave kernel with the couplings in registers, where the plan asks for it
+    if (b->plan.kernel[cls] == QB_ANNEAL_ONE_WAVE_REG) {
+        if (int8_tile) {
+            switch (cls) {
+            case 1: if (launch_anneal_dc<8, int8_t, 1>(QB_ARGS)) return true; break;
+            case 2: if (launch_anneal_dc<4, int8_t, 0>(QB_ARGS)) return true; break;
+            case 3: if (launch_anneal_dc<2, int8_t, 0>(QB_ARGS)) return true; break;
+            case 4: if (launch_anneal_dc<1, int8_t, 0>(QB_ARGS)) return true; break;
+            }
+        } else {
+            switch (cls) {
+            case 3: if (launch_anneal_dc<2, int16_t, 0>(QB_ARGS)) return true; break;
+            case 4: if (launch_anneal_dc<1, int16_t, 0>(QB_ARGS)) return true; break;
+            }
+        }
+    }
     // the multi-wave kernel where its replicas fit one workgroup
-    if (int8_tile) {
+    if (b->plan.kernel[cls] != QB_ANNEAL_ONE_WAVE && int8_tile) {
         switch (cls) {
         case 0: if (launch_anneal_mw_g<16, int8_t>(QB_ARGS)) return true; break;
         case 1: if (launch_anneal_mw<8, int8_t, 1>(QB_ARGS)) return true; break;
         case 2: if (launch_anneal_mw<4, int8_t, 0>(QB_ARGS)) return true; break;
         case 3: if (launch_anneal_mw<2, int8_t, 0>(QB_ARGS)) return true; break;
         }
-    } else {
+    } else if (b->plan.kernel[cls] != QB_ANNEAL_ONE_WAVE) {
         switch (cls) {
         case 1: if (launch_anneal_mw_g<8, int16_t>(QB_ARGS)) return true; break;
         case 2: if (launch_anneal_mw<4, int16_t, 0>(QB_ARGS)) return true; break;
@@ -987,22 +1299,36 @@ qb_status qb_anneal_x(qb_batch b, const void *tile_d, int32_t int8_tile, const i
     if ((uintptr_t)tile_d & 15) return QB_E_ARG;
     if ((uint64_t)inst_base + (uint64_t)b->J > (1ull << 28)) return QB_E_RANGE;
     hipStream_t s = qb_stream(stream);
-    bool first = true, forked = false;
+    // every size class starts at once: the fork precedes the first launch
+    int ncls = 0;
+    for (int c = 0; c < QB_NCLASS; ++c) ncls += b->cls_end[c] > b->cls_begin[c];
+    if (ncls == 0) return QB_OK;
+    const bool persist = b->plan.persistent != 0;
+    if (persist) {
+        k_reset_queues<<<1, 64, 0, s>>>(b->queue_d, QB_NCLASS);
+        QB_LAUNCH_CHECK();
+    }
+    if (ncls > 1) QB_TRY_HIP(hipEventRecord(b->ev_fork, s));
+    int ncu = 0;
+    if (persist) QB_TRY_HIP(qb_cu_count(&ncu));
+    bool first = true;
     for (int c = 0; c < QB_NCLASS; ++c) {
         const int nblk = b->cls_end[c] - b->cls_begin[c];
         if (nblk <= 0) continue;
         hipStream_t ls = s;
         if (!first) {
-            if (!forked) {
-                QB_TRY_HIP(hipEventRecord(b->ev_fork, s));
-                forked = true;
-            }
             ls = b->side[c];
             QB_TRY_HIP(hipStreamWaitEvent(ls, b->ev_fork, 0));
         }
-        if (!dispatch_anneal(c, int8_tile != 0, nblk, R, ls, b->lpt_d + b->cls_begin[c], b, tile_d, F0_d, y0_d,
-                             nsw, B, thr_d, seed, inst_base, it, Y_d, e_d))
-            return QB_E_UNSUPPORTED;
+        // persistent: a grid of workgroups pulls the class's jobs from its queue
+        b->lq = persist ? b->queue_d + c : nullptr;
+        b->lgrid = persist ? std::min(nblk, std::max(1, ncu * b->plan.wgs_per_cu)) : 0;
+        const int32_t *order = (b->plan.lpt ? b->lpt_d : b->iord_d) + b->cls_begin[c];
+        const bool ok = dispatch_anneal(c, int8_tile != 0, nblk, R, ls, order, b, tile_d, F0_d, y0_d, nsw, B, thr_d,
+                                        seed, inst_base, it, Y_d, e_d);
+        b->lq = nullptr;
+        b->lgrid = 0;
+        if (!ok) return QB_E_UNSUPPORTED;
         QB_LAUNCH_CHECK();
         if (!first) {
             QB_TRY_HIP(hipEventRecord(b->ev_join[c], ls));

@@ -466,7 +466,11 @@ qb_status qb_anneal_ell_x(qb_batch b, int32_t W, const uint32_t *tile_d, const i
     if ((uintptr_t)tile_d & 15) return QB_E_ARG;
     if ((uint64_t)inst_base + (uint64_t)b->J > (1ull << 28)) return QB_E_RANGE;
     hipStream_t s = qb_stream(stream);
-    bool first = true, forked = false;
+    // every size class starts at once: the fork precedes the first launch
+    int ncls = 0;
+    for (int c = 0; c < QB_NCLASS; ++c) ncls += b->cls_end[c] > b->cls_begin[c];
+    if (ncls > 1) QB_TRY_HIP(hipEventRecord(b->ev_fork, s));
+    bool first = true;
     for (int c = 0; c < QB_NCLASS; ++c) {
         const int nj = b->cls_end[c] - b->cls_begin[c];
         if (nj <= 0) continue;
@@ -480,10 +484,6 @@ qb_status qb_anneal_ell_x(qb_batch b, int32_t W, const uint32_t *tile_d, const i
         if (ell_lds_bytes(ms, W, r2) > LDS_MAX) return QB_E_CAPACITY;
         hipStream_t ls = s;
         if (!first) {
-            if (!forked) {
-                QB_TRY_HIP(hipEventRecord(b->ev_fork, s));
-                forked = true;
-            }
             ls = b->side[c];
             QB_TRY_HIP(hipStreamWaitEvent(ls, b->ev_fork, 0));
         }

@@ -144,7 +144,11 @@ struct qb_batch_s {
     hipStream_t side[QB_NCLASS] = {nullptr};
     int32_t *status_d = nullptr;      // device status word (QB_FLAG_STATE: a job had a failed replica)
     int32_t *acnt_d = nullptr;        // optional, caller's: accepted moves per replica of the last annealing
-    qb_anneal_plan plan = {16, 8};    // annealer schedule (result-invariant)
+    qb_anneal_plan plan = {16, 8, {0, 0, 0, 0, 0}, 0, 1, 1};   // annealer schedule (result-invariant)
+    int32_t *iord_d = nullptr;        // [J] jobs by class, then job index (the queue order without LPT)
+    int *queue_d = nullptr;           // [QB_NCLASS] job counters of the persistent annealer
+    int *lq = nullptr;                // launch in progress: its class's counter (persistent) or null
+    int lgrid = 0;                    // launch in progress: persistent grid (0: one workgroup per job)
     int32_t *dboff_d = nullptr;       // [J] first diagonal block of each job (sparse tiles)
     int64_t dblk_words = 0;           // words of all jobs' int8 diagonal blocks (1024 per block)
     bool dblk_valid = false;          // the last sparse extraction wrote the diagonal blocks
@@ -184,6 +188,11 @@ qb_status qb_random_keys_x(int32_t n, int32_t z, int32_t t, const qb_iter *it, u
 qb_status qb_trace_x(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_d, const int64_t *e_d,
                      const uint8_t *y0_d, uint16_t *outF_d, uint8_t *outL_d, const qb_iter *it, int64_t cap,
                      void *stream);
+
+// Workgroups of an annealer launch: the persistent grid, else one per job.
+static inline int qb_grid(const qb_batch_s *b, int njobs) { return b->lgrid ? b->lgrid : njobs; }
+// Compute units of the current device (cached per device).
+hipError_t qb_cu_count(int *out);
 
 // Column counts c_j = sum_p X[p][j] into P->colcnt (enqueued on stream).
 qb_status qb_column_counts(qb_problem P, int z, const uint8_t *X, void *stream);
@@ -248,6 +257,20 @@ __device__ __forceinline__ int qb_best_replica(const int64_t *__restrict__ eq, i
     }
     *failed = f;
     return rb;
+}
+
+// Job slot of a workgroup's pass `pass`: without a queue, blockIdx.x on the
+// first pass only; with one (the persistent annealer), the next slot of the
+// atomic counter, taken by thread 0 and shared through slot_s (every thread
+// of the workgroup calls this).  -1 when no job is left.
+__device__ __forceinline__ int qb_next_slot(int *queue, int njobs, int pass, int *slot_s)
+{
+    if (!queue) return pass == 0 ? (int)blockIdx.x : -1;
+    if (threadIdx.x == 0) *slot_s = atomicAdd(queue, 1);
+    __syncthreads();
+    const int v = *slot_s;
+    __syncthreads();
+    return v < njobs ? v : -1;
 }
 
 __device__ __forceinline__ uint32_t qb_word(uint4 v, int w)

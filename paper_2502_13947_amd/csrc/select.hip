@@ -422,7 +422,7 @@ extern "C" void qb_batch_destroy(qb_batch b)
     if (!b) return;
     for (void *ptr : {(void *)b->sol_d, (void *)b->off_d, (void *)b->rank0_d, (void *)b->idx_d,
                       (void *)b->sol_begin_d, (void *)b->tile_off_d, (void *)b->lpt_d, (void *)b->status_d,
-                      (void *)b->dboff_d})
+                      (void *)b->dboff_d, (void *)b->iord_d, (void *)b->queue_d})
         if (ptr) (void)hipFree(ptr);
     for (int c = 0; c < QB_NCLASS; ++c) {
         if (b->side[c]) (void)hipStreamDestroy(b->side[c]);
@@ -495,6 +495,10 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
         if (cls(a) != cls(c)) return cls(a) < cls(c);
         return size_h[a] > size_h[c];
     });
+    // the same classes in job index order (the queue order without LPT)
+    std::vector<int32_t> iord(J);
+    std::iota(iord.begin(), iord.end(), 0);
+    std::stable_sort(iord.begin(), iord.end(), [&](int a, int c) { return cls(a) < cls(c); });
     for (int c = 0; c < QB_NCLASS; ++c) { b->cls_begin[c] = J; b->cls_end[c] = J; }
     for (int i = J - 1; i >= 0; --i) b->cls_begin[cls(lpt[i])] = i;
     for (int i = 0; i < J; ++i) b->cls_end[cls(lpt[i])] = i + 1;
@@ -515,6 +519,8 @@ extern "C" qb_status qb_batch_create(qb_batch *out, int32_t n, int32_t z, int32_
         !up((void **)&b->lpt_d, lpt.data(), sizeof(int32_t) * J) ||
         !up((void **)&b->status_d, nullptr, 0) ||
         !up((void **)&b->dboff_d, dbo.data(), sizeof(int32_t) * J) ||
+        !up((void **)&b->iord_d, iord.data(), sizeof(int32_t) * J) ||
+        !up((void **)&b->queue_d, nullptr, 0) ||
         hipMalloc((void **)&b->idx_d, sizeof(int32_t) * std::max(b->total, 4)) != hipSuccess ||
         hipMemset(b->idx_d, 0, sizeof(int32_t) * std::max(b->total, 4)) != hipSuccess)
         rc = QB_E_HIP;
@@ -562,6 +568,10 @@ extern "C" qb_status qb_batch_set_anneal_plan(qb_batch b, const qb_anneal_plan *
 {
     if (!b || !plan || plan->sleep_after < 0 ||
         (plan->depth != 8 && plan->depth != 16 && plan->depth != 32))
+        return QB_E_ARG;
+    for (int c = 0; c < QB_NCLASS; ++c)
+        if (plan->kernel[c] < QB_ANNEAL_AUTO || plan->kernel[c] > QB_ANNEAL_MULTI_WAVE_GLOBAL) return QB_E_ARG;
+    if ((plan->persistent & ~1) || (plan->lpt & ~1) || plan->wgs_per_cu < 1 || plan->wgs_per_cu > 16)
         return QB_E_ARG;
     b->plan = *plan;
     return QB_OK;

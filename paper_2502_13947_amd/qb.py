@@ -43,7 +43,8 @@ class BatchInfo(ctypes.Structure):
 
 
 class AnnealPlan(ctypes.Structure):
-    _fields_ = [("sleep_after", ctypes.c_int32), ("depth", ctypes.c_int32)]
+    _fields_ = [("sleep_after", ctypes.c_int32), ("depth", ctypes.c_int32), ("kernel", ctypes.c_int32 * 5),
+                ("persistent", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("lpt", ctypes.c_int32)]
 
 
 class RunCfg(ctypes.Structure):
@@ -66,6 +67,7 @@ class StateBuffers(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in STATE_BUFFERS]
 
 
+ANNEAL_AUTO, ANNEAL_MULTI_WAVE, ANNEAL_ONE_WAVE, ANNEAL_ONE_WAVE_REG, ANNEAL_MULTI_WAVE_GLOBAL = 0, 1, 2, 3, 4
 RUN_RANDOM_SELECT, RUN_NO_IM, RUN_INIT_JACOBI, RUN_WB_NOT_WORSE, RUN_LEARNED = 1, 2, 4, 8, 16
 
 
@@ -141,6 +143,8 @@ SIGNATURES = {
     "qb_state_enable_timing": (_I32, [_P, _I32]),
     "qb_state_stage_ms": (_I32, [_P, _P, _P]),
     "qb_state_check": (_I32, [_P, _P]),
+    "qb_autotune_anneal": (_I32, [_P, _P, _I32, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _I32,
+                                  ctypes.POINTER(AnnealPlan), ctypes.POINTER(ctypes.c_float), _P]),
     "qb_autotune_anneal_ell": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _I32, _U64, _U32, _I32,
                                       ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float), _P]),
 }
@@ -266,7 +270,11 @@ class Batch:
         """Annealer schedule (qb_anneal_plan fields; unnamed ones kept)."""
         p = self.plan()
         for k, v in kw.items():
-            setattr(p, k, int(v))
+            if k == "kernel":
+                for c, kk in enumerate(v):
+                    p.kernel[c] = int(kk)
+            else:
+                setattr(p, k, int(v))
         _chk(lib().qb_batch_set_anneal_plan(self.h, ctypes.byref(p)), "qb_batch_set_anneal_plan")
 
     def plan(self) -> AnnealPlan:
@@ -446,6 +454,23 @@ def anneal_ell(b: Batch, W, tile, F0, y0, thr, R, seed, inst_base, Y, e, B, rw=0
     assert thr.shape[1] == (1 << B) and tile.dtype == torch.int32
     _chk(lib().qb_anneal_ell(b.h, int(W), _ptr(tile), _ptr(F0), _ptr(y0), nsw, B, _ptr(thr), R, int(rw), seed,
                              inst_base, _ptr(Y), _ptr(e), _stream(stream)), "qb_anneal_ell")
+
+
+def autotune_anneal(b: Batch, tile, F0, y0, thr, R, seed, inst_base, B, reps=2, stream=None):
+    """qb_autotune_anneal: (plan as a dict, ms)."""
+    nsw = thr.shape[0]
+    plan = AnnealPlan()
+    ms = ctypes.c_float()
+    int8_tile = 1 if tile.dtype == torch.int8 else 0
+    _chk(lib().qb_autotune_anneal(b.h, _ptr(tile), int8_tile, _ptr(F0), _ptr(y0), nsw, B, _ptr(thr), R, seed,
+                                  inst_base, int(reps), ctypes.byref(plan), ctypes.byref(ms), _stream(stream)),
+         "qb_autotune_anneal")
+    return plan_dict(plan), float(ms.value)
+
+
+def plan_dict(p: "AnnealPlan") -> dict:
+    return dict(sleep_after=p.sleep_after, depth=p.depth, kernel=list(p.kernel), persistent=p.persistent,
+                wgs_per_cu=p.wgs_per_cu, lpt=p.lpt)
 
 
 def autotune_anneal_ell(b: Batch, W, tile, F0, y0, thr, R, seed, inst_base, B, reps=2, stream=None):

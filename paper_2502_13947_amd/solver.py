@@ -223,21 +223,27 @@ class Solver:
         return self.rankk_variant, ms
 
     def autotune_anneal(self, reps=2):
-        """Sparse problems: pick the annealer's replicas per workgroup on the
-        current state's plain selection (results are identical for every
-        choice; the autotuner checks it).  Leaves the solver state as it was
-        apart from scratch buffers the next iteration overwrites."""
-        if not self.sparse:
-            return None
+        """Pick the annealer's schedule on the current state's plain selection:
+        the plan (kernel per size class, persistent queue and its grid and
+        order) of a dense problem, the replicas per workgroup of a sparse one.
+        Results are identical for every choice (the autotuners check it).
+        Leaves the solver state as it was apart from scratch buffers the next
+        iteration overwrites; returns (choice, ms)."""
         s, b = self.stream, self.batch
         qb.keys(self.P, self.X, self.T, self.K, self.W, t_bound=max(self.alpha, 1), stream=s)
         qb.rank(self.K, self.order, stream=s)
         qb.select(b, self.order, stream=s)
         self._extract(b, self.tiles, self.F0, self.y0, s)
-        self.anneal_rw, ms = qb.autotune_anneal_ell(b, self.P.ell_width, self.tiles, self.F0, self.y0, self.thr,
-                                                    self.R, self.seed ^ 0x5A5A, 0, self.B, reps=reps, stream=s)
+        if self.sparse:
+            self.anneal_rw, ms = qb.autotune_anneal_ell(b, self.P.ell_width, self.tiles, self.F0, self.y0, self.thr,
+                                                        self.R, self.seed ^ 0x5A5A, 0, self.B, reps=reps, stream=s)
+            choice = self.anneal_rw
+        else:
+            choice, ms = qb.autotune_anneal(b, self.tiles, self.F0, self.y0, self.thr, self.R, self.seed ^ 0x5A5A, 0,
+                                            self.B, reps=reps, stream=s)
+        # the plan lives in the batch; the captured iteration is captured again
         self.state.set_variants(self.rankk_variant, self.anneal_rw)
-        return self.anneal_rw, ms
+        return choice, ms
 
     def run(self, iters: int, patience: int = 0, graph: bool = True):
         """init() and up to ``iters`` outer iterations (qb_iterate, by default

@@ -461,6 +461,93 @@ def test_anneal_accept_counts_match_oracle(R):
         assert (ah[q * R:(q + 1) * R] == no).all(), (q, mm, ah[q * R:(q + 1) * R], no)
 
 
+PLANS = [
+    dict(),
+    dict(kernel=[4, 4, 4, 4, 4]),
+    dict(kernel=[2, 2, 2, 2, 2]),
+    dict(kernel=[1, 3, 3, 3, 3]),
+    dict(kernel=[0, 4, 3, 2, 1], persistent=1, wgs_per_cu=1),
+    dict(kernel=[0, 4, 4, 0, 3], persistent=1, wgs_per_cu=2, lpt=0),
+    dict(persistent=1, wgs_per_cu=4, depth=16, sleep_after=0),
+    dict(persistent=1, wgs_per_cu=1, depth=32, lpt=0),
+]
+
+
+@pytest.mark.parametrize("int8,R", [(True, 1), (True, 3), (False, 1)])
+def test_anneal_plans_are_result_invariant(int8, R):
+    """Every plan of the annealer (kernel per size class, persistent job queue
+    with its grid and order, consumers' loads in flight, polling) gives the
+    oracle's Y and e on a batch with every size class, the queue taken in
+    LPT order or in job order."""
+    n, z, sizes, nsw = 2600, 3, [1024, 512, 256, 100, 40], 6
+    say("anneal plans", int8, R)
+    Q = inputs.dense_qubo(n, 0.4, 171) if int8 else wide_qubo(n, 171, 0.4)
+    X = inputs.random_solutions(z, n, 172)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, sizes, 173)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    tiles = torch.zeros(b.tile_elems, dtype=qb().tile_dtype(P), device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
+    thr = oracle.thresholds(Q, nsw)
+    thr_d = torch.as_tensor(thr, device=DEV)
+    ref = []
+    for q in range(b.J):
+        Tq, c, F, yy = oracle.extract(Q, X[sol[q]], H[sol[q]], idx[b.off[q]:b.off[q + 1]])
+        ref.append(oracle.anneal(Tq, F, yy, thr, R, 31, 5 + q, 10))
+    Y = torch.zeros(b.total * R, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J * R, dtype=torch.int64, device=DEV)
+    for plan in PLANS:
+        b.set_plan(sleep_after=16, depth=8, kernel=[0] * 5, persistent=0, wgs_per_cu=1, lpt=1)
+        b.set_plan(**plan)
+        Y.fill_(7)
+        e.fill_(123)
+        qb().anneal(b, tiles, F0, y0, thr_d, R, 31, 5, Y, e, 10)
+        Yh, eh = Y.cpu().numpy(), e.cpu().numpy()
+        for q in range(b.J):
+            mm = int(b.off[q + 1] - b.off[q])
+            Yo, eo = ref[q]
+            assert (Yh[b.off[q] * R:(b.off[q] + mm) * R].reshape(R, mm) == Yo).all(), (plan, q, mm)
+            assert (eh[q * R:(q + 1) * R] == eo).all(), (plan, q, mm)
+    with pytest.raises(qb().QBError):
+        b.set_plan(kernel=[9, 0, 0, 0, 0])
+    with pytest.raises(qb().QBError):
+        b.set_plan(kernel=[0] * 5, wgs_per_cu=0)
+
+
+def test_plan_autotuner_checks_every_plan_and_keeps_parity():
+    """qb_autotune_anneal on a mixed batch: it returns a plan (left set on the
+    batch) whose results are the oracle's."""
+    n, z, sizes, nsw = 3000, 8, [1024, 512, 256, 128], 5
+    Q = inputs.dense_qubo(n, 0.6, 181)
+    X = inputs.random_solutions(z, n, 182)
+    H = oracle.field(Q, X)
+    sol, m, idx = _jobs(n, z, sizes, 183)
+    P = qb().Problem(dq(Q))
+    b = qb().Batch(n, z, sol, m)
+    b.set_idx(idx)
+    tiles = torch.zeros(b.tile_elems, dtype=torch.int8, device=DEV)
+    F0 = torch.zeros(b.total, dtype=torch.int32, device=DEV)
+    y0 = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    qb().extract(P, b, torch.as_tensor(X, device=DEV), torch.as_tensor(H, device=DEV), tiles, F0, y0)
+    thr = oracle.thresholds(Q, nsw)
+    thr_d = torch.as_tensor(thr, device=DEV)
+    plan, ms = qb().autotune_anneal(b, tiles, F0, y0, thr_d, 1, 41, 0, 10, reps=1)
+    assert ms > 0 and plan == qb().plan_dict(b.plan())
+    Y = torch.zeros(b.total, dtype=torch.uint8, device=DEV)
+    e = torch.zeros(b.J, dtype=torch.int64, device=DEV)
+    qb().anneal(b, tiles, F0, y0, thr_d, 1, 41, 2, Y, e, 10)
+    Yh, eh = Y.cpu().numpy(), e.cpu().numpy()
+    for q in range(b.J):
+        mm = int(b.off[q + 1] - b.off[q])
+        Tq, c, F, yy = oracle.extract(Q, X[sol[q]], H[sol[q]], idx[b.off[q]:b.off[q + 1]])
+        Yo, eo = oracle.anneal(Tq, F, yy, thr, 1, 41, 2 + q, 10)
+        assert (Yh[b.off[q]:b.off[q] + mm] == Yo[0]).all() and eh[q] == eo[0], (plan, q)
+
+
 def test_threshold_table_matches_oracle():
     for nsw, B, tmax, tmin in [(1, 10, 100.0, 1.0), (200, 10, 2047.3, 8.2), (37, 4, 5.0, 0.0),
                                (3, 16, 1e9, 1e8)]:
@@ -696,10 +783,32 @@ def test_autotuner_picks_a_variant_and_keeps_parity():
     S.init()
     v, ms = S.autotune()
     assert v in (1, 2) and ms > 0
+    plan, ms2 = S.autotune_anneal(reps=1)
+    assert ms2 > 0 and len(plan["kernel"]) == 5
     H0 = S.H.clone()
     S.stream.synchronize()
     assert (S.H.cpu().numpy() == oracle.field(Q, S.X.cpu().numpy())).all()
     assert (H0 == S.H).all()
+
+
+def test_trajectory_with_an_autotuned_plan_matches_oracle():
+    """Alg. 2 with every size class and the annealer plan the autotuner
+    chose (a persistent queue or not, any kernel per class): the oracle's
+    trajectory."""
+    from paper_2502_13947_amd.solver import Solver
+    n, z, iters, B = 1500, 6, 3, 10
+    Q = inputs.dense_qubo(n, 0.3, 191)
+    thr = oracle.thresholds(Q, 20, B)
+    job_m = np.tile([512, 256, 128, 100], (z, 1)).astype(np.int32)
+    kw = dict(z=z, seed=29, job_m=job_m, init_m=0, thr_init=thr, thr=thr, B=B, R=1, alpha=5 * n,
+              tenure=max(1, n // 150))
+    S = Solver(dq(Q), **kw)
+    S.init()
+    S.autotune_anneal(reps=1)
+    trace = S.run(iters)
+    ref = oracle.run(Q, iters=iters, **kw)
+    assert trace == list(ref["trace"])
+    assert (S.X.cpu().numpy() == ref["X"]).all() and (S.H.cpu().numpy() == ref["H"]).all()
 
 
 # ----------------------------------------------------------------------------- a3' / a10
