@@ -80,14 +80,27 @@ qb_status qb_problem_create_dense(qb_problem *out, int32_t n, const int16_t *Q_d
  * [nnz]; a diagonal entry is optional, a stored zero is allowed.  Checks the
  * structure (QB_E_ARG), symmetry (every (i, j, v) has (j, i, v):
  * QB_E_NOT_SYMMETRIC) and the dense form's range bound (QB_E_RANGE).  The
- * handle COPIES what it needs -- the off-diagonal entries as a column-major
- * ELL of width ell_width (word (v << 16) | j at [t][i]), the diagonal and eta
+ * handle COPIES what it needs -- the off-diagonal entries as a row-major
+ * ELL of width ell_width (word (v << 16) | j at [i][t]), the diagonal and eta
  * -- so the caller's arrays may be released once the call returns.
  * Synchronises `stream`.  n in [1, 65535]. */
 qb_status qb_problem_create_csr(qb_problem *out, int32_t n, const int32_t *rowptr_d, const int32_t *col_d,
                                 const int16_t *val_d, void *stream);
 void qb_problem_destroy(qb_problem P);
 qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info_h);
+/* Which kernel qb_tabu runs on a sparse problem (all give the same result):
+ * QB_TABU_AUTO the tree kernel where it fits, else the lane kernel;
+ * QB_TABU_LANES one 1024-thread workgroup per solution holding the move
+ * values in registers, an argmin over all of them per step (n <= 20480);
+ * QB_TABU_TREE one wave per solution with the move values in an LDS min-tree
+ * of 64-leaf nodes, repairing per step only the nodes the flip touches
+ * (n <= 25536 by LDS, ell_width <= 64, (2 dmax + 1) 2^ceil(log2 n) < 2^32
+ * with dmax = max|Q_kk| + 2 max eta; qb_tabu returns QB_E_CAPACITY or
+ * QB_E_RANGE beyond).  QB_E_ARG for a dense problem or another value. */
+#define QB_TABU_AUTO 0
+#define QB_TABU_LANES 1
+#define QB_TABU_TREE 2
+qb_status qb_problem_set_tabu_variant(qb_problem P, int32_t variant);
 /* Copies eta (int64 [n]) into eta_d. */
 qb_status qb_problem_eta(qb_problem P, int64_t *eta_d, void *stream);
 /* Synchronises `stream` and returns QB_E_STATE if any kernel latched an error

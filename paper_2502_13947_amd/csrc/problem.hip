@@ -432,6 +432,13 @@ extern "C" qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info)
     return QB_OK;
 }
 
+extern "C" qb_status qb_problem_set_tabu_variant(qb_problem P, int32_t variant)
+{
+    if (!P || !P->sparse || variant < QB_TABU_AUTO || variant > QB_TABU_TREE) return QB_E_ARG;
+    P->tabu_variant = variant;
+    return QB_OK;
+}
+
 extern "C" qb_status qb_problem_eta(qb_problem P, int64_t *eta_d, void *stream)
 {
     if (!P || !eta_d) return QB_E_ARG;

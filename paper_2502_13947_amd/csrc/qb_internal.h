@@ -36,6 +36,7 @@ struct qb_problem_s {
     int ellw = 0;                 // padded to a multiple of 4
     uint32_t *ell = nullptr;      // owned, device [n * ellw]
     int32_t *ecnt = nullptr;      // owned, device [n]
+    int tabu_variant = 0;         // QB_TABU_* (sparse problems)
 };
 
 // ELL word of a sparse entry and its two halves.

@@ -344,9 +344,16 @@ __global__ void __launch_bounds__(TB) k_tabu_sp(const uint32_t *__restrict__ ell
 
 }  // namespace
 
+qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha, int tenure,
+                              int asp, int32_t *T, int32_t *LF, hipStream_t s);
+
 qb_status qb_tabu_sparse_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha, int tenure,
                                 int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
+    if (P->tabu_variant != QB_TABU_LANES) {
+        const qb_status rc = qb_tabu_tree_launch(P, z, X, H, E, alpha, tenure, asp, T, LF, s);
+        if ((rc != QB_E_CAPACITY && rc != QB_E_RANGE) || P->tabu_variant == QB_TABU_TREE) return rc;
+    }
     const int ept = qb_tabu_sp_ept(P->n);
     if (ept == 0) return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;

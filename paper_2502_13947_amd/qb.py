@@ -67,6 +67,7 @@ class StateBuffers(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in STATE_BUFFERS]
 
 
+TABU_AUTO, TABU_LANES, TABU_TREE = 0, 1, 2
 ANNEAL_AUTO, ANNEAL_MULTI_WAVE, ANNEAL_ONE_WAVE, ANNEAL_ONE_WAVE_REG, ANNEAL_MULTI_WAVE_GLOBAL = 0, 1, 2, 3, 4
 RUN_RANDOM_SELECT, RUN_NO_IM, RUN_INIT_JACOBI, RUN_WB_NOT_WORSE, RUN_LEARNED = 1, 2, 4, 8, 16
 
@@ -84,6 +85,7 @@ SIGNATURES = {
     "qb_problem_destroy": (None, [_P]),
     "qb_problem_get_info": (_I32, [_P, ctypes.POINTER(ProblemInfo)]),
     "qb_problem_eta": (_I32, [_P, _P, _P]),
+    "qb_problem_set_tabu_variant": (_I32, [_P, _I32]),
     "qb_check": (_I32, [_P, _P]),
     "qb_init_solutions": (_I32, [_I32, _I32, _U64, _P, _P]),
     "qb_field": (_I32, [_P, _I32, _P, _P, _P]),
@@ -222,6 +224,11 @@ class Problem:
             return torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a).to(
                 device=device, dtype=dt).contiguous()
         return cls(stream=stream, csr=(dev(rowptr, torch.int32), dev(col, torch.int32), dev(val, torch.int16)))
+
+    def set_tabu_variant(self, variant: int):
+        """Sparse problems: which Tabu kernel qb_tabu runs (TABU_AUTO,
+        TABU_LANES or TABU_TREE)."""
+        _chk(lib().qb_problem_set_tabu_variant(self.h, int(variant)), "qb_problem_set_tabu_variant")
 
     def eta(self, stream=None) -> torch.Tensor:
         out = torch.empty(self.n, dtype=torch.int64, device=self.device)

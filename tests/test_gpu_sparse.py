@@ -144,20 +144,38 @@ def test_sparse_field_energy_rankk(case, z):
     ("w:2900", 1, 4000, 19, True),
     ("t:100x200", 1, 3000, 133, True),   # n = 20000, twenty per thread
     ("d:1500", 2, 3000, 10, True),       # rows of ~120 entries: wider than a wave
+    ("v:2900", 2, 4000, 19, True),       # weights of +-300 with a diagonal (the tree's 16-bit moves)
+    ("t:1x1", 2, 20, 1, True),           # n = 1: a single variable, always the winner
+    ("t:9x7", 4, 400, 70, True),         # tenure beyond n: everything tabu, argmin over all
+    ("t:9x7", 3, 400, 0, False),         # tenure 0: nothing is ever tabu
 ])
-def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp):
-    say("sparse tabu", case, z, alpha, tenure, asp)
+@pytest.mark.parametrize("variant", ["lanes", "tree"])
+def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):
+    say("sparse tabu", case, z, alpha, tenure, asp, variant)
     if case.startswith("t:"):
         r, c = (int(v) for v in case[2:].split("x"))
         n, csr, Q = torus(r, c, 8)
     elif case.startswith("w:"):
         n, csr, Q = sparse_wide(int(case[2:]), 0.01, 9)
+    elif case.startswith("v:"):
+        n, csr, Q = sparse_wide(int(case[2:]), 0.01, 9, lo=-300, hi=300)
     else:
         n, csr, Q = sparse_wide(int(case[2:]), 0.08, 9, lo=-100, hi=100)
     X = inputs.random_solutions(z, n, 10)
     H = field_csr(csr, X)
     E = oracle.energy(X, H)
     P = csr_problem(csr)
+    dmax = P.qmax + 2 * P.eta_max
+    if variant == "tree" and (P.ell_width > 64 or 2 * dmax > 0xFFFF or
+                              (2 * dmax + 1) << max(0, (n - 1).bit_length()) >= 2**32):
+        # the tree kernel reads a row with one lane per entry and keeps
+        # move values in 16 bits
+        P.set_tabu_variant(qb().TABU_TREE)
+        with pytest.raises(qb().QBError) as ei:
+            qb().tabu(P, dev(X), dev(H), dev(E), 1, tenure, asp, dev(H), dev(H))
+        assert ei.value.status == (-5 if P.ell_width > 64 else -3)
+        return
+    P.set_tabu_variant(qb().TABU_TREE if variant == "tree" else qb().TABU_LANES)
     Xd, Hd, Ed = dev(X), dev(H), dev(E)
     T = torch.full((z, n), 7, dtype=torch.int32, device=DEV)     # overwritten
     LF = torch.full((z, n), 7, dtype=torch.int32, device=DEV)
@@ -172,15 +190,32 @@ def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp):
 
 
 def test_sparse_tabu_capacity():
-    n, csr, Q = torus(103, 200, 11)             # n = 20600 > 20 x 1024
+    # n = 20600: beyond the lane kernel (20 x 1024), within the tree's LDS
+    n, csr, Q = torus(103, 200, 11)
     P = csr_problem(csr)
-    z = 1
-    X = torch.zeros((z, n), dtype=torch.uint8, device=DEV)
-    H = torch.zeros((z, n), dtype=torch.int32, device=DEV)
-    E = torch.zeros(z, dtype=torch.int64, device=DEV)
+    z = 2
+    X = inputs.random_solutions(z, n, 12)
+    H = field_csr(csr, X)
+    E = oracle.energy(X, H)
     T = torch.zeros((z, n), dtype=torch.int32, device=DEV)
+    P.set_tabu_variant(qb().TABU_LANES)
     with pytest.raises(qb().QBError) as ei:
-        qb().tabu(P, X, H, E, 10, 3, True, T, T.clone())
+        qb().tabu(P, dev(X), dev(H), dev(E), 10, 3, True, T, T.clone())
+    assert ei.value.status == -5
+    P.set_tabu_variant(qb().TABU_AUTO)
+    Xd, Hd, Ed, LF = dev(X), dev(H), dev(E), T.clone()
+    qb().tabu(P, Xd, Hd, Ed, 2000, 50, True, T, LF)
+    for p in range(z):
+        x, h, ov, To, LFo = oracle.tabu(Q, X[p], H[p], int(E[p]), 2000, 50, True)
+        assert (Xd[p].cpu().numpy() == x).all() and (Hd[p].cpu().numpy() == h).all(), p
+        assert int(Ed[p].item()) == ov and (T[p].cpu().numpy() == To).all() and (LF[p].cpu().numpy() == LFo).all()
+    # n = 26000: beyond the tree's LDS as well
+    n2, csr2, _ = torus(130, 200, 11)
+    P2 = csr_problem(csr2)
+    z2 = torch.zeros((1, n2), dtype=torch.int32, device=DEV)
+    with pytest.raises(qb().QBError) as ei:
+        qb().tabu(P2, torch.zeros((1, n2), dtype=torch.uint8, device=DEV), z2, torch.zeros(1, dtype=torch.int64,
+                  device=DEV), 10, 3, True, z2.clone(), z2.clone())
     assert ei.value.status == -5
 
 
