@@ -5,30 +5,35 @@
 // flip changes only a handful of move values: the flipped variable's own
 // (negated), its neighbours' (the O(degree) update of the Tabu section) and
 // the tabu state of the variable whose tenure runs out.  So instead of an
-// argmin over all n values per step, the kernel keeps the move values in
-// LDS under one level of 64-leaf nodes and repairs only the nodes a step
-// touches.
+// argmin over all n values per step, the kernel keeps the move values of the
+// free variables under one level of 64-leaf nodes in LDS and repairs only
+// the nodes a step touches, while the few tabu variables (about `tenure` of
+// them) sit in slots held in registers.
 //
-// Layout per solution (one 64-lane workgroup, all state in LDS):
-//   dl[j]  move value D_j + bias (uint16; bias bounds |D|),
-//   Ul[j]  the last step at which j is tabu (0: free),
-//   xw, pw bit vectors of x and of "flipped since the last improvement",
-//   per node q (leaves 64q .. 64q+63): the least key over its free leaves,
-//   the least key over its tabu leaves and the least Ul over its tabu
-//   leaves (the step after which one of them becomes free).
+// Layout per solution (one 64-lane workgroup):
+//   dl[j]   move value D_j + bias (uint16 in LDS; bias bounds |D|),
+//   Ul[j]   the last step at which j is tabu (0: free; LDS),
+//   xw, pw  bit vectors of x and of "flipped since the last improvement",
+//   nf[q]   the least key over the free leaves of node q (leaves 64q..64q+63),
+//   slots   S (variable, last tabu step) pairs per lane for tabu variables,
+//   ob      bit vector of tabu variables that found no slot (normally empty;
+//           scanned at every step while it is not, so the result never
+//           depends on the slot count).
 // A key is (D_j + bias) << IB | j, so the unsigned minimum is the least move
-// value, then the lowest index, exactly the oracle's tie rule.
+// value, then the lowest index: the oracle's tie rule.
 //
-// Step t: the wave reads every node (a few per lane) and takes the two
-// minima; the smallest tabu key is allowed when it reaches OV + D < OV_min
-// (aspiration), and when nothing is free and nothing aspirates it wins
-// anyway (the argmin over all).  The winner's ELL row is requested from
-// memory at once; while it is in flight the wave rewrites the winner's leaf
-// and recomputes its node and every node whose least tabu step has passed.
-// Then each lane with a neighbour c updates D_c in place: a key that fell
-// only needs an LDS atomic minimum on its node, a key that rose is a repair
-// only when it was its node's minimum.  Every node is exact for step t+1
-// when the step ends.
+// Step t: the least free key is the minimum over the nodes and over the
+// slots whose tenure ran out at t (they rejoin the tree with an LDS atomic
+// minimum); the least tabu key comes from the remaining slots, each reading
+// its variable's current move value.  The smallest tabu key is allowed when
+// it reaches OV + D < OV_min (aspiration); when nothing is free and nothing
+// aspirates it wins anyway (the argmin over all).  The winner's ELL row is
+// requested from memory at once; while it is in flight the wave rewrites the
+// winner's leaf, moves it into a slot when it becomes tabu and recomputes its
+// node.  Then each lane with a neighbour c updates D_c in place: for a free
+// c a key that fell needs only an atomic minimum on its node, a key that
+// rose is a node repair only when it was the node's minimum; a tabu c needs
+// nothing, its slot reads the new value at the next step.
 #include "qb_internal.h"
 
 namespace {
@@ -36,86 +41,75 @@ namespace {
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int TT_MAX_NR = 8;   // nodes per lane: n <= 64 * 64 * 8
 
-// Wave minimum left in lane 63 (the row minima by quad and mirror moves,
-// then the row broadcasts); the other lanes hold partial minima.
-__device__ __forceinline__ uint32_t min_to63(uint32_t v)
+// Wave minimum, returned uniform: the row minima by quad and mirror moves,
+// then the row broadcasts leave the minimum in lane 63.
+__device__ __forceinline__ uint32_t min_uniform(uint32_t a)
 {
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xA, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xC, 0xF, false));
-    return v;
+    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x140, 0xF, 0xF, false));   // row_mirror
+    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)a, 0x142, 0xA, 0xF, false));  // row_bcast 15
+    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)a, 0x143, 0xC, 0xF, false));  // row_bcast 31
+    return (uint32_t)__builtin_amdgcn_readlane((int)a, 63);
 }
 
-// Two wave minima at once (the steps interleaved), returned uniform.
-__device__ __forceinline__ void min2_uniform(uint32_t &a, uint32_t &b)
+// Wave sum, uniform (the overflow path only).
+__device__ __forceinline__ int wave_sum(int v)
 {
-#define TT_STEP(CTL, RM, ID)                                                                     \
-    a = min(a, (uint32_t)__builtin_amdgcn_update_dpp((ID), (int)a, CTL, RM, 0xF, false));       \
-    b = min(b, (uint32_t)__builtin_amdgcn_update_dpp((ID), (int)b, CTL, RM, 0xF, false));
-    TT_STEP(0xB1, 0xF, 0)
-    TT_STEP(0x4E, 0xF, 0)
-    TT_STEP(0x141, 0xF, 0)
-    TT_STEP(0x140, 0xF, 0)
-    TT_STEP(0x142, 0xA, -1)
-    TT_STEP(0x143, 0xC, -1)
-#undef TT_STEP
-    a = (uint32_t)__builtin_amdgcn_readlane((int)a, 63);
-    b = (uint32_t)__builtin_amdgcn_readlane((int)b, 63);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 struct TreeLds {
     int32_t *Ul;
-    uint2 *nd;       // (least free key, least tabu key) per node, NR * 64 slots
-    uint32_t *ne;    // least Ul over the node's tabu leaves, NR * 64 slots
+    uint32_t *nf;    // NR * 64 slots, NONE past the last node
     uint32_t *xw;
     uint32_t *pw;
+    uint32_t *ob;
+    uint32_t *dump;  // 64 words: where the lanes that must not store a value store it
     uint16_t *dl;
 };
 
-// Slots past the last node hold empty nodes, so every lane reads its NR
-// slots unconditionally.
 __device__ __forceinline__ TreeLds tree_lds(uint32_t *sm, int NN, int NR)
 {
     const int NP = NN << 6, NXW = NP >> 5;
     TreeLds L;
     L.Ul = (int32_t *)sm;
-    L.nd = (uint2 *)(sm + NP);
-    L.ne = sm + NP + 2 * 64 * NR;
-    L.xw = L.ne + 64 * NR;
+    L.nf = sm + NP;
+    L.xw = L.nf + 64 * NR;
     L.pw = L.xw + NXW;
-    L.dl = (uint16_t *)(L.pw + NXW);
+    L.ob = L.pw + NXW;
+    L.dump = L.ob + NXW;
+    L.dl = (uint16_t *)(L.dump + 64);
     return L;
 }
 
-// Node q from its leaves, tabu meaning "Ul > t" (the state at step t + 1).
+// A store of a uniform value by one lane without a branch: the other lanes
+// store into their own word of the dump area (so no two lanes meet in a bank).
+template <typename T>
+__device__ __forceinline__ T *one_lane(const TreeLds &L, T *addr, int lane, int writer)
+{
+    return lane == writer ? addr : reinterpret_cast<T *>(L.dump + lane);
+}
+
+// nf[q] from its leaves, free meaning Ul <= t (the state at step t + 1).
 __device__ __forceinline__ void recompute(const TreeLds &L, int q, int t, int n, int IB, int lane)
 {
     const int j = (q << 6) + lane;
     const uint32_t d = L.dl[j];
     const int32_t u = L.Ul[j];
-    uint32_t f = NONE, g = NONE, e = NONE;
-    if (j < n) {
-        const uint32_t key = (d << IB) | (uint32_t)j;
-        if (u > t) {
-            g = key;
-            e = (uint32_t)u;
-        } else {
-            f = key;
-        }
-    }
-    f = min_to63(f);
-    g = min_to63(g);
-    e = min_to63(e);
-    if (lane == 63) {
-        L.nd[q] = make_uint2(f, g);
-        L.ne[q] = e;
-    }
+    uint32_t f = (j < n && u <= t) ? ((d << IB) | (uint32_t)j) : NONE;
+    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false));
+    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x4E, 0xF, 0xF, false));
+    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x141, 0xF, 0xF, false));
+    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x140, 0xF, 0xF, false));
+    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)f, 0x142, 0xA, 0xF, false));
+    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)f, 0x143, 0xC, 0xF, false));
+    *one_lane(L, L.nf + q, lane, 63) = f;
 }
 
-template <int NR>
+template <int NR, int S>
 __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ ell, int W,
                                                   const int32_t *__restrict__ diag, int n,
                                                   uint8_t *__restrict__ X, int32_t *__restrict__ H,
@@ -146,36 +140,77 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         if (lane < 2) {
             L.xw[(j0 >> 5) + lane] = lane ? (uint32_t)(bx >> 32) : (uint32_t)bx;
             L.pw[(j0 >> 5) + lane] = 0u;
+            L.ob[(j0 >> 5) + lane] = 0u;
         }
     }
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        L.nd[lane + 64 * r] = make_uint2(NONE, NONE);
-        L.ne[lane + 64 * r] = NONE;
-    }
+    for (int r = 0; r < NR; ++r) L.nf[lane + 64 * r] = NONE;
     __syncthreads();
     for (int q = 0; q < NN; ++q) recompute(L, q, 0, n, IB, lane);
     __syncthreads();
 
+    int sj[S], su[S];   // tabu slots: variable (-1: empty) and its last tabu step
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        sj[s] = -1;
+        su[s] = 0;
+    }
+    int ovf = 0;        // tabu variables outside the slots (their bits in ob)
     int64_t OV = E[p];
-    int64_t gap = 0;   // OV - OV_min, never negative
+    int64_t gap = 0;    // OV - OV_min, never negative
 
     for (int step = 1; step <= alpha; ++step) {
-        // the least free key and the least tabu key over all nodes
-        uint32_t fm = NONE, tm = NONE;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const uint2 v = L.nd[lane + 64 * r];
-            fm = min(fm, v.x);
-            tm = min(tm, v.y);
-        }
-        min2_uniform(fm, tm);
-        // a tabu key aspirates when D < OV_min - OV = -gap
+        // a tabu key k aspirates when D < OV_min - OV = -gap, that is k < tbk
         uint32_t tbk = 0;
         if (asp && gap < (int64_t)bias) tbk = (bias - (uint32_t)gap) << IB;
-        uint32_t best = fm;
-        if (tm < tbk) best = min(best, tm);
-        if (best == NONE) best = tm;   // everything tabu and nothing aspirates
+        // candidates: the free keys (nodes, and slots whose tenure ended:
+        // free at this step) and the tabu keys (the other slots) that
+        // aspirate; tm keeps the least tabu key for the case where nothing
+        // is free and nothing aspirates
+        uint32_t fm = NONE, tm = NONE;
+        uint32_t nv[NR], dv[S];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) nv[r] = L.nf[lane + 64 * r];
+#pragma unroll
+        for (int s = 0; s < S; ++s) dv[s] = L.dl[max(sj[s], 0)];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) fm = min(fm, nv[r]);
+        uint32_t sk[S];
+        bool sx[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bool used = sj[s] >= 0;
+            sk[s] = used ? ((dv[s] << IB) | (uint32_t)sj[s]) : NONE;
+            sx[s] = used && su[s] < step;
+            const uint32_t tk = sx[s] ? NONE : sk[s];
+            fm = min(fm, sx[s] ? sk[s] : NONE);
+            fm = min(fm, tk < tbk ? tk : NONE);
+            tm = min(tm, tk);
+        }
+        if (ovf > 0) {
+            // tabu variables without a slot: scan their bits
+            int freed = 0;
+            for (int w = lane; w < NXW; w += 64) {
+                uint32_t keep = L.ob[w];
+                for (uint32_t bits = keep; bits; bits &= bits - 1u) {
+                    const int j = (w << 5) + __builtin_ctz(bits);
+                    const uint32_t key = ((uint32_t)L.dl[j] << IB) | (uint32_t)j;
+                    if (L.Ul[j] < step) {
+                        fm = min(fm, key);
+                        __hip_atomic_fetch_min(L.nf + (j >> 6), key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        keep &= ~(1u << (j & 31));
+                        ++freed;
+                    } else {
+                        tm = min(tm, key);
+                        if (key < tbk) fm = min(fm, key);
+                    }
+                }
+                L.ob[w] = keep;
+            }
+            ovf -= wave_sum(freed);
+        }
+        uint32_t best = min_uniform(fm);
+        if (best == NONE) best = min_uniform(tm);   // everything tabu and nothing aspirates
         const int i = (int)(best & IMASK);
         const uint32_t dib = best >> IB;
 
@@ -183,38 +218,83 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         uint32_t wd = 0u;
         if (lane < W) wd = ell[(int64_t)i * W + lane];
 
-        const uint32_t xword = L.xw[i >> 5];
-        const int32_t Ui = L.Ul[i];
+        // slots whose tenure ended rejoin the tree
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            __hip_atomic_fetch_min(sx[s] ? L.nf + (sj[s] >> 6) : L.dump + lane, sx[s] ? sk[s] : NONE,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            sj[s] = sx[s] ? -1 : sj[s];
+        }
+
+        const uint32_t xword = __builtin_amdgcn_readfirstlane(L.xw[i >> 5]);
+        const uint32_t pword = __builtin_amdgcn_readfirstlane(L.pw[i >> 5]);
+        const int32_t Ui = __builtin_amdgcn_readfirstlane(L.Ul[i]);
         const uint32_t bit = 1u << (i & 31);
-        const int32_t s = (xword & bit) ? -1 : 1;   // h_j += s Q_ji
+        const int32_t sgn = (xword & bit) ? -1 : 1;   // h_j += sgn Q_ji
         const int32_t Un = step + max(max(Ui - (step - 1), 0) + tenure - 1, 0);
         const int32_t dmove = (int32_t)dib - (int32_t)bias;
+        const uint32_t dnew_i = 2u * bias - dib;   // D_i -> -D_i
         OV += dmove;
         gap += dmove;
         const bool improved = gap < 0;
         if (improved) gap = 0;
-        if (lane == 0) {
-            L.Ul[i] = Un;
-            L.dl[i] = (uint16_t)(2u * bias - dib);   // D_i -> -D_i
-            L.xw[i >> 5] = xword ^ bit;
-            if (!improved) __hip_atomic_fetch_xor(L.pw + (i >> 5), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        if (improved)   // x_min is the current x
+        *one_lane(L, L.Ul + i, lane, 0) = Un;
+        *one_lane(L, L.dl + i, lane, 0) = (uint16_t)dnew_i;
+        *one_lane(L, L.xw + (i >> 5), lane, 0) = xword ^ bit;
+        if (improved) {   // x_min is the current x
             for (int w = lane; w < NXW; w += 64) L.pw[w] = 0u;
+        } else {
+            *one_lane(L, L.pw + (i >> 5), lane, 0) = pword ^ bit;
+        }
 
-        recompute(L, i >> 6, step, n, IB, lane);
-        // nodes with a tabu leaf that is free at step + 1
-        uint32_t nev[NR];
+        const bool was_tabu = Ui >= step, now_tabu = Un > step;
+        if (!was_tabu) {
+            if (now_tabu) {
+                // into the first empty slot, else the overflow bits
+                int ps = -1, pl = 0;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) nev[r] = L.ne[lane + 64 * r];
-        uint64_t exm[NR];
+                for (int s = S - 1; s >= 0; --s) {
+                    const uint64_t em = __ballot(sj[s] < 0);
+                    if (em) {
+                        ps = s;
+                        pl = (int)__builtin_ctzll(em);
+                    }
+                }
 #pragma unroll
-        for (int r = 0; r < NR; ++r) exm[r] = __ballot(nev[r] <= (uint32_t)step);
+                for (int s = 0; s < S; ++s) {
+                    const bool mine = s == ps && lane == pl;
+                    sj[s] = mine ? i : sj[s];
+                    su[s] = mine ? Un : su[s];
+                }
+                if (ps < 0) {
+                    if (lane == 0) __hip_atomic_fetch_or(L.ob + (i >> 5), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    ++ovf;
+                }
+            }
+            // i leaves the free set or changes its key
+            recompute(L, i >> 6, step, n, IB, lane);
+        } else {
+            bool inslot = false;
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            for (uint64_t m = exm[r]; m; m &= m - 1) recompute(L, __builtin_ctzll(m) + 64 * r, step, n, IB, lane);
+            for (int s = 0; s < S; ++s) {
+                const bool hit = sj[s] == i;
+                inslot = inslot || hit;
+                su[s] = hit && now_tabu ? Un : su[s];
+                sj[s] = hit && !now_tabu ? -1 : sj[s];
+            }
+            if (!now_tabu) {
+                // tenure 0: free again at once
+                if (__ballot(inslot) == 0ull) {
+                    if (lane == 0) __hip_atomic_fetch_and(L.ob + (i >> 5), ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    --ovf;
+                }
+                if (lane == 0)
+                    __hip_atomic_fetch_min(L.nf + (i >> 6), (dnew_i << IB) | (uint32_t)i, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
 
-        // neighbours: D_c += 2(1 - 2x_c) s Q_ci
+        // neighbours: D_c += 2(1 - 2x_c) sgn Q_ci
         bool need = false;
         int cq = 0;
         if (wd != 0u) {
@@ -224,17 +304,16 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             const uint32_t xcw = L.xw[c >> 5];
             const uint32_t dold = L.dl[c];
             const int32_t uc = L.Ul[c];
-            const uint2 nq = L.nd[cq];
+            const uint32_t nq = L.nf[cq];
             const int32_t sg = ((xcw >> (c & 31)) & 1u) ? -2 : 2;
-            const uint32_t dnew = (uint32_t)((int32_t)dold + sg * s * v);
+            const uint32_t dnew = (uint32_t)((int32_t)dold + sg * sgn * v);
             L.dl[c] = (uint16_t)dnew;
-            const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
-            const bool tb = uc > step;
-            if (knew < kold) {
-                __hip_atomic_fetch_min(tb ? &L.nd[cq].y : &L.nd[cq].x, knew, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-            } else {
-                need = knew > kold && (tb ? nq.y : nq.x) == kold;
+            if (uc <= step) {   // free at step + 1: the tree holds it (or may, when its tenure ends now)
+                const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
+                if (knew < kold)
+                    __hip_atomic_fetch_min(L.nf + cq, knew, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    need = knew > kold && nq == kold;
             }
         }
         for (uint64_t m = __ballot(need); m;) {
@@ -286,12 +365,13 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
 size_t qb_tabu_tree_lds(int n)
 {
     const size_t NN = ((size_t)n + 63) / 64, NP = NN * 64, NR = (NN + 63) / 64;
-    return NP * 4 + NR * 64 * 12 + NP / 32 * 8 + NP * 2;
+    return NP * 4 + NR * 64 * 4 + NP / 32 * 12 + 64 * 4 + NP * 2;
 }
 
 // QB_E_CAPACITY when the problem does not fit the tree kernel (the caller
 // then runs the lane kernel), QB_E_RANGE when its keys cannot hold the move
-// values.
+// values.  Slots per lane: enough for `tenure` tabu variables with a wave's
+// worth to spare, at most eight (beyond, the overflow bits take the rest).
 qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha, int tenure,
                               int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
@@ -302,14 +382,18 @@ qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64
     const int IB = qb_ceil_log2(n);
     if (2 * dmax > 0xFFFF || ((2 * dmax + 1) << IB) >= (int64_t(1) << 32)) return QB_E_RANGE;
     const int NR = (n + 4095) / 4096;
-#define QB_TT(K)                                                                                              \
-    if (NR == K) {                                                                                            \
-        QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_tree<K>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                       (int)lds));                                                            \
-        k_tabu_tree<K><<<z, 64, lds, s>>>(P->ell, P->ellw, P->diag, n, X, H, E, alpha, tenure, asp, T, LF,     \
-                                          (uint32_t)dmax, IB);                                                \
+    const int need = (int)std::min<int64_t>((int64_t)tenure + 64, n);
+    const int S = need <= 128 ? 2 : need <= 256 ? 4 : 8;
+#define QB_TT(K, SL)                                                                                           \
+    if (NR == K && S == SL) {                                                                                  \
+        QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_tree<K, SL>,                                       \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                 \
+        k_tabu_tree<K, SL><<<z, 64, lds, s>>>(P->ell, P->ellw, P->diag, n, X, H, E, alpha, tenure, asp, T, LF, \
+                                              (uint32_t)dmax, IB);                                             \
     }
-    QB_TT(1) QB_TT(2) QB_TT(3) QB_TT(4) QB_TT(5) QB_TT(6) QB_TT(7) QB_TT(8)
+#define QB_TT3(K) QB_TT(K, 2) QB_TT(K, 4) QB_TT(K, 8)
+    QB_TT3(1) QB_TT3(2) QB_TT3(3) QB_TT3(4) QB_TT3(5) QB_TT3(6) QB_TT3(7) QB_TT3(8)
+#undef QB_TT3
 #undef QB_TT
     QB_LAUNCH_CHECK();
     return QB_OK;
