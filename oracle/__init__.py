@@ -93,6 +93,7 @@ def lib():
         L.qbo_mlp_scores.argtypes = [i32, P, P, P, P]
         L.qbo_mlp_grad.argtypes = [P, i32, P, P, P, P, i32]
         L.qbo_adam.argtypes = [i32, P, P, P, P, i32, f32, f32, f32, f32, P]
+        L.qbo_mlp_init.argtypes = [u64, f32, f32, f32, P, P]
         _lib = L
     return _lib
 
@@ -437,6 +438,20 @@ def mlp_grad(Wbf, feat, label, round_acts=True):
     loss = np.zeros(1, np.float64)
     lib().qbo_mlp_grad(_p(Wbf), feat.shape[0], _p(feat), _p(label), _p(g), _p(loss), int(bool(round_acts)))
     return g, float(loss[0])
+
+
+# layer bounds of the initial weights: He-uniform for the ReLU layers,
+# Glorot-uniform for the linear output
+MLP_INIT_BOUNDS = (float(np.float32(np.sqrt(6.0 / 8))), float(np.float32(np.sqrt(6.0 / 64))),
+                   float(np.float32(np.sqrt(3.0 / 64))))
+
+
+def mlp_init(seed, bounds=MLP_INIT_BOUNDS):
+    """FP32 master parameters and their BF16 bits (qbo_mlp_init)."""
+    master = np.zeros(NPARAM, np.float32)
+    W = np.zeros(NPARAM, np.uint16)
+    lib().qbo_mlp_init(int(seed) & (2**64 - 1), *[float(b) for b in bounds], _p(master), _p(W))
+    return master, W
 
 
 def adam(master, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -971,6 +971,35 @@ void qbo_mlp_grad(const uint16_t *W, int B, const uint16_t *feat, const uint8_t 
     if (loss) *loss = L / B;
 }
 
+/* Initial parameters of the selector MLP (the learned selector is not in the
+ * paper; its reading fixes this start).  Weights are uniform on
+ * [-a_l, a_l) per layer (a_1 for W1, a_2 for W2, a_3 for W3, passed as FP32
+ * constants), biases zero:
+ *   u = word (k mod 4) of Philox4x32-10 at counter (k/4, 0, 0, 5<<28), key
+ *       the 64-bit seed, for parameter index k;
+ *   r = (u >> 8) 2^-24, exactly representable;  w = (2r - 1) a_l, one FP32
+ *       rounding;  W = BF16(w), round to nearest even.
+ * Pinned in the tests by its range, zero biases, per-layer spread and the
+ * uniformity of r. */
+void qbo_mlp_init(uint64_t seed, float a1, float a2, float a3, float *master, uint16_t *W)
+{
+    for (int k = 0; k < QBO_NPARAM; ++k) {
+        float a = 0.0f;
+        if (k >= QBO_W1 && k < QBO_B1) a = a1;
+        else if (k >= QBO_W2 && k < QBO_B2) a = a2;
+        else if (k >= QBO_W3 && k < QBO_B3) a = a3;
+        float w = 0.0f;
+        if (a != 0.0f) {
+            const uint32_t u = philox_word((uint32_t)(k >> 2), 0u, 0u, 5u << 28, seed, k & 3);
+            const float r = (float)(u >> 8) * (1.0f / 16777216.0f);
+            const float c = 2.0f * r - 1.0f;
+            w = c * a;
+        }
+        master[k] = w;
+        W[k] = qbo_bf16_rne(w);
+    }
+}
+
 /* Adam (Kingma & Ba) on FP32 master weights, then the BF16 copy. */
 void qbo_adam(int count, float *master, float *m, float *v, const float *grad, int step, float lr,
               float beta1, float beta2, float eps, uint16_t *Wbf)

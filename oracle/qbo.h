@@ -117,6 +117,7 @@ int64_t qbo_score_key(float s);
 void qbo_mlp_scores(int count, const uint16_t *W, const uint16_t *F, float *score, int64_t *K);
 void qbo_mlp_grad(const uint16_t *W, int B, const uint16_t *feat, const uint8_t *label, double *grad,
                   double *loss, int round_acts);
+void qbo_mlp_init(uint64_t seed, float a1, float a2, float a3, float *master, uint16_t *W);
 void qbo_adam(int count, float *master, float *m, float *v, const float *grad, int step, float lr,
               float beta1, float beta2, float eps, uint16_t *Wbf);
 

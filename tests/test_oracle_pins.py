@@ -665,6 +665,34 @@ def test_bf16_rounding_matches_torch_round_to_nearest_even():
     assert (oracle.bf16(vals) == ref).all()
 
 
+def test_mlp_init_pins():
+    """Initial parameters: zero biases, per-layer ranges [-a, a), the uniform
+    draw behind them, BF16 copies by round to nearest even (torch's
+    conversion), determinism in the seed."""
+    import torch
+    from scipy import stats
+    a1, a2, a3 = oracle.MLP_INIT_BOUNDS
+    master, W = oracle.mlp_init(11)
+    assert master.dtype == np.float32 and W.dtype == np.uint16
+    for lo, hi in ((512, 576), (4672, 4736), (4800, 4801)):
+        assert (master[lo:hi] == 0).all() and (W[lo:hi] == 0).all()
+    for (lo, hi), a in (((0, 512), a1), ((576, 4672), a2), ((4736, 4800), a3)):
+        w = master[lo:hi].astype(np.float64)
+        assert w.min() >= -a and w.max() < a
+        r = (w / a + 1) / 2                 # the draw in [0, 1)
+        assert stats.kstest(r, "uniform").pvalue > 1e-4
+        assert abs(w.std() - a / np.sqrt(3)) < 0.15 * a / np.sqrt(3)
+        # exactly 24-bit multiples of 2^-24 before the scale: 2r - 1 = w / a
+        # up to one FP32 rounding of the product
+        assert np.all(np.abs(w - np.round((w / a + 1) * 2**23) / 2**23 * a + a) <= 2 * np.spacing(np.float32(a)))
+    ref = torch.from_numpy(master).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert (W == ref).all()
+    m2, W2 = oracle.mlp_init(11)
+    assert (m2 == master).all() and (W2 == W).all()
+    m3, _ = oracle.mlp_init(12)
+    assert (m3[:512] != master[:512]).mean() > 0.99
+
+
 def test_mlp_forward_closed_forms():
     W = np.zeros(oracle.NPARAM, np.uint16)
     W[4800] = oracle.bf16([0.75])[0]
