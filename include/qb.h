@@ -455,6 +455,14 @@ qb_status qb_mlp_grad(int32_t B, const uint16_t *feat_d, const uint8_t *label_d,
 #define QB_MLP_GRAD_NOALLOC_MAX_B 8192
 qb_status qb_mlp_grad_noalloc(int32_t B, const uint16_t *feat_d, const uint8_t *label_d, const uint16_t *W_d,
                               float *grad_d, float *loss_d, void *stream);
+/* Initial parameters of the MLP (the learned selector is this library's
+ * addition to the method, so its start is this library's choice): weights
+ * uniform on [-a_l, a_l) for W1, W2, W3 (a1, a2, a3), biases zero.
+ * Parameter k draws word (k mod 4) of Philox4x32-10 at counter
+ * (k/4, 0, 0, 5<<28), key (seed lo, seed hi); r = (u >> 8) 2^-24 and
+ * master[k] = (2r - 1) a_l in FP32 (one rounding), W_d[k] = BF16(master[k])
+ * (round to nearest even).  master_d float [4801], W_d uint16 [4801]. */
+qb_status qb_mlp_init(uint64_t seed, float a1, float a2, float a3, float *master_d, uint16_t *W_d, void *stream);
 /* Adam on FP32 master weights (count 4801), then W_d = BF16(master). */
 qb_status qb_mlp_adam(const float *grad_d, float *master_d, float *m_d, float *v_d, int32_t step, float lr,
                       float beta1, float beta2, float eps, uint16_t *W_d, void *stream);

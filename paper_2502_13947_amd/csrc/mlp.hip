@@ -280,6 +280,27 @@ __global__ void k_mlp_reduce(int nblk, const float *__restrict__ partial, const 
     }
 }
 
+// Initial parameters: weights uniform on [-a, a) per layer from Philox
+// words (parameter k: word k mod 4 at counter (k/4, 0, 0, 5<<28)), the
+// 24-bit draw r = (u >> 8) 2^-24 scaled as (2r - 1) a in one FP32 rounding;
+// biases zero; W = BF16(master).
+__global__ void k_mlp_init(uint32_t s0, uint32_t s1, float a1, float a2, float a3, float *__restrict__ master,
+                           uint16_t *__restrict__ Wbf)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NPARAM) return;
+    const float a = k < OB1 ? a1 : (k >= OW2 && k < OB2) ? a2 : (k >= OW3 && k < OB3) ? a3 : 0.0f;
+    float w = 0.0f;
+    if (a != 0.0f) {
+        const uint4 r = qb_philox(make_uint4((uint32_t)k >> 2, 0u, 0u, 5u << 28), s0, s1);
+        const uint32_t u = (k & 3) == 0 ? r.x : (k & 3) == 1 ? r.y : (k & 3) == 2 ? r.z : r.w;
+        const float c = 2.0f * ((float)(u >> 8) * (1.0f / 16777216.0f)) - 1.0f;
+        w = c * a;
+    }
+    master[k] = w;
+    Wbf[k] = bf16_rne(w);
+}
+
 __global__ void k_adam(const float *__restrict__ grad, float *__restrict__ master, float *__restrict__ m,
                        float *__restrict__ v, float lr, float beta1, float beta2, float eps, float c1, float c2,
                        uint16_t *__restrict__ Wbf)
@@ -420,6 +441,16 @@ extern "C" qb_status qb_mlp_grad_noalloc(int32_t B, const uint16_t *feat_d, cons
     float *lossp = partial + (size_t)nblk * NPARAM;
     k_mlp_grad<<<nblk, 64, 0, s>>>(B, feat_d, label_d, W_d, partial, lossp);
     k_mlp_reduce<<<(NPARAM + 255) / 256, 256, 0, s>>>(nblk, partial, lossp, B, grad_d, loss_d);
+    QB_LAUNCH_CHECK();
+    return QB_OK;
+}
+
+extern "C" qb_status qb_mlp_init(uint64_t seed, float a1, float a2, float a3, float *master_d, uint16_t *W_d,
+                                 void *stream)
+{
+    if (!master_d || !W_d) return QB_E_ARG;
+    k_mlp_init<<<(NPARAM + 255) / 256, 256, 0, qb_stream(stream)>>>((uint32_t)seed, (uint32_t)(seed >> 32), a1, a2,
+                                                                     a3, master_d, W_d);
     QB_LAUNCH_CHECK();
     return QB_OK;
 }

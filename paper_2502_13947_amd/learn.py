@@ -39,25 +39,16 @@ def collect_traces(workloads, seeds, iters, device, capacity=None):
     return torch.cat(feats), torch.cat(labels)
 
 
-def init_params(seed=0):
-    """He-style FP32 master weights (zero biases)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    w = np.zeros(qb.NPARAM, np.float32)
-    w[0:512] = rng.normal(0, np.sqrt(2 / 8), 512)
-    w[576:4672] = rng.normal(0, np.sqrt(2 / 64), 4096)
-    w[4736:4800] = rng.normal(0, np.sqrt(1 / 64), 64)
-    return w
-
-
 class Trainer:
     def __init__(self, device, batch=4096, lr=2e-3, seed=0):
         self.dev = device
         self.batch = batch
         self.lr = lr
-        self.master = torch.as_tensor(init_params(seed), device=device)
+        self.master = torch.zeros(qb.NPARAM, dtype=torch.float32, device=device)
+        self.W = torch.zeros(qb.NPARAM, dtype=torch.int16, device=device)
+        qb.mlp_init(seed, self.master, self.W)
         self.m = torch.zeros_like(self.master)
         self.v = torch.zeros_like(self.master)
-        self.W = self.master.to(torch.bfloat16).view(torch.int16).clone()
         self.grad = torch.zeros_like(self.master)
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
         self.work = torch.zeros(qb.mlp_train_workspace(batch), dtype=torch.uint8, device=device)

@@ -121,6 +121,7 @@ SIGNATURES = {
     "qb_mlp_train_workspace": (_SZ, [_I32]),
     "qb_mlp_grad": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _P]),
     "qb_mlp_grad_noalloc": (_I32, [_I32, _P, _P, _P, _P, _P, _P]),
+    "qb_mlp_init": (_I32, [_U64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "qb_mlp_adam": (_I32, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, _P, _P]),
     "qb_graph_begin": (_I32, [_P]),
@@ -583,6 +584,19 @@ def mlp_grad_noalloc(feat, label, W, grad, loss, stream=None):
     B = label.numel()
     _chk(lib().qb_mlp_grad_noalloc(B, _ptr(feat), _ptr(label), _ptr(W), _ptr(grad), _ptr(loss), _stream(stream)),
          "qb_mlp_grad_noalloc")
+
+
+# layer bounds of the initial weights: He-uniform for the ReLU layers,
+# Glorot-uniform for the linear output
+MLP_INIT_BOUNDS = (float(np.float32(np.sqrt(6.0 / 8))), float(np.float32(np.sqrt(6.0 / 64))),
+                   float(np.float32(np.sqrt(3.0 / 64))))
+
+
+def mlp_init(seed, master, W, bounds=MLP_INIT_BOUNDS, stream=None):
+    """Initial FP32 master parameters and their BF16 bits (qb_mlp_init)."""
+    assert master.dtype == torch.float32 and master.numel() == NPARAM and W.numel() == NPARAM
+    _chk(lib().qb_mlp_init(int(seed) & (2**64 - 1), *[float(b) for b in bounds], _ptr(master), _ptr(W),
+                           _stream(stream)), "qb_mlp_init")
 
 
 def mlp_adam(grad, master, m, v, step, lr, W, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

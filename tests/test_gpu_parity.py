@@ -850,6 +850,17 @@ def test_mlp_scores_bit_exact(count):
     assert (K.cpu().numpy() == Ko).all()
 
 
+@pytest.mark.parametrize("seed", [0, 7, 2**63 + 5])
+def test_mlp_init_bit_exact(seed):
+    say("mlp init", seed)
+    master = torch.full((qb().NPARAM,), 3.0, dtype=torch.float32, device=DEV)
+    W = torch.zeros(qb().NPARAM, dtype=torch.int16, device=DEV)
+    qb().mlp_init(seed, master, W)
+    mo, Wo = oracle.mlp_init(seed, qb().MLP_INIT_BOUNDS)
+    assert (master.cpu().numpy().view(np.uint32) == mo.view(np.uint32)).all()
+    assert (W.cpu().numpy().view(np.uint16) == Wo).all()
+
+
 @pytest.mark.parametrize("B", [1, 64, 1000, 4096])
 def test_mlp_gradient_and_adam_vs_oracle(B):
     W = _rand_params(86, 0.2)
