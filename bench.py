@@ -57,13 +57,17 @@ def parse():
     ap.add_argument("--no-init-pass", action="store_true")
     ap.add_argument("--ttt", action="store_true",
                     help="time-to-target: learned vs plain selection (trains the selector first)")
-    ap.add_argument("--ttt-seeds", type=int, default=5)
+    ap.add_argument("--ttt-seeds", type=int, default=3)
     ap.add_argument("--ablation", action="store_true",
                     help="the paper's ablations (full / random selection / no IM) and hyperparameter sweeps "
                          "on n=2500 10%%-dense stand-in instances")
     ap.add_argument("--ablation-seeds", type=int, default=5)
     ap.add_argument("--ablation-epochs", type=int, default=40)
-    ap.add_argument("--ttt-iters", type=int, default=10)
+    ap.add_argument("--ttt-iters", type=int, default=30)
+    ap.add_argument("--ttt-workload", default="c3_n7000_d100",
+                    help="instance shape of the time-to-target comparison (training traces come from other "
+                         "instances of the same shape)")
+    ap.add_argument("--ttt-train-iters", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (counter calibration)")
     return ap.parse_args()
@@ -181,17 +185,19 @@ def run_timed(S, iters, torch):
 
 
 def ttt_main(a):
-    """Time to reach the plain selector's best energy, learned vs plain, on
-    n=5000 / 50% instances never used for training (median over seeds)."""
+    """Time to reach the plain selector's best energy after `ttt_iters`
+    outer iterations, learned vs plain selection, on instances never used for
+    training (median over seeds); and how well each ranks the variables that
+    improved a sub-QUBO on held-out traces (AUC)."""
     import torch
 
     from paper_2502_13947_amd import inputs, learn, qb
     from paper_2502_13947_amd.solver import Solver, default_thresholds
     dev = torch.device("cuda:0")
+    name = a.ttt_workload
     t0 = time.perf_counter()
-    feat1, lab1 = learn.collect_traces(["c1_n2500_d10"], seeds=[1, 2, 3], iters=10, device=dev)
-    feat2, lab2 = learn.collect_traces(["c2_n5000_d50"], seeds=[1, 2], iters=4, device=dev)
-    feat, lab = torch.cat([feat1, feat2]), torch.cat([lab1, lab2])
+    feat, lab = learn.collect_traces([name], seeds=[1, 2], iters=a.ttt_train_iters, device=dev)
+    hfeat, hlab = learn.collect_traces([name], seeds=[3], iters=a.ttt_train_iters, device=dev)
     t_collect = time.perf_counter() - t0
     tr = learn.Trainer(dev, batch=4096, lr=2e-3, seed=0)
     torch.cuda.synchronize()
@@ -201,23 +207,29 @@ def ttt_main(a):
     t_train = time.perf_counter() - t0
     W = tr.weights()
 
-    w = workload("c2_n5000_d50")
+    # selection quality on the held-out traces: the network's score against
+    # the plain aggregate A of Alg. 4 rebuilt from the same features
+    quality = learn.selection_quality(hfeat, hlab, W, dev)
+
+    w = workload(name)
     n, z = w["n"], w["z"]
     rows = []
     for sd in range(a.ttt_seeds):
-        Q = inputs.dense_qubo(n, 0.5, 7000 + sd)
+        Q = inputs.dense_qubo(n, w["density"], 7000 + sd)
         Qd = torch.as_tensor(Q, device=dev)
-        sigma = qb.Problem(Qd).sigma
         thr = default_thresholds(qb.Problem(Qd), w["nsw"])
         kw = dict(z=z, seed=9000 + sd, job_m=w["job_m"], init_m=w["init_m"], thr_init=thr, thr=thr, B=10,
                   R=w["R"], alpha=w["alpha"], tenure=w["tenure"])
+        print(f"[bench] ttt seed {sd}: plain", file=sys.stderr, flush=True)
         P = Solver(Qd, **kw)
         P.init()
         P.autotune()
         tp, bp = run_timed(P, a.ttt_iters, torch)
         target = bp[-1]
         t_plain = next(t for t, b in zip(tp, bp) if b <= target)
+        it_plain = next(i for i, b in enumerate(bp) if b <= target) + 1
         del P
+        print(f"[bench] ttt seed {sd}: learned", file=sys.stderr, flush=True)
         L = Solver(Qd, mlp_W=W, **kw)
         L.init()
         L.autotune()
@@ -226,20 +238,22 @@ def ttt_main(a):
         t_learned = hit[0] if hit else None
         # best energy of the learned run within the plain run's wall-clock
         within = [b for t, b in zip(tl, bl) if t <= tp[-1]]
-        rows.append(dict(seed=sd, target=target, t_plain_ms=t_plain, t_learned_ms=t_learned,
+        rows.append(dict(seed=sd, target=target, t_plain_ms=t_plain, iters_plain=it_plain, t_learned_ms=t_learned,
                          learned_best_at_equal_time=min(within) if within else None,
-                         plain_best=bp[-1], learned_best_2x=bl[-1]))
+                         plain_best=bp[-1], learned_best_2x=bl[-1], plain_trace=bp, learned_trace=bl,
+                         ms_per_iter_plain=tp[-1] / len(tp), ms_per_iter_learned=tl[-1] / len(tl)))
         del L
     ratios = [r["t_learned_ms"] / r["t_plain_ms"] for r in rows if r["t_learned_ms"] is not None]
     out = {
         "metric": "time-to-target-energy, learned vs plain selection",
-        "workload": "n=5000, 50% dense, z=256, one 512-variable sub-QUBO per solution, 1000 sweeps",
+        "workload": name,
         "target": "best energy of the plain selector after %d outer iterations" % a.ttt_iters,
         "seeds": a.ttt_seeds,
         "reached": len(ratios),
         "median_ratio_learned_over_plain": float(np.median(ratios)) if ratios else None,
         "learned_wins_at_equal_time": sum(1 for r in rows if r["learned_best_at_equal_time"] is not None
                                           and r["learned_best_at_equal_time"] <= r["plain_best"]),
+        "selection_quality": quality,
         "training": {"samples": int(lab.numel()), "positive_rate": float(lab.float().mean()),
                      "collect_s": t_collect, "train_s": t_train, "epochs": 3, "batch": 4096,
                      "loss_per_epoch": losses},

@@ -18,10 +18,11 @@ from .solver import Solver, default_thresholds
 
 def collect_traces(workloads, seeds, iters, device, capacity=None):
     """Run the plain method on each (workload, seed) and return all traces as
-    device tensors (features int16-viewed BF16 [N, 8], labels uint8 [N])."""
+    device tensors (features int16-viewed BF16 [N, 8], labels uint8 [N]).
+    A workload is a name of inputs.WORKLOADS or a dict of the same keys."""
     feats, labels = [], []
     for name in workloads:
-        w = dict(inputs.WORKLOADS[name])
+        w = dict(inputs.WORKLOADS[name] if isinstance(name, str) else name)
         n = w["n"]
         for sd in seeds:
             Q = inputs.dense_qubo(n, w["density"], 1000 + 17 * sd + w["qseed"])
@@ -73,3 +74,35 @@ class Trainer:
 
     def weights(self) -> np.ndarray:
         return self.W.cpu().numpy().view(np.uint16).copy()
+
+
+def auc(score, label):
+    """Area under the ROC curve of `score` for the binary `label` (ties count
+    half): how well a score ranks the variables that improved a sub-QUBO."""
+    from scipy.stats import rankdata
+    score = np.asarray(score, np.float64)
+    label = np.asarray(label, bool)
+    npos, nneg = int(label.sum()), int((~label).sum())
+    if npos == 0 or nneg == 0:
+        return None
+    r = rankdata(score)
+    return float((r[label].sum() - npos * (npos + 1) / 2) / (npos * nneg))
+
+
+def plain_aggregate(feat):
+    """A of Alg. 4 with Table 1's weights (1, 1, 0.5), up to a factor, from
+    trace features (5: eta / eta_max, 6: gamma, 7: Delta), as float64."""
+    f = (np.ascontiguousarray(feat).view(np.uint16).reshape(-1, 8).astype(np.uint32) << 16).view(np.float32)
+    return 2.0 * f[:, 5] + 2.0 * f[:, 6] - f[:, 7].astype(np.float64)
+
+
+def selection_quality(feat, label, W, device):
+    """AUC of the network's scores and of the plain aggregate on traces."""
+    Wd = torch.as_tensor(np.ascontiguousarray(W).view(np.int16), device=device)
+    n = label.numel()
+    sc = torch.zeros(n, dtype=torch.float32, device=device)
+    K = torch.zeros(n, dtype=torch.int64, device=device)
+    qb.mlp_score(feat, Wd, K, sc)
+    lab = label.cpu().numpy()
+    return dict(samples=int(n), positive_rate=float(lab.mean()), auc_learned=auc(sc.cpu().numpy(), lab),
+                auc_plain_A=auc(plain_aggregate(feat.cpu().numpy()), lab))

@@ -1,0 +1,84 @@
+"""What the trained selector gains, measured on the GPU: the network is
+trained on the plain method's own improvement traces and then ranks the
+variables of held-out traces (instances and seeds it never saw).  The
+variables that a sub-QUBO improved must rank higher under the network's
+score than under the plain control-parameter aggregate A of Alg. 4 (area
+under the ROC curve), and a run that lets the network pick the IM variables
+must reach at least the plain run's best energy within the same number of
+outer iterations on most of a few fresh instances.
+
+The shape is a smaller cousin of the n = 7000 fully dense workload (several
+sub-QUBOs of mixed sizes per solution, one replica), where the plain
+selector does not plateau within a few iterations."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+SHAPE = dict(n=4000, density=1.0, qseed=41, z=128, k=3, sizes=(128, 256, 512, 1024), nsw=1000, iters=6,
+             init_m=1024, R=1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    from paper_2502_13947_amd import qb
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    qb.lib()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    from paper_2502_13947_amd import learn
+    say("learned: traces")
+    feat, lab = learn.collect_traces([SHAPE], seeds=[1, 2, 3], iters=SHAPE["iters"], device=DEV)
+    hfeat, hlab = learn.collect_traces([SHAPE], seeds=[4, 5], iters=SHAPE["iters"], device=DEV)
+    assert int(lab.sum()) >= 50 and int(hlab.sum()) >= 30, "too few improving traces to judge"
+    say("learned: train", lab.numel(), int(lab.sum()))
+    tr = learn.Trainer(DEV, batch=4096, lr=2e-3, seed=0)
+    tr.fit(feat, lab, epochs=3)
+    return tr.weights(), hfeat, hlab
+
+
+def test_trained_selector_ranks_improving_variables_above_the_plain_keys(trained):
+    from paper_2502_13947_amd import learn
+    W, hfeat, hlab = trained
+    q = learn.selection_quality(hfeat, hlab, W, DEV)
+    say("learned: held-out", q)
+    assert q["auc_learned"] > q["auc_plain_A"] + 0.02
+    assert q["auc_learned"] > 0.8
+
+
+def test_learned_run_reaches_the_plain_best_in_as_many_iterations(trained):
+    from paper_2502_13947_amd import inputs, qb
+    from paper_2502_13947_amd.solver import Solver, default_thresholds
+    W, _, _ = trained
+    iters = 8
+    n, z = SHAPE["n"], SHAPE["z"]
+    wins = 0
+    for sd in range(3):
+        Q = inputs.dense_qubo(n, SHAPE["density"], 7100 + sd)
+        Qd = torch.as_tensor(Q, device=DEV)
+        thr = default_thresholds(qb.Problem(Qd), SHAPE["nsw"])
+        job_m = inputs.job_sizes(z, SHAPE["k"], SHAPE["sizes"], seed=300 + sd)
+        kw = dict(z=z, seed=9100 + sd, job_m=job_m, init_m=SHAPE["init_m"], thr_init=thr, thr=thr, B=10,
+                  R=SHAPE["R"], alpha=5 * n, tenure=max(1, n // 150))
+        best = {}
+        for name, extra in (("plain", {}), ("learned", {"mlp_W": W})):
+            S = Solver(Qd, **kw, **extra)
+            S.init()
+            S.run(iters, graph=False)
+            S.check()
+            best[name] = int(S.ebest.item())
+            # the reported best is the energy of the reported solution
+            xb = S.xbest.cpu().numpy().astype(np.int64)
+            assert best[name] == int(xb @ Q.astype(np.int64) @ xb)
+            del S
+        say("learned: seed", sd, best)
+        wins += best["learned"] <= best["plain"]
+    assert wins >= 2
