@@ -11,9 +11,10 @@
 // them) sit in slots held in registers.
 //
 // Layout per solution (one 64-lane workgroup):
-//   dl[j]   move value D_j + bias (uint16 in LDS; bias bounds |D|),
+//   dl[j]   x_j << 15 | (D_j + bias) (uint16 in LDS; bias bounds |D|, and
+//           2 bias < 2^15),
 //   Ul[j]   the last step at which j is tabu (0: free; LDS),
-//   xw, pw  bit vectors of x and of "flipped since the last improvement",
+//   pw      bit vector of "flipped since the last improvement",
 //   nf[q]   the least key over the free leaves of node q (leaves 64q..64q+63),
 //   slots   S (variable, last tabu step) pairs per lane for tabu variables,
 //   ob      bit vector of tabu variables that found no slot (normally empty;
@@ -28,9 +29,10 @@
 // its variable's current move value.  The smallest tabu key is allowed when
 // it reaches OV + D < OV_min (aspiration); when nothing is free and nothing
 // aspirates it wins anyway (the argmin over all).  The winner's ELL row is
-// requested from memory at once; while it is in flight the wave rewrites the
-// winner's leaf, moves it into a slot when it becomes tabu and recomputes its
-// node.  Then each lane with a neighbour c updates D_c in place: for a free
+// requested from memory at once; while it is in flight the wave reads the
+// winner's node once, takes the winner's x and tabu step from its lane,
+// rewrites the leaf in that lane's registers and recomputes the node from
+// them, and moves the winner into a slot when it becomes tabu.  Then each lane with a neighbour c updates D_c in place: for a free
 // c a key that fell needs only an atomic minimum on its node, a key that
 // rose is a node repair only when it was the node's minimum; a tabu c needs
 // nothing, its slot reads the new value at the next step.
@@ -64,7 +66,6 @@ __device__ __forceinline__ int wave_sum(int v)
 struct TreeLds {
     int32_t *Ul;
     uint32_t *nf;    // NR * 64 slots, NONE past the last node
-    uint32_t *xw;
     uint32_t *pw;
     uint32_t *ob;
     uint32_t *dump;  // 64 words: where the lanes that must not store a value store it
@@ -77,8 +78,7 @@ __device__ __forceinline__ TreeLds tree_lds(uint32_t *sm, int NN, int NR)
     TreeLds L;
     L.Ul = (int32_t *)sm;
     L.nf = sm + NP;
-    L.xw = L.nf + 64 * NR;
-    L.pw = L.xw + NXW;
+    L.pw = L.nf + 64 * NR;
     L.ob = L.pw + NXW;
     L.dump = L.ob + NXW;
     L.dl = (uint16_t *)(L.dump + 64);
@@ -93,13 +93,15 @@ __device__ __forceinline__ T *one_lane(const TreeLds &L, T *addr, int lane, int 
     return lane == writer ? addr : reinterpret_cast<T *>(L.dump + lane);
 }
 
-// nf[q] from its leaves, free meaning Ul <= t (the state at step t + 1).
-__device__ __forceinline__ void recompute(const TreeLds &L, int q, int t, int n, int IB, int lane)
+constexpr uint32_t DMASK = 0x7FFFu;   // the move-value field of a leaf
+
+// nf[q] from leaf values already in registers (lane L: leaf 64q + L), free
+// meaning Ul <= t (the state at step t + 1).
+__device__ __forceinline__ void node_from(const TreeLds &L, int q, uint32_t d, int32_t u, int t, int n, int IB,
+                                          int lane)
 {
     const int j = (q << 6) + lane;
-    const uint32_t d = L.dl[j];
-    const int32_t u = L.Ul[j];
-    uint32_t f = (j < n && u <= t) ? ((d << IB) | (uint32_t)j) : NONE;
+    uint32_t f = (j < n && u <= t) ? (((d & DMASK) << IB) | (uint32_t)j) : NONE;
     f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false));
     f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x4E, 0xF, 0xF, false));
     f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x141, 0xF, 0xF, false));
@@ -107,6 +109,12 @@ __device__ __forceinline__ void recompute(const TreeLds &L, int q, int t, int n,
     f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)f, 0x142, 0xA, 0xF, false));
     f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)f, 0x143, 0xC, 0xF, false));
     *one_lane(L, L.nf + q, lane, 63) = f;
+}
+
+__device__ __forceinline__ void recompute(const TreeLds &L, int q, int t, int n, int IB, int lane)
+{
+    const int j = (q << 6) + lane;
+    node_from(L, q, L.dl[j], L.Ul[j], t, n, IB, lane);
 }
 
 template <int NR, int S>
@@ -132,13 +140,11 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             Tout[ro + j] = 0;
             LFout[ro + j] = 0;
             x = X[ro + j] & 1u;
-            dv = (uint32_t)(diag[j] + (x ? -2 : 2) * H[ro + j] + (int32_t)bias);
+            dv = (uint32_t)(diag[j] + (x ? -2 : 2) * H[ro + j] + (int32_t)bias) | (x << 15);
         }
         L.dl[j] = (uint16_t)dv;
         L.Ul[j] = 0;
-        const uint64_t bx = __ballot(x != 0u);
         if (lane < 2) {
-            L.xw[(j0 >> 5) + lane] = lane ? (uint32_t)(bx >> 32) : (uint32_t)bx;
             L.pw[(j0 >> 5) + lane] = 0u;
             L.ob[(j0 >> 5) + lane] = 0u;
         }
@@ -180,7 +186,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const bool used = sj[s] >= 0;
-            sk[s] = used ? ((dv[s] << IB) | (uint32_t)sj[s]) : NONE;
+            sk[s] = used ? (((dv[s] & DMASK) << IB) | (uint32_t)sj[s]) : NONE;
             sx[s] = used && su[s] < step;
             const uint32_t tk = sx[s] ? NONE : sk[s];
             fm = min(fm, sx[s] ? sk[s] : NONE);
@@ -194,7 +200,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                 uint32_t keep = L.ob[w];
                 for (uint32_t bits = keep; bits; bits &= bits - 1u) {
                     const int j = (w << 5) + __builtin_ctz(bits);
-                    const uint32_t key = ((uint32_t)L.dl[j] << IB) | (uint32_t)j;
+                    const uint32_t key = (((uint32_t)L.dl[j] & DMASK) << IB) | (uint32_t)j;
                     if (L.Ul[j] < step) {
                         fm = min(fm, key);
                         __hip_atomic_fetch_min(L.nf + (j >> 6), key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -226,11 +232,17 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             sj[s] = sx[s] ? -1 : sj[s];
         }
 
-        const uint32_t xword = __builtin_amdgcn_readfirstlane(L.xw[i >> 5]);
-        const uint32_t pword = __builtin_amdgcn_readfirstlane(L.pw[i >> 5]);
-        const int32_t Ui = __builtin_amdgcn_readfirstlane(L.Ul[i]);
+        // the winner's node, read once: its lane gives x_i and U_i, and the
+        // node is recomputed from registers with the winner's leaf rewritten
+        const int qi = i >> 6, li = i & 63;
+        const int jl = (qi << 6) + lane;
+        uint32_t dl_l = L.dl[jl];
+        int32_t ul_l = L.Ul[jl];
+        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dl_l, li);
+        const int32_t Ui = __builtin_amdgcn_readlane(ul_l, li);
+        const uint32_t xi = di >> 15;
         const uint32_t bit = 1u << (i & 31);
-        const int32_t sgn = (xword & bit) ? -1 : 1;   // h_j += sgn Q_ji
+        const int32_t sgn = xi ? -1 : 1;   // h_j += sgn Q_ji
         const int32_t Un = step + max(max(Ui - (step - 1), 0) + tenure - 1, 0);
         const int32_t dmove = (int32_t)dib - (int32_t)bias;
         const uint32_t dnew_i = 2u * bias - dib;   // D_i -> -D_i
@@ -238,14 +250,21 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         gap += dmove;
         const bool improved = gap < 0;
         if (improved) gap = 0;
-        *one_lane(L, L.Ul + i, lane, 0) = Un;
-        *one_lane(L, L.dl + i, lane, 0) = (uint16_t)dnew_i;
-        *one_lane(L, L.xw + (i >> 5), lane, 0) = xword ^ bit;
+        if (lane == li) {
+            dl_l = ((xi ^ 1u) << 15) | dnew_i;
+            ul_l = Un;
+        }
+        *one_lane(L, L.dl + i, lane, li) = (uint16_t)dl_l;
+        *one_lane(L, L.Ul + i, lane, li) = ul_l;
         if (improved) {   // x_min is the current x
             for (int w = lane; w < NXW; w += 64) L.pw[w] = 0u;
         } else {
-            *one_lane(L, L.pw + (i >> 5), lane, 0) = pword ^ bit;
+            __hip_atomic_fetch_xor(one_lane(L, L.pw + (i >> 5), lane, 0), bit, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        // i leaves the free set, changes its key or (tabu before and after)
+        // stays out of it
+        node_from(L, qi, dl_l, ul_l, step, n, IB, lane);
 
         const bool was_tabu = Ui >= step, now_tabu = Un > step;
         if (!was_tabu) {
@@ -271,8 +290,6 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                     ++ovf;
                 }
             }
-            // i leaves the free set or changes its key
-            recompute(L, i >> 6, step, n, IB, lane);
         } else {
             bool inslot = false;
 #pragma unroll
@@ -282,15 +299,10 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                 su[s] = hit && now_tabu ? Un : su[s];
                 sj[s] = hit && !now_tabu ? -1 : sj[s];
             }
-            if (!now_tabu) {
-                // tenure 0: free again at once
-                if (__ballot(inslot) == 0ull) {
-                    if (lane == 0) __hip_atomic_fetch_and(L.ob + (i >> 5), ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    --ovf;
-                }
-                if (lane == 0)
-                    __hip_atomic_fetch_min(L.nf + (i >> 6), (dnew_i << IB) | (uint32_t)i, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (!now_tabu && __ballot(inslot) == 0ull) {
+                // tenure 0: free again at once (the node above took it back)
+                if (lane == 0) __hip_atomic_fetch_and(L.ob + (i >> 5), ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                --ovf;
             }
         }
 
@@ -301,13 +313,13 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             const int c = qb_ell_col(wd);
             const int32_t v = qb_ell_val(wd);
             cq = c >> 6;
-            const uint32_t xcw = L.xw[c >> 5];
-            const uint32_t dold = L.dl[c];
+            const uint32_t lold = L.dl[c];
             const int32_t uc = L.Ul[c];
             const uint32_t nq = L.nf[cq];
-            const int32_t sg = ((xcw >> (c & 31)) & 1u) ? -2 : 2;
+            const int32_t sg = (lold >> 15) ? -2 : 2;
+            const uint32_t dold = lold & DMASK;
             const uint32_t dnew = (uint32_t)((int32_t)dold + sg * sgn * v);
-            L.dl[c] = (uint16_t)dnew;
+            L.dl[c] = (uint16_t)((lold & ~DMASK) | dnew);
             if (uc <= step) {   // free at step + 1: the tree holds it (or may, when its tenure ends now)
                 const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
                 if (knew < kold)
@@ -334,14 +346,15 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     // in Ul, then moved to x_min = x ^ pw by the rows of the differing
     // variables (their own diagonal term and their neighbours)
     for (int j = lane; j < n; j += 64) {
-        const int32_t sg = ((L.xw[j >> 5] >> (j & 31)) & 1u) ? -2 : 2;
-        L.Ul[j] = ((int32_t)L.dl[j] - (int32_t)bias - diag[j]) * sg / 4;
+        const uint32_t lj = L.dl[j];
+        const int32_t sg = (lj >> 15) ? -2 : 2;
+        L.Ul[j] = ((int32_t)(lj & DMASK) - (int32_t)bias - diag[j]) * sg / 4;
     }
     __syncthreads();
     for (int w = lane; w < NXW; w += 64) {
         for (uint32_t bits = L.pw[w]; bits; bits &= bits - 1u) {
             const int j = (w << 5) + __builtin_ctz(bits);
-            const int32_t sg = ((L.xw[w] >> (j & 31)) & 1u) ? -1 : 1;
+            const int32_t sg = (L.dl[j] >> 15) ? -1 : 1;
             __hip_atomic_fetch_add(L.Ul + j, sg * diag[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             for (int t = 0; t < W; ++t) {
                 const uint32_t w2 = ell[(int64_t)j * W + t];
@@ -353,7 +366,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     }
     __syncthreads();
     for (int j = lane; j < n; j += 64) {
-        X[ro + j] = (uint8_t)(((L.xw[j >> 5] ^ L.pw[j >> 5]) >> (j & 31)) & 1u);
+        X[ro + j] = (uint8_t)(((uint32_t)L.dl[j] >> 15) ^ ((L.pw[j >> 5] >> (j & 31)) & 1u));
         H[ro + j] = L.Ul[j];
     }
     if (lane == 0) E[p] = OV - gap;
@@ -365,7 +378,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
 size_t qb_tabu_tree_lds(int n)
 {
     const size_t NN = ((size_t)n + 63) / 64, NP = NN * 64, NR = (NN + 63) / 64;
-    return NP * 4 + NR * 64 * 4 + NP / 32 * 12 + 64 * 4 + NP * 2;
+    return NP * 4 + NR * 64 * 4 + NP / 32 * 8 + 64 * 4 + NP * 2;
 }
 
 // QB_E_CAPACITY when the problem does not fit the tree kernel (the caller
@@ -380,7 +393,7 @@ qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64
     if (P->ellw > 64 || n > 64 * 64 * TT_MAX_NR || lds > 160 * 1024) return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
     const int IB = qb_ceil_log2(n);
-    if (2 * dmax > 0xFFFF || ((2 * dmax + 1) << IB) >= (int64_t(1) << 32)) return QB_E_RANGE;
+    if (2 * dmax > 0x7FFF || ((2 * dmax + 1) << IB) >= (int64_t(1) << 32)) return QB_E_RANGE;
     const int NR = (n + 4095) / 4096;
     const int need = (int)std::min<int64_t>((int64_t)tenure + 64, n);
     const int S = need <= 128 ? 2 : need <= 256 ? 4 : 8;

@@ -166,7 +166,7 @@ def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):
     E = oracle.energy(X, H)
     P = csr_problem(csr)
     dmax = P.qmax + 2 * P.eta_max
-    if variant == "tree" and (P.ell_width > 64 or 2 * dmax > 0xFFFF or
+    if variant == "tree" and (P.ell_width > 64 or 2 * dmax > 0x7FFF or
                               (2 * dmax + 1) << max(0, (n - 1).bit_length()) >= 2**32):
         # the tree kernel reads a row with one lane per entry and keeps
         # move values in 16 bits
