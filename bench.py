@@ -454,8 +454,9 @@ def measure_workload(a, name, steps, warmup, cpu_seconds, headline):
         # compare-select each); the row a step reads is a few dozen bytes
         ops = z * w["alpha"] * n
         ach = ops / t_tabu / 1e12
-        roof = dict(kernel="k_tabu_sp", bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
-                    frac=ach / ALU_PEAK_TOPS, traffic=measured_traffic(name, "k_tabu_sp"),
+        kname = "k_tabu_tree" if S.P.tabu_kernel == qb.TABU_TREE else "k_tabu_sp"
+        roof = dict(kernel=kname, bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s",
+                    frac=ach / ALU_PEAK_TOPS, traffic=measured_traffic(name, kname),
                     algorithmic=f"{z} solutions x {w['alpha']} steps x an argmin over {n} move values",
                     ns_per_step=t_tabu * 1e9 / w["alpha"])
     elif t_tabu >= t_ann:

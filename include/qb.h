@@ -58,6 +58,9 @@ typedef struct {
     double sigma;        /* sqrt(sum_{i != j} Q_ij^2 / n): the typical |dE| scale */
     int32_t sparse;      /* 1 for a problem made by qb_problem_create_csr */
     int32_t ell_width;   /* sparse: most off-diagonal entries in one row (>= 1) */
+    int32_t tabu_kernel; /* what qb_tabu runs under the problem's Tabu variant: 0 the dense
+                            kernel, 1 the sparse lane kernel, 2 the sparse tree kernel
+                            (QB_TABU_*), -1 none (n beyond the kernels' capacity) */
 } qb_problem_info;
 
 const char *qb_status_str(qb_status s);

@@ -429,6 +429,13 @@ extern "C" qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info)
     info->sigma = P->sigma;
     info->sparse = P->sparse;
     info->ell_width = P->ellw;
+    if (!P->sparse) {
+        info->tabu_kernel = P->tabu_ept ? 0 : -1;
+    } else {
+        const bool tree = P->tabu_variant != QB_TABU_LANES && qb_tabu_tree_fits(P) == QB_OK;
+        const bool lanes = P->tabu_variant != QB_TABU_TREE && qb_tabu_sp_ept(P->n) != 0;
+        info->tabu_kernel = tree ? QB_TABU_TREE : lanes ? QB_TABU_LANES : -1;
+    }
     return QB_OK;
 }
 

@@ -111,6 +111,10 @@ static inline __host__ __device__ int qb_tabu_pos(int e, int t, int ept, int esz
     return -1;
 }
 
+// QB_OK when the sparse Tabu tree kernel can run the problem (else
+// QB_E_CAPACITY or QB_E_RANGE).
+qb_status qb_tabu_tree_fits(qb_problem P);
+
 // Sparse Tabu: 1024 threads, EPT variables each (n <= 20480).
 #define QB_TABU_SP_THREADS 1024
 static inline int qb_tabu_sp_ept(int n)

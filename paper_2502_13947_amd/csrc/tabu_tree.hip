@@ -381,6 +381,16 @@ size_t qb_tabu_tree_lds(int n)
     return NP * 4 + NR * 64 * 4 + NP / 32 * 8 + 64 * 4 + NP * 2;
 }
 
+qb_status qb_tabu_tree_fits(qb_problem P)
+{
+    const int n = P->n;
+    if (!P->sparse || P->ellw > 64 || n > 64 * 64 * TT_MAX_NR || qb_tabu_tree_lds(n) > 160 * 1024)
+        return QB_E_CAPACITY;
+    const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
+    if (2 * dmax > 0x7FFF || ((2 * dmax + 1) << qb_ceil_log2(n)) >= (int64_t(1) << 32)) return QB_E_RANGE;
+    return QB_OK;
+}
+
 // QB_E_CAPACITY when the problem does not fit the tree kernel (the caller
 // then runs the lane kernel), QB_E_RANGE when its keys cannot hold the move
 // values.  Slots per lane: enough for `tenure` tabu variables with a wave's
@@ -388,12 +398,12 @@ size_t qb_tabu_tree_lds(int n)
 qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha, int tenure,
                               int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
+    const qb_status fit = qb_tabu_tree_fits(P);
+    if (fit != QB_OK) return fit;
     const int n = P->n;
     const size_t lds = qb_tabu_tree_lds(n);
-    if (P->ellw > 64 || n > 64 * 64 * TT_MAX_NR || lds > 160 * 1024) return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
     const int IB = qb_ceil_log2(n);
-    if (2 * dmax > 0x7FFF || ((2 * dmax + 1) << IB) >= (int64_t(1) << 32)) return QB_E_RANGE;
     const int NR = (n + 4095) / 4096;
     const int need = (int)std::min<int64_t>((int64_t)tenure + 64, n);
     const int S = need <= 128 ? 2 : need <= 256 ? 4 : 8;

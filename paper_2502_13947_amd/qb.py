@@ -33,7 +33,7 @@ class QBError(RuntimeError):
 class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("int8_ok", ctypes.c_int32), ("qmax", ctypes.c_int32),
                 ("eta_max", ctypes.c_int64), ("sigma", ctypes.c_double), ("sparse", ctypes.c_int32),
-                ("ell_width", ctypes.c_int32)]
+                ("ell_width", ctypes.c_int32), ("tabu_kernel", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -216,6 +216,13 @@ class Problem:
         self.n, self.int8_ok, self.qmax = info.n, bool(info.int8_ok), info.qmax
         self.eta_max, self.sigma = info.eta_max, info.sigma
         self.sparse, self.ell_width = bool(info.sparse), int(info.ell_width)
+
+    @property
+    def tabu_kernel(self) -> int:
+        """0 dense kernel, TABU_LANES or TABU_TREE (sparse), -1 none."""
+        info = ProblemInfo()
+        _chk(lib().qb_problem_get_info(self.h, ctypes.byref(info)), "qb_problem_get_info")
+        return int(info.tabu_kernel)
 
     @classmethod
     def from_csr(cls, rowptr, col, val, device, stream=None) -> "Problem":

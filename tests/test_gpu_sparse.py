@@ -171,11 +171,13 @@ def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):
         # the tree kernel reads a row with one lane per entry and keeps
         # move values in 16 bits
         P.set_tabu_variant(qb().TABU_TREE)
+        assert P.tabu_kernel == -1
         with pytest.raises(qb().QBError) as ei:
             qb().tabu(P, dev(X), dev(H), dev(E), 1, tenure, asp, dev(H), dev(H))
         assert ei.value.status == (-5 if P.ell_width > 64 else -3)
         return
     P.set_tabu_variant(qb().TABU_TREE if variant == "tree" else qb().TABU_LANES)
+    assert P.tabu_kernel == (qb().TABU_TREE if variant == "tree" else qb().TABU_LANES)
     Xd, Hd, Ed = dev(X), dev(H), dev(E)
     T = torch.full((z, n), 7, dtype=torch.int32, device=DEV)     # overwritten
     LF = torch.full((z, n), 7, dtype=torch.int32, device=DEV)
