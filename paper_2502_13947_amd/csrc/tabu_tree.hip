@@ -32,10 +32,16 @@
 // requested from memory at once; while it is in flight the wave reads the
 // winner's node once, takes the winner's x and tabu step from its lane,
 // rewrites the leaf in that lane's registers and recomputes the node from
-// them, and moves the winner into a slot when it becomes tabu.  Then each lane with a neighbour c updates D_c in place: for a free
-// c a key that fell needs only an atomic minimum on its node, a key that
-// rose is a node repair only when it was the node's minimum; a tabu c needs
-// nothing, its slot reads the new value at the next step.
+// them, and moves the winner into a slot when it becomes tabu.  Then each
+// lane with a neighbour c updates D_c in place: for a free c a key that fell
+// needs only an atomic minimum on its node, a key that rose is a node repair
+// only when it was the node's minimum; a tabu c needs nothing, its slot
+// reads the new value at the next step.
+//
+// Invariant at the start of step t: a node's value is the minimum over a set
+// of its leaves that holds every leaf free at t, except possibly those whose
+// tenure ends exactly at t (they are still in slots and enter the minimum
+// from there), and no leaf tabu at t.
 #include "qb_internal.h"
 
 namespace {
@@ -43,9 +49,9 @@ namespace {
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int TT_MAX_NR = 8;   // nodes per lane: n <= 64 * 64 * 8
 
-// Wave minimum, returned uniform: the row minima by quad and mirror moves,
-// then the row broadcasts leave the minimum in lane 63.
-__device__ __forceinline__ uint32_t min_uniform(uint32_t a)
+// Wave minimum left in lane 63: the row minima by quad and mirror moves,
+// then the row broadcasts (the other lanes hold partial minima).
+__device__ __forceinline__ uint32_t min_to63(uint32_t a)
 {
     a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
     a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
@@ -53,7 +59,13 @@ __device__ __forceinline__ uint32_t min_uniform(uint32_t a)
     a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x140, 0xF, 0xF, false));   // row_mirror
     a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)a, 0x142, 0xA, 0xF, false));  // row_bcast 15
     a = min(a, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)a, 0x143, 0xC, 0xF, false));  // row_bcast 31
-    return (uint32_t)__builtin_amdgcn_readlane((int)a, 63);
+    return a;
+}
+
+// Wave minimum, returned uniform.
+__device__ __forceinline__ uint32_t min_uniform(uint32_t a)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)min_to63(a), 63);
 }
 
 // Wave sum, uniform (the overflow path only).
@@ -101,14 +113,8 @@ __device__ __forceinline__ void node_from(const TreeLds &L, int q, uint32_t d, i
                                           int lane)
 {
     const int j = (q << 6) + lane;
-    uint32_t f = (j < n && u <= t) ? (((d & DMASK) << IB) | (uint32_t)j) : NONE;
-    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0xB1, 0xF, 0xF, false));
-    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x4E, 0xF, 0xF, false));
-    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x141, 0xF, 0xF, false));
-    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, 0x140, 0xF, 0xF, false));
-    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)f, 0x142, 0xA, 0xF, false));
-    f = min(f, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)f, 0x143, 0xC, 0xF, false));
-    *one_lane(L, L.nf + q, lane, 63) = f;
+    const uint32_t f = (j < n && u <= t) ? (((d & DMASK) << IB) | (uint32_t)j) : NONE;
+    *one_lane(L, L.nf + q, lane, 63) = min_to63(f);
 }
 
 __device__ __forceinline__ void recompute(const TreeLds &L, int q, int t, int n, int IB, int lane)
