@@ -148,6 +148,7 @@ def test_sparse_field_energy_rankk(case, z):
     ("t:1x1", 2, 20, 1, True),           # n = 1: a single variable, always the winner
     ("t:9x7", 4, 400, 70, True),         # tenure beyond n: everything tabu, argmin over all
     ("t:9x7", 3, 400, 0, False),         # tenure 0: nothing is ever tabu
+    ("t:50x60", 2, 4000, 1000, True),    # up to 999 tabu variables: beyond the tree's 512 slots
 ])
 @pytest.mark.parametrize("variant", ["lanes", "tree"])
 def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):
