@@ -271,6 +271,8 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
 
     uint32_t *tl = dl;                                   // [m][W]
     int32_t *F = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + wid * MP;
+    // the wave's 64 words where lanes with no entry of the row add their zero
+    int32_t *dump = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + rw * MP + wid * 64;
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(tiles + (int64_t)base * W);
         uint4 *dst = reinterpret_cast<uint4 *>(tl);
@@ -346,9 +348,13 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
             int32_t dE = (fs ^ M0) - M0;
             uint64_t ym = __ballot(M0 != 0);
             uint64_t acc = __ballot(dE <= tv[s]) & pend;
-            // the previous accept's row word and factor (its adds are issued one accept late)
-            uint32_t pw = 0u;
+            // the previous accept's row word (as read: lanes past the row hold a
+            // copy of its last word) and factor; its adds are issued one accept
+            // late, and the word is masked only then, so the read is not
+            // waited for on the accept chain
+            uint32_t pwr = 0u;
             int32_t pd2 = 0;
+            const int wl = min(lane, W - 1);
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
@@ -363,12 +369,20 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
                 // the chain of this accept is done: only now wait for the
                 // previous accept's row word and add it, then read this one's
                 __builtin_amdgcn_sched_barrier(0);
-                if (lane < W && pw != 0u) atomicAdd(&F[qb_ell_col(pw)], pd2 * qb_ell_val(pw));
-                pw = lane < W ? tl[(size_t)(64 * s + k) * W + lane] : 0u;
+                {
+                    // every lane adds, without a branch: a padding word, or a
+                    // lane past the row, adds zero to its own dump word
+                    const uint32_t pw = lane < W ? pwr : 0u;
+                    atomicAdd(pw != 0u ? &F[qb_ell_col(pw)] : dump + lane, pd2 * qb_ell_val(pw));
+                }
+                pwr = tl[(size_t)(64 * s + k) * W + wl];
                 pd2 = d2;
                 acc = accn;
             }
-            if (lane < W && pw != 0u) atomicAdd(&F[qb_ell_col(pw)], pd2 * qb_ell_val(pw));
+            {
+                const uint32_t pw = lane < W ? pwr : 0u;
+                atomicAdd(pw != 0u ? &F[qb_ell_col(pw)] : dump + lane, pd2 * qb_ell_val(pw));
+            }
             if ((ym >> lane) & 1ull)
                 ybits |= 1u << s;
             else
@@ -389,7 +403,12 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
 
 constexpr size_t LDS_MAX = 160 * 1024;
 
-inline size_t ell_lds_bytes(int ms, int W, int rw) { return sizeof(uint32_t) * (size_t)64 * ms * (W + rw); }
+// The job's ELL tile, each replica's fields, and 64 words per replica (the
+// register-block kernel's dump area).
+inline size_t ell_lds_bytes(int ms, int W, int rw)
+{
+    return sizeof(uint32_t) * ((size_t)64 * ms * (W + rw) + (size_t)64 * rw);
+}
 
 template <int MS>
 qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *jobs, qb_batch b, int W,
