@@ -168,6 +168,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         su[s] = 0;
     }
     int ovf = 0;        // tabu variables outside the slots (their bits in ob)
+    int bi = 0;         // the variable flipped at step 64 b + lane of the current batch b
     int64_t OV = E[p];
     int64_t gap = 0;    // OV - OV_min, never negative
 
@@ -339,11 +340,17 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             recompute(L, q, step, n, IB, lane);
             m &= ~__ballot(need && cq == q);
         }
-        // the flip count and last-flip step go out after the row has been
-        // waited for, so that wait never covers them
-        if (lane == 0) {
-            __hip_atomic_fetch_add(Tout + ro + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            LFout[ro + i] = step;
+        // the flip count and last-flip step: lane (step mod 64) keeps this
+        // step's flip, and every 64 steps the wave sends the 64 of them at
+        // once (an atomic add and an atomic maximum each, so a variable
+        // flipped twice in a batch is counted twice and keeps its later step)
+        bi = lane == (step & 63) ? i : bi;
+        if ((step & 63) == 63 || step == alpha) {
+            if (lane <= (step & 63) && (step & ~63) + lane >= 1) {
+                __hip_atomic_fetch_add(Tout + ro + bi, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(LFout + ro + bi, (step & ~63) + lane, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
     __syncthreads();
