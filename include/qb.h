@@ -439,10 +439,17 @@ qb_status qb_trace(qb_batch b, int32_t R, const uint16_t *F_d, const uint8_t *Y_
 qb_status qb_gain_update(qb_batch b, int32_t R, const uint8_t *Y_d, const int64_t *e_d, const uint8_t *y0_d,
                          int32_t *G_d, void *stream);
 /* Mean binary cross-entropy of sigmoid(score) against the labels over B
- * samples and its gradient (float [4801]) with respect to the parameters:
- * the forward pass is the inference pass, the BF16 rounding is taken as the
- * identity backward, per-64-sample partial sums are added in a fixed order
- * (deterministic).  work_d: qb_mlp_train_workspace(B) bytes. */
+ * samples and its gradient (float [4801]) with respect to the parameters.
+ * The forward pass rounds as the inference pass does (BF16 activations,
+ * FP32 sums); the three 64 x 64 products of the second layer (forward, the
+ * backward into the first layer, and the W2 gradient) run on the matrix
+ * cores with BF16 operands and FP32 accumulation, the output gradient dZ2
+ * entering them as a BF16 pair hi + lo.  So the loss and the activations
+ * agree with qb_mlp_score up to the summation order of the second layer (an
+ * activation can round to the neighbouring BF16 value).  The BF16 rounding
+ * is taken as the identity backward; per-64-sample partial sums are added in
+ * a fixed order (deterministic: the same inputs give the same bits).
+ * work_d: qb_mlp_train_workspace(B) bytes. */
 size_t qb_mlp_train_workspace(int32_t B);
 qb_status qb_mlp_grad(int32_t B, const uint16_t *feat_d, const uint8_t *label_d, const uint16_t *W_d,
                       float *grad_d, float *loss_d, void *work_d, void *stream);

