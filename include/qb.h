@@ -97,7 +97,7 @@ qb_status qb_problem_get_info(qb_problem P, qb_problem_info *info_h);
  * values in registers, an argmin over all of them per step (n <= 20480);
  * QB_TABU_TREE one wave per solution with the move values in an LDS min-tree
  * of 64-leaf nodes, repairing per step only the nodes the flip touches
- * (n <= 25856 by LDS, ell_width <= 64, 2 dmax < 2^15 and
+ * (n <= 25856 by LDS, ell_width <= 64, 2 dmax < 2^15 - 1 and
  * (2 dmax + 1) 2^ceil(log2 n) < 2^32 with dmax = max|Q_kk| + 2 max eta;
  * qb_tabu returns QB_E_CAPACITY or QB_E_RANGE beyond).  QB_E_ARG for a dense problem or another value. */
 #define QB_TABU_AUTO 0

@@ -12,11 +12,15 @@
 //
 // Layout per solution (one 64-lane workgroup):
 //   dl[j]   x_j << 15 | (D_j + bias) (uint16 in LDS; bias bounds |D|, and
-//           2 bias < 2^15),
+//           2 bias < 2^15 - 1; one more leaf past the last node holds the
+//           all-ones value, the sentinel of the empty slots),
 //   Ul[j]   the last step at which j is tabu (0: free; LDS),
 //   pw      bit vector of "flipped since the last improvement",
 //   nf[q]   the least key over the free leaves of node q (leaves 64q..64q+63),
-//   slots   S (variable, last tabu step) pairs per lane for tabu variables,
+//   slots   S (variable, last tabu step) pairs per lane for tabu variables;
+//           the variable that turns tabu at step t goes to row (t / 64) mod S
+//           of lane t mod 64, a slot that is empty unless an earlier
+//           occupant's tenure was extended (then the first empty slot),
 //   ob      bit vector of tabu variables that found no slot (normally empty;
 //           scanned at every step while it is not, so the result never
 //           depends on the slot count).
@@ -137,6 +141,8 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     const TreeLds L = tree_lds(sm, NN, NR);
     const int64_t ro = (int64_t)p * n;
     const uint32_t IMASK = (1u << IB) - 1u;
+    const int SENT = NP;              // the sentinel leaf of the empty slots
+    constexpr int32_t NEVER = 0x7FFFFFFF;
 
     // leaves from x and the field: D_j = Q_jj + 2(1 - 2x_j) h_j
     for (int j0 = 0; j0 < NP; j0 += 64) {
@@ -157,18 +163,23 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) L.nf[lane + 64 * r] = NONE;
+    if (lane == 0) L.dl[SENT] = (uint16_t)DMASK;
     __syncthreads();
     for (int q = 0; q < NN; ++q) recompute(L, q, 0, n, IB, lane);
     __syncthreads();
 
-    int sj[S], su[S];   // tabu slots: variable (-1: empty) and its last tabu step
+    // tabu slots: variable and its last tabu step; an empty slot holds the
+    // sentinel leaf (its key is above every real key, so it never wins and
+    // never aspirates) and a step that never comes (it never expires)
+    int sj[S], su[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        sj[s] = -1;
-        su[s] = 0;
+        sj[s] = SENT;
+        su[s] = NEVER;
     }
     int ovf = 0;        // tabu variables outside the slots (their bits in ob)
     int bi = 0;         // the variable flipped at step 64 b + lane of the current batch b
+    int rs = 0;         // slot row of this step's ring position, (step / 64) mod S
     int64_t OV = E[p];
     int64_t gap = 0;    // OV - OV_min, never negative
 
@@ -178,28 +189,25 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         if (asp && gap < (int64_t)bias) tbk = (bias - (uint32_t)gap) << IB;
         // candidates: the free keys (nodes, and slots whose tenure ended:
         // free at this step) and the tabu keys (the other slots) that
-        // aspirate; tm keeps the least tabu key for the case where nothing
-        // is free and nothing aspirates
-        uint32_t fm = NONE, tm = NONE;
+        // aspirate
+        uint32_t fm = NONE;
         uint32_t nv[NR], dv[S];
 #pragma unroll
         for (int r = 0; r < NR; ++r) nv[r] = L.nf[lane + 64 * r];
 #pragma unroll
-        for (int s = 0; s < S; ++s) dv[s] = L.dl[max(sj[s], 0)];
+        for (int s = 0; s < S; ++s) dv[s] = L.dl[sj[s]];
+        __builtin_amdgcn_sched_barrier(0);   // every read issued before the first wait: one round trip
 #pragma unroll
         for (int r = 0; r < NR; ++r) fm = min(fm, nv[r]);
         uint32_t sk[S];
         bool sx[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const bool used = sj[s] >= 0;
-            sk[s] = used ? (((dv[s] & DMASK) << IB) | (uint32_t)sj[s]) : NONE;
-            sx[s] = used && su[s] < step;
-            const uint32_t tk = sx[s] ? NONE : sk[s];
-            fm = min(fm, sx[s] ? sk[s] : NONE);
-            fm = min(fm, tk < tbk ? tk : NONE);
-            tm = min(tm, tk);
+            sk[s] = ((dv[s] & DMASK) << IB) | (uint32_t)sj[s];
+            sx[s] = su[s] < step;
+            fm = min(fm, sx[s] || sk[s] < tbk ? sk[s] : NONE);
         }
+        uint32_t tov = NONE;   // least tabu key among the overflow bits
         if (ovf > 0) {
             // tabu variables without a slot: scan their bits
             int freed = 0;
@@ -214,7 +222,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                         keep &= ~(1u << (j & 31));
                         ++freed;
                     } else {
-                        tm = min(tm, key);
+                        tov = min(tov, key);
                         if (key < tbk) fm = min(fm, key);
                     }
                 }
@@ -223,7 +231,13 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             ovf -= wave_sum(freed);
         }
         uint32_t best = min_uniform(fm);
-        if (best == NONE) best = min_uniform(tm);   // everything tabu and nothing aspirates
+        if (best == NONE) {
+            // everything tabu and nothing aspirates: the least tabu key
+            uint32_t tm = tov;
+#pragma unroll
+            for (int s = 0; s < S; ++s) tm = min(tm, sx[s] ? NONE : sk[s]);
+            best = min_uniform(tm);
+        }
         const int i = (int)(best & IMASK);
         const uint32_t dib = best >> IB;
 
@@ -236,7 +250,8 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         for (int s = 0; s < S; ++s) {
             __hip_atomic_fetch_min(sx[s] ? L.nf + (sj[s] >> 6) : L.dump + lane, sx[s] ? sk[s] : NONE,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            sj[s] = sx[s] ? -1 : sj[s];
+            sj[s] = sx[s] ? SENT : sj[s];
+            su[s] = sx[s] ? NEVER : su[s];
         }
 
         // the winner's node, read once: its lane gives x_i and U_i, and the
@@ -276,19 +291,31 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         const bool was_tabu = Ui >= step, now_tabu = Un > step;
         if (!was_tabu) {
             if (now_tabu) {
-                // into the first empty slot, else the overflow bits
-                int ps = -1, pl = 0;
+                // into the ring position of this step (row rs, lane step mod
+                // 64): its last occupant came 64 S steps ago or earlier, so
+                // with 64 S >= tenure it is empty unless that variable's
+                // tenure was extended; else into the first empty slot, else
+                // the overflow bits (where a tabu variable sits never
+                // changes a key or a result)
+                const int pl = step & 63;
+                int cur = sj[0];
 #pragma unroll
-                for (int s = S - 1; s >= 0; --s) {
-                    const uint64_t em = __ballot(sj[s] < 0);
-                    if (em) {
-                        ps = s;
-                        pl = (int)__builtin_ctzll(em);
+                for (int s = 1; s < S; ++s) cur = rs == s ? sj[s] : cur;
+                int ps = rs, plane = pl;
+                if (__builtin_amdgcn_readlane(cur, pl) != SENT) {
+                    ps = -1;
+#pragma unroll
+                    for (int s = S - 1; s >= 0; --s) {
+                        const uint64_t em = __ballot(sj[s] == SENT);
+                        if (em) {
+                            ps = s;
+                            plane = (int)__builtin_ctzll(em);
+                        }
                     }
                 }
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const bool mine = s == ps && lane == pl;
+                    const bool mine = s == ps && lane == plane;
                     sj[s] = mine ? i : sj[s];
                     su[s] = mine ? Un : su[s];
                 }
@@ -303,8 +330,8 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             for (int s = 0; s < S; ++s) {
                 const bool hit = sj[s] == i;
                 inslot = inslot || hit;
-                su[s] = hit && now_tabu ? Un : su[s];
-                sj[s] = hit && !now_tabu ? -1 : sj[s];
+                su[s] = hit ? (now_tabu ? Un : NEVER) : su[s];
+                sj[s] = hit && !now_tabu ? SENT : sj[s];
             }
             if (!now_tabu && __ballot(inslot) == 0ull) {
                 // tenure 0: free again at once (the node above took it back)
@@ -313,27 +340,32 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             }
         }
 
-        // neighbours: D_c += 2(1 - 2x_c) sgn Q_ci
-        bool need = false;
-        int cq = 0;
-        if (wd != 0u) {
+        // neighbours: D_c += 2(1 - 2x_c) sgn Q_ci, without a branch (a lane
+        // without a neighbour reads leaf 0 and stores into the dump area):
+        // the leaf, its tabu step and its node are read in one round trip
+        bool need;
+        int cq;
+        {
+            const bool has = wd != 0u;
             const int c = qb_ell_col(wd);
             const int32_t v = qb_ell_val(wd);
             cq = c >> 6;
             const uint32_t lold = L.dl[c];
             const int32_t uc = L.Ul[c];
             const uint32_t nq = L.nf[cq];
+            __builtin_amdgcn_sched_barrier(0);
             const int32_t sg = (lold >> 15) ? -2 : 2;
             const uint32_t dold = lold & DMASK;
             const uint32_t dnew = (uint32_t)((int32_t)dold + sg * sgn * v);
-            L.dl[c] = (uint16_t)((lold & ~DMASK) | dnew);
-            if (uc <= step) {   // free at step + 1: the tree holds it (or may, when its tenure ends now)
-                const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
-                if (knew < kold)
-                    __hip_atomic_fetch_min(L.nf + cq, knew, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                else
-                    need = knew > kold && nq == kold;
-            }
+            *(has ? L.dl + c : reinterpret_cast<uint16_t *>(L.dump + lane)) = (uint16_t)((lold & ~DMASK) | dnew);
+            // free at step + 1: the tree holds it (or may, when its tenure ends now)
+            const bool intree = has && uc <= step;
+            const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
+            const bool fell = intree && knew < kold;
+            __hip_atomic_fetch_min(fell ? L.nf + cq : L.dump + lane, fell ? knew : NONE, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            // a key that rose repairs its node only when it was the node's minimum
+            need = intree && knew > kold && nq == kold;
         }
         for (uint64_t m = __ballot(need); m;) {
             const int q = __builtin_amdgcn_readlane(cq, __builtin_ctzll(m));
@@ -351,6 +383,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                 __hip_atomic_fetch_max(LFout + ro + bi, (step & ~63) + lane, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
+            rs = rs + 1 == S ? 0 : rs + 1;
         }
     }
     __syncthreads();
@@ -391,7 +424,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
 size_t qb_tabu_tree_lds(int n)
 {
     const size_t NN = ((size_t)n + 63) / 64, NP = NN * 64, NR = (NN + 63) / 64;
-    return NP * 4 + NR * 64 * 4 + NP / 32 * 8 + 64 * 4 + NP * 2;
+    return NP * 4 + NR * 64 * 4 + NP / 32 * 8 + 64 * 4 + NP * 2 + 4;
 }
 
 qb_status qb_tabu_tree_fits(qb_problem P)
@@ -400,14 +433,14 @@ qb_status qb_tabu_tree_fits(qb_problem P)
     if (!P->sparse || P->ellw > 64 || n > 64 * 64 * TT_MAX_NR || qb_tabu_tree_lds(n) > 160 * 1024)
         return QB_E_CAPACITY;
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
-    if (2 * dmax > 0x7FFF || ((2 * dmax + 1) << qb_ceil_log2(n)) >= (int64_t(1) << 32)) return QB_E_RANGE;
+    if (2 * dmax >= (int64_t)DMASK || ((2 * dmax + 1) << qb_ceil_log2(n)) >= (int64_t(1) << 32)) return QB_E_RANGE;
     return QB_OK;
 }
 
 // QB_E_CAPACITY when the problem does not fit the tree kernel (the caller
 // then runs the lane kernel), QB_E_RANGE when its keys cannot hold the move
-// values.  Slots per lane: enough for `tenure` tabu variables with a wave's
-// worth to spare, at most eight (beyond, the overflow bits take the rest).
+// values.  Slots per lane: enough for `tenure` tabu variables with 16 to
+// spare, at most eight (beyond, the overflow bits take the rest).
 qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64_t *E, int alpha, int tenure,
                               int asp, int32_t *T, int32_t *LF, hipStream_t s)
 {
@@ -418,8 +451,8 @@ qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64
     const int64_t dmax = (int64_t)P->qmax + 2 * P->eta_max;
     const int IB = qb_ceil_log2(n);
     const int NR = (n + 4095) / 4096;
-    const int need = (int)std::min<int64_t>((int64_t)tenure + 64, n);
-    const int S = need <= 128 ? 2 : need <= 256 ? 4 : 8;
+    const int need = (int)std::min<int64_t>((int64_t)tenure + 16, n);
+    const int S = need <= 64 ? 1 : need <= 128 ? 2 : need <= 192 ? 3 : need <= 256 ? 4 : 8;
 #define QB_TT(K, SL)                                                                                           \
     if (NR == K && S == SL) {                                                                                  \
         QB_TRY_HIP(hipFuncSetAttribute((const void *)k_tabu_tree<K, SL>,                                       \
@@ -427,7 +460,7 @@ qb_status qb_tabu_tree_launch(qb_problem P, int z, uint8_t *X, int32_t *H, int64
         k_tabu_tree<K, SL><<<z, 64, lds, s>>>(P->ell, P->ellw, P->diag, n, X, H, E, alpha, tenure, asp, T, LF, \
                                               (uint32_t)dmax, IB);                                             \
     }
-#define QB_TT3(K) QB_TT(K, 2) QB_TT(K, 4) QB_TT(K, 8)
+#define QB_TT3(K) QB_TT(K, 1) QB_TT(K, 2) QB_TT(K, 3) QB_TT(K, 4) QB_TT(K, 8)
     QB_TT3(1) QB_TT3(2) QB_TT3(3) QB_TT3(4) QB_TT3(5) QB_TT3(6) QB_TT3(7) QB_TT3(8)
 #undef QB_TT3
 #undef QB_TT

@@ -149,6 +149,9 @@ def test_sparse_field_energy_rankk(case, z):
     ("t:9x7", 4, 400, 70, True),         # tenure beyond n: everything tabu, argmin over all
     ("t:9x7", 3, 400, 0, False),         # tenure 0: nothing is ever tabu
     ("t:50x60", 2, 4000, 1000, True),    # up to 999 tabu variables: beyond the tree's 512 slots
+    ("t:30x37", 2, 3000, 100, True),     # two slots per lane on the tree
+    ("t:30x37", 2, 3000, 176, True),     # three slots, the ring position free only 16 steps early
+    ("t:30x37", 2, 3000, 230, True),     # four slots
 ])
 @pytest.mark.parametrize("variant", ["lanes", "tree"])
 def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):
@@ -167,7 +170,7 @@ def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):
     E = oracle.energy(X, H)
     P = csr_problem(csr)
     dmax = P.qmax + 2 * P.eta_max
-    if variant == "tree" and (P.ell_width > 64 or 2 * dmax > 0x7FFF or
+    if variant == "tree" and (P.ell_width > 64 or 2 * dmax >= 0x7FFF or
                               (2 * dmax + 1) << max(0, (n - 1).bit_length()) >= 2**32):
         # the tree kernel reads a row with one lane per entry and keeps
         # move values in 16 bits
