@@ -183,208 +183,226 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     int64_t OV = E[p];
     int64_t gap = 0;    // OV - OV_min, never negative
 
-    for (int step = 1; step <= alpha; ++step) {
-        // a tabu key k aspirates when D < OV_min - OV = -gap, that is k < tbk
-        uint32_t tbk = 0;
-        if (asp && gap < (int64_t)bias) tbk = (bias - (uint32_t)gap) << IB;
-        // candidates: the free keys (nodes, and slots whose tenure ended:
-        // free at this step) and the tabu keys (the other slots) that
-        // aspirate
-        uint32_t fm = NONE;
-        uint32_t nv[NR], dv[S];
+    // steps in batches of 64 (batch b: steps 64 b .. 64 b + 63), the flip
+    // counts sent at the end of each
+    for (int b0 = 0; b0 <= alpha; b0 += 64) {
+        const int shi = min(b0 + 63, alpha);
+        for (int step = max(b0, 1); step <= shi; ++step) {
+            // a tabu key k aspirates when D < OV_min - OV = -gap, that is k < tbk
+            uint32_t tbk = 0;
+            if (asp && gap < (int64_t)bias) tbk = (bias - (uint32_t)gap) << IB;
+            // candidates: the free keys (nodes, and slots whose tenure ended:
+            // free at this step) and the tabu keys (the other slots) that
+            // aspirate
+            uint32_t fm = NONE;
+            uint32_t nv[NR], dv[S];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) nv[r] = L.nf[lane + 64 * r];
+            for (int r = 0; r < NR; ++r) nv[r] = L.nf[lane + 64 * r];
 #pragma unroll
-        for (int s = 0; s < S; ++s) dv[s] = L.dl[sj[s]];
-        __builtin_amdgcn_sched_barrier(0);   // every read issued before the first wait: one round trip
+            for (int s = 0; s < S; ++s) dv[s] = L.dl[sj[s]];
+            __builtin_amdgcn_sched_barrier(0);   // every read issued before the first wait: one round trip
 #pragma unroll
-        for (int r = 0; r < NR; ++r) fm = min(fm, nv[r]);
-        uint32_t sk[S];
-        bool sx[S];
+            for (int r = 0; r < NR; ++r) fm = min(fm, nv[r]);
+            uint32_t sk[S];
+            bool sx[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            sk[s] = ((dv[s] & DMASK) << IB) | (uint32_t)sj[s];
-            sx[s] = su[s] < step;
-            fm = min(fm, sx[s] || sk[s] < tbk ? sk[s] : NONE);
-        }
-        uint32_t tov = NONE;   // least tabu key among the overflow bits
-        if (ovf > 0) {
-            // tabu variables without a slot: scan their bits
-            int freed = 0;
-            for (int w = lane; w < NXW; w += 64) {
-                uint32_t keep = L.ob[w];
-                for (uint32_t bits = keep; bits; bits &= bits - 1u) {
-                    const int j = (w << 5) + __builtin_ctz(bits);
-                    const uint32_t key = (((uint32_t)L.dl[j] & DMASK) << IB) | (uint32_t)j;
-                    if (L.Ul[j] < step) {
-                        fm = min(fm, key);
-                        __hip_atomic_fetch_min(L.nf + (j >> 6), key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        keep &= ~(1u << (j & 31));
-                        ++freed;
-                    } else {
-                        tov = min(tov, key);
-                        if (key < tbk) fm = min(fm, key);
-                    }
-                }
-                L.ob[w] = keep;
+            for (int s = 0; s < S; ++s) {
+                sk[s] = ((dv[s] & DMASK) << IB) | (uint32_t)sj[s];
+                sx[s] = su[s] < step;
+                fm = min(fm, sx[s] || sk[s] < tbk ? sk[s] : NONE);
             }
-            ovf -= wave_sum(freed);
-        }
-        uint32_t best = min_uniform(fm);
-        if (best == NONE) {
-            // everything tabu and nothing aspirates: the least tabu key
-            uint32_t tm = tov;
+            uint32_t tov = NONE;   // least tabu key among the overflow bits
+            if (ovf > 0) {
+                // tabu variables without a slot: scan their bits
+                int freed = 0;
+                for (int w = lane; w < NXW; w += 64) {
+                    uint32_t keep = L.ob[w];
+                    for (uint32_t bits = keep; bits; bits &= bits - 1u) {
+                        const int j = (w << 5) + __builtin_ctz(bits);
+                        const uint32_t key = (((uint32_t)L.dl[j] & DMASK) << IB) | (uint32_t)j;
+                        if (L.Ul[j] < step) {
+                            fm = min(fm, key);
+                            __hip_atomic_fetch_min(L.nf + (j >> 6), key, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            keep &= ~(1u << (j & 31));
+                            ++freed;
+                        } else {
+                            tov = min(tov, key);
+                            if (key < tbk) fm = min(fm, key);
+                        }
+                    }
+                    L.ob[w] = keep;
+                }
+                ovf -= wave_sum(freed);
+            }
+            uint32_t best = min_uniform(fm);
+            if (best == NONE) {
+                // everything tabu and nothing aspirates: the least tabu key
+                uint32_t tm = tov;
 #pragma unroll
-            for (int s = 0; s < S; ++s) tm = min(tm, sx[s] ? NONE : sk[s]);
-            best = min_uniform(tm);
-        }
-        const int i = (int)(best & IMASK);
-        const uint32_t dib = best >> IB;
+                for (int s = 0; s < S; ++s) tm = min(tm, sx[s] ? NONE : sk[s]);
+                best = min_uniform(tm);
+            }
+            const int i = (int)(best & IMASK);
+            const uint32_t dib = best >> IB;
 
-        // the winner's row, in flight while its own leaf and node are redone
-        uint32_t wd = 0u;
-        if (lane < W) wd = ell[(int64_t)i * W + lane];
+            // the winner's row, in flight while its own leaf and node are redone
+            uint32_t wd = 0u;
+            if (lane < W) wd = ell[(int64_t)i * W + lane];
 
-        // slots whose tenure ended rejoin the tree
+            // slots whose tenure ended rejoin the tree
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            __hip_atomic_fetch_min(sx[s] ? L.nf + (sj[s] >> 6) : L.dump + lane, sx[s] ? sk[s] : NONE,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            sj[s] = sx[s] ? SENT : sj[s];
-            su[s] = sx[s] ? NEVER : su[s];
-        }
+            for (int s = 0; s < S; ++s) {
+                __hip_atomic_fetch_min(sx[s] ? L.nf + (sj[s] >> 6) : L.dump + lane, sx[s] ? sk[s] : NONE,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                sj[s] = sx[s] ? SENT : sj[s];
+                su[s] = sx[s] ? NEVER : su[s];
+            }
 
-        // the winner's node, read once: its lane gives x_i and U_i, and the
-        // node is recomputed from registers with the winner's leaf rewritten
-        const int qi = i >> 6, li = i & 63;
-        const int jl = (qi << 6) + lane;
-        uint32_t dl_l = L.dl[jl];
-        int32_t ul_l = L.Ul[jl];
-        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dl_l, li);
-        const int32_t Ui = __builtin_amdgcn_readlane(ul_l, li);
-        const uint32_t xi = di >> 15;
-        const uint32_t bit = 1u << (i & 31);
-        const int32_t sgn = xi ? -1 : 1;   // h_j += sgn Q_ji
-        const int32_t Un = step + max(max(Ui - (step - 1), 0) + tenure - 1, 0);
-        const int32_t dmove = (int32_t)dib - (int32_t)bias;
-        const uint32_t dnew_i = 2u * bias - dib;   // D_i -> -D_i
-        OV += dmove;
-        gap += dmove;
-        const bool improved = gap < 0;
-        if (improved) gap = 0;
-        if (lane == li) {
-            dl_l = ((xi ^ 1u) << 15) | dnew_i;
-            ul_l = Un;
-        }
-        *one_lane(L, L.dl + i, lane, li) = (uint16_t)dl_l;
-        *one_lane(L, L.Ul + i, lane, li) = ul_l;
-        if (improved) {   // x_min is the current x
-            for (int w = lane; w < NXW; w += 64) L.pw[w] = 0u;
-        } else {
-            __hip_atomic_fetch_xor(one_lane(L, L.pw + (i >> 5), lane, 0), bit, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        // i leaves the free set, changes its key or (tabu before and after)
-        // stays out of it
-        node_from(L, qi, dl_l, ul_l, step, n, IB, lane);
+            // the winner's node, read once: its lane gives x_i and U_i, and the
+            // node is recomputed from registers with the winner's leaf rewritten
+            const int qi = i >> 6, li = i & 63;
+            const int jl = (qi << 6) + lane;
+            uint32_t dl_l = L.dl[jl];
+            int32_t ul_l = L.Ul[jl];
+            const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dl_l, li);
+            const int32_t Ui = __builtin_amdgcn_readlane(ul_l, li);
+            const uint32_t xi = di >> 15;
+            const uint32_t bit = 1u << (i & 31);
+            const int32_t sgn = xi ? -1 : 1;   // h_j += sgn Q_ji
+            const int32_t Un = step + max(max(Ui - (step - 1), 0) + tenure - 1, 0);
+            const int32_t dmove = (int32_t)dib - (int32_t)bias;
+            const uint32_t dnew_i = 2u * bias - dib;   // D_i -> -D_i
+            OV += dmove;
+            gap += dmove;
+            const bool improved = gap < 0;
+            if (improved) gap = 0;
+            if (lane == li) {
+                dl_l = ((xi ^ 1u) << 15) | dnew_i;
+                ul_l = Un;
+            }
+            *one_lane(L, L.dl + i, lane, li) = (uint16_t)dl_l;
+            *one_lane(L, L.Ul + i, lane, li) = ul_l;
+            if (improved) {   // x_min is the current x
+                for (int w = lane; w < NXW; w += 64) L.pw[w] = 0u;
+            } else {
+                __hip_atomic_fetch_xor(one_lane(L, L.pw + (i >> 5), lane, 0), bit, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            // i leaves the free set, changes its key or (tabu before and after)
+            // stays out of it
+            node_from(L, qi, dl_l, ul_l, step, n, IB, lane);
 
-        const bool was_tabu = Ui >= step, now_tabu = Un > step;
-        if (!was_tabu) {
-            if (now_tabu) {
-                // into the ring position of this step (row rs, lane step mod
-                // 64): its last occupant came 64 S steps ago or earlier, so
-                // with 64 S >= tenure it is empty unless that variable's
-                // tenure was extended; else into the first empty slot, else
-                // the overflow bits (where a tabu variable sits never
-                // changes a key or a result)
-                const int pl = step & 63;
-                int cur = sj[0];
+            // the slots: a free variable that turns tabu goes into the ring
+            // position of this step (row rs, lane step mod 64), whose last
+            // occupant came 64 S steps ago or earlier, so with 64 S >= tenure
+            // it is empty unless that variable's tenure was extended; else
+            // into the first empty slot, else the overflow bits (where a tabu
+            // variable sits never changes a key or a result).  A tabu variable
+            // that flips again keeps its slot with the new step, or leaves it
+            // at tenure 0.  Either way one slot (row ps, lane plane) takes the
+            // pair (sjv, suv), written without a branch.
+            const bool was_tabu = Ui >= step, now_tabu = Un > step;
+            int ps = -1, plane = 0, sjv = i;
+            int32_t suv = Un;
+            if (!was_tabu) {
+                if (now_tabu) {
+                    plane = step & 63;
+                    int cur = sj[0];
 #pragma unroll
-                for (int s = 1; s < S; ++s) cur = rs == s ? sj[s] : cur;
-                int ps = rs, plane = pl;
-                if (__builtin_amdgcn_readlane(cur, pl) != SENT) {
-                    ps = -1;
+                    for (int s = 1; s < S; ++s) cur = rs == s ? sj[s] : cur;
+                    ps = rs;
+                    if (__builtin_amdgcn_readlane(cur, plane) != SENT) {
+                        ps = -1;
 #pragma unroll
-                    for (int s = S - 1; s >= 0; --s) {
-                        const uint64_t em = __ballot(sj[s] == SENT);
-                        if (em) {
-                            ps = s;
-                            plane = (int)__builtin_ctzll(em);
+                        for (int s = S - 1; s >= 0; --s) {
+                            const uint64_t em = __ballot(sj[s] == SENT);
+                            if (em) {
+                                ps = s;
+                                plane = (int)__builtin_ctzll(em);
+                            }
+                        }
+                        if (ps < 0) {
+                            if (lane == 0)
+                                __hip_atomic_fetch_or(L.ob + (i >> 5), bit, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                            ++ovf;
                         }
                     }
                 }
+            } else {
+                // i sits in a slot (an expired slot was emptied above, so only
+                // a tabu i can), or in the overflow bits
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    const bool mine = s == ps && lane == plane;
-                    sj[s] = mine ? i : sj[s];
-                    su[s] = mine ? Un : su[s];
+                for (int s = S - 1; s >= 0; --s) {
+                    const uint64_t em = __ballot(sj[s] == i);
+                    if (em) {
+                        ps = s;
+                        plane = (int)__builtin_ctzll(em);
+                    }
                 }
-                if (ps < 0) {
-                    if (lane == 0) __hip_atomic_fetch_or(L.ob + (i >> 5), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    ++ovf;
+                if (!now_tabu) {
+                    sjv = SENT;
+                    suv = NEVER;
+                    if (ps < 0) {
+                        // tenure 0: free again at once (the node above took it back)
+                        if (lane == 0)
+                            __hip_atomic_fetch_and(L.ob + (i >> 5), ~bit, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        --ovf;
+                    }
                 }
             }
-        } else {
-            bool inslot = false;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const bool hit = sj[s] == i;
-                inslot = inslot || hit;
-                su[s] = hit ? (now_tabu ? Un : NEVER) : su[s];
-                sj[s] = hit && !now_tabu ? SENT : sj[s];
+                const bool mine = s == ps && lane == plane;
+                sj[s] = mine ? sjv : sj[s];
+                su[s] = mine ? suv : su[s];
             }
-            if (!now_tabu && __ballot(inslot) == 0ull) {
-                // tenure 0: free again at once (the node above took it back)
-                if (lane == 0) __hip_atomic_fetch_and(L.ob + (i >> 5), ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                --ovf;
-            }
-        }
 
-        // neighbours: D_c += 2(1 - 2x_c) sgn Q_ci, without a branch (a lane
-        // without a neighbour reads leaf 0 and stores into the dump area):
-        // the leaf, its tabu step and its node are read in one round trip
-        bool need;
-        int cq;
-        {
-            const bool has = wd != 0u;
-            const int c = qb_ell_col(wd);
-            const int32_t v = qb_ell_val(wd);
-            cq = c >> 6;
-            const uint32_t lold = L.dl[c];
-            const int32_t uc = L.Ul[c];
-            const uint32_t nq = L.nf[cq];
-            __builtin_amdgcn_sched_barrier(0);
-            const int32_t sg = (lold >> 15) ? -2 : 2;
-            const uint32_t dold = lold & DMASK;
-            const uint32_t dnew = (uint32_t)((int32_t)dold + sg * sgn * v);
-            *(has ? L.dl + c : reinterpret_cast<uint16_t *>(L.dump + lane)) = (uint16_t)((lold & ~DMASK) | dnew);
-            // free at step + 1: the tree holds it (or may, when its tenure ends now)
-            const bool intree = has && uc <= step;
-            const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
-            const bool fell = intree && knew < kold;
-            __hip_atomic_fetch_min(fell ? L.nf + cq : L.dump + lane, fell ? knew : NONE, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            // a key that rose repairs its node only when it was the node's minimum
-            need = intree && knew > kold && nq == kold;
-        }
-        for (uint64_t m = __ballot(need); m;) {
-            const int q = __builtin_amdgcn_readlane(cq, __builtin_ctzll(m));
-            recompute(L, q, step, n, IB, lane);
-            m &= ~__ballot(need && cq == q);
-        }
-        // the flip count and last-flip step: lane (step mod 64) keeps this
-        // step's flip, and every 64 steps the wave sends the 64 of them at
-        // once (an atomic add and an atomic maximum each, so a variable
-        // flipped twice in a batch is counted twice and keeps its later step)
-        bi = lane == (step & 63) ? i : bi;
-        if ((step & 63) == 63 || step == alpha) {
-            if (lane <= (step & 63) && (step & ~63) + lane >= 1) {
-                __hip_atomic_fetch_add(Tout + ro + bi, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_max(LFout + ro + bi, (step & ~63) + lane, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            // neighbours: D_c += 2(1 - 2x_c) sgn Q_ci, without a branch (a lane
+            // without a neighbour reads leaf 0 and stores into the dump area):
+            // the leaf, its tabu step and its node are read in one round trip
+            bool need;
+            int cq;
+            {
+                const bool has = wd != 0u;
+                const int c = qb_ell_col(wd);
+                const int32_t v = qb_ell_val(wd);
+                cq = c >> 6;
+                const uint32_t lold = L.dl[c];
+                const int32_t uc = L.Ul[c];
+                const uint32_t nq = L.nf[cq];
+                __builtin_amdgcn_sched_barrier(0);
+                const int32_t sg = (lold >> 15) ? -2 : 2;
+                const uint32_t dold = lold & DMASK;
+                const uint32_t dnew = (uint32_t)((int32_t)dold + sg * sgn * v);
+                *(has ? L.dl + c : reinterpret_cast<uint16_t *>(L.dump + lane)) = (uint16_t)((lold & ~DMASK) | dnew);
+                // free at step + 1: the tree holds it (or may, when its tenure ends now)
+                const bool intree = has && uc <= step;
+                const uint32_t kold = (dold << IB) | (uint32_t)c, knew = (dnew << IB) | (uint32_t)c;
+                const bool fell = intree && knew < kold;
+                __hip_atomic_fetch_min(fell ? L.nf + cq : L.dump + lane, fell ? knew : NONE, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                // a key that rose repairs its node only when it was the node's minimum
+                need = intree && knew > kold && nq == kold;
             }
-            rs = rs + 1 == S ? 0 : rs + 1;
+            for (uint64_t m = __ballot(need); m;) {
+                const int q = __builtin_amdgcn_readlane(cq, __builtin_ctzll(m));
+                recompute(L, q, step, n, IB, lane);
+                m &= ~__ballot(need && cq == q);
+            }
+            // the flip count and last-flip step: lane (step mod 64) keeps this
+            // step's flip, and every 64 steps the wave sends the 64 of them at
+            // once (an atomic add and an atomic maximum each, so a variable
+            // flipped twice in a batch is counted twice and keeps its later step)
+            bi = lane == (step & 63) ? i : bi;
         }
+        if (lane <= shi - b0 && b0 + lane >= 1) {
+            __hip_atomic_fetch_add(Tout + ro + bi, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(LFout + ro + bi, b0 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        rs = rs + 1 == S ? 0 : rs + 1;
     }
     __syncthreads();
 
