@@ -181,16 +181,25 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     int bi = 0;         // the variable flipped at step 64 b + lane of the current batch b
     int rs = 0;         // slot row of this step's ring position, (step / 64) mod S
     int64_t OV = E[p];
-    int64_t gap = 0;    // OV - OV_min, never negative
+    int64_t OVmin = OV;
+    // gap = OV - OV_min >= 0 in 32 bits: exact from each batch start (where it
+    // is recomputed, saturated at GCAP) for as long as it stays below GCAP;
+    // a step moves it by |D_i| < 2^15, so within a batch a saturated gap stays
+    // above GCAP - 2^21, far above every value its two tests (gap < bias, and
+    // gap + D_i < 0) tell apart
+    constexpr int32_t GCAP = 1 << 30;
+    int32_t gap = 0;
+    const int ten1 = max(tenure - 1, 0);
 
     // steps in batches of 64 (batch b: steps 64 b .. 64 b + 63), the flip
     // counts sent at the end of each
     for (int b0 = 0; b0 <= alpha; b0 += 64) {
         const int shi = min(b0 + 63, alpha);
+        gap = OV - OVmin < (int64_t)GCAP ? (int32_t)(OV - OVmin) : GCAP;
         for (int step = max(b0, 1); step <= shi; ++step) {
             // a tabu key k aspirates when D < OV_min - OV = -gap, that is k < tbk
             uint32_t tbk = 0;
-            if (asp && gap < (int64_t)bias) tbk = (bias - (uint32_t)gap) << IB;
+            if (asp && gap < (int32_t)bias) tbk = (bias - (uint32_t)gap) << IB;
             // candidates: the free keys (nodes, and slots whose tenure ended:
             // free at this step) and the tabu keys (the other slots) that
             // aspirate
@@ -270,13 +279,20 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             const uint32_t xi = di >> 15;
             const uint32_t bit = 1u << (i & 31);
             const int32_t sgn = xi ? -1 : 1;   // h_j += sgn Q_ji
-            const int32_t Un = step + max(max(Ui - (step - 1), 0) + tenure - 1, 0);
+            // the last tabu step: step + max(max(Ui - step + 1, 0) + tenure - 1, 0),
+            // which equals max(Ui + tenure, step + max(tenure - 1, 0))
+            const int32_t Un = max(Ui + tenure, step + ten1);
             const int32_t dmove = (int32_t)dib - (int32_t)bias;
             const uint32_t dnew_i = 2u * bias - dib;   // D_i -> -D_i
             OV += dmove;
             gap += dmove;
             const bool improved = gap < 0;
-            if (improved) gap = 0;
+            if (improved) {
+                gap = 0;
+                OVmin = OV;
+            } else {
+                gap = min(gap, GCAP);
+            }
             if (lane == li) {
                 dl_l = ((xi ^ 1u) << 15) | dnew_i;
                 ul_l = Un;
@@ -433,7 +449,7 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
         X[ro + j] = (uint8_t)(((uint32_t)L.dl[j] >> 15) ^ ((L.pw[j >> 5] >> (j & 31)) & 1u));
         H[ro + j] = L.Ul[j];
     }
-    if (lane == 0) E[p] = OV - gap;
+    if (lane == 0) E[p] = OVmin;
 }
 
 }  // namespace
