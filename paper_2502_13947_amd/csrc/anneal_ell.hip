@@ -232,7 +232,9 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
 // The next block's column is loaded two blocks ahead.
 __device__ __forceinline__ int32_t dcol_at(const uint32_t (&d)[16], int k)
 {
-    return __builtin_amdgcn_sbfe((int)d[k >> 2], (uint32_t)(k & 3) * 8u, 8u);
+    // v_bfe_i32 takes its offset modulo 32 (bits [4:0]), so 8 k selects
+    // byte k & 3 without a mask
+    return __builtin_amdgcn_sbfe((int)d[k >> 2], (uint32_t)k * 8u, 8u);
 }
 
 __device__ __forceinline__ void load_dcol(uint32_t (&d)[16], const uint8_t *__restrict__ src)
@@ -346,7 +348,11 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
             const int32_t M0 = ((ybits >> s) & 1u) ? -1 : 0;
             const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;   // 2 sigma
             int32_t dE = (fs ^ M0) - M0;
-            uint64_t ym = __ballot(M0 != 0);
+            // y of the block's lanes at its start: a lane accepts at most once
+            // in the block, so an accepted lane's y is still this bit
+            const uint64_t ym0 = __ballot(M0 != 0);
+            uint64_t amask = 0;        // lanes accepted in the block
+            int32_t eb = 0;            // their dE: at most 64 moves of |dE| < 2^24
             uint64_t acc = __ballot(dE <= tv[s]) & pend;
             // the previous accept's row word (as read: lanes past the row hold a
             // copy of its last word) and factor; its adds are issued one accept
@@ -357,11 +363,10 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
             const int wl = min(lane, W - 1);
             while (acc) {
                 const int k = __builtin_ctzll(acc);
-                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
-                const int32_t mk = (int32_t)((ym >> k) & 1ull);
-                ym ^= 1ull << k;
-                e += dEk;
-                ++nacc;
+                const uint64_t bk = 1ull << k;
+                eb += __builtin_amdgcn_readlane(dE, k);
+                amask |= bk;
+                const bool mk = (ym0 & bk) != 0ull;
                 const int32_t d2 = mk ? -2 : 2;
                 dE += (mk ? ns2 : s2) * dcol_at(dc, k);
                 pend &= (~0ull << k) << 1;
@@ -383,7 +388,9 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
                 const uint32_t pw = lane < W ? pwr : 0u;
                 atomicAdd(pw != 0u ? &F[qb_ell_col(pw)] : dump + lane, pd2 * qb_ell_val(pw));
             }
-            if ((ym >> lane) & 1ull)
+            e += eb;
+            nacc += __builtin_popcountll(amask);
+            if (((ym0 ^ amask) >> lane) & 1ull)
                 ybits |= 1u << s;
             else
                 ybits &= ~(1u << s);
