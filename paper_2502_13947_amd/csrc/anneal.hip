@@ -20,6 +20,7 @@
 // (156,672 bytes, rows padded to 68 bytes so that both row and column reads
 // of a block are bank-conflict free); otherwise rows stay in L2/HBM.
 #include <atomic>
+#include <type_traits>
 
 #include "qb_internal.h"
 
@@ -141,6 +142,12 @@ __device__ __forceinline__ int sym_block_index(int a, int b)   // a <= b < 8
     return a * 8 - (a * (a - 1)) / 2 + (b - a);
 }
 
+// Sum of the accepted dE of one block (at most 64 moves).  With int8 tiles
+// the problem has |Q| <= 127, so |dE| <= |F| <= 127 (2n + 1) < 2^24 and 32
+// bits hold the sum; int16 tiles sum in 64 bits.
+template <typename TT>
+using block_esum = typename std::conditional<sizeof(TT) == 1, int32_t, int64_t>::type;
+
 template <int MS, typename TT>
 struct RowVec {
     TT v[MS];
@@ -255,6 +262,8 @@ __device__ __forceinline__ void anneal_job(int slot, const int32_t *__restrict__
 #pragma unroll
         for (int s = 0; s < MS; ++s) {
             uint64_t pend = active[s];
+            block_esum<TT> eb = 0;
+            int cb = 0;
             while (true) {
                 const uint32_t yb = (ybits >> s) & 1u;
                 const int32_t dE = yb ? -F[s] : F[s];
@@ -263,8 +272,8 @@ __device__ __forceinline__ void anneal_job(int slot, const int32_t *__restrict__
                 const int k = __builtin_ctzll(acc);
                 const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
                 const int32_t ykb = __builtin_amdgcn_readlane((int32_t)yb, k);
-                e += dEk;
-                ++nacc;
+                eb += dEk;
+                ++cb;
                 const int32_t d2 = ykb ? -2 : 2;
                 if (lane == k) ybits ^= 1u << s;
                 int32_t rv[MS];
@@ -273,6 +282,8 @@ __device__ __forceinline__ void anneal_job(int slot, const int32_t *__restrict__
                 for (int s2 = 0; s2 < MS; ++s2) F[s2] += d2 * rv[s2];
                 pend &= ~((2ull << k) - 1ull);
             }
+            e += eb;
+            nacc += cb;
         }
     }
 
@@ -390,10 +401,12 @@ __device__ __forceinline__ int32_t elem_at(const uint8_t *lds, const ElemAddr &e
 template <typename TT, int DW>
 __device__ __forceinline__ int32_t diag_at(const uint32_t (&d)[DW], int k)
 {
+    // v_bfe_i32 takes its offset modulo 32 (bits [4:0]): 8 k and 16 k select
+    // the element within the word without a mask
     if constexpr (sizeof(TT) == 1)
-        return __builtin_amdgcn_sbfe((int)d[k >> 2], (uint32_t)(k & 3) * 8u, 8u);
+        return __builtin_amdgcn_sbfe((int)d[k >> 2], (uint32_t)k * 8u, 8u);
     else
-        return __builtin_amdgcn_sbfe((int)d[k >> 1], (uint32_t)(k & 1) * 16u, 16u);
+        return __builtin_amdgcn_sbfe((int)d[k >> 1], (uint32_t)k * 16u, 16u);
 }
 
 template <int MS, typename TT, int MODE, bool LIM>
@@ -541,7 +554,7 @@ __device__ __forceinline__ void anneal_mw_job(int slot, const int32_t *__restric
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj) ea[jj] = elem_addr<MS, TT, MODE>(s, s0 + jj);
             uint64_t pend = active[j];
-            int32_t ej = 0;            // at most 64 moves of |dE| < 2^24
+            block_esum<TT> ej = 0;
             int c = 0;
             // the turn works on dE = sigma F (sigma = 1 - 2y) itself.  A lane
             // that flips has its sigma negated, but its dE is not read again
@@ -553,27 +566,46 @@ __device__ __forceinline__ void anneal_mw_job(int slot, const int32_t *__restric
             const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;    // 2 sigma
             int32_t dE = (F[j] ^ M0) - M0;
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
-            uint64_t ym = __ballot(M0 != 0);             // y of the block's lanes, in scalar registers
+            // y of the block's lanes at the turn's start, in scalar registers:
+            // a lane accepts at most once in the turn, so an accepted lane's y
+            // is still this bit
+            const uint64_t ym0 = __ballot(M0 != 0);
+            uint64_t amask = 0;                          // lanes accepted in the turn
+            // the accepted row's elements in the wave's other blocks are read
+            // after the accept's decision and added one accept later, so the
+            // LDS read is not waited for on the accept chain
+            int32_t pt[NB];
+            int32_t pd2 = 0;
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) pt[jj] = 0;
             while (acc) {
                 const int k = __builtin_ctzll(acc);
-                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
-                const int32_t mk = (int32_t)((ym >> k) & 1ull);
-                ym ^= 1ull << k;
-                ej += dEk;
+                const uint64_t bk = 1ull << k;
+                ej += __builtin_amdgcn_readlane(dE, k);
+                amask |= bk;
+                const bool mk = (ym0 & bk) != 0ull;
                 const int32_t d2 = mk ? -2 : 2;                // y_k = 0: +2, y_k = 1: -2
                 dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol[j], k);
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj)
-                    if (jj != j) F[jj] += d2 * elem_at<TT, MODE>(lds, ea[jj], k, lane);
                 // every lane stores the same word
-                __hip_atomic_store(&out[c], gt | ((uint32_t)k << 1) | (uint32_t)(mk & 1), __ATOMIC_RELAXED,
+                __hip_atomic_store(&out[c], gt | ((uint32_t)k << 1) | (mk ? 1u : 0u), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
                 pend &= (~0ull << k) << 1;
                 acc = __ballot(dE <= tv[j]) & pend;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj)
+                    if (jj != j) {
+                        F[jj] += pd2 * pt[jj];
+                        pt[jj] = elem_at<TT, MODE>(lds, ea[jj], k, lane);
+                    }
+                pd2 = d2;
             }
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj)
+                if (jj != j) F[jj] += pd2 * pt[jj];
             F[j] = (dE ^ M0) - M0;
-            M[j] = ((ym >> lane) & 1ull) ? -1 : 0;
+            M[j] = (((ym0 ^ amask) >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gt | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             e += ej;
             nacc += c;
@@ -844,7 +876,7 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
             uint32_t *out = lists[s];
             const uint32_t gtag = (uint32_t)(G + 1) << 8;
             uint64_t pend = active[j];
-            int32_t ej = 0;
+            block_esum<TT> ej = 0;
             int c = 0;
             // dE = sigma F itself, the flips applied at the end of the turn, as
             // in the in-LDS kernel
@@ -852,13 +884,14 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
             const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;    // 2 sigma
             int32_t dE = (F[j] ^ M0) - M0;
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
-            uint64_t ym = __ballot(M0 != 0);             // y of the block's lanes, in scalar registers
+            const uint64_t ym0 = __ballot(M0 != 0);      // y at the turn's start, as in the in-LDS kernel
+            uint64_t amask = 0;
             while (acc) {
                 const int k = __builtin_ctzll(acc);
-                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
-                const int32_t mk = (int32_t)((ym >> k) & 1ull);
-                ym ^= 1ull << k;
-                ej += dEk;
+                const uint64_t bk = 1ull << k;
+                ej += __builtin_amdgcn_readlane(dE, k);
+                amask |= bk;
+                const bool mk = (ym0 & bk) != 0ull;
                 const int32_t d2 = mk ? -2 : 2;
                 dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol(j), k);
 #pragma unroll
@@ -868,14 +901,14 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
                                          : own_pair(jj, j, NB) * C::OBLK + lane * C::OSTR + k * (int)sizeof(TT);
                     F[jj] += d2 * (int32_t)*reinterpret_cast<const TT *>(ow + o);
                 }
-                __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (uint32_t)(mk & 1), __ATOMIC_RELAXED,
+                __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (mk ? 1u : 0u), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
                 pend &= (~0ull << k) << 1;
                 acc = __ballot(dE <= tv[j]) & pend;
             }
             F[j] = (dE ^ M0) - M0;
-            M[j] = ((ym >> lane) & 1ull) ? -1 : 0;
+            M[j] = (((ym0 ^ amask) >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gtag | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             e += ej;
             nacc += c;
@@ -1080,17 +1113,18 @@ __device__ __forceinline__ void anneal_dc_job(int slot, const int32_t *__restric
             const int32_t M0 = ((ybits >> s) & 1u) ? -1 : 0;
             const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;   // 2 sigma
             int32_t dE = (F[s] ^ M0) - M0;
-            uint64_t ym = __ballot(M0 != 0);
+            const uint64_t ym0 = __ballot(M0 != 0);      // y at the block's start (a lane accepts once)
+            uint64_t amask = 0;                          // lanes accepted in the block
+            block_esum<TT> eb = 0;
             uint64_t acc = __ballot(dE <= tv[s]) & pend;
             int32_t pr[MS];
             int32_t pd2 = 0;                             // 0: nothing pending
             while (acc) {
                 const int k = __builtin_ctzll(acc);
-                const int32_t dEk = __builtin_amdgcn_readlane(dE, k);
-                const int32_t mk = (int32_t)((ym >> k) & 1ull);
-                ym ^= 1ull << k;
-                e += dEk;
-                ++nacc;
+                const uint64_t bk = 1ull << k;
+                eb += __builtin_amdgcn_readlane(dE, k);
+                amask |= bk;
+                const bool mk = (ym0 & bk) != 0ull;
                 const int32_t d2 = mk ? -2 : 2;
                 dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcl, k);
                 pend &= (~0ull << k) << 1;
@@ -1113,7 +1147,9 @@ __device__ __forceinline__ void anneal_dc_job(int slot, const int32_t *__restric
                     if (s3 != s) F[s3] += pd2 * pr[s3];
             }
             F[s] = (dE ^ M0) - M0;
-            if ((ym >> lane) & 1ull)
+            e += eb;
+            nacc += __builtin_popcountll(amask);
+            if (((ym0 ^ amask) >> lane) & 1ull)
                 ybits |= 1u << s;
             else
                 ybits &= ~(1u << s);
