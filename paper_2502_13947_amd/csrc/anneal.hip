@@ -886,6 +886,12 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
             uint64_t acc = __ballot(dE <= tv[j]) & pend;
             const uint64_t ym0 = __ballot(M0 != 0);      // y at the turn's start, as in the in-LDS kernel
             uint64_t amask = 0;
+            // the other own blocks' elements of the accepted row: read after
+            // the decision, added one accept later (off the accept chain)
+            int32_t pt[NB];
+            int32_t pd2 = 0;
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) pt[jj] = 0;
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const uint64_t bk = 1ull << k;
@@ -894,19 +900,25 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
                 const bool mk = (ym0 & bk) != 0ull;
                 const int32_t d2 = mk ? -2 : 2;
                 dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol(j), k);
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj) {
-                    if (jj == j) continue;
-                    const int o = jj > j ? own_pair(j, jj, NB) * C::OBLK + k * C::OSTR + lane * (int)sizeof(TT)
-                                         : own_pair(jj, j, NB) * C::OBLK + lane * C::OSTR + k * (int)sizeof(TT);
-                    F[jj] += d2 * (int32_t)*reinterpret_cast<const TT *>(ow + o);
-                }
                 __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (mk ? 1u : 0u), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
                 pend &= (~0ull << k) << 1;
                 acc = __ballot(dE <= tv[j]) & pend;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) {
+                    if (jj == j) continue;
+                    F[jj] += pd2 * pt[jj];
+                    const int o = jj > j ? own_pair(j, jj, NB) * C::OBLK + k * C::OSTR + lane * (int)sizeof(TT)
+                                         : own_pair(jj, j, NB) * C::OBLK + lane * C::OSTR + k * (int)sizeof(TT);
+                    pt[jj] = (int32_t)*reinterpret_cast<const TT *>(ow + o);
+                }
+                pd2 = d2;
             }
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj)
+                if (jj != j) F[jj] += pd2 * pt[jj];
             F[j] = (dE ^ M0) - M0;
             M[j] = (((ym0 ^ amask) >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gtag | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
