@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(1024) k_anneal_ell(const int32_t *__restrict__
 // chain) and are never read back within the block.  A lane that flips has
 // its sigma negated, but its dE is not read again in the block and the
 // negation commutes with the later updates (the dense kernel's argument).
-// The next block's column is loaded two blocks ahead.
+// The next block's column is loaded a whole block ahead, into the other of
+// two register sets (even and odd blocks).
 __device__ __forceinline__ int32_t dcol_at(const uint32_t (&d)[16], int k)
 {
     // v_bfe_i32 takes its offset modulo 32 (bits [4:0]), so 8 k selects
@@ -251,7 +252,7 @@ __device__ __forceinline__ void load_dcol(uint32_t (&d)[16], const uint8_t *__re
 }
 
 template <int MS>
-__global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restrict__ jobs, int rgroups,
+__global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict__ jobs, int rgroups,
                                                         const int32_t *__restrict__ off, int W,
                                                         const uint32_t *__restrict__ tiles,
                                                         const uint8_t *__restrict__ dblk,
@@ -302,10 +303,15 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
     constexpr int G = (MS + 3) / 4;
     const int sh = 32 - B;
     const int nblk = (m + 63) >> 6;                      // blocks with positions
-    // columns of the next two blocks (in sweep order, wrapping to the next sweep)
-    uint32_t c1[16], c2[16];
-    load_dcol(c1, dq);
-    load_dcol(c2, dq + (size_t)(nblk > 1 ? 1 : 0) * DBLK_BYTES);
+    // the columns of the even and of the odd blocks: once block s is done,
+    // its set is refilled with block s + 2 (in sweep order), a whole block
+    // ahead of its use.  An odd block count is padded with one block without
+    // positions, so that a block's parity, and with it its set, is the same
+    // in every sweep.  With one block the column never changes.
+    uint32_t cA[16], cB[16];
+    const int nbe = nblk + (nblk & 1);
+    load_dcol(cA, dq);
+    if (MS > 1 && nblk > 1) load_dcol(cB, dq + DBLK_BYTES);
     auto thresholds = [&](int sw, int32_t (&tv)[MS]) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -319,7 +325,6 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
     };
     int32_t tvn[MS];
     thresholds(0, tvn);
-    int bcount = 0;                                      // blocks visited, for the column stream
 
     for (int sw = 0; sw < nsw; ++sw) {
         int32_t tv[MS];
@@ -331,18 +336,7 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
             if (s < nblk) {
             const int na = min(m - 64 * s, 64);
             uint64_t pend = na == 64 ? ~0ull : ((1ull << na) - 1ull);
-            uint32_t dc[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                dc[i] = c1[i];
-                c1[i] = c2[i];
-            }
-            ++bcount;
-            {
-                int nb = bcount + 1;                     // the block two ahead of the one just started
-                nb %= nblk;
-                load_dcol(c2, dq + (size_t)nb * DBLK_BYTES);
-            }
+            const uint32_t(&dc)[16] = (s & 1) ? cB : cA;
             // F of the block, exact: every earlier atomic add of this wave precedes this read
             const int32_t fs = F[64 * s + lane];
             const int32_t M0 = ((ybits >> s) & 1u) ? -1 : 0;
@@ -395,6 +389,11 @@ __global__ void __launch_bounds__(1024) k_anneal_ell_dc(const int32_t *__restric
             else
                 ybits &= ~(1u << s);
             }
+            if (MS > 1 && s < nbe) {
+                int t = s + 2;
+                if (t >= nbe) t -= nbe;
+                if (t < nblk) load_dcol((s & 1) ? cB : cA, dq + (size_t)t * DBLK_BYTES);
+            }
         }
     }
 
@@ -423,8 +422,10 @@ qb_status launch_ell(int njobs, int rw, int R, hipStream_t s, const int32_t *job
                      uint64_t seed, uint32_t inst_base, const qb_iter *it, uint8_t *Y, int64_t *e)
 {
     const size_t lds = ell_lds_bytes(MS, W, rw);
-    if (b->dblk_valid && W <= 64) {
+    if (b->dblk_valid && W <= 64 && rw <= 8) {
         // the extraction wrote the int8 diagonal blocks after the ELL rows
+        // (at most 8 replicas per workgroup: up to 256 registers per lane
+        // hold the two column sets; beyond, the in-LDS kernel, same result)
         QB_TRY_HIP(hipFuncSetAttribute((const void *)k_anneal_ell_dc<MS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)LDS_MAX));
         const int rgroups = (R + rw - 1) / rw;

@@ -297,8 +297,9 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                 dl_l = ((xi ^ 1u) << 15) | dnew_i;
                 ul_l = Un;
             }
-            *one_lane(L, L.dl + i, lane, li) = (uint16_t)dl_l;
-            *one_lane(L, L.Ul + i, lane, li) = ul_l;
+            // (lane li's leaf of the node is i itself: jl == i there)
+            *one_lane(L, L.dl + jl, lane, li) = (uint16_t)dl_l;
+            *one_lane(L, L.Ul + jl, lane, li) = ul_l;
             if (improved) {   // x_min is the current x
                 for (int w = lane; w < NXW; w += 64) L.pw[w] = 0u;
             } else {
@@ -369,11 +370,14 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                     }
                 }
             }
+            {
+                const int trow = lane == plane ? ps : -1;   // the row this lane rewrites, if any
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const bool mine = s == ps && lane == plane;
-                sj[s] = mine ? sjv : sj[s];
-                su[s] = mine ? suv : su[s];
+                for (int s = 0; s < S; ++s) {
+                    const bool mine = trow == s;
+                    sj[s] = mine ? sjv : sj[s];
+                    su[s] = mine ? suv : su[s];
+                }
             }
 
             // neighbours: D_c += 2(1 - 2x_c) sgn Q_ci, without a branch (a lane
