@@ -243,14 +243,17 @@ def ttt_main(a):
                          plain_best=bp[-1], learned_best_2x=bl[-1], plain_trace=bp, learned_trace=bl,
                          ms_per_iter_plain=tp[-1] / len(tp), ms_per_iter_learned=tl[-1] / len(tl)))
         del L
-    ratios = [r["t_learned_ms"] / r["t_plain_ms"] for r in rows if r["t_learned_ms"] is not None]
+    # a seed where the learned run never reaches the target counts as an
+    # infinite ratio (a loss), so the median is over every seed
+    ratios = [r["t_learned_ms"] / r["t_plain_ms"] if r["t_learned_ms"] is not None else float("inf") for r in rows]
+    med = float(np.median(ratios)) if ratios else float("inf")
     out = {
         "metric": "time-to-target-energy, learned vs plain selection",
         "workload": name,
         "target": "best energy of the plain selector after %d outer iterations" % a.ttt_iters,
         "seeds": a.ttt_seeds,
-        "reached": len(ratios),
-        "median_ratio_learned_over_plain": float(np.median(ratios)) if ratios else None,
+        "reached": sum(1 for r in rows if r["t_learned_ms"] is not None),
+        "median_ratio_learned_over_plain": med if med != float("inf") else None,
         "learned_wins_at_equal_time": sum(1 for r in rows if r["learned_best_at_equal_time"] is not None
                                           and r["learned_best_at_equal_time"] <= r["plain_best"]),
         "selection_quality": quality,

@@ -62,14 +62,17 @@ class Trainer:
         losses = []
         for ep in range(epochs):
             perm = torch.as_tensor(rng.permutation(N), device=self.dev)
+            tot, nb = 0.0, 0
             for b0 in range(0, N - self.batch + 1, self.batch):
                 sel = perm[b0:b0 + self.batch]
                 fb = feat[sel].contiguous()
                 lb = label[sel].contiguous()
                 qb.mlp_grad(fb, lb, self.W, self.grad, self.loss, self.work)
+                tot += float(self.loss.item())   # the batch's mean loss, before its step
+                nb += 1
                 self.step += 1
                 qb.mlp_adam(self.grad, self.master, self.m, self.v, self.step, self.lr, self.W)
-            losses.append(float(self.loss.item()))
+            losses.append(tot / max(nb, 1))      # mean over the epoch's batches
         return losses
 
     def weights(self) -> np.ndarray:
