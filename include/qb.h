@@ -135,12 +135,14 @@ qb_status qb_best(int32_t n, int32_t z, const uint8_t *X_d, const int64_t *E_d, 
  * allowed, the argmin over all); then C_i += tenure and every positive C is
  * decremented.  On return X[p] = x_min, H[p] = Q x_min, E[p] = OV_min
  * (E[p] must hold x^T Q x on entry), T[p][j] = flips of j, LF[p][j] = the
- * 1-based step of j's last flip (0 if none).  Capacity: n <= 16384 (dense
+ * 1-based step of j's last flip (0 if none).  A tenure beyond alpha + 1
+ * is taken as alpha + 1 (the same search).  Capacity: n <= 16384 (dense
  * problems; one workgroup of 512 or 1024 threads per solution, fixed when
  * the problem is created from n and the range of the move values, every
- * step reads one row of Q) or n <= 20480 (sparse problems; 1024 threads per
- * solution, every step reads the flipped variable's off-diagonal entries
- * only); QB_E_CAPACITY beyond.  QB_E_RANGE when |Q_kk| + 2 max_k eta_k
+ * step reads one row of Q) or, for sparse problems (every step reads the
+ * flipped variable's off-diagonal entries only), n <= 25856 on the tree
+ * kernel and n <= 20480 on the lane kernel (qb_problem_set_tabu_variant);
+ * QB_E_CAPACITY beyond.  QB_E_RANGE when |Q_kk| + 2 max_k eta_k
  * leaves too few bits for the kernel's 32-bit (move, element) keys.  T_d
  * and LF_d may not be NULL. */
 qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d, int64_t *E_d,

@@ -28,6 +28,8 @@
 // element.  x_min is never copied: per-variable "flipped since the last
 // improvement" bits recover it, and the field is moved to x_min with the
 // rows of the differing variables.
+#include <algorithm>
+
 #include "qb_internal.h"
 
 #include <type_traits>
@@ -431,6 +433,10 @@ extern "C" qb_status qb_tabu(qb_problem P, int32_t z, uint8_t *X_d, int32_t *H_d
 {
     if (!P || z < 1 || !X_d || !H_d || !E_d || !T_d || !LF_d || alpha < 0 || tenure < 0)
         return QB_E_ARG;
+    // a tenure that reaches past the last step keeps a variable tabu to the
+    // end either way: alpha + 1 gives the same search and keeps the kernels'
+    // step and counter arithmetic far from int32 overflow
+    tenure = (int32_t)std::min<int64_t>(tenure, (int64_t)alpha + 1);
     hipStream_t s = qb_stream(stream);
     if (P->sparse)
         return qb_tabu_sparse_launch(P, z, X_d, H_d, E_d, alpha, tenure, aspiration != 0, T_d, LF_d, s);

@@ -280,8 +280,10 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             const uint32_t bit = 1u << (i & 31);
             const int32_t sgn = xi ? -1 : 1;   // h_j += sgn Q_ji
             // the last tabu step: step + max(max(Ui - step + 1, 0) + tenure - 1, 0),
-            // which equals max(Ui + tenure, step + max(tenure - 1, 0))
-            const int32_t Un = max(Ui + tenure, step + ten1);
+            // which equals max(Ui + tenure, step + max(tenure - 1, 0)); any
+            // value past alpha means tabu to the end, so it is held at
+            // alpha + 1 (repeated extensions cannot grow it)
+            const int32_t Un = min(max(Ui + tenure, step + ten1), alpha + 1);
             const int32_t dmove = (int32_t)dib - (int32_t)bias;
             const uint32_t dnew_i = 2u * bias - dib;   // D_i -> -D_i
             OV += dmove;

@@ -103,7 +103,9 @@ def test_field_energy_best(n, z, int8):
                                                   (2200, 1, 1500, 2300, True),
                                                   # the ends of the eight-wave sizes: the first one,
                                                   # and a row with no padding at all
-                                                  (2049, 2, 900, 13, True), (5120, 2, 700, 34, True)])
+                                                  (2049, 2, 900, 13, True), (5120, 2, 700, 34, True),
+                                                  # a tenure far past the last step (taken as alpha + 1)
+                                                  (300, 2, 400, 1_000_000, True)])
 def test_tabu_bit_exact(n, z, alpha, tenure, asp, int8):
     say("tabu", n, z, alpha, tenure, asp, int8)
     Q = inputs.dense_qubo(n, 0.3, 5) if int8 else wide_qubo(n, 5)

@@ -152,6 +152,7 @@ def test_sparse_field_energy_rankk(case, z):
     ("t:30x37", 2, 3000, 100, True),     # two slots per lane on the tree
     ("t:30x37", 2, 3000, 176, True),     # three slots, the ring position free only 16 steps early
     ("t:30x37", 2, 3000, 230, True),     # four slots
+    ("t:20x20", 2, 600, 1_000_000, True),  # a tenure far past the last step (taken as alpha + 1)
 ])
 @pytest.mark.parametrize("variant", ["lanes", "tree"])
 def test_sparse_tabu_bit_exact(case, z, alpha, tenure, asp, variant):

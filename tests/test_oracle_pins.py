@@ -174,6 +174,23 @@ def test_tabu_zero_steps_is_identity():
     assert (x == x0).all() and (h == h0).all() and ov == ov0 and T.sum() == 0
 
 
+@pytest.mark.parametrize("asp", [True, False])
+def test_tabu_tenure_past_the_last_step_equals_alpha_plus_one(asp):
+    # Alg. 1: once C_i >= the steps left, i stays tabu to the end whatever its
+    # exact value, so every tenure beyond alpha + 1 gives the same search (the
+    # library takes such a tenure as alpha + 1)
+    for seed in range(4):
+        n, alpha = 30, 45
+        Q = rand_sym(n, 300 + seed)
+        x0 = inputs.random_solutions(1, n, 310 + seed)[0]
+        h0 = oracle.field(Q, x0)[0]
+        ov0 = oracle.energy_def(Q, x0)
+        ref = oracle.tabu(Q, x0, h0, ov0, alpha, alpha + 1, asp)
+        for tenure in (alpha + 2, 1000, 1_000_000):
+            got = oracle.tabu(Q, x0, h0, ov0, alpha, tenure, asp)
+            assert all((np.asarray(a) == np.asarray(b)).all() for a, b in zip(ref, got)), (seed, tenure)
+
+
 def test_tabu_reaches_brute_force_optimum_on_tiny_instances():
     hits = 0
     for seed in range(10):
