@@ -875,7 +875,6 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
             const int G = G0 + j;
             uint32_t *out = lists[s];
             const uint32_t gtag = (uint32_t)(G + 1) << 8;
-            uint64_t pend = active[j];
             block_esum<TT> ej = 0;
             int c = 0;
             // dE = sigma F itself, the flips applied at the end of the turn, as
@@ -883,7 +882,12 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
             const int32_t M0 = M[j];
             const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;    // 2 sigma
             int32_t dE = (F[j] ^ M0) - M0;
-            uint64_t acc = __ballot(dE <= tv[j]) & pend;
+            // a lane past the block, or at or below the last accept, compares
+            // against INT32_MIN, which no dE reaches (|dE| <= |F| <= (2n + 1)
+            // max|Q| < 2^31, checked when the problem is created): no mask of
+            // pending lanes on the accept chain
+            int32_t tk = (active[j] >> lane) & 1ull ? tv[j] : INT32_MIN;
+            uint64_t acc = __ballot(dE <= tk);
             const uint64_t ym0 = __ballot(M0 != 0);      // y at the turn's start, as in the in-LDS kernel
             uint64_t amask = 0;
             // the other own blocks' elements of the accepted row: read after
@@ -903,8 +907,8 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
                 __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (mk ? 1u : 0u), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
-                pend &= (~0ull << k) << 1;
-                acc = __ballot(dE <= tv[j]) & pend;
+                tk = lane <= k ? INT32_MIN : tk;
+                acc = __ballot(dE <= tk);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int jj = 0; jj < NB; ++jj) {

@@ -272,25 +272,40 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int r = rg * rw + wid;
 
+    // Per wave MP fields and then 64 dump words: dump word L (F[MP + L])
+    // holds the ELL word (column MP + L, value 0) and only ever receives
+    // zeros.  A padding word at position w of a staged row becomes that same
+    // word for column MP + w, so every lane adds its row word without a
+    // branch or mask: a padding word, or a lane past the row reading its own
+    // dump word, adds zero into its own dump word (no two lanes share one).
     uint32_t *tl = dl;                                   // [m][W]
-    int32_t *F = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + wid * MP;
-    // the wave's 64 words where lanes with no entry of the row add their zero
-    int32_t *dump = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + rw * MP + wid * 64;
+    int32_t *F = reinterpret_cast<int32_t *>(dl + (size_t)MP * W) + wid * (MP + 64);
     {
-        const uint4 *src = reinterpret_cast<const uint4 *>(tiles + (int64_t)base * W);
-        uint4 *dst = reinterpret_cast<uint4 *>(tl);
-        const int n16 = m * W / 4;
-        for (int t = tid; t < n16; t += blockDim.x) dst[t] = src[t];
+        const uint32_t *src = tiles + (int64_t)base * W;
+        const int nw = m * W;
+        for (int t = tid; t < nw; t += blockDim.x) {
+            const uint32_t v = src[t];
+            tl[t] = v != 0u ? v : (uint32_t)(MP + t % W);
+        }
     }
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
         const int pos = 64 * s + lane;
         F[pos] = pos < m ? F0[base + pos] : 0;
     }
+    F[MP + lane] = MP + lane;
     __syncthreads();
     if (r >= R) return;   // no barrier follows
 
     const uint8_t *dq = dblk + (size_t)dboff[q] * DBLK_BYTES + lane * 64;
+    // byte offset of a row word in LDS: row_offset * rsel + rbase, with rsel =
+    // 1 and rbase = 4 L for a lane L < W, else rsel = 0 and rbase the lane's
+    // dump word
+    uint32_t rsel = lane < W ? 1u : 0u;
+    asm volatile("" : "+v"(rsel));   // opaque: one multiply-add, not a select
+    const uint32_t rbase = lane < W ? 4u * (uint32_t)lane
+                                    : (uint32_t)(reinterpret_cast<const char *>(F + MP + lane) -
+                                                 reinterpret_cast<const char *>(dl));
     uint32_t ybits = 0;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
@@ -335,7 +350,6 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
         for (int s = 0; s < MS; ++s) {
             if (s < nblk) {
             const int na = min(m - 64 * s, 64);
-            uint64_t pend = na == 64 ? ~0ull : ((1ull << na) - 1ull);
             const uint32_t(&dc)[16] = (s & 1) ? cB : cA;
             // F of the block, exact: every earlier atomic add of this wave precedes this read
             const int32_t fs = F[64 * s + lane];
@@ -347,41 +361,39 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
             const uint64_t ym0 = __ballot(M0 != 0);
             uint64_t amask = 0;        // lanes accepted in the block
             int32_t eb = 0;            // their dE: at most 64 moves of |dE| < 2^24
-            uint64_t acc = __ballot(dE <= tv[s]) & pend;
-            // the previous accept's row word (as read: lanes past the row hold a
-            // copy of its last word) and factor; its adds are issued one accept
-            // late, and the word is masked only then, so the read is not
-            // waited for on the accept chain
-            uint32_t pwr = 0u;
+            // the lane's threshold while it may still accept in the block: a
+            // lane past the block, or at or below the last accept, gets
+            // INT32_MIN, which no dE reaches (|dE| < 2^24), so the ballot
+            // needs no mask of pending lanes
+            int32_t tk = lane < na ? tv[s] : INT32_MIN;
+            uint64_t acc = __ballot(dE <= tk);
+            // the previous accept's row word and factor (a lane's own dump
+            // word before the first accept); its adds are issued one accept
+            // late, so the read is not waited for on the accept chain
+            uint32_t pwr = (uint32_t)(MP + lane);
             int32_t pd2 = 0;
-            const int wl = min(lane, W - 1);
             while (acc) {
                 const int k = __builtin_ctzll(acc);
                 const uint64_t bk = 1ull << k;
                 eb += __builtin_amdgcn_readlane(dE, k);
                 amask |= bk;
-                const bool mk = (ym0 & bk) != 0ull;
+                const bool mk = (ym0 >> k) & 1ull;
                 const int32_t d2 = mk ? -2 : 2;
                 dE += (mk ? ns2 : s2) * dcol_at(dc, k);
-                pend &= (~0ull << k) << 1;
-                const uint64_t accn = __ballot(dE <= tv[s]) & pend;
+                tk = lane <= k ? INT32_MIN : tk;
+                const uint64_t accn = __ballot(dE <= tk);
                 // the chain of this accept is done: only now wait for the
                 // previous accept's row word and add it, then read this one's
                 __builtin_amdgcn_sched_barrier(0);
-                {
-                    // every lane adds, without a branch: a padding word, or a
-                    // lane past the row, adds zero to its own dump word
-                    const uint32_t pw = lane < W ? pwr : 0u;
-                    atomicAdd(pw != 0u ? &F[qb_ell_col(pw)] : dump + lane, pd2 * qb_ell_val(pw));
-                }
-                pwr = tl[(size_t)(64 * s + k) * W + wl];
+                atomicAdd(&F[qb_ell_col(pwr)], pd2 * qb_ell_val(pwr));
+                // row word of lane L < W, else the lane's dump word
+                pwr = *reinterpret_cast<const uint32_t *>(
+                    reinterpret_cast<const char *>(dl) +
+                    __umul24((uint32_t)((64 * s + k) * W * 4), rsel) + rbase);
                 pd2 = d2;
                 acc = accn;
             }
-            {
-                const uint32_t pw = lane < W ? pwr : 0u;
-                atomicAdd(pw != 0u ? &F[qb_ell_col(pw)] : dump + lane, pd2 * qb_ell_val(pw));
-            }
+            atomicAdd(&F[qb_ell_col(pwr)], pd2 * qb_ell_val(pwr));
             e += eb;
             nacc += __builtin_popcountll(amask);
             if (((ym0 ^ amask) >> lane) & 1ull)
