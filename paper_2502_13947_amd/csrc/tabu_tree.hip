@@ -18,9 +18,11 @@
 //   pw      bit vector of "flipped since the last improvement",
 //   nf[q]   the least key over the free leaves of node q (leaves 64q..64q+63),
 //   slots   S (variable, last tabu step) pairs per lane for tabu variables;
-//           the variable that turns tabu at step t goes to row (t / 64) mod S
-//           of lane t mod 64, a slot that is empty unless an earlier
-//           occupant's tenure was extended (then the first empty slot),
+//           the variable that turns tabu at step t goes to row 0 of lane
+//           t mod 64, and the rows rotate by one after every 64 steps, so
+//           that slot last took a variable 64 S steps earlier: it is empty
+//           unless that occupant's tenure was extended (then the first empty
+//           slot),
 //   ob      bit vector of tabu variables that found no slot (normally empty;
 //           scanned at every step while it is not, so the result never
 //           depends on the slot count).
@@ -179,7 +181,6 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
     }
     int ovf = 0;        // tabu variables outside the slots (their bits in ob)
     int bi = 0;         // the variable flipped at step 64 b + lane of the current batch b
-    int rs = 0;         // slot row of this step's ring position, (step / 64) mod S
     int64_t OV = E[p];
     int64_t OVmin = OV;
     // gap = OV - OV_min >= 0 in 32 bits: exact from each batch start (where it
@@ -313,28 +314,31 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             node_from(L, qi, dl_l, ul_l, step, n, IB, lane);
 
             // the slots: a free variable that turns tabu goes into the ring
-            // position of this step (row rs, lane step mod 64), whose last
-            // occupant came 64 S steps ago or earlier, so with 64 S >= tenure
-            // it is empty unless that variable's tenure was extended; else
-            // into the first empty slot, else the overflow bits (where a tabu
-            // variable sits never changes a key or a result).  A tabu variable
-            // that flips again keeps its slot with the new step, or leaves it
-            // at tenure 0.  Either way one slot (row ps, lane plane) takes the
-            // pair (sjv, suv), written without a branch.
+            // position of this step (row 0, lane step mod 64), whose last
+            // occupant came 64 S steps ago or earlier (the rows rotate every
+            // 64 steps), so with 64 S >= tenure it is empty unless that
+            // variable's tenure was extended; else into the first empty slot,
+            // else the overflow bits (where a tabu variable sits never changes
+            // a key or a result).  A tabu variable that flips again keeps its
+            // slot with the new step, or leaves it at tenure 0.  Either way one
+            // slot (row ps, lane plane) takes the pair (sjv, suv): row 0
+            // without a branch, the other rows (only after a search) behind
+            // one uniform branch.
             const bool was_tabu = Ui >= step, now_tabu = Un > step;
             int ps = -1, plane = 0, sjv = i;
             int32_t suv = Un;
             if (!was_tabu) {
                 if (now_tabu) {
                     plane = step & 63;
-                    int cur = sj[0];
-#pragma unroll
-                    for (int s = 1; s < S; ++s) cur = rs == s ? sj[s] : cur;
-                    ps = rs;
-                    if (__builtin_amdgcn_readlane(cur, plane) != SENT) {
+                    ps = 0;
+                    if (__builtin_amdgcn_readlane(sj[0], plane) != SENT) {
                         ps = -1;
+                        // the highest row with an empty slot: row r is the ring
+                        // row again after r rotations, and row 0 (this batch's
+                        // ring row, whose later lanes the next steps take) only
+                        // when no other row has one
 #pragma unroll
-                        for (int s = S - 1; s >= 0; --s) {
+                        for (int s = 0; s < S; ++s) {
                             const uint64_t em = __ballot(sj[s] == SENT);
                             if (em) {
                                 ps = s;
@@ -374,11 +378,15 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             }
             {
                 const int trow = lane == plane ? ps : -1;   // the row this lane rewrites, if any
+                sj[0] = trow == 0 ? sjv : sj[0];
+                su[0] = trow == 0 ? suv : su[0];
+                if (S > 1 && ps > 0) {
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    const bool mine = trow == s;
-                    sj[s] = mine ? sjv : sj[s];
-                    su[s] = mine ? suv : su[s];
+                    for (int s = 1; s < S; ++s) {
+                        const bool mine = trow == s;
+                        sj[s] = mine ? sjv : sj[s];
+                        su[s] = mine ? suv : su[s];
+                    }
                 }
             }
 
@@ -424,7 +432,17 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             __hip_atomic_fetch_add(Tout + ro + bi, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_max(LFout + ro + bi, b0 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        rs = rs + 1 == S ? 0 : rs + 1;
+        // the next batch's ring row becomes row 0
+        if (S > 1) {
+            const int j0 = sj[0], u0 = su[0];
+#pragma unroll
+            for (int s = 0; s + 1 < S; ++s) {
+                sj[s] = sj[s + 1];
+                su[s] = su[s + 1];
+            }
+            sj[S - 1] = j0;
+            su[S - 1] = u0;
+        }
     }
     __syncthreads();
 
