@@ -300,7 +300,8 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
     const uint8_t *dq = dblk + (size_t)dboff[q] * DBLK_BYTES + lane * 64;
     // byte offset of a row word in LDS: row_offset * rsel + rbase, with rsel =
     // 1 and rbase = 4 L for a lane L < W, else rsel = 0 and rbase the lane's
-    // dump word
+    // dump word (row offsets stay below 1024 * 64 * 4 < 2^24, the range of
+    // the 24-bit multiply)
     uint32_t rsel = lane < W ? 1u : 0u;
     asm volatile("" : "+v"(rsel));   // opaque: one multiply-add, not a select
     const uint32_t rbase = lane < W ? 4u * (uint32_t)lane
