@@ -583,6 +583,7 @@ __device__ __forceinline__ void anneal_mw_job(int slot, const int32_t *__restric
                 const uint64_t bk = 1ull << k;
                 ej += __builtin_amdgcn_readlane(dE, k);
                 amask |= bk;
+                // (the bit test of qb_accept_sign measured slower in this kernel)
                 const bool mk = (ym0 & bk) != 0ull;
                 const int32_t d2 = mk ? -2 : 2;                // y_k = 0: +2, y_k = 1: -2
                 dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol[j], k);
@@ -901,10 +902,10 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
                 const uint64_t bk = 1ull << k;
                 ej += __builtin_amdgcn_readlane(dE, k);
                 amask |= bk;
-                const bool mk = (ym0 & bk) != 0ull;
-                const int32_t d2 = mk ? -2 : 2;
-                dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcol(j), k);
-                __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (mk ? 1u : 0u), __ATOMIC_RELAXED,
+                int32_t f, d2, yk;
+                qb_accept_sign<true>(ym0, k, s2, ns2, f, d2, yk);
+                dE += __mul24(f, diag_at<TT, DW>(dcol(j), k));
+                __hip_atomic_store(&out[c], gtag | ((uint32_t)k << 1) | (uint32_t)yk, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 ++c;
                 tk = lane <= k ? INT32_MIN : tk;
@@ -913,7 +914,7 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
 #pragma unroll
                 for (int jj = 0; jj < NB; ++jj) {
                     if (jj == j) continue;
-                    F[jj] += pd2 * pt[jj];
+                    F[jj] += __mul24(pd2, pt[jj]);
                     const int o = jj > j ? own_pair(j, jj, NB) * C::OBLK + k * C::OSTR + lane * (int)sizeof(TT)
                                          : own_pair(jj, j, NB) * C::OBLK + lane * C::OSTR + k * (int)sizeof(TT);
                     pt[jj] = (int32_t)*reinterpret_cast<const TT *>(ow + o);
@@ -922,7 +923,7 @@ __device__ __forceinline__ void anneal_mw_g_job(int slot, const int32_t *__restr
             }
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj)
-                if (jj != j) F[jj] += pd2 * pt[jj];
+                if (jj != j) F[jj] += __mul24(pd2, pt[jj]);
             F[j] = (dE ^ M0) - M0;
             M[j] = (((ym0 ^ amask) >> lane) & 1ull) ? -1 : 0;
             __hip_atomic_store(&out[c], gtag | (64u << 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1140,9 +1141,9 @@ __device__ __forceinline__ void anneal_dc_job(int slot, const int32_t *__restric
                 const uint64_t bk = 1ull << k;
                 eb += __builtin_amdgcn_readlane(dE, k);
                 amask |= bk;
-                const bool mk = (ym0 & bk) != 0ull;
-                const int32_t d2 = mk ? -2 : 2;
-                dE += (mk ? ns2 : s2) * diag_at<TT, DW>(dcl, k);
+                int32_t f, d2, yk;
+                qb_accept_sign<false>(ym0, k, s2, ns2, f, d2, yk);
+                dE += __mul24(f, diag_at<TT, DW>(dcl, k));
                 pend &= (~0ull << k) << 1;
                 const uint64_t accn = __ballot(dE <= tv[s]) & pend;
                 // the chain is done: add the previous accepted row to the
@@ -1151,7 +1152,7 @@ __device__ __forceinline__ void anneal_dc_job(int slot, const int32_t *__restric
                 if (pd2) {
 #pragma unroll
                     for (int s3 = 0; s3 < MS; ++s3)
-                        if (s3 != s) F[s3] += pd2 * pr[s3];
+                        if (s3 != s) F[s3] += __mul24(pd2, pr[s3]);
                 }
                 fetch_row<MS, TT, MODE>(lds, gtile, 64 * s + k, lane, pr);
                 pd2 = d2;
@@ -1160,7 +1161,7 @@ __device__ __forceinline__ void anneal_dc_job(int slot, const int32_t *__restric
             if (pd2) {
 #pragma unroll
                 for (int s3 = 0; s3 < MS; ++s3)
-                    if (s3 != s) F[s3] += pd2 * pr[s3];
+                    if (s3 != s) F[s3] += __mul24(pd2, pr[s3]);
             }
             F[s] = (dE ^ M0) - M0;
             e += eb;

@@ -378,15 +378,15 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
                 const uint64_t bk = 1ull << k;
                 eb += __builtin_amdgcn_readlane(dE, k);
                 amask |= bk;
-                const bool mk = (ym0 >> k) & 1ull;
-                const int32_t d2 = mk ? -2 : 2;
-                dE += (mk ? ns2 : s2) * dcol_at(dc, k);
+                int32_t f, d2, yk;
+                qb_accept_sign<false>(ym0, k, s2, ns2, f, d2, yk);
+                dE += __mul24(f, dcol_at(dc, k));
                 tk = lane <= k ? INT32_MIN : tk;
                 const uint64_t accn = __ballot(dE <= tk);
                 // the chain of this accept is done: only now wait for the
                 // previous accept's row word and add it, then read this one's
                 __builtin_amdgcn_sched_barrier(0);
-                atomicAdd(&F[qb_ell_col(pwr)], pd2 * qb_ell_val(pwr));
+                atomicAdd(&F[qb_ell_col(pwr)], __mul24(pd2, qb_ell_val(pwr)));
                 // row word of lane L < W, else the lane's dump word
                 pwr = *reinterpret_cast<const uint32_t *>(
                     reinterpret_cast<const char *>(dl) +

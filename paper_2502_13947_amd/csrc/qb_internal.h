@@ -283,6 +283,38 @@ __device__ __forceinline__ uint32_t qb_word(uint4 v, int w)
     return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
 }
 
+// The annealers' accepted spin k: y_k is bit k of the uniform mask ym (y of
+// the block's lanes at its start).  One bit test feeds the selects: first
+// f = y_k ? n : p per lane (the lane's factor sigma d2 on the accepted row's
+// coupling, the next step of the accept chain), then, off the chain, d2 =
+// y_k ? -2 : 2 and, with YK, yk = y_k (uniform).  Written as one ALU
+// sequence: the compiler otherwise builds y_k through a 64-bit shift, and,
+// compare and select, all on the accept chain.
+template <bool YK>
+__device__ __forceinline__ void qb_accept_sign(uint64_t ym, int k, int32_t p, int32_t n, int32_t &f, int32_t &d2,
+                                               int32_t &yk)
+{
+    if constexpr (YK) {
+        asm("s_bitcmp1_b64 %[ym], %[k]\n\t"
+            "s_cselect_b64 vcc, -1, 0\n\t"
+            "v_cndmask_b32 %[f], %[p], %[n], vcc\n\t"
+            "s_cselect_b32 %[d2], -2, 2\n\t"
+            "s_cselect_b32 %[yk], 1, 0"
+            : [f] "=v"(f), [d2] "=s"(d2), [yk] "=s"(yk)
+            : [ym] "s"(ym), [k] "s"(k), [p] "v"(p), [n] "v"(n)
+            : "vcc", "scc");
+    } else {
+        asm("s_bitcmp1_b64 %[ym], %[k]\n\t"
+            "s_cselect_b64 vcc, -1, 0\n\t"
+            "v_cndmask_b32 %[f], %[p], %[n], vcc\n\t"
+            "s_cselect_b32 %[d2], -2, 2"
+            : [f] "=v"(f), [d2] "=s"(d2)
+            : [ym] "s"(ym), [k] "s"(k), [p] "v"(p), [n] "v"(n)
+            : "vcc", "scc");
+        yk = 0;
+    }
+}
+
 __device__ __forceinline__ int64_t qb_wave_sum_i64(int64_t v)
 {
 #pragma unroll
