@@ -211,16 +211,26 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
 #pragma unroll
             for (int s = 0; s < S; ++s) dv[s] = L.dl[sj[s]];
             __builtin_amdgcn_sched_barrier(0);   // every read issued before the first wait: one round trip
-#pragma unroll
-            for (int r = 0; r < NR; ++r) fm = min(fm, nv[r]);
-            uint32_t sk[S];
+            // a slot's key is a candidate when it is below st: all ones for a
+            // slot whose tenure ended (free), tbk for a tabu one (aspiration);
+            // formed while the reads are in flight, so each slot needs one
+            // compare and one select after them
+            uint32_t sk[S], st[S];
             bool sx[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                sk[s] = ((dv[s] & DMASK) << IB) | (uint32_t)sj[s];
                 sx[s] = su[s] < step;
-                fm = min(fm, sx[s] || sk[s] < tbk ? sk[s] : NONE);
+                st[s] = sx[s] ? NONE : tbk;
             }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) fm = min(fm, nv[r]);
+            uint32_t cm = NONE;   // least slot candidate, apart from fm's chain
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                sk[s] = (__builtin_amdgcn_ubfe(dv[s], 0, 15) << IB) | (uint32_t)sj[s];
+                cm = min(cm, sk[s] < st[s] ? sk[s] : NONE);
+            }
+            fm = min(fm, cm);
             uint32_t tov = NONE;   // least tabu key among the overflow bits
             if (ovf > 0) {
                 // tabu variables without a slot: scan their bits
