@@ -270,7 +270,17 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
             uint32_t wd = 0u;
             if (lane < W) wd = ell[(int64_t)i * W + lane];
 
-            // slots whose tenure ended rejoin the tree
+            // the winner's node, read once: its lane gives x_i and U_i, and the
+            // node is recomputed from registers with the winner's leaf rewritten
+            const int qi = i >> 6, li = i & 63;
+            const int jl = (qi << 6) + lane;
+            uint32_t dl_l = L.dl[jl];
+            int32_t ul_l = L.Ul[jl];
+
+            // slots whose tenure ended rejoin the tree (issued after the node
+            // read, which waits for nothing of theirs, and before the node's
+            // recompute is stored, which must land after them: the winner may
+            // be one of these variables)
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 __hip_atomic_fetch_min(sx[s] ? L.nf + (sj[s] >> 6) : L.dump + lane, sx[s] ? sk[s] : NONE,
@@ -278,13 +288,6 @@ __global__ void __launch_bounds__(64) k_tabu_tree(const uint32_t *__restrict__ e
                 sj[s] = sx[s] ? SENT : sj[s];
                 su[s] = sx[s] ? NEVER : su[s];
             }
-
-            // the winner's node, read once: its lane gives x_i and U_i, and the
-            // node is recomputed from registers with the winner's leaf rewritten
-            const int qi = i >> 6, li = i & 63;
-            const int jl = (qi << 6) + lane;
-            uint32_t dl_l = L.dl[jl];
-            int32_t ul_l = L.Ul[jl];
             const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)dl_l, li);
             const int32_t Ui = __builtin_amdgcn_readlane(ul_l, li);
             const uint32_t xi = di >> 15;
