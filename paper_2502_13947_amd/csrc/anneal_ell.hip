@@ -341,6 +341,10 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
     };
     int32_t tvn[MS];
     thresholds(0, tvn);
+    // F of the next block, read as soon as the block before it has issued
+    // its last add (every earlier atomic add of this wave precedes the read,
+    // so it is exact), so that its latency overlaps that block's bookkeeping
+    int32_t fsn = F[lane];
 
     for (int sw = 0; sw < nsw; ++sw) {
         int32_t tv[MS];
@@ -352,8 +356,7 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
             if (s < nblk) {
             const int na = min(m - 64 * s, 64);
             const uint32_t(&dc)[16] = (s & 1) ? cB : cA;
-            // F of the block, exact: every earlier atomic add of this wave precedes this read
-            const int32_t fs = F[64 * s + lane];
+            const int32_t fs = fsn;
             const int32_t M0 = ((ybits >> s) & 1u) ? -1 : 0;
             const int32_t s2 = M0 ? -2 : 2, ns2 = -s2;   // 2 sigma
             int32_t dE = (fs ^ M0) - M0;
@@ -394,13 +397,12 @@ __global__ void __launch_bounds__(512) k_anneal_ell_dc(const int32_t *__restrict
                 pd2 = d2;
                 acc = accn;
             }
-            atomicAdd(&F[qb_ell_col(pwr)], pd2 * qb_ell_val(pwr));
+            atomicAdd(&F[qb_ell_col(pwr)], __mul24(pd2, qb_ell_val(pwr)));
+            fsn = F[64 * (s + 1 < nblk ? s + 1 : 0) + lane];
             e += eb;
             nacc += __builtin_popcountll(amask);
-            if (((ym0 ^ amask) >> lane) & 1ull)
-                ybits |= 1u << s;
-            else
-                ybits &= ~(1u << s);
+            const uint32_t yb = (uint32_t)((ym0 ^ amask) >> lane) & 1u;
+            ybits = (ybits & ~(1u << s)) | (yb << s);
             }
             if (MS > 1 && s < nbe) {
                 int t = s + 2;
